@@ -1,0 +1,148 @@
+"""Spherical (Bessel) parameterisation of the Richards-Wolf integral, FP64 oracle.
+
+Test infrastructure only.
+
+* ``field_polar``  -- the polar double integral, eq. "polar vectorial" (Sec. 3.3)
+  with the correction factors of eq. "vectorial general with correction":
+  d Omega = sin t dt dp, Gauss-Legendre in theta, trapezoid in phi (spectrally
+  exact for the periodic phi integrand), evaluated point by point with the full
+  plane-wave phase k s . rho -- no Bessel identity is used.
+* ``field_bessel`` -- the 1-D form, eq. "polar vectorial final" with the three
+  integrals of eq. "I0", J_n from SciPy; valid for an axisymmetric pupil.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+from scipy import special
+
+from . import optics as O
+
+
+def _axisymmetric_phase(sin_t, opt: O.Optics, zernike=None, t_s: float = 0.0,
+                        gl_compensated: bool = False):
+    """W(theta) for an axisymmetric pupil: Gibson-Lanni and m = 0 Zernike terms."""
+    w = np.zeros(np.shape(sin_t), dtype=np.complex128)
+    if opt.gl is not None:
+        w = w + O.gibson_lanni_opd(sin_t, opt, t_s, compensated=gl_compensated)
+    if zernike is not None:
+        r = np.asarray(sin_t) / opt.s_max
+        for j, c in enumerate(np.asarray(zernike, dtype=np.float64), start=1):
+            if c == 0.0:
+                continue
+            n, m = O.noll_to_nm(j)
+            if m != 0:
+                raise ValueError("the Bessel form needs an axisymmetric pupil (m = 0 Zernike only)")
+            w = w + 2.0 * math.pi * c * O.zernike_noll(j, r, 0.0)
+    return w
+
+
+def theta_rule(opt: O.Optics, n_theta: int):
+    """GL nodes on [0, theta_max]; split at the sample's critical angle when one lies inside."""
+    tmax = opt.theta_max
+    cuts = [0.0, tmax]
+    if opt.gl is not None and opt.gl.n_s < opt.na:
+        cuts = [0.0, math.asin(opt.gl.n_s / opt.n_i), tmax]
+    ts, ws = [], []
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        t, w = O.gauss_legendre(n_theta, a, b)
+        ts.append(t)
+        ws.append(w)
+    return np.concatenate(ts), np.concatenate(ws)
+
+
+def bessel_integrals(rho, z, opt: O.Optics, n_theta: int = 256, zernike=None, t_s: float = 0.0,
+                     gl_compensated: bool = False, scalar: bool = False, extra_cos: bool = False):
+    """I_0, I_1, I_2 (eq. "I0") without the polarisation factor e_inc^a.
+
+    Shapes: rho (R,), z (Z,) -> each (Z, R) complex128.  The pupil factor
+    p(theta) = a(theta) exp(i W(theta)) multiplies every integrand.  With
+    ``scalar`` only I_0 with weight sin t is returned (eq. "polar scalar final").
+    """
+    t, w = theta_rule(opt, n_theta)
+    sin_t, cos_t = np.sin(t), np.cos(t)
+    p = O.amplitude(cos_t, sin_t, opt) * np.exp(1j * _axisymmetric_phase(sin_t, opt, zernike, t_s,
+                                                                       gl_compensated))
+    if extra_cos:
+        p = p * cos_t
+    k = opt.k
+    rho = np.atleast_1d(np.asarray(rho, dtype=np.float64))
+    z = np.atleast_1d(np.asarray(z, dtype=np.float64))
+    arg = k * np.outer(rho, sin_t)                      # (R, T)
+    defocus = np.exp(1j * k * np.outer(z, cos_t))       # (Z, T)
+    if scalar:
+        g = [sin_t]
+    else:
+        g = [sin_t * (cos_t + 1.0), sin_t ** 2, sin_t * (cos_t - 1.0)]
+    out = []
+    for n, gn in enumerate(g):
+        kern = special.jv(n, arg) * (w * gn * p)[None, :]   # (R, T)
+        out.append(defocus @ kern.T)                         # (Z, R)
+    return out
+
+
+def field_bessel(opt: O.Optics, nx: int, ny: int, dx: float, dy: float, z, x0: float = 0.0,
+                 y0: float = 0.0, n_theta: int = 256, zernike=None, t_s: float = 0.0,
+                 gl_compensated: bool = False):
+    """Vectorial field (Z, 3, nx, ny) from eq. "polar vectorial final" at exact pixel radii."""
+    xs = O.output_axis(nx, dx, x0)
+    ys = O.output_axis(ny, dy, y0)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    rho = np.hypot(X, Y).ravel()
+    varphi = np.arctan2(Y, X).ravel()            # 0 on the axis
+    I0, I1, I2 = bessel_integrals(rho, z, opt, n_theta, zernike, t_s, gl_compensated)
+    ex, ey = opt.e_inc
+    c1, s1 = np.cos(varphi), np.sin(varphi)
+    c2, s2 = np.cos(2 * varphi), np.sin(2 * varphi)
+    Ex = ex * (I0 - I2 * c2) - ey * I2 * s2
+    Ey = -ex * I2 * s2 + ey * (I0 + I2 * c2)
+    Ez = -2j * ex * I1 * c1 - 2j * ey * I1 * s1
+    E = np.stack([Ex, Ey, Ez], axis=1)           # (Z, 3, R)
+    pref = -1j * opt.f * opt.k / 2.0
+    return pref * E.reshape(E.shape[0], 3, nx, ny)
+
+
+def field_polar(opt: O.Optics, points, x0: float = 0.0, y0: float = 0.0, n_theta: int = 256,
+                n_phi: int = 96, zernike=None, phase_fn=None, t_s: float = 0.0,
+                gl_compensated: bool = False, scalar: bool = False, extra_cos: bool = False,
+                chunk: int = 32):
+    """Polar double integral at points (K, 3) -> (C, K), C = 3 (vectorial) or 1 (scalar).
+
+    ``zernike`` may hold any Noll terms (the polar integral needs no symmetry);
+    ``phase_fn(theta, phi)`` adds an arbitrary pupil phase (e.g. a vortex).
+    """
+    t, w = theta_rule(opt, n_theta)
+    p = 2.0 * math.pi * np.arange(n_phi) / n_phi
+    T, P = np.meshgrid(t, p, indexing="ij")
+    Wt = np.repeat(w[:, None], n_phi, axis=1) * (2.0 * math.pi / n_phi)
+    sin_t, cos_t = np.sin(T), np.cos(T)
+    cos_p, sin_p = np.cos(P), np.sin(P)
+    phase = np.zeros(T.shape, dtype=np.complex128)
+    if opt.gl is not None:
+        phase = phase + O.gibson_lanni_opd(sin_t, opt, t_s, compensated=gl_compensated)
+    if zernike is not None:
+        r = sin_t / opt.s_max
+        for j, c in enumerate(np.asarray(zernike, dtype=np.float64), start=1):
+            if c != 0.0:
+                phase = phase + 2.0 * math.pi * c * O.zernike_noll(j, r, P)
+    if phase_fn is not None:
+        phase = phase + phase_fn(T, P)
+    amp = O.amplitude(cos_t, sin_t, opt) * np.exp(1j * phase) * Wt * sin_t
+    if extra_cos:
+        amp = amp * cos_t
+    if scalar:
+        field = amp[None]
+    else:
+        ex, ey = opt.e_inc
+        field = O.far_field(ex, ey, cos_t, sin_t, cos_p, sin_p) * amp[None]
+    field = field.reshape(field.shape[0], -1)
+    sx, sy, sz = (sin_t * cos_p).ravel(), (sin_t * sin_p).ravel(), cos_t.ravel()
+    pts = np.atleast_2d(np.asarray(points, dtype=np.float64))
+    k = opt.k
+    out = np.empty((field.shape[0], pts.shape[0]), dtype=np.complex128)
+    for a in range(0, pts.shape[0], chunk):
+        q = pts[a:a + chunk]
+        ph = k * (np.outer(q[:, 0] - x0, sx) + np.outer(q[:, 1] - y0, sy) + np.outer(q[:, 2], sz))
+        out[:, a:a + chunk] = field @ np.exp(1j * ph).T
+    return (-1j * opt.f * opt.k / (2.0 * math.pi)) * out
