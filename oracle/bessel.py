@@ -38,18 +38,29 @@ def _axisymmetric_phase(sin_t, opt: O.Optics, zernike=None, t_s: float = 0.0,
     return w
 
 
-def theta_rule(opt: O.Optics, n_theta: int):
-    """GL nodes on [0, theta_max]; split at the sample's critical angle when one lies inside."""
+def theta_rule(opt: O.Optics, n_theta: int, substitute: bool = True):
+    """Quadrature nodes/weights on [0, theta_max].
+
+    Without a sample layer: n_theta Gauss-Legendre nodes.  With Gibson-Lanni and a
+    critical angle t_c inside the aperture, sqrt(n_s^2 - n_i^2 sin^2 t) has a
+    square-root branch point at t_c; the range is split there and, with
+    ``substitute``, each side is mapped by t = t_c - t_c (1 - u)^2 resp.
+    t = t_c + (t_max - t_c) u^2 (an exact change of variables that makes the
+    integrand smooth in u), with n_theta GL nodes in u on each side.
+    """
     tmax = opt.theta_max
-    cuts = [0.0, tmax]
-    if opt.gl is not None and opt.gl.n_s < opt.na:
-        cuts = [0.0, math.asin(opt.gl.n_s / opt.n_i), tmax]
-    ts, ws = [], []
-    for a, b in zip(cuts[:-1], cuts[1:]):
-        t, w = O.gauss_legendre(n_theta, a, b)
-        ts.append(t)
-        ws.append(w)
-    return np.concatenate(ts), np.concatenate(ws)
+    if opt.gl is None or opt.gl.n_s >= opt.na:
+        return O.gauss_legendre(n_theta, 0.0, tmax)
+    tc = math.asin(opt.gl.n_s / opt.n_i)
+    if not substitute:
+        a, wa = O.gauss_legendre(n_theta, 0.0, tc)
+        b, wb = O.gauss_legendre(n_theta, tc, tmax)
+        return np.concatenate([a, b]), np.concatenate([wa, wb])
+    u, wu = O.gauss_legendre(n_theta, 0.0, 1.0)
+    v = 1.0 - u
+    t1, w1 = tc - tc * v * v, wu * 2.0 * tc * v
+    t2, w2 = tc + (tmax - tc) * u * u, wu * 2.0 * (tmax - tc) * u
+    return np.concatenate([t1, t2]), np.concatenate([w1, w2])
 
 
 def bessel_integrals(rho, z, opt: O.Optics, n_theta: int = 256, zernike=None, t_s: float = 0.0,

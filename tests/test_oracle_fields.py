@@ -232,3 +232,27 @@ def test_gibson_lanni_literal_focus_is_shifted_by_depth():
     E_lit = F.field_separable(P_lit, g, opt, 9, 9, 30.0, 30.0, z)
     E_cmp = F.field_separable(P_cmp, g, opt, 9, 9, 30.0, 30.0, z + t_s)
     np.testing.assert_allclose(E_lit, E_cmp, rtol=0, atol=1e-12 * np.abs(E_cmp).max())
+
+
+def test_critical_angle_substitution_matches_brute_force_rule():
+    # the substituted rule equals plain Gauss-Legendre with many nodes on each side of t_c
+    opt = O.Optics(na=1.4, wavelength=532.0, n_i=1.518, gl=O.GibsonLanni(n_s=1.33, n_i_design=1.518))
+    rho = np.array([0.0, 150.0, 420.0])
+    z = np.array([-2200.0, -1900.0])
+    sub = B.bessel_integrals(rho, z, opt, 128, t_s=2000.0)
+    brute = B.bessel_integrals(rho, z, opt, 4096, t_s=2000.0)      # substitute=True path
+    t, w = B.theta_rule(opt, 4096, substitute=False)
+    assert abs(np.sum(w) - opt.theta_max) < 1e-13
+    plain = []
+    for n in (512, 4096):
+        tt, ww = B.theta_rule(opt, n, substitute=False)
+        f = np.exp(1j * O.gibson_lanni_opd(np.sin(tt), opt, 2000.0)) * np.sqrt(np.cos(tt)) * np.sin(tt)
+        plain.append(np.sum(ww * f))
+    tt, ww = B.theta_rule(opt, 64)
+    f = np.exp(1j * O.gibson_lanni_opd(np.sin(tt), opt, 2000.0)) * np.sqrt(np.cos(tt)) * np.sin(tt)
+    smooth = np.sum(ww * f)
+    # plain GL converges as n^-3 towards the substituted value
+    assert abs(plain[1] - smooth) < 1e-8 * abs(smooth)
+    assert abs(plain[1] - smooth) < abs(plain[0] - smooth) / 100
+    for a, b in zip(sub, brute):
+        assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(b))
