@@ -1,0 +1,167 @@
+/*
+ * rwpsf.h -- C ABI of the MI355X (gfx950) vectorial Richards-Wolf PSF engine.
+ *
+ * The library evaluates the focal field E = (Ex, Ey, Ez) and the intensity
+ * |E|^2 of a high-NA objective over a z-stack (Liu et al., arXiv 2502.03170):
+ *
+ *   E(rho) = -(i f k / 2 pi) Iint_Omega a(s) exp(i W(s)) e_inf(s) exp(i k s.rho) dOmega
+ *
+ * (Sec. 3.1 eq. "initial vectorial" with the correction factors of Sec. 3.4,
+ * eq. "vectorial general with correction"), in either of the two
+ * parameterisations the paper proves equivalent:
+ *
+ *   RWPSF_FORM_FOURIER -- Cartesian form, Sec. 3.3 eq. "cartesian vectorial":
+ *       the pupil on a cell-centred N x N grid, one 2-D discrete transform
+ *       per z-plane (a separable matrix DFT on the matrix cores).
+ *   RWPSF_FORM_BESSEL  -- spherical form, Sec. 3.3 eq. "polar vectorial final"
+ *       and eq. "I0": three 1-D theta integrals of J0/J1/J2 kernels by
+ *       Gauss-Legendre quadrature, sampled on a radial grid and interpolated
+ *       onto the pixels.  Needs an axisymmetric pupil (Sec. 3.4.2, Sec. 4.1).
+ *
+ * Conventions (all calls):
+ *   - lengths in nanometres, Zernike coefficients in waves (Noll index 1..K,
+ *     orthonormal on the unit pupil disk), phase maps in radians;
+ *   - k = 2 pi n_i / lambda, s_max = NA / n_i (Sec. 3.1);
+ *   - pixel (i, j) sits at x = (i - nx/2) dx, y = (j - ny/2) dy (integer
+ *     division), the emitter at (x0, y0), the defocus of plane p is
+ *     z[p] + z_offset (observation plane minus emitter plane);
+ *   - outputs follow the paper's (z, channel, x, y) order (Sec. 4.1), y
+ *     fastest: E as interleaved complex64 [stack][z][3][nx][ny], I as float
+ *     [stack][z][nx][ny];
+ *   - status codes: 0 = RWPSF_OK, negative = error (rwpsf_status_string).
+ *     Argument errors are reported before anything is enqueued; kernel
+ *     faults surface at the caller's next synchronisation.  No call blocks
+ *     the host on the GPU unless stated.
+ *   - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *     default stream).  A plan may be used on one stream at a time.
+ *   - Device pointers are owned by the caller; a plan owns its tables and
+ *     workspace on the device that was current when it was created.
+ */
+#ifndef RWPSF_H
+#define RWPSF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RWPSF_ABI_VERSION 1
+
+enum rwpsf_status_code {
+  RWPSF_OK = 0,
+  RWPSF_ERR_INVALID_ARG = -1,      /* sizes <= 0, NA >= n_i, non-finite values, NULL where required */
+  RWPSF_ERR_NOT_AXISYMMETRIC = -2, /* Bessel form given m != 0 Zernike terms or a phase map */
+  RWPSF_ERR_UNSUPPORTED = -3,      /* option not implemented for this form */
+  RWPSF_ERR_OOM = -4,              /* device or host allocation failed */
+  RWPSF_ERR_HIP = -5,              /* a HIP runtime call failed; rwpsf_last_hip_error() has the code */
+  RWPSF_ERR_NO_DEVICE = -6         /* no usable gfx950 device */
+};
+
+enum rwpsf_form { RWPSF_FORM_BESSEL = 0, RWPSF_FORM_FOURIER = 1 };
+
+/* Physical parameters (Sec. 3.1, 3.3, 3.4). */
+typedef struct rwpsf_optics {
+  double na;             /* numerical aperture, 0 < na < n_i */
+  double wavelength_nm;  /* vacuum wavelength */
+  double n_i;            /* immersion index (the propagation medium of the integral) */
+  double focal_length;   /* f of eq. "initial vectorial"; scales E only (1 = unit) */
+  double ex_re, ex_im;   /* incident polarisation e_inc = (ex, ey, 0), eq. "field Gaussian sphere" */
+  double ey_re, ey_im;
+  int apodization;       /* 1: a(s) *= sqrt(cos theta) (Sec. 3.4.3) */
+  double s_env;          /* > 0: a(s) *= exp(-sin^2 theta / s_env^2) (Sec. 3.4.4); 0 = off */
+  int gibson_lanni;      /* 1: add the stratified-layer OPD of Sec. 3.4.1 */
+  double n_s, n_g, n_g_design, n_i_design;        /* sample, glass (actual, design), immersion design */
+  double t_g_nm, t_g_design_nm, t_i_design_nm;    /* thicknesses; t_i from eq. "gibson lanni t_i" */
+} rwpsf_optics;
+
+/* Output sampling.  z_nm (host, nz values) is copied at plan creation. */
+typedef struct rwpsf_grid {
+  int nx, ny;
+  double dx_nm, dy_nm;
+  int nz;
+  const double* z_nm;
+} rwpsf_grid;
+
+/* Numerical parameters. */
+typedef struct rwpsf_numerics {
+  int form;     /* rwpsf_form */
+  int n_pupil;  /* Fourier: pupil cells per axis, 2..1024 */
+  int n_theta;  /* Bessel: Gauss-Legendre nodes on [0, theta_max], 2..4096 */
+  int n_rho;    /* Bessel: radial samples, 8..65536 */
+} rwpsf_numerics;
+
+/* One stack of a compute call: emitter and aberration (Sec. 3.4.1, 3.4.2). */
+typedef struct rwpsf_stack {
+  double t_s_nm;               /* emitter depth below the coverslip (Gibson-Lanni only) */
+  double x0_nm, y0_nm;         /* lateral emitter position */
+  double z_offset_nm;          /* added to every plane's z */
+  int n_zernike;               /* 0..RWPSF_MAX_ZERNIKE */
+  const double* zernike_waves; /* host, n_zernike Noll coefficients (j = 1..n_zernike) */
+  const float* phase_map;      /* device [n_pupil][n_pupil] radians (W0 of eq. "Zernike
+                                  aberrations"), pupil cell (j, l) <-> (s_x, s_y); NULL = none.
+                                  Fourier form only. */
+} rwpsf_stack;
+
+#define RWPSF_MAX_ZERNIKE 36
+#define RWPSF_MAX_STACKS_PER_CALL 4096
+
+typedef struct rwpsf_plan rwpsf_plan;
+
+/* ABI version of the loaded library (RWPSF_ABI_VERSION it was built with). */
+int rwpsf_abi_version(void);
+
+/* Static string for a status code; never NULL. */
+const char* rwpsf_status_string(int status);
+
+/* HIP error code behind the most recent RWPSF_ERR_HIP on this thread (0 if none). */
+int rwpsf_last_hip_error(void);
+
+/* Host-only validation of a plan description; makes no HIP call. */
+int rwpsf_validate(const rwpsf_optics* optics, const rwpsf_grid* grid, const rwpsf_numerics* num);
+
+/* Host-only validation of stacks against a plan description (form-specific rules,
+   e.g. the Bessel form rejects m != 0 Zernike terms and phase maps). */
+int rwpsf_validate_stacks(const rwpsf_optics* optics, const rwpsf_grid* grid,
+                          const rwpsf_numerics* num, int n_stacks, const rwpsf_stack* stacks);
+
+/* Build a plan on the current device: copies the description, evaluates the
+   FP64 tables (pupil geometry, Zernike basis, DFT matrices or Gauss-Legendre
+   rule and Bessel table) and uploads them.  Synchronous.  *out is NULL on error. */
+int rwpsf_plan_create(const rwpsf_optics* optics, const rwpsf_grid* grid,
+                      const rwpsf_numerics* num, rwpsf_plan** out);
+
+/* Release a plan and its device memory (synchronises its device). NULL is a no-op. */
+void rwpsf_plan_destroy(rwpsf_plan* plan);
+
+/* Device bytes held by the plan (tables + workspace). */
+size_t rwpsf_plan_device_bytes(const rwpsf_plan* plan);
+
+/* Plain forward evaluation of n_stacks stacks (1..RWPSF_MAX_STACKS_PER_CALL).
+   E_out: device complex64 [n_stacks][nz][3][nx][ny] or NULL;
+   I_out: device float [n_stacks][nz][nx][ny] or NULL (not both NULL).
+   Enqueued on `stream`; returns after the enqueue. */
+int rwpsf_compute(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
+                  void* E_out, float* I_out, void* stream);
+
+/* ---- host-only reference routines used to build the plan tables ----------
+   Exported so that the tables can be checked on a machine without a GPU. */
+
+/* n-point Gauss-Legendre rule on [a, b] (Newton iteration on the three-term
+   Legendre recurrence).  x, w: host arrays of n doubles. */
+int rwpsf_gauss_legendre(int n, double a, double b, double* x, double* w);
+
+/* Bessel function of the first kind J_order(x), order 0..8, x >= 0, evaluated as the
+   periodic trapezoid rule on Bessel's integral (1/pi) int_0^pi cos(n t - x sin t) dt.
+   x, out: host arrays of `count` doubles. */
+int rwpsf_bessel_j(int order, int count, const double* x, double* out);
+
+/* Orthonormal Noll Zernike polynomial Z_j(r, phi), j >= 1. Host arrays of `count`. */
+int rwpsf_zernike(int j, int count, const double* r, const double* phi, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RWPSF_H */

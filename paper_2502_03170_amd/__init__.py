@@ -1,0 +1,250 @@
+"""Python binding of librwpsf (the MI355X vectorial Richards-Wolf PSF engine).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``librwpsf.so``; PyTorch provides device memory and the stream.
+The names follow the C ABI in ``include/rwpsf.h`` without the ``rwpsf_``
+prefix.  If the library is missing this module raises -- there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from ctypes import POINTER, byref, c_double, c_int, c_size_t, c_void_p
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librwpsf.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_NOT_AXISYMMETRIC = -2
+ERR_UNSUPPORTED = -3
+ERR_OOM = -4
+ERR_HIP = -5
+ERR_NO_DEVICE = -6
+FORM_BESSEL = 0
+FORM_FOURIER = 1
+MAX_ZERNIKE = 36
+CIRCULAR = (1 / math.sqrt(2), 1j / math.sqrt(2))
+
+
+class RwpsfError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"rwpsf error {status}: {msg}")
+        self.status = status
+
+
+class Optics(ctypes.Structure):
+    _fields_ = [("na", c_double), ("wavelength_nm", c_double), ("n_i", c_double),
+                ("focal_length", c_double), ("ex_re", c_double), ("ex_im", c_double),
+                ("ey_re", c_double), ("ey_im", c_double), ("apodization", c_int), ("s_env", c_double),
+                ("gibson_lanni", c_int), ("n_s", c_double), ("n_g", c_double),
+                ("n_g_design", c_double), ("n_i_design", c_double), ("t_g_nm", c_double),
+                ("t_g_design_nm", c_double), ("t_i_design_nm", c_double)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", c_int), ("ny", c_int), ("dx_nm", c_double), ("dy_nm", c_double),
+                ("nz", c_int), ("z_nm", POINTER(c_double))]
+
+
+class Numerics(ctypes.Structure):
+    _fields_ = [("form", c_int), ("n_pupil", c_int), ("n_theta", c_int), ("n_rho", c_int)]
+
+
+class Stack(ctypes.Structure):
+    _fields_ = [("t_s_nm", c_double), ("x0_nm", c_double), ("y0_nm", c_double),
+                ("z_offset_nm", c_double), ("n_zernike", c_int), ("zernike_waves", POINTER(c_double)),
+                ("phase_map", c_void_p)]
+
+
+_lib = None
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load librwpsf.so (built by ``python -m paper_2502_03170_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"librwpsf.so not found at {path}; build it with "
+                           "`python -m paper_2502_03170_amd.build` (no CPU fallback exists)")
+    lib = ctypes.CDLL(path)
+    sig = {
+        "rwpsf_abi_version": (c_int, []),
+        "rwpsf_status_string": (ctypes.c_char_p, [c_int]),
+        "rwpsf_last_hip_error": (c_int, []),
+        "rwpsf_validate": (c_int, [POINTER(Optics), POINTER(Grid), POINTER(Numerics)]),
+        "rwpsf_validate_stacks": (c_int, [POINTER(Optics), POINTER(Grid), POINTER(Numerics), c_int,
+                                          POINTER(Stack)]),
+        "rwpsf_plan_create": (c_int, [POINTER(Optics), POINTER(Grid), POINTER(Numerics),
+                                      POINTER(c_void_p)]),
+        "rwpsf_plan_destroy": (None, [c_void_p]),
+        "rwpsf_plan_device_bytes": (c_size_t, [c_void_p]),
+        "rwpsf_compute": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_void_p]),
+        "rwpsf_gauss_legendre": (c_int, [c_int, c_double, c_double, POINTER(c_double), POINTER(c_double)]),
+        "rwpsf_bessel_j": (c_int, [c_int, c_int, POINTER(c_double), POINTER(c_double)]),
+        "rwpsf_zernike": (c_int, [c_int, c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(status: int) -> str:
+    return load().rwpsf_status_string(status).decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise RwpsfError(status, status_string(status))
+
+
+def abi_version() -> int:
+    return load().rwpsf_abi_version()
+
+
+# ---------------------------------------------------------------- struct builders
+def make_optics(na, wavelength, n_i, e_inc=CIRCULAR, focal_length=1.0, apodization=True, s_env=0.0,
+                gibson_lanni: dict | None = None) -> Optics:
+    ex, ey = complex(e_inc[0]), complex(e_inc[1])
+    o = Optics(na=na, wavelength_nm=wavelength, n_i=n_i, focal_length=focal_length, ex_re=ex.real,
+               ex_im=ex.imag, ey_re=ey.real, ey_im=ey.imag, apodization=int(bool(apodization)),
+               s_env=s_env)
+    if gibson_lanni:
+        g = gibson_lanni
+        o.gibson_lanni = 1
+        o.n_s = g["n_s"]
+        o.n_g = g.get("n_g", 1.5)
+        o.n_g_design = g.get("n_g_design", 1.5)
+        o.n_i_design = g.get("n_i_design", n_i) or n_i
+        o.t_g_nm = g.get("t_g", 170e3)
+        o.t_g_design_nm = g.get("t_g_design", 170e3)
+        o.t_i_design_nm = g.get("t_i_design", 150e3)
+    return o
+
+
+def make_grid(nx, ny, dx, dy, z):
+    zarr = (c_double * len(z))(*[float(v) for v in z])
+    g = Grid(nx=nx, ny=ny, dx_nm=dx, dy_nm=dy, nz=len(z), z_nm=zarr)
+    g._keep = zarr
+    return g
+
+
+def make_stacks(stacks: list[dict]):
+    arr = (Stack * len(stacks))()
+    keep = []
+    for i, s in enumerate(stacks):
+        c = s.get("zernike")
+        arr[i].t_s_nm = float(s.get("t_s", 0.0))
+        arr[i].x0_nm = float(s.get("x0", 0.0))
+        arr[i].y0_nm = float(s.get("y0", 0.0))
+        arr[i].z_offset_nm = float(s.get("z_offset", 0.0))
+        if c is not None and len(c):
+            buf = (c_double * len(c))(*[float(v) for v in c])
+            keep.append(buf)
+            arr[i].n_zernike = len(c)
+            arr[i].zernike_waves = ctypes.cast(buf, POINTER(c_double))
+        pm = s.get("phase_map")
+        if pm is not None:
+            keep.append(pm)
+            arr[i].phase_map = c_void_p(pm.data_ptr())
+    return arr, keep
+
+
+# ---------------------------------------------------------------- ABI mirrors
+def validate(optics: Optics, grid: Grid, num: Numerics) -> int:
+    return load().rwpsf_validate(byref(optics), byref(grid), byref(num))
+
+
+def validate_stacks(optics: Optics, grid: Grid, num: Numerics, stacks: list[dict]) -> int:
+    arr, _keep = make_stacks(stacks)
+    return load().rwpsf_validate_stacks(byref(optics), byref(grid), byref(num), len(stacks), arr)
+
+
+def gauss_legendre(n: int, a: float, b: float):
+    x, w = (c_double * n)(), (c_double * n)()
+    _check(load().rwpsf_gauss_legendre(n, a, b, x, w))
+    return list(x), list(w)
+
+
+def bessel_j(order: int, xs):
+    n = len(xs)
+    x, out = (c_double * n)(*[float(v) for v in xs]), (c_double * n)()
+    _check(load().rwpsf_bessel_j(order, n, x, out))
+    return list(out)
+
+
+def zernike(j: int, r, phi):
+    n = len(r)
+    ra, pa, out = (c_double * n)(*map(float, r)), (c_double * n)(*map(float, phi)), (c_double * n)()
+    _check(load().rwpsf_zernike(j, n, ra, pa, out))
+    return list(out)
+
+
+def plan_create(optics: Optics, grid: Grid, num: Numerics) -> c_void_p:
+    h = c_void_p()
+    _check(load().rwpsf_plan_create(byref(optics), byref(grid), byref(num), byref(h)))
+    return h
+
+
+def plan_destroy(handle) -> None:
+    load().rwpsf_plan_destroy(handle)
+
+
+def compute(handle, stacks: list[dict], E=None, I=None, stream=None) -> None:
+    """Enqueue rwpsf_compute; E (complex64) and I (float32) are CUDA tensors or None."""
+    import torch
+    arr, _keep = make_stacks(stacks)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    for t, dt in ((E, torch.complex64), (I, torch.float32)):
+        if t is not None and (not t.is_cuda or t.dtype != dt or not t.is_contiguous()):
+            raise ValueError("outputs must be contiguous CUDA tensors of complex64 (E) / float32 (I)")
+    _check(load().rwpsf_compute(handle, len(stacks), arr, c_void_p(E.data_ptr() if E is not None else 0),
+                                c_void_p(I.data_ptr() if I is not None else 0), c_void_p(stream)))
+
+
+class Plan:
+    """A plan of the C ABI with torch-allocated outputs."""
+
+    def __init__(self, *, form: int, na: float, wavelength: float, n_i: float, nx: int, ny: int,
+                 dx: float, dy: float, z, e_inc=CIRCULAR, focal_length: float = 1.0,
+                 apodization: bool = True, s_env: float = 0.0, gibson_lanni: dict | None = None,
+                 n_pupil: int = 256, n_theta: int = 200, n_rho: int = 256):
+        self.optics = make_optics(na, wavelength, n_i, e_inc, focal_length, apodization, s_env,
+                                  gibson_lanni)
+        self.grid = make_grid(nx, ny, dx, dy, list(z))
+        self.num = Numerics(form=form, n_pupil=n_pupil, n_theta=n_theta, n_rho=n_rho)
+        self.nx, self.ny, self.nz = nx, ny, len(z)
+        self.handle = plan_create(self.optics, self.grid, self.num)
+
+    def device_bytes(self) -> int:
+        return load().rwpsf_plan_device_bytes(self.handle)
+
+    def compute(self, stacks: list[dict], fields: bool = True, intensity: bool = True, E=None, I=None,
+                stream=None):
+        import torch
+        b = len(stacks)
+        if fields and E is None:
+            E = torch.empty((b, self.nz, 3, self.nx, self.ny), dtype=torch.complex64, device="cuda")
+        if intensity and I is None:
+            I = torch.empty((b, self.nz, self.nx, self.ny), dtype=torch.float32, device="cuda")
+        compute(self.handle, stacks, E if fields else None, I if intensity else None, stream)
+        return E, I
+
+    def close(self):
+        if self.handle:
+            plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,389 @@
+// Bessel (spherical) form of the vectorial Richards-Wolf integral on gfx950.
+//
+// Sec. 3.3 eq. "polar vectorial final" and eq. "I0": for an axisymmetric pupil
+// p(theta) = a(theta) exp(i W(theta)) and constant polarisation (ex, ey),
+//   I_n(rho, z) = int_0^theta_max p(t) g_n(t) J_n(k rho sin t) exp(i k z cos t) dt
+//   g_0 = sin t (1 + cos t), g_1 = sin^2 t, g_2 = sin t (cos t - 1)
+//   E = -(i f k / 2) [ ex (I0 - I2 cos 2v) - ey I2 sin 2v,
+//                     -ex I2 sin 2v + ey (I0 + I2 cos 2v),
+//                     -2i (ex cos v + ey sin v) I1 ]
+// with v the azimuth of the pixel.  Evaluated as
+//   plan:  Gauss-Legendre nodes t_q, weights w_q on [0, theta_max] (split at the
+//          sample's critical angle when it lies inside), radial samples
+//          rho_r = r drho, and the table B[q][n R + r] = w_q g_n(t_q) J_n(k rho_r sin t_q)
+//          (FP64 kernel, stored FP32);
+//   call:  Phi[q][s, z] = p_s(t_q) exp(i k z cos t_q)            (FP64 phase -> FP32)
+//          I_n[s, z, :, r] = sum_q Phi[q][s, z] B[q][n R + r]    (real GEMM on MFMA,
+//                                                                 re/im as two rows)
+//          radial epilogue: 4-point Lagrange in rho (parity ghosts
+//          I_n(-rho) = (-1)^n I_n(rho)), angular combination, |E|^2.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "rw_common.h"
+#include "rw_plan.h"
+
+namespace rw {
+
+typedef float f16v_b __attribute__((ext_vector_type(16)));
+
+// --------------------------------------------------------------------------
+// Plan-time Bessel table (FP64 arithmetic).
+// --------------------------------------------------------------------------
+__global__ void bessel_table_kernel(float* __restrict__ out, const double* __restrict__ theta,
+                                    const double* __restrict__ wt, int T, int R, double k, double drho) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 3 * R * T) return;
+  const int q = idx / (3 * R);
+  const int nr = idx % (3 * R);
+  const int n = nr / R, r = nr % R;
+  const double t = theta[q];
+  const double st = sin(t), ct = cos(t);
+  const double g = n == 0 ? st * (1.0 + ct) : (n == 1 ? st * st : st * (ct - 1.0));
+  out[(size_t)q * 3 * R + nr] = (float)(wt[q] * g * bessel_j(n, k * (r * drho) * st));
+}
+
+// --------------------------------------------------------------------------
+// Per call: pupil x defocus on the theta nodes, Phi[q][s * nz + z] (complex64).
+// --------------------------------------------------------------------------
+struct PhiStack {
+  double t_s, zoff;
+  double coef[RWPSF_MAX_ZERNIKE];  // only m = 0 terms are non-zero (validated)
+};
+constexpr int kPhiStacks = 8;
+struct PhiArgs {
+  int T, nz, nstk, s_base_unused, max_zernike, gibson_lanni, apod;
+  double k, s_max, s_env;
+  GLParams gl;
+  PhiStack s[kPhiStacks];
+};
+
+__global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
+                                  const double* __restrict__ z, float2* __restrict__ phi,
+                                  int ld_cols, int col0) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int per_q = a.nstk * a.nz;
+  if (idx >= a.T * per_q) return;
+  const int q = idx / per_q, rem = idx % per_q;
+  const int si = rem / a.nz, zi = rem % a.nz;
+  const PhiStack& st = a.s[si];
+  const double t = theta[q];
+  const double sin_t = sin(t), cos_t = cos(t);
+  double amp = 1.0;
+  if (a.apod) amp *= sqrt(cos_t);
+  if (a.s_env > 0.0) amp *= exp(-(sin_t * sin_t) / (a.s_env * a.s_env));
+  double w_re = 0.0, w_im = 0.0;
+  if (a.gibson_lanni) gl_opd(a.gl, st.t_s, sin_t, &w_re, &w_im);
+  const double r = sin_t / a.s_max;
+  for (int j = 0; j < a.max_zernike; ++j)
+    if (st.coef[j] != 0.0) w_re += kTwoPi * st.coef[j] * zernike_noll(j + 1, r, 1.0, 0.0);
+  const double ph = w_re + a.k * (z[zi] + st.zoff) * cos_t;
+  float sn, cs;
+  sincosf((float)reduce_2pi(ph), &sn, &cs);
+  const float m = (float)(amp * exp(-w_im));
+  phi[(size_t)q * ld_cols + col0 + rem] = make_float2(m * cs, m * sn);
+}
+
+// --------------------------------------------------------------------------
+// Real FP32 GEMM on the matrix cores for the theta contraction:
+//   C[row][col] = sum_q A[q][row] B[q][col]
+// rows = (stack, plane, re/im) read from Phi viewed as real [T][2 S nz],
+// cols = (n, r) from the Bessel table [T][3R].  Output In[row][col].
+// Workgroup 64 x 128, 4 waves of 32 x 64, k-stage 16, LDS double buffer.
+// --------------------------------------------------------------------------
+constexpr int RBM = 64, RBN = 128, RBK = 16, RWM = 32, RWN = 64;
+constexpr int RLDA = RBM + 4, RLDB = RBN + 4;
+constexpr int RSTAGE = RBK * RLDA + RBK * RLDB;
+
+__global__ void __launch_bounds__(256) bessel_contract_kernel(const float* __restrict__ A, int lda,
+                                                               const float* __restrict__ B, int ldb,
+                                                               float* __restrict__ C, int M, int N,
+                                                               int K) {
+  __shared__ float lds[2 * RSTAGE];
+  const int tiles_n = (N + RBN - 1) / RBN;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wrow = (wave / 2) * RWM, wcol = (wave % 2) * RWN;
+  const int row0 = tm * RBM, col0 = tn * RBN;
+  f16v_b acc[2];
+  for (int j = 0; j < 2; ++j)
+    for (int r = 0; r < 16; ++r) acc[j][r] = 0.f;
+
+  // loads: A tile RBK x RBM (1024 floats, 4 per thread), B tile RBK x RBN (2048, 8 per thread)
+  float ra[4], rb[8];
+  auto gload = [&](int k0) {
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + i * 256;
+      const int kk = e / RBM, c = e % RBM;
+      const int k = k0 + kk, gc = row0 + c;
+      ra[i] = (k < K && gc < M) ? A[(size_t)k * lda + gc] : 0.f;
+    }
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + i * 256;
+      const int kk = e / RBN, c = e % RBN;
+      const int k = k0 + kk, gc = col0 + c;
+      rb[i] = (k < K && gc < N) ? B[(size_t)k * ldb + gc] : 0.f;
+    }
+  };
+  auto sstore = [&](float* st) {
+    for (int i = 0; i < 4; ++i) {
+      const int e = tid + i * 256;
+      st[(e / RBM) * RLDA + (e % RBM)] = ra[i];
+    }
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid + i * 256;
+      st[RBK * RLDA + (e / RBN) * RLDB + (e % RBN)] = rb[i];
+    }
+  };
+  const int KT = (K + RBK - 1) / RBK;
+  gload(0);
+  sstore(lds);
+  __syncthreads();
+  const int h = lane >> 5, l32 = lane & 31;
+  for (int kt = 0; kt < KT; ++kt) {
+    float* cur = lds + (kt & 1) * RSTAGE;
+    float* nxt = lds + ((kt + 1) & 1) * RSTAGE;
+    const bool more = kt + 1 < KT;
+    if (more) gload((kt + 1) * RBK);
+#pragma unroll
+    for (int kp = 0; kp < RBK / 2; ++kp) {
+      const int kk = 2 * kp + h;
+      const float a = cur[kk * RLDA + wrow + l32];
+      const float b0 = cur[RBK * RLDA + kk * RLDB + wcol + l32];
+      const float b1 = cur[RBK * RLDA + kk * RLDB + wcol + 32 + l32];
+      acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0, acc[0], 0, 0, 0);
+      acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1, acc[1], 0, 0, 0);
+    }
+    if (more) sstore(nxt);
+    __syncthreads();
+  }
+  for (int j = 0; j < 2; ++j) {
+    const int col = col0 + wcol + 32 * j + l32;
+    for (int r = 0; r < 16; ++r) {
+      const int row = row0 + wrow + (r >> 2) * 8 + h * 4 + (r & 3);
+      if (row < M && col < N) C[(size_t)row * N + col] = acc[j][r];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// Radial epilogue: one workgroup per (stack, plane).  In rows of this plane:
+// re and im planes of [3][R] floats, staged in LDS.
+// --------------------------------------------------------------------------
+struct EpiArgs {
+  int nx, ny, nz, R, nstk, s_base;
+  float dx, dy, inv_drho;
+  float exr, exi, eyr, eyi;   // polarisation times -(i f k / 2)
+  float x0[kPhiStacks], y0[kPhiStacks];
+};
+
+__global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const float* __restrict__ In,
+                                                              float2* __restrict__ E,
+                                                              float* __restrict__ I) {
+  extern __shared__ float sh[];  // [2][3][R]
+  const int si = blockIdx.x / a.nz, zi = blockIdx.x % a.nz;
+  const int R = a.R;
+  const float* src = In + ((size_t)si * a.nz + zi) * 2 * 3 * R;
+  for (int i = threadIdx.x; i < 6 * R; i += blockDim.x) sh[i] = src[i];
+  __syncthreads();
+  const float* re = sh;
+  const float* im = sh + 3 * R;
+  const size_t plane = (size_t)a.nx * a.ny;
+  const size_t gs = (size_t)(a.s_base + si);
+  float2* Eb = E ? E + (gs * a.nz + zi) * 3 * plane : nullptr;
+  float* Ib = I ? I + (gs * a.nz + zi) * plane : nullptr;
+  const float x0 = a.x0[si], y0 = a.y0[si];
+  for (int pix = threadIdx.x; pix < (int)plane; pix += blockDim.x) {
+    const int i = pix / a.ny, j = pix % a.ny;
+    const float x = (float)(i - a.nx / 2) * a.dx - x0;
+    const float y = (float)(j - a.ny / 2) * a.dy - y0;
+    const float rho = sqrtf(x * x + y * y);
+    const float t = rho * a.inv_drho;
+    int r0 = (int)t;
+    r0 = min(r0, R - 3);
+    const float f = t - (float)r0;
+    // 4-point Lagrange weights on nodes -1, 0, 1, 2 (relative to r0)
+    const float wm = -f * (f - 1.f) * (f - 2.f) * (1.f / 6.f);
+    const float w0 = (f + 1.f) * (f - 1.f) * (f - 2.f) * 0.5f;
+    const float w1 = -(f + 1.f) * f * (f - 2.f) * 0.5f;
+    const float w2 = (f + 1.f) * f * (f - 1.f) * (1.f / 6.f);
+    float vr[3], vi[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const float* pr = re + n * R;
+      const float* pi = im + n * R;
+      float gr, gi;
+      if (r0 == 0) {  // ghost at -drho: I_n(-rho) = (-1)^n I_n(rho)
+        const float sg = (n == 1) ? -1.f : 1.f;
+        gr = sg * pr[1];
+        gi = sg * pi[1];
+      } else {
+        gr = pr[r0 - 1];
+        gi = pi[r0 - 1];
+      }
+      vr[n] = wm * gr + w0 * pr[r0] + w1 * pr[r0 + 1] + w2 * pr[r0 + 2];
+      vi[n] = wm * gi + w0 * pi[r0] + w1 * pi[r0 + 1] + w2 * pi[r0 + 2];
+    }
+    float c1 = 1.f, s1 = 0.f;
+    if (rho > 0.f) {
+      c1 = x / rho;
+      s1 = y / rho;
+    }
+    const float c2 = c1 * c1 - s1 * s1, s2 = 2.f * s1 * c1;
+    // A = I0 - I2 c2, Bv = I2 s2, Cv = I0 + I2 c2
+    const float Ar = vr[0] - vr[2] * c2, Ai = vi[0] - vi[2] * c2;
+    const float Br = vr[2] * s2, Bi = vi[2] * s2;
+    const float Cr = vr[0] + vr[2] * c2, Ci = vi[0] + vi[2] * c2;
+    // Ex = ex A - ey B ; Ey = -ex B + ey C ; Ez = -2i (ex c1 + ey s1) I1
+    const float exr = a.exr, exi = a.exi, eyr = a.eyr, eyi = a.eyi;
+    const float Exr = exr * Ar - exi * Ai - (eyr * Br - eyi * Bi);
+    const float Exi = exr * Ai + exi * Ar - (eyr * Bi + eyi * Br);
+    const float Eyr = -(exr * Br - exi * Bi) + (eyr * Cr - eyi * Ci);
+    const float Eyi = -(exr * Bi + exi * Br) + (eyr * Ci + eyi * Cr);
+    const float pr_ = exr * c1 + eyr * s1, pi_ = exi * c1 + eyi * s1;  // ex c1 + ey s1
+    const float qr = pr_ * vr[1] - pi_ * vi[1], qi = pr_ * vi[1] + pi_ * vr[1];
+    const float Ezr = 2.f * qi, Ezi = -2.f * qr;  // -2i q
+    if (Eb) {
+      Eb[pix] = make_float2(Exr, Exi);
+      Eb[plane + pix] = make_float2(Eyr, Eyi);
+      Eb[2 * plane + pix] = make_float2(Ezr, Ezi);
+    }
+    if (Ib) Ib[pix] = Exr * Exr + Exi * Exi + Eyr * Eyr + Eyi * Eyi + Ezr * Ezr + Ezi * Ezi;
+  }
+}
+
+// --------------------------------------------------------------------------
+// Plan and dispatch
+// --------------------------------------------------------------------------
+int bessel_plan_init(rwpsf_plan* p) {
+  const int R = p->num.n_rho;
+  if (6 * R * (int)sizeof(float) > 160 * 1024) return RWPSF_ERR_UNSUPPORTED;  // epilogue stages 6R floats
+  // theta rule, split at the critical angle of the sample layer when it lies inside
+  std::vector<double> th, wt;
+  const double tmax = p->theta_max;
+  double tc = -1.0;
+  if (p->opt.gibson_lanni && p->opt.n_s < p->opt.na) tc = std::asin(p->opt.n_s / p->opt.n_i);
+  auto add_rule = [&](int n, double a, double b) {
+    std::vector<double> x(n), w(n);
+    gauss_legendre(n, a, b, x.data(), w.data());
+    th.insert(th.end(), x.begin(), x.end());
+    wt.insert(wt.end(), w.begin(), w.end());
+  };
+  if (tc > 0.0) {
+    // sqrt(n_s^2 - n_i^2 sin^2 t) has a square-root branch point at the critical angle
+    // t_c; on each side t = t_c -+ d u^2 makes the integrand smooth in u, so the
+    // Gauss-Legendre rule in u keeps its exponential convergence.
+    int n1 = (int)std::lround(p->num.n_theta * tc / tmax);
+    n1 = std::max(2, std::min(p->num.n_theta - 2, n1));
+    const int n2 = p->num.n_theta - n1;
+    std::vector<double> u(std::max(n1, n2)), wu(std::max(n1, n2));
+    gauss_legendre(n1, 0.0, 1.0, u.data(), wu.data());
+    for (int i = 0; i < n1; ++i) {        // [0, t_c]: t = t_c - t_c (1 - u)^2
+      const double v = 1.0 - u[i];
+      th.push_back(tc - tc * v * v);
+      wt.push_back(wu[i] * 2.0 * tc * v);
+    }
+    gauss_legendre(n2, 0.0, 1.0, u.data(), wu.data());
+    for (int i = 0; i < n2; ++i) {        // [t_c, t_max]: t = t_c + (t_max - t_c) u^2
+      th.push_back(tc + (tmax - tc) * u[i] * u[i]);
+      wt.push_back(wu[i] * 2.0 * (tmax - tc) * u[i]);
+    }
+  } else {
+    add_rule(p->num.n_theta, 0.0, tmax);
+  }
+  const int T = (int)th.size();
+  p->n_theta_total = T;
+  // radial samples cover the farthest pixel plus a one-pixel emitter shift
+  const double hx = (p->grid.nx / 2) * p->grid.dx_nm + p->grid.dx_nm;
+  const double hy = (p->grid.ny / 2) * p->grid.dy_nm + p->grid.dy_nm;
+  p->drho = std::sqrt(hx * hx + hy * hy) / (R - 3);
+  int st;
+  if ((st = dev_alloc(p, &p->d_theta, T))) return st;
+  if ((st = dev_alloc(p, &p->d_wtheta, T))) return st;
+  if ((st = dev_alloc(p, &p->d_btab, (size_t)3 * R * T))) return st;
+  if ((st = dev_alloc(p, &p->d_z, (size_t)p->grid.nz))) return st;
+  p->bessel_stacks = kPhiStacks;
+  if ((st = dev_alloc(p, &p->d_phi, (size_t)T * p->bessel_stacks * p->grid.nz))) return st;
+  if ((st = dev_alloc(p, (float**)&p->d_In, (size_t)p->bessel_stacks * p->grid.nz * 2 * 3 * R))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_theta, th.data(), T * sizeof(double), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_wtheta, wt.data(), T * sizeof(double), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_z, p->z.data(), p->z.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
+  const int total = 3 * R * T;
+  hipLaunchKernelGGL(bessel_table_kernel, dim3((total + 255) / 256), dim3(256), 0, 0, p->d_btab,
+                     p->d_theta, p->d_wtheta, T, R, p->k, p->drho);
+  if ((st = hip_check(hipGetLastError()))) return st;
+  if ((st = hip_check(hipFuncSetAttribute((const void*)bessel_epilogue_kernel,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 6 * R * 4))))
+    return st;
+  return hip_check(hipDeviceSynchronize());
+}
+
+int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
+  int cur = -1;
+  hipGetDevice(&cur);
+  if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
+  if (6 * p->num.n_rho * 4 > 160 * 1024) return RWPSF_ERR_UNSUPPORTED;
+  const int T = p->n_theta_total, R = p->num.n_rho, nz = p->grid.nz;
+  const std::complex<double> pref(0.0, -0.5 * p->opt.focal_length * p->k);
+  const std::complex<double> ex = pref * std::complex<double>(p->opt.ex_re, p->opt.ex_im);
+  const std::complex<double> ey = pref * std::complex<double>(p->opt.ey_re, p->opt.ey_im);
+  for (int b0 = 0; b0 < n; b0 += kPhiStacks) {
+    const int nb = std::min(kPhiStacks, n - b0);
+    PhiArgs pa{};
+    pa.T = T;
+    pa.nz = nz;
+    pa.nstk = nb;
+    pa.gibson_lanni = p->opt.gibson_lanni;
+    pa.apod = p->opt.apodization;
+    pa.k = p->k;
+    pa.s_max = p->s_max;
+    pa.s_env = p->opt.s_env;
+    pa.gl = p->gl;
+    int maxz = 0;
+    for (int i = 0; i < nb; ++i) {
+      const rwpsf_stack& x = s[b0 + i];
+      pa.s[i].t_s = x.t_s_nm;
+      pa.s[i].zoff = x.z_offset_nm;
+      for (int q = 0; q < RWPSF_MAX_ZERNIKE; ++q) pa.s[i].coef[q] = q < x.n_zernike ? x.zernike_waves[q] : 0.0;
+      maxz = std::max(maxz, x.n_zernike);
+    }
+    pa.max_zernike = maxz;
+    const int cols = nb * nz;   // complex columns of Phi
+    const int total = T * cols;
+    hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, p->d_theta,
+                       p->d_z, p->d_phi, cols, 0);
+    int rc = hip_check(hipGetLastError());
+    if (rc) return rc;
+    const int M = 2 * cols, N = 3 * R;
+    const int blocks = ((M + RBM - 1) / RBM) * ((N + RBN - 1) / RBN);
+    hipLaunchKernelGGL(bessel_contract_kernel, dim3(blocks), dim3(256), 0, st, (const float*)p->d_phi,
+                       M, (const float*)p->d_btab, N, (float*)p->d_In, M, N, T);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+    EpiArgs ea{};
+    ea.nx = p->grid.nx;
+    ea.ny = p->grid.ny;
+    ea.nz = nz;
+    ea.R = R;
+    ea.nstk = nb;
+    ea.s_base = b0;
+    ea.dx = (float)p->grid.dx_nm;
+    ea.dy = (float)p->grid.dy_nm;
+    ea.inv_drho = (float)(1.0 / p->drho);
+    ea.exr = (float)ex.real();
+    ea.exi = (float)ex.imag();
+    ea.eyr = (float)ey.real();
+    ea.eyi = (float)ey.imag();
+    for (int i = 0; i < nb; ++i) {
+      ea.x0[i] = (float)s[b0 + i].x0_nm;
+      ea.y0[i] = (float)s[b0 + i].y0_nm;
+    }
+    hipLaunchKernelGGL(bessel_epilogue_kernel, dim3(nb * nz), dim3(256), 6 * R * sizeof(float), st, ea,
+                       (const float*)p->d_In, E, I);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+  }
+  return RWPSF_OK;
+}
+
+}  // namespace rw

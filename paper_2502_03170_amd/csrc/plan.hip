@@ -1,0 +1,225 @@
+// Plan construction (FP64 tables on the host, uploaded once) and the Fourier-form
+// dispatch.  Tables of the Fourier form (Sec. 3.3 eq. "cartesian vectorial",
+// Sec. 3.4 correction factors) on the cell-centred pupil grid
+//   s_x[j] = (2j + 1 - N) s_max / N,  s_y[l] likewise,  cell area ds^2 = (2 s_max / N)^2,
+// disk mask (2j+1-N)^2 + (2l+1-N)^2 <= N^2 decided in integers:
+//   Q_c[j,l]  = ds^2 a(s) e_inf,c(s) / s_z          (complex64, 0 outside the disk)
+//   ksz[j,l]  = k s_z                                (FP64, for the defocus phase)
+//   AyT[l,n]  = exp(i k s_y[l] y_n)                  (complex64)
+//   AxT[j,m]  = -(i f k / 2 pi) exp(i k s_x[j] x_m)  (complex64, prefactor folded in)
+// with x_m = (m - nx/2) dx, y_n = (n - ny/2) dy.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <vector>
+
+#include "rw_common.h"
+#include "rw_fourier.h"
+#include "rw_plan.h"
+
+namespace rw {
+
+int bessel_plan_init(rwpsf_plan* p);
+
+static int fourier_plan_init(rwpsf_plan* p) {
+  const int N = p->num.n_pupil, nx = p->grid.nx, ny = p->grid.ny;
+  const double s_max = p->s_max, k = p->k;
+  const std::complex<double> ex(p->opt.ex_re, p->opt.ex_im), ey(p->opt.ey_re, p->opt.ey_im);
+  const size_t nn = (size_t)N * N;
+  std::vector<float2> Q(3 * nn);
+  std::vector<double> ksz(nn);
+  const double ds = 2.0 * s_max / N;
+  for (int j = 0; j < N; ++j)
+    for (int l = 0; l < N; ++l) {
+      const long u = 2L * j + 1 - N, v = 2L * l + 1 - N;
+      const size_t cell = (size_t)j * N + l;
+      if (u * u + v * v > (long)N * N) {
+        for (int c = 0; c < 3; ++c) Q[c * nn + cell] = make_float2(0.f, 0.f);
+        ksz[cell] = 0.0;
+        continue;
+      }
+      const double sx = u * s_max / N, sy = v * s_max / N;
+      const double s2 = sx * sx + sy * sy;
+      const double sin_t = std::sqrt(s2), cos_t = std::sqrt(1.0 - s2);
+      const double cp = sin_t > 0 ? sx / sin_t : 1.0, sp = sin_t > 0 ? sy / sin_t : 0.0;
+      std::complex<double> e[3];
+      far_field(ex, ey, cos_t, sin_t, cp, sp, e);
+      const double w = ds * ds * amplitude(p->opt, cos_t, sin_t) / cos_t;
+      for (int c = 0; c < 3; ++c)
+        Q[c * nn + cell] = make_float2((float)(w * e[c].real()), (float)(w * e[c].imag()));
+      ksz[cell] = k * cos_t;
+    }
+  std::vector<float2> AyT((size_t)N * ny), AxT((size_t)N * nx);
+  const double pref = p->opt.focal_length * k / kTwoPi;  // C = -i pref
+  for (int l = 0; l < N; ++l) {
+    const double sy = (2.0 * l + 1.0 - N) * s_max / N;
+    for (int n = 0; n < ny; ++n) {
+      const double y = (double)(n - ny / 2) * p->grid.dy_nm;
+      const double ph = k * sy * y;
+      AyT[(size_t)l * ny + n] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+    }
+  }
+  for (int j = 0; j < N; ++j) {
+    const double sx = (2.0 * j + 1.0 - N) * s_max / N;
+    for (int m = 0; m < nx; ++m) {
+      const double x = (double)(m - nx / 2) * p->grid.dx_nm;
+      const double ph = k * sx * x;
+      // -i pref (cos + i sin) = pref (sin - i cos)
+      AxT[(size_t)j * nx + m] = make_float2((float)(pref * std::sin(ph)), (float)(-pref * std::cos(ph)));
+    }
+  }
+  int st;
+  if ((st = dev_alloc(p, &p->d_Q, 3 * nn))) return st;
+  if ((st = dev_alloc(p, &p->d_ksz, nn))) return st;
+  if ((st = dev_alloc(p, &p->d_AyT, (size_t)N * ny))) return st;
+  if ((st = dev_alloc(p, &p->d_AxT, (size_t)N * nx))) return st;
+  if ((st = dev_alloc(p, &p->d_ztab, (size_t)RWPSF_MAX_ZERNIKE * nn))) return st;
+  if ((st = dev_alloc(p, &p->d_z, (size_t)p->grid.nz))) return st;
+  p->P_stacks = kPupilStacks;
+  if ((st = dev_alloc(p, &p->d_P, (size_t)p->P_stacks * 3 * nn))) return st;
+  // plane workspace: whole chunk of stacks x planes, capped at 512 MiB
+  const size_t plane_bytes = 3 * (size_t)N * ny * sizeof(float2);
+  const size_t want = (size_t)kPupilStacks * p->grid.nz;
+  p->T_planes = std::max<size_t>(1, std::min(want, (size_t)(512u << 20) / plane_bytes));
+  if ((st = dev_alloc(p, &p->d_T, p->T_planes * 3 * (size_t)N * ny))) return st;
+
+  if ((st = hip_check(hipMemcpy(p->d_Q, Q.data(), Q.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_ksz, ksz.data(), ksz.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_AyT, AyT.data(), AyT.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_AxT, AxT.data(), AxT.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_z, p->z.data(), p->z.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(launch_zernike_table(p->d_ztab, N, RWPSF_MAX_ZERNIKE, 0)))) return st;
+  if ((st = hip_check(fourier_kernel_attributes()))) return st;
+  return hip_check(hipDeviceSynchronize());
+}
+
+int plan_init(rwpsf_plan* p, const rwpsf_optics& o, const rwpsf_grid& g, const rwpsf_numerics& nm) {
+  int dev_count = 0;
+  if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) return RWPSF_ERR_NO_DEVICE;
+  hipError_t e = hipGetDevice(&p->device);
+  if (e != hipSuccess) return hip_check(e);
+  p->opt = o;
+  p->grid = g;
+  p->num = nm;
+  p->z.assign(g.z_nm, g.z_nm + g.nz);
+  p->grid.z_nm = nullptr;
+  p->k = kTwoPi * o.n_i / o.wavelength_nm;
+  p->s_max = o.na / o.n_i;
+  p->theta_max = std::asin(p->s_max);
+  p->gl.k0 = kTwoPi / o.wavelength_nm;
+  p->gl.n_i = o.n_i;
+  p->gl.n_s = o.n_s;
+  p->gl.n_g = o.n_g;
+  p->gl.n_g_d = o.n_g_design;
+  p->gl.n_i_d = o.n_i_design;
+  p->gl.t_g = o.t_g_nm;
+  p->gl.t_g_d = o.t_g_design_nm;
+  p->gl.t_i_d = o.t_i_design_nm;
+  if (nm.form == RWPSF_FORM_FOURIER) return fourier_plan_init(p);
+  return bessel_plan_init(p);
+}
+
+// --------------------------------------------------------------------------
+// Fourier dispatch: chunks of up to 8 stacks (pupil build), then slabs of
+// stack-planes through the two GEMM kernels.
+// --------------------------------------------------------------------------
+int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
+  int cur = -1;
+  hipGetDevice(&cur);
+  if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
+  const int N = p->num.n_pupil, nz = p->grid.nz;
+  for (int b0 = 0; b0 < n; b0 += kPupilStacks) {
+    const int nb = std::min(kPupilStacks, n - b0);
+    PupilArgs pa{};
+    pa.n = N;
+    pa.nstk = nb;
+    pa.gibson_lanni = p->opt.gibson_lanni;
+    pa.s_max = p->s_max;
+    pa.k = p->k;
+    pa.gl = p->gl;
+    int maxz = 0;
+    for (int i = 0; i < nb; ++i) {
+      const rwpsf_stack& x = s[b0 + i];
+      PupilStack& d = pa.s[i];
+      d.t_s = x.t_s_nm;
+      d.x0 = x.x0_nm;
+      d.y0 = x.y0_nm;
+      for (int q = 0; q < RWPSF_MAX_ZERNIKE; ++q) d.coef[q] = q < x.n_zernike ? x.zernike_waves[q] : 0.0;
+      d.w0 = x.phase_map;
+      maxz = std::max(maxz, x.n_zernike);
+    }
+    pa.max_zernike = maxz;
+    int rc = hip_check(launch_pupil_build(pa, p->d_Q, p->d_ztab, p->d_P, st));
+    if (rc) return rc;
+    // slabs over (stack, plane): a slab is a run of planes of one or more stacks
+    const size_t cap = p->T_planes;
+    if ((size_t)nz <= cap) {
+      const int stk_per = (int)std::min<size_t>(nb, cap / nz);
+      for (int s0 = 0; s0 < nb; s0 += stk_per) {
+        const int ns = std::min(stk_per, nb - s0);
+        Gemm1Args g1{};
+        g1.P = p->d_P + (size_t)s0 * 3 * N * N;
+        g1.ksz = p->d_ksz;
+        g1.z = p->d_z;
+        g1.AyT = p->d_AyT;
+        g1.T = p->d_T;
+        for (int i = 0; i < ns; ++i) g1.zoff[i] = s[b0 + s0 + i].z_offset_nm;
+        g1.n = N;
+        g1.ny = p->grid.ny;
+        g1.nstk = ns;
+        g1.z0 = 0;
+        g1.nzs = nz;
+        if ((rc = hip_check(launch_gemm_pupil(g1, st)))) return rc;
+        Gemm2Args g2{};
+        g2.AxT = p->d_AxT;
+        g2.T = p->d_T;
+        g2.E = E;
+        g2.I = I;
+        g2.n = N;
+        g2.nx = p->grid.nx;
+        g2.ny = p->grid.ny;
+        g2.nz = nz;
+        g2.nstk = ns;
+        g2.s_base = b0 + s0;
+        g2.z0 = 0;
+        g2.nzs = nz;
+        if ((rc = hip_check(launch_gemm_image(g2, st)))) return rc;
+      }
+    } else {
+      for (int i = 0; i < nb; ++i)
+        for (int z0 = 0; z0 < nz; z0 += (int)cap) {
+          const int nzs = (int)std::min<size_t>(cap, nz - z0);
+          Gemm1Args g1{};
+          g1.P = p->d_P + (size_t)i * 3 * N * N;
+          g1.ksz = p->d_ksz;
+          g1.z = p->d_z;
+          g1.AyT = p->d_AyT;
+          g1.T = p->d_T;
+          g1.zoff[0] = s[b0 + i].z_offset_nm;
+          g1.n = N;
+          g1.ny = p->grid.ny;
+          g1.nstk = 1;
+          g1.z0 = z0;
+          g1.nzs = nzs;
+          if ((rc = hip_check(launch_gemm_pupil(g1, st)))) return rc;
+          Gemm2Args g2{};
+          g2.AxT = p->d_AxT;
+          g2.T = p->d_T;
+          g2.E = E;
+          g2.I = I;
+          g2.n = N;
+          g2.nx = p->grid.nx;
+          g2.ny = p->grid.ny;
+          g2.nz = nz;
+          g2.nstk = 1;
+          g2.s_base = b0 + i;
+          g2.z0 = z0;
+          g2.nzs = nzs;
+          if ((rc = hip_check(launch_gemm_image(g2, st)))) return rc;
+        }
+    }
+  }
+  return RWPSF_OK;
+}
+
+}  // namespace rw

@@ -1,0 +1,174 @@
+// Internal declarations of the rwpsf library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <vector>
+
+#include "rwpsf.h"
+
+#define RW_HD __host__ __device__ inline
+
+namespace rw {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+
+// ---------------------------------------------------------------------------
+// Bessel functions of the first kind, J_n(x) = (1/pi) int_0^pi cos(n t - x sin t) dt.
+// The integrand is 2 pi periodic and even about pi, so the M-point trapezoid rule
+// on [0, 2 pi) is exact up to the aliased orders J_{n +- M} (Jacobi-Anger).  J_nu(x)
+// decays past the turning point nu = x on the scale x^(1/3) (Airy transition), so
+// M = n + x + 12 x^(1/3) + 32 keeps the aliased terms below 1e-20.
+// ---------------------------------------------------------------------------
+RW_HD double bessel_j(int n, double x) {
+  if (x == 0.0) return n == 0 ? 1.0 : 0.0;
+  const double ax = fabs(x);
+  int m = n + (int)ceil(ax + 12.0 * cbrt(ax)) + 32;
+  m += m & 1;
+  const double h = kTwoPi / m;
+  double s = 0.0;
+  for (int i = 0; i < m; ++i) {
+    const double t = h * i;
+    s += cos(n * t - x * sin(t));
+  }
+  return s / m;
+}
+
+// ---------------------------------------------------------------------------
+// Noll-indexed Zernike polynomials, orthonormal on the unit disk (Sec. 3.4.2).
+// ---------------------------------------------------------------------------
+RW_HD void noll_nm(int j, int* n_out, int* m_out) {
+  int n = 0;
+  while ((n + 1) * (n + 2) / 2 < j) ++n;
+  const int p = j - n * (n + 1) / 2 - 1;
+  const int am = (n % 2 == 0) ? 2 * ((p + 1) / 2) : 2 * (p / 2) + 1;
+  *n_out = n;
+  *m_out = (am == 0) ? 0 : ((j % 2 == 0) ? am : -am);
+}
+
+RW_HD double factorial_d(int k) {
+  double f = 1.0;
+  for (int i = 2; i <= k; ++i) f *= i;
+  return f;
+}
+
+// Coefficient of r^(n-2s) in R_n^|m|, times the orthonormalisation factor.
+RW_HD double zernike_radial_coef(int n, int am, int s) {
+  const double sign = (s & 1) ? -1.0 : 1.0;
+  return sign * factorial_d(n - s) /
+         (factorial_d(s) * factorial_d((n + am) / 2 - s) * factorial_d((n - am) / 2 - s));
+}
+
+RW_HD double zernike_noll(int j, double r, double cp, double sp) {
+  int n, m;
+  noll_nm(j, &n, &m);
+  const int am = m < 0 ? -m : m;
+  double rad = 0.0;
+  for (int s = 0; s <= (n - am) / 2; ++s) rad += zernike_radial_coef(n, am, s) * pow(r, n - 2 * s);
+  if (m == 0) return sqrt((double)(n + 1)) * rad;
+  // cos(am p), sin(am p) by the angle-addition recurrence
+  double c = 1.0, s = 0.0;
+  for (int i = 0; i < am; ++i) {
+    const double c2 = c * cp - s * sp;
+    s = s * cp + c * sp;
+    c = c2;
+  }
+  return sqrt(2.0 * (n + 1)) * rad * (m > 0 ? c : s);
+}
+
+// ---------------------------------------------------------------------------
+// Gibson-Lanni OPD (Sec. 3.4.1, eq. "stratified layers general formula"), with
+// t_i from the focusing condition eq. "gibson lanni t_i" as printed.  Returns
+// W = (re, im): a principal-branch square root makes im >= 0 past a critical angle.
+// ---------------------------------------------------------------------------
+struct GLParams {
+  double k0;  // 2 pi / lambda
+  double n_i, n_s, n_g, n_g_d, n_i_d;
+  double t_g, t_g_d, t_i_d;
+};
+
+RW_HD double gl_ti(const GLParams& g, double t_s) {
+  return t_s + g.n_i * (-t_s / g.n_s - g.t_g / g.n_g + g.t_g_d / g.n_g_d + g.t_i_d / g.n_i_d);
+}
+
+// sqrt(n^2 - q) for real arguments, principal branch: (re, im)
+RW_HD void csqrt_real(double v, double* re, double* im) {
+  if (v >= 0.0) {
+    *re = sqrt(v);
+    *im = 0.0;
+  } else {
+    *re = 0.0;
+    *im = sqrt(-v);
+  }
+}
+
+RW_HD void gl_opd(const GLParams& g, double t_s, double sin_t, double* w_re, double* w_im) {
+  const double q = g.n_i * g.n_i * sin_t * sin_t;
+  const double t_i = gl_ti(g, t_s);
+  const double n[5] = {g.n_s, g.n_i, g.n_i_d, g.n_g, g.n_g_d};
+  const double t[5] = {t_s, t_i, -g.t_i_d, g.t_g, -g.t_g_d};
+  double re = 0.0, im = 0.0;
+  for (int i = 0; i < 5; ++i) {
+    double a, b;
+    csqrt_real(n[i] * n[i] - q, &a, &b);
+    re += t[i] * a;
+    im += t[i] * b;
+  }
+  *w_re = g.k0 * re;
+  *w_im = g.k0 * im;
+}
+
+// Reduce an FP64 phase to [-pi, pi] before it is rounded to FP32.
+RW_HD double reduce_2pi(double p) { return p - kTwoPi * rint(p * (1.0 / kTwoPi)); }
+
+// ---------------------------------------------------------------------------
+// Host helpers
+// ---------------------------------------------------------------------------
+int gauss_legendre(int n, double a, double b, double* x, double* w);
+void set_hip_error(hipError_t e);
+
+struct PlanDevice;  // per-form device state
+
+}  // namespace rw
+
+// ---------------------------------------------------------------------------
+// Plan
+// ---------------------------------------------------------------------------
+struct rwpsf_plan {
+  int device = 0;
+  rwpsf_optics opt{};
+  rwpsf_grid grid{};
+  rwpsf_numerics num{};
+  std::vector<double> z;
+  double k = 0, s_max = 0, theta_max = 0;
+  rw::GLParams gl{};
+  size_t device_bytes = 0;
+  std::vector<void*> allocations;
+
+  // Fourier form
+  double* d_z = nullptr;        // [nz]
+  double* d_ksz = nullptr;      // [N*N] k * s_z (0 outside the disk)
+  float2* d_Q = nullptr;        // [3][N][N] ds^2 a e_inf,c / s_z (0 outside)
+  float2* d_AyT = nullptr;      // [N][ny] exp(i k s_y[l] y_n)
+  float2* d_AxT = nullptr;      // [N][nx] C exp(i k s_x[j] x_m), C = -i f k / 2 pi
+  float* d_ztab = nullptr;      // [RWPSF_MAX_ZERNIKE][N][N] Noll basis on the pupil cells
+  float2* d_P = nullptr;        // workspace [chunk][3][N][N]
+  float2* d_T = nullptr;        // workspace [planes][3][N][ny]
+  size_t T_planes = 0;          // capacity of d_T in stack-planes
+  int P_stacks = 0;             // capacity of d_P in stacks
+
+  // Bessel form
+  int n_theta_total = 0;        // nodes after the critical-angle split
+  double* d_theta = nullptr;    // [T] nodes
+  double* d_wtheta = nullptr;   // [T] weights
+  float* d_btab = nullptr;      // [3][R][T] w_t g_n(t) J_n(k rho_r sin t)
+  float2* d_phi = nullptr;      // workspace [stacks][T][nz] pupil x defocus
+  float2* d_In = nullptr;       // workspace [stacks][3][nz][R]
+  int bessel_stacks = 0;        // capacity of the Bessel workspaces
+  double drho = 0;              // radial sample pitch
+
+  ~rwpsf_plan();
+};

@@ -1,0 +1,48 @@
+// Kernel argument blocks and launchers of the Fourier form (internal).
+#pragma once
+
+#include "rw_common.h"
+
+namespace rw {
+
+constexpr int kPupilStacks = 8;  // stacks per pupil launch (by-value arguments stay < 4 KB)
+
+struct PupilStack {
+  double t_s, x0, y0;
+  double coef[RWPSF_MAX_ZERNIKE];
+  const float* w0;
+};
+
+struct PupilArgs {
+  int n, nstk, max_zernike, gibson_lanni;
+  double s_max, k;
+  GLParams gl;
+  PupilStack s[kPupilStacks];
+};
+
+struct Gemm1Args {
+  const float2* P;     // [nstk][3][n][n]
+  const double* ksz;   // [n][n]
+  const double* z;     // plan planes
+  const float2* AyT;   // [n][ny]
+  float2* T;           // [nstk][nzs][3][n][ny]
+  double zoff[kPupilStacks];
+  int n, ny, nstk, z0, nzs;
+};
+
+struct Gemm2Args {
+  const float2* AxT;   // [n][nx]
+  const float2* T;     // [nstk][nzs][3][n][ny]
+  float2* E;           // [stacks][nz][3][nx][ny] or null
+  float* I;            // [stacks][nz][nx][ny] or null
+  int n, nx, ny, nz, nstk, s_base, z0, nzs;
+};
+
+hipError_t launch_zernike_table(float* out, int n, int nj, hipStream_t st);
+hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* ztab, float2* P,
+                              hipStream_t st);
+hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st);
+hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st);
+hipError_t fourier_kernel_attributes();
+
+}  // namespace rw

@@ -1,0 +1,121 @@
+"""The C-ABI library loads, exports every declared symbol, and its host-only routines
+(table builders and validation) are right -- no GPU needed."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+from scipy import special
+
+import paper_2502_03170_amd as rw
+from oracle import optics as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    inc = os.path.join(ROOT, "include")
+    for f in os.listdir(inc):
+        if f.endswith(".h"):
+            text = open(os.path.join(inc, f)).read()
+            names |= set(re.findall(r"\b(rwpsf_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = rw.load()
+    names = declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert rw.abi_version() == 1
+
+
+def test_status_strings():
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert rw.status_string(s)
+    assert "unknown" in rw.status_string(-99)
+
+
+@pytest.mark.parametrize("n", [2, 7, 64, 200, 513])
+def test_gauss_legendre_rule(n):
+    a, b = 0.0, 1.1739
+    x, w = np.array(rw.gauss_legendre(n, a, b)[0]), np.array(rw.gauss_legendre(n, a, b)[1])
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    np.testing.assert_allclose(x, 0.5 * (b - a) * (xr + 1), rtol=0, atol=5e-16)
+    np.testing.assert_allclose(w, 0.5 * (b - a) * wr, rtol=5e-9, atol=0)
+    # exact on polynomials of degree <= 2n - 1 (checked on Legendre-stable monomials of (t - mid))
+    mid, half = 0.5 * (a + b), 0.5 * (b - a)
+    for p in range(0, min(2 * n, 40)):
+        exact = 0.0 if p % 2 else 2 * half ** (p + 1) / (p + 1)
+        assert abs(np.sum(w * (x - mid) ** p) - exact) < 1e-13
+
+
+@pytest.mark.parametrize("order", [0, 1, 2, 3])
+def test_bessel_j_matches_scipy(order):
+    xs = np.concatenate([np.linspace(0, 25, 501), [1e-9]])
+    np.testing.assert_allclose(rw.bessel_j(order, xs), special.jv(order, xs), rtol=0, atol=2e-15)
+    big = np.array([60.0, 120.0, 400.0])    # more trapezoid nodes, more rounding
+    np.testing.assert_allclose(rw.bessel_j(order, big), special.jv(order, big), rtol=0, atol=2e-13)
+
+
+def test_bessel_j_identities():
+    xs = np.linspace(0.1, 20, 200)
+    j0, j1, j2 = (np.array(rw.bessel_j(n, xs)) for n in range(3))
+    np.testing.assert_allclose(j0 + j2, 2 * j1 / xs, rtol=0, atol=1e-14)
+    assert rw.bessel_j(0, [0.0]) == [1.0] and rw.bessel_j(1, [0.0]) == [0.0]
+
+
+def test_zernike_matches_oracle():
+    rng = np.random.default_rng(5)
+    r = rng.uniform(0, 1, 300)
+    p = rng.uniform(0, 2 * math.pi, 300)
+    for j in range(1, rw.MAX_ZERNIKE + 1):
+        np.testing.assert_allclose(rw.zernike(j, r, p), O.zernike_noll(j, r, p), rtol=0, atol=1e-13)
+
+
+def _plan_desc(form=rw.FORM_BESSEL, **kw):
+    o = rw.make_optics(kw.get("na", 1.4), 532.0, 1.518)
+    g = rw.make_grid(kw.get("nx", 65), 65, 20.0, 20.0, kw.get("z", np.linspace(-1000, 1000, 33)))
+    nm = rw.Numerics(form=form, n_pupil=kw.get("n_pupil", 256), n_theta=200, n_rho=256)
+    return o, g, nm
+
+
+def test_validation_error_codes():
+    o, g, nm = _plan_desc()
+    assert rw.validate(o, g, nm) == rw.OK
+    assert rw.validate(rw.make_optics(1.6, 532.0, 1.518), g, nm) == rw.ERR_INVALID_ARG   # NA >= n_i
+    assert rw.validate(rw.make_optics(0.0, 532.0, 1.518), g, nm) == rw.ERR_INVALID_ARG
+    assert rw.validate(rw.make_optics(1.4, float("nan"), 1.518), g, nm) == rw.ERR_INVALID_ARG
+    assert rw.validate(o, rw.make_grid(0, 65, 20.0, 20.0, [0.0]), nm) == rw.ERR_INVALID_ARG
+    assert rw.validate(o, rw.make_grid(65, 65, -1.0, 20.0, [0.0]), nm) == rw.ERR_INVALID_ARG
+    assert rw.validate(o, rw.make_grid(65, 65, 20.0, 20.0, [0.0, float("inf")]), nm) == rw.ERR_INVALID_ARG
+    assert rw.validate(o, g, rw.Numerics(form=7, n_pupil=256, n_theta=200, n_rho=256)) == rw.ERR_INVALID_ARG
+    assert rw.validate(o, g, rw.Numerics(form=0, n_pupil=256, n_theta=1, n_rho=256)) == rw.ERR_INVALID_ARG
+    assert rw.validate(o, g, rw.Numerics(form=1, n_pupil=4096, n_theta=200, n_rho=256)) == rw.ERR_INVALID_ARG
+
+
+def test_stack_validation_bessel_needs_axisymmetry():
+    o, g, nm = _plan_desc()
+    assert rw.validate_stacks(o, g, nm, [dict(zernike=[0, 0, 0, 0.1, 0, 0, 0, 0, 0, 0, -0.05])]) == rw.OK
+    assert rw.validate_stacks(o, g, nm, [dict(zernike=[0, 0.1])]) == rw.ERR_NOT_AXISYMMETRIC     # tilt
+    assert rw.validate_stacks(o, g, nm, [dict(zernike=[0, 0, 0, 0, 0.02])]) == rw.ERR_NOT_AXISYMMETRIC
+    assert rw.validate_stacks(o, g, nm, [dict(x0=25.0)]) == rw.ERR_INVALID_ARG   # beyond one pixel
+    assert rw.validate_stacks(o, g, nm, [dict(zernike=[float("nan")])]) == rw.ERR_INVALID_ARG
+    assert rw.validate_stacks(o, g, nm, [dict(zernike=[0.0] * 37)]) == rw.ERR_INVALID_ARG
+    assert rw.validate_stacks(o, g, nm, []) == rw.ERR_INVALID_ARG
+    of, gf, nmf = _plan_desc(form=rw.FORM_FOURIER)
+    assert rw.validate_stacks(of, gf, nmf, [dict(zernike=[0, 0.1], x0=500.0)]) == rw.OK
+
+
+def test_plan_create_without_device_reports_no_device_or_works():
+    # on a machine without a GPU plan creation fails cleanly with a status, not a crash
+    import torch
+    o, g, nm = _plan_desc()
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    with pytest.raises(rw.RwpsfError) as ei:
+        rw.plan_create(o, g, nm)
+    assert ei.value.status in (rw.ERR_NO_DEVICE, rw.ERR_HIP)
