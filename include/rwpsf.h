@@ -145,6 +145,23 @@ size_t rwpsf_plan_device_bytes(const rwpsf_plan* plan);
 int rwpsf_compute(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
                   void* E_out, float* I_out, void* stream);
 
+/* ---- per-kernel timing, for benchmarking -------------------------------------
+   When enabled, every kernel the plan launches is bracketed by HIP events on
+   the call's stream.  rwpsf_plan_timing waits for the recorded events, folds them
+   into per-kernel totals and returns the total milliseconds and launch count of
+   one kernel since timing was last enabled. */
+enum rwpsf_kernel_id {
+  RWPSF_KERNEL_PUPIL_BUILD = 0,       /* Fourier: base pupil with FP64 phases */
+  RWPSF_KERNEL_GEMM_PUPIL = 1,        /* Fourier: (pupil x defocus) x Ay^T */
+  RWPSF_KERNEL_GEMM_IMAGE = 2,        /* Fourier: Ax x T, fields and |E|^2 */
+  RWPSF_KERNEL_BESSEL_PHI = 3,        /* Bessel: pupil x defocus on the theta nodes */
+  RWPSF_KERNEL_BESSEL_CONTRACT = 4,   /* Bessel: theta contraction on the matrix cores */
+  RWPSF_KERNEL_BESSEL_EPILOGUE = 5,   /* Bessel: radial interpolation, fields and |E|^2 */
+  RWPSF_KERNEL_COUNT = 16
+};
+int rwpsf_plan_set_timing(rwpsf_plan* plan, int enable);   /* also resets the totals */
+int rwpsf_plan_timing(rwpsf_plan* plan, int kernel, double* total_ms, int64_t* launches);
+
 /* ---- host-only reference routines used to build the plan tables ----------
    Exported so that the tables can be checked on a machine without a GPU. */
 

@@ -25,6 +25,12 @@ ERR_HIP = -5
 ERR_NO_DEVICE = -6
 FORM_BESSEL = 0
 FORM_FOURIER = 1
+KERNEL_PUPIL_BUILD = 0
+KERNEL_GEMM_PUPIL = 1
+KERNEL_GEMM_IMAGE = 2
+KERNEL_BESSEL_PHI = 3
+KERNEL_BESSEL_CONTRACT = 4
+KERNEL_BESSEL_EPILOGUE = 5
 MAX_ZERNIKE = 36
 CIRCULAR = (1 / math.sqrt(2), 1j / math.sqrt(2))
 
@@ -84,6 +90,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "rwpsf_plan_destroy": (None, [c_void_p]),
         "rwpsf_plan_device_bytes": (c_size_t, [c_void_p]),
         "rwpsf_compute": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_void_p]),
+        "rwpsf_plan_set_timing": (c_int, [c_void_p, c_int]),
+        "rwpsf_plan_timing": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(ctypes.c_int64)]),
         "rwpsf_gauss_legendre": (c_int, [c_int, c_double, c_double, POINTER(c_double), POINTER(c_double)]),
         "rwpsf_bessel_j": (c_int, [c_int, c_int, POINTER(c_double), POINTER(c_double)]),
         "rwpsf_zernike": (c_int, [c_int, c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
@@ -197,6 +205,17 @@ def plan_destroy(handle) -> None:
     load().rwpsf_plan_destroy(handle)
 
 
+def plan_set_timing(handle, enable: bool) -> None:
+    _check(load().rwpsf_plan_set_timing(handle, int(bool(enable))))
+
+
+def plan_timing(handle, kernel: int):
+    """(total milliseconds, launches) of one kernel since timing was enabled."""
+    ms, n = c_double(), ctypes.c_int64()
+    _check(load().rwpsf_plan_timing(handle, kernel, byref(ms), byref(n)))
+    return ms.value, n.value
+
+
 def compute(handle, stacks: list[dict], E=None, I=None, stream=None) -> None:
     """Enqueue rwpsf_compute; E (complex64) and I (float32) are CUDA tensors or None."""
     import torch
@@ -223,6 +242,12 @@ class Plan:
         self.num = Numerics(form=form, n_pupil=n_pupil, n_theta=n_theta, n_rho=n_rho)
         self.nx, self.ny, self.nz = nx, ny, len(z)
         self.handle = plan_create(self.optics, self.grid, self.num)
+
+    def set_timing(self, enable: bool) -> None:
+        plan_set_timing(self.handle, enable)
+
+    def timing(self, kernel: int):
+        return plan_timing(self.handle, kernel)
 
     def device_bytes(self) -> int:
         return load().rwpsf_plan_device_bytes(self.handle)

@@ -130,7 +130,49 @@ int validate_stacks(const rwpsf_optics* o, const rwpsf_grid* g, const rwpsf_nume
 
 }  // namespace rw
 
+static hipEvent_t pool_get(std::vector<hipEvent_t>& pool) {
+  if (!pool.empty()) {
+    hipEvent_t e = pool.back();
+    pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+int rwpsf_plan::time_begin(int kernel, hipStream_t st) {
+  if (!timing) return -1;
+  TimingRec r{kernel, pool_get(event_pool), pool_get(event_pool)};
+  if (!r.a || !r.b) return -1;
+  hipEventRecord(r.a, st);
+  timing_recs.push_back(r);
+  return (int)timing_recs.size() - 1;
+}
+
+void rwpsf_plan::time_end(int rec, hipStream_t st) {
+  if (rec >= 0) hipEventRecord(timing_recs[rec].b, st);
+}
+
+void rwpsf_plan::timing_flush() {
+  for (TimingRec& r : timing_recs) {
+    float ms = 0.f;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      timing_ms[r.kernel] += ms;
+      timing_launches[r.kernel] += 1;
+    }
+    event_pool.push_back(r.a);
+    event_pool.push_back(r.b);
+  }
+  timing_recs.clear();
+}
+
 rwpsf_plan::~rwpsf_plan() {
+  for (TimingRec& r : timing_recs) {
+    hipEventDestroy(r.a);
+    hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : event_pool) hipEventDestroy(e);
   for (void* p : allocations) hipFree(p);
 }
 
@@ -211,6 +253,26 @@ void rwpsf_plan_destroy(rwpsf_plan* p) {
 }
 
 size_t rwpsf_plan_device_bytes(const rwpsf_plan* p) { return p ? p->device_bytes : 0; }
+
+int rwpsf_plan_set_timing(rwpsf_plan* p, int enable) {
+  if (!p) return RWPSF_ERR_INVALID_ARG;
+  p->timing_flush();
+  for (int i = 0; i < RWPSF_KERNEL_COUNT; ++i) {
+    p->timing_ms[i] = 0.0;
+    p->timing_launches[i] = 0;
+  }
+  p->timing = enable != 0;
+  return RWPSF_OK;
+}
+
+int rwpsf_plan_timing(rwpsf_plan* p, int kernel, double* total_ms, int64_t* launches) {
+  if (!p || kernel < 0 || kernel >= RWPSF_KERNEL_COUNT || !total_ms || !launches)
+    return RWPSF_ERR_INVALID_ARG;
+  p->timing_flush();
+  *total_ms = p->timing_ms[kernel];
+  *launches = p->timing_launches[kernel];
+  return RWPSF_OK;
+}
 
 int rwpsf_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, void* E, float* I, void* stream) {
   if (!p) return RWPSF_ERR_INVALID_ARG;

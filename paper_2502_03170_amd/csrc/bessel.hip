@@ -352,15 +352,19 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
     pa.max_zernike = maxz;
     const int cols = nb * nz;   // complex columns of Phi
     const int total = T * cols;
+    int tr = p->time_begin(RWPSF_KERNEL_BESSEL_PHI, st);
     hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, p->d_theta,
                        p->d_z, p->d_phi, cols, 0);
     int rc = hip_check(hipGetLastError());
     if (rc) return rc;
+    p->time_end(tr, st);
     const int M = 2 * cols, N = 3 * R;
     const int blocks = ((M + RBM - 1) / RBM) * ((N + RBN - 1) / RBN);
+    tr = p->time_begin(RWPSF_KERNEL_BESSEL_CONTRACT, st);
     hipLaunchKernelGGL(bessel_contract_kernel, dim3(blocks), dim3(256), 0, st, (const float*)p->d_phi,
                        M, (const float*)p->d_btab, N, (float*)p->d_In, M, N, T);
     if ((rc = hip_check(hipGetLastError()))) return rc;
+    p->time_end(tr, st);
     EpiArgs ea{};
     ea.nx = p->grid.nx;
     ea.ny = p->grid.ny;
@@ -379,9 +383,11 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
       ea.x0[i] = (float)s[b0 + i].x0_nm;
       ea.y0[i] = (float)s[b0 + i].y0_nm;
     }
+    tr = p->time_begin(RWPSF_KERNEL_BESSEL_EPILOGUE, st);
     hipLaunchKernelGGL(bessel_epilogue_kernel, dim3(nb * nz), dim3(256), 6 * R * sizeof(float), st, ea,
                        (const float*)p->d_In, E, I);
     if ((rc = hip_check(hipGetLastError()))) return rc;
+    p->time_end(tr, st);
   }
   return RWPSF_OK;
 }

@@ -38,13 +38,17 @@ struct CgCfg {
 
 // Loader of a k-major complex operand: element (k, c) at src[k * ld + c], used
 // for B operands ([k][n]) and for constant A operands stored transposed ([k][m]).
-// Each thread moves pairs of adjacent complex values (one float4).
+// Operands are zero-padded to whole tiles (rows to a multiple of BK, columns to
+// a multiple of the tile width, ld even), so every load is an unconditional,
+// aligned float4 (two adjacent complex values) and the prefetch stays in flight
+// while the MFMAs of the current stage run.
 template <class Cfg, int BW>
 struct KMajorLoader {
   static constexpr int PAIRS_PER_ROW = BW / 2;
-  static constexpr int PER_THREAD = (Cfg::BK * PAIRS_PER_ROW + Cfg::NT - 1) / Cfg::NT;
-  const float2* src;
-  int ld, K, ncols, c0;
+  static constexpr int PER_THREAD = Cfg::BK * PAIRS_PER_ROW / Cfg::NT;
+  static_assert(Cfg::BK * PAIRS_PER_ROW % Cfg::NT == 0, "loader shape");
+  const float2* src;  // already offset to column c0
+  int ld;
   float4 v[PER_THREAD];
 
   __device__ void load(int k0, int tid) {
@@ -53,25 +57,13 @@ struct KMajorLoader {
       const int idx = tid + i * Cfg::NT;
       const int kk = idx / PAIRS_PER_ROW;
       const int cc = 2 * (idx % PAIRS_PER_ROW);
-      const int k = k0 + kk, c = c0 + cc;
-      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (idx < Cfg::BK * PAIRS_PER_ROW && k < K) {
-        const float2* p = src + (size_t)k * ld + c;
-        if (c + 1 < ncols && ((((uintptr_t)p) & 15) == 0)) {
-          x = *reinterpret_cast<const float4*>(p);
-        } else {
-          if (c < ncols) { x.x = p[0].x; x.y = p[0].y; }
-          if (c + 1 < ncols) { x.z = p[1].x; x.w = p[1].y; }
-        }
-      }
-      v[i] = x;
+      v[i] = *reinterpret_cast<const float4*>(src + (size_t)(k0 + kk) * ld + cc);
     }
   }
   __device__ void store(float* re, float* im, int ldl, int tid) const {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
-      if (idx >= Cfg::BK * PAIRS_PER_ROW) break;
       const int kk = idx / PAIRS_PER_ROW;
       const int cc = 2 * (idx % PAIRS_PER_ROW);
       *reinterpret_cast<float2*>(re + kk * ldl + cc) = make_float2(v[i].x, v[i].z);
@@ -139,20 +131,21 @@ __device__ __forceinline__ void cg_stage_mma(CgAcc<Cfg>& acc, const float* a_re,
   }
 }
 
-// Full K loop: acc += A[rows, 0:K] * B[0:K, cols] with double-buffered LDS.
+// Full K loop: acc += A[rows, 0:K] * B[0:K, cols] with double-buffered LDS (K a multiple of BK).
 template <class Cfg, class ALoader, class BLoader>
 __device__ __forceinline__ void cg_mainloop(CgAcc<Cfg>& acc, ALoader& la, BLoader& lb, int K,
                                             float* lds, int tid, int wrow, int wcol, int lane) {
-  float* st[2] = {lds, lds + Cfg::STAGE_FLOATS};
-  const int KT = (K + Cfg::BK - 1) / Cfg::BK;
+  // stage pointers by arithmetic on the __shared__ base: a pointer picked from a
+  // local array loses its address space and turns the LDS reads into flat loads
+  const int KT = K / Cfg::BK;
   la.load(0, tid);
   lb.load(0, tid);
-  la.store(st[0], st[0] + Cfg::BK * Cfg::LDA, Cfg::LDA, tid);
-  lb.store(st[0] + Cfg::A_FLOATS, st[0] + Cfg::A_FLOATS + Cfg::BK * Cfg::LDB, Cfg::LDB, tid);
+  la.store(lds, lds + Cfg::BK * Cfg::LDA, Cfg::LDA, tid);
+  lb.store(lds + Cfg::A_FLOATS, lds + Cfg::A_FLOATS + Cfg::BK * Cfg::LDB, Cfg::LDB, tid);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
-    float* cur = st[kt & 1];
-    float* nxt = st[(kt + 1) & 1];
+    float* cur = lds + (kt & 1) * Cfg::STAGE_FLOATS;
+    float* nxt = lds + ((kt + 1) & 1) * Cfg::STAGE_FLOATS;
     const bool more = kt + 1 < KT;
     if (more) {
       la.load((kt + 1) * Cfg::BK, tid);

@@ -39,19 +39,25 @@ __global__ void zernike_table_kernel(float* __restrict__ out, int n, int nj, dou
 __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const float2* __restrict__ Q,
                                                           const float* __restrict__ ztab,
                                                           float2* __restrict__ P) {
-  const int n = a.n;
-  const int nn = n * n;
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
-  if (cell >= nn) return;
-  const float2 q0 = Q[cell], q1 = Q[nn + cell], q2 = Q[2 * nn + cell];
+  const int n = a.n, np = a.np;
+  const size_t npp = (size_t)np * np;
+  const int pcell = blockIdx.x * blockDim.x + threadIdx.x;   // padded cell
+  if (pcell >= np * np) return;
+  const int j = pcell / np, l = pcell % np;
+  float2 q0 = make_float2(0.f, 0.f), q1 = q0, q2 = q0;
+  if (j < n && l < n) {
+    q0 = Q[pcell];
+    q1 = Q[npp + pcell];
+    q2 = Q[2 * npp + pcell];
+  }
   const bool inside = (q0.x != 0.f || q0.y != 0.f || q1.x != 0.f || q1.y != 0.f || q2.x != 0.f ||
                        q2.y != 0.f);
   if (!inside) {
     for (int s = 0; s < a.nstk; ++s)
-      for (int c = 0; c < 3; ++c) P[((size_t)s * 3 + c) * nn + cell] = make_float2(0.f, 0.f);
+      for (int c = 0; c < 3; ++c) P[((size_t)s * 3 + c) * npp + pcell] = make_float2(0.f, 0.f);
     return;
   }
-  const int j = cell / n, l = cell % n;
+  const int cell = j * n + l;   // unpadded index: Zernike table and user phase map
   const double sx = (2.0 * j + 1.0 - n) * a.s_max / n;
   const double sy = (2.0 * l + 1.0 - n) * a.s_max / n;
   const double sin_t = sqrt(sx * sx + sy * sy);
@@ -73,7 +79,7 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
     if (st.w0) w_re[s] += (double)st.w0[cell];
   }
   for (int q = 0; q < a.max_zernike; ++q) {
-    const double zq = (double)ztab[(size_t)q * nn + cell];
+    const double zq = (double)ztab[(size_t)q * n * n + cell];
     for (int s = 0; s < a.nstk; ++s) w_re[s] += kTwoPi * a.s[s].coef[q] * zq;
   }
   for (int s = 0; s < a.nstk; ++s) {
@@ -82,10 +88,10 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
     float sn, cs;
     sincosf(ph, &sn, &cs);
     const float er = amp * cs, ei = amp * sn;
-    float2* out = P + (size_t)s * 3 * nn + cell;
+    float2* out = P + (size_t)s * 3 * npp + pcell;
     out[0] = make_float2(q0.x * er - q0.y * ei, q0.x * ei + q0.y * er);
-    out[nn] = make_float2(q1.x * er - q1.y * ei, q1.x * ei + q1.y * er);
-    out[2 * nn] = make_float2(q2.x * er - q2.y * ei, q2.x * ei + q2.y * er);
+    out[npp] = make_float2(q1.x * er - q1.y * ei, q1.x * ei + q1.y * er);
+    out[2 * npp] = make_float2(q2.x * er - q2.y * ei, q2.x * ei + q2.y * er);
   }
 }
 
@@ -97,11 +103,12 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
 template <class Cfg>
 struct DefocusLoader {
   static constexpr int PAIRS = Cfg::BK / 2;
-  static constexpr int PER_THREAD = (Cfg::BM * PAIRS + Cfg::NT - 1) / Cfg::NT;
-  const float2* P;    // [n][n] of this stack and component
-  const double* ksz;  // [n][n]
+  static constexpr int PER_THREAD = Cfg::BM * PAIRS / Cfg::NT;
+  static_assert(Cfg::BM * PAIRS % Cfg::NT == 0, "loader shape");
+  const float2* P;    // [np][np] of this stack and component, rows from row0
+  const double* ksz;  // [np][np], rows from row0
   double z;
-  int n, row0;
+  int ld;
   float4 v[PER_THREAD];
   double2 kz[PER_THREAD];
 
@@ -110,34 +117,15 @@ struct DefocusLoader {
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
       const int row = idx / PAIRS, kk = 2 * (idx % PAIRS);
-      const int gr = row0 + row, k = k0 + kk;
-      float4 x = make_float4(0.f, 0.f, 0.f, 0.f);
-      double2 q = make_double2(0.0, 0.0);
-      if (idx < Cfg::BM * PAIRS && gr < n && k < n) {
-        const size_t off = (size_t)gr * n + k;
-        if ((n & 1) == 0) {
-          x = *reinterpret_cast<const float4*>(P + off);
-          q = *reinterpret_cast<const double2*>(ksz + off);
-        } else {
-          x.x = P[off].x;
-          x.y = P[off].y;
-          q.x = ksz[off];
-          if (k + 1 < n) {
-            x.z = P[off + 1].x;
-            x.w = P[off + 1].y;
-            q.y = ksz[off + 1];
-          }
-        }
-      }
-      v[i] = x;
-      kz[i] = q;
+      const size_t off = (size_t)row * ld + k0 + kk;
+      v[i] = *reinterpret_cast<const float4*>(P + off);
+      kz[i] = *reinterpret_cast<const double2*>(ksz + off);
     }
   }
   __device__ void store(float* re, float* im, int ldl, int tid) const {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
-      if (idx >= Cfg::BM * PAIRS) break;
       const int row = idx / PAIRS, kk = 2 * (idx % PAIRS);
       float s0, c0, s1, c1;
       sincosf((float)reduce_2pi(kz[i].x * z), &s0, &c0);
@@ -150,15 +138,28 @@ struct DefocusLoader {
   }
 };
 
-using CfgPupil = CgCfg<64, 128, 8, 64, 32>;
-using CfgImage = CgCfg<64, 128, 8, 64, 32>;
+#ifndef RW_PUPIL_BK
+#define RW_PUPIL_BK 16
+#endif
+#ifndef RW_IMAGE_BK
+#define RW_IMAGE_BK 8
+#endif
+#ifndef RW_PUPIL_OCC
+#define RW_PUPIL_OCC 2
+#endif
+#ifndef RW_IMAGE_OCC
+#define RW_IMAGE_OCC 2
+#endif
+static_assert(kPadPupil % 64 == 0 && kPadY % 128 == 0 && kPadX % 64 == 0, "tile padding");
+using CfgPupil = CgCfg<64, 128, RW_PUPIL_BK, 64, 32>;
+using CfgImage = CgCfg<64, 128, RW_IMAGE_BK, 64, 32>;
 
 // K2: T[s][z][c] = P~[s][c](z) * Ay^T   ([n x n] * [n x ny])
-__global__ void __launch_bounds__(CfgPupil::NT, 2) gemm_pupil_kernel(Gemm1Args a) {
+__global__ void __launch_bounds__(CfgPupil::NT, RW_PUPIL_OCC) gemm_pupil_kernel(Gemm1Args a) {
   using Cfg = CfgPupil;
   extern __shared__ float lds[];
-  const int tiles_m = (a.n + Cfg::BM - 1) / Cfg::BM;
-  const int tiles_n = (a.ny + Cfg::BN - 1) / Cfg::BN;
+  const int tiles_m = a.np / Cfg::BM;
+  const int tiles_n = a.nyp / Cfg::BN;
   const int nblocks = a.nstk * a.nzs * 3 * tiles_m * tiles_n;
   int id = xcd_remap(blockIdx.x, nblocks);
   const int tn = id % tiles_n; id /= tiles_n;
@@ -168,46 +169,42 @@ __global__ void __launch_bounds__(CfgPupil::NT, 2) gemm_pupil_kernel(Gemm1Args a
   const int s = id;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wrow = (wave / Cfg::WAVES_N) * Cfg::WM, wcol = (wave % Cfg::WAVES_N) * Cfg::WN;
-  const size_t nn = (size_t)a.n * a.n;
+  const size_t npp = (size_t)a.np * a.np;
+  const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
 
   DefocusLoader<Cfg> la;
-  la.P = a.P + ((size_t)s * 3 + c) * nn;
-  la.ksz = a.ksz;
+  la.P = a.P + ((size_t)s * 3 + c) * npp + (size_t)row0 * a.np;
+  la.ksz = a.ksz + (size_t)row0 * a.np;
   la.z = a.z[a.z0 + zi] + a.zoff[s];
-  la.n = a.n;
-  la.row0 = tm * Cfg::BM;
+  la.ld = a.np;
   KMajorLoader<Cfg, Cfg::BN> lb;
-  lb.src = a.AyT;
-  lb.ld = a.ny;
-  lb.K = a.n;
-  lb.ncols = a.ny;
-  lb.c0 = tn * Cfg::BN;
+  lb.src = a.AyT + col0;
+  lb.ld = a.nyp;
 
   CgAcc<Cfg> acc;
   acc.zero();
-  cg_mainloop<Cfg>(acc, la, lb, a.n, lds, tid, wrow, wcol, lane);
+  cg_mainloop<Cfg>(acc, la, lb, a.np, lds, tid, wrow, wcol, lane);
 
-  float2* T = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)a.n * a.ny;
+  float2* T = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)a.np * a.nyp;
 #pragma unroll
   for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
     for (int jj = 0; jj < Cfg::TN; ++jj) {
-      const int col = tn * Cfg::BN + cg_col(wcol, jj, lane);
+      const int col = col0 + cg_col(wcol, jj, lane);
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int row = tm * Cfg::BM + cg_row(wrow, i, r, lane);
-        if (row < a.n && col < a.ny)
-          T[(size_t)row * a.ny + col] = make_float2(acc.re[i][jj][r], acc.im[i][jj][r]);
+        const int row = row0 + cg_row(wrow, i, r, lane);
+        T[(size_t)row * a.nyp + col] = make_float2(acc.re[i][jj][r], acc.im[i][jj][r]);
       }
     }
 }
 
 // K3: E[s][z][c] = Ax T[s][z][c] for c = 0..2 and I = sum_c |E_c|^2
-__global__ void __launch_bounds__(CfgImage::NT, 2) gemm_image_kernel(Gemm2Args a) {
+__global__ void __launch_bounds__(CfgImage::NT, RW_IMAGE_OCC) gemm_image_kernel(Gemm2Args a) {
   using Cfg = CfgImage;
   extern __shared__ float lds[];
-  const int tiles_m = (a.nx + Cfg::BM - 1) / Cfg::BM;
-  const int tiles_n = (a.ny + Cfg::BN - 1) / Cfg::BN;
+  const int tiles_m = a.nxp / Cfg::BM;
+  const int tiles_n = a.nyp / Cfg::BN;
   const int nblocks = a.nstk * a.nzs * tiles_m * tiles_n;
   int id = xcd_remap(blockIdx.x, nblocks);
   const int tn = id % tiles_n; id /= tiles_n;
@@ -218,6 +215,7 @@ __global__ void __launch_bounds__(CfgImage::NT, 2) gemm_image_kernel(Gemm2Args a
   const int wrow = (wave / Cfg::WAVES_N) * Cfg::WM, wcol = (wave % Cfg::WAVES_N) * Cfg::WN;
   const size_t plane = (size_t)a.nx * a.ny;
   const size_t gstk = (size_t)(a.s_base + s), gz = (size_t)(a.z0 + zi);
+  const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
 
   float isum[Cfg::TM][Cfg::TN][16];
 #pragma unroll
@@ -230,30 +228,24 @@ __global__ void __launch_bounds__(CfgImage::NT, 2) gemm_image_kernel(Gemm2Args a
 #pragma unroll 1
   for (int c = 0; c < 3; ++c) {
     KMajorLoader<Cfg, Cfg::BM> la;
-    la.src = a.AxT;
-    la.ld = a.nx;
-    la.K = a.n;
-    la.ncols = a.nx;
-    la.c0 = tm * Cfg::BM;
+    la.src = a.AxT + row0;
+    la.ld = a.nxp;
     KMajorLoader<Cfg, Cfg::BN> lb;
-    lb.src = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)a.n * a.ny;
-    lb.ld = a.ny;
-    lb.K = a.n;
-    lb.ncols = a.ny;
-    lb.c0 = tn * Cfg::BN;
+    lb.src = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)a.np * a.nyp + col0;
+    lb.ld = a.nyp;
     CgAcc<Cfg> acc;
     acc.zero();
-    cg_mainloop<Cfg>(acc, la, lb, a.n, lds, tid, wrow, wcol, lane);
+    cg_mainloop<Cfg>(acc, la, lb, a.np, lds, tid, wrow, wcol, lane);
 
     float2* E = a.E ? a.E + ((gstk * a.nz + gz) * 3 + c) * plane : nullptr;
 #pragma unroll
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
       for (int jj = 0; jj < Cfg::TN; ++jj) {
-        const int col = tn * Cfg::BN + cg_col(wcol, jj, lane);
+        const int col = col0 + cg_col(wcol, jj, lane);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int row = tm * Cfg::BM + cg_row(wrow, i, r, lane);
+          const int row = row0 + cg_row(wrow, i, r, lane);
           const float er = acc.re[i][jj][r], ei = acc.im[i][jj][r];
           isum[i][jj][r] += er * er + ei * ei;
           if (E && row < a.nx && col < a.ny) E[(size_t)row * a.ny + col] = make_float2(er, ei);
@@ -266,10 +258,10 @@ __global__ void __launch_bounds__(CfgImage::NT, 2) gemm_image_kernel(Gemm2Args a
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
       for (int jj = 0; jj < Cfg::TN; ++jj) {
-        const int col = tn * Cfg::BN + cg_col(wcol, jj, lane);
+        const int col = col0 + cg_col(wcol, jj, lane);
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int row = tm * Cfg::BM + cg_row(wrow, i, r, lane);
+          const int row = row0 + cg_row(wrow, i, r, lane);
           if (row < a.nx && col < a.ny) I[(size_t)row * a.ny + col] = isum[i][jj][r];
         }
       }
@@ -288,14 +280,14 @@ hipError_t launch_zernike_table(float* out, int n, int nj, hipStream_t st) {
 
 hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* ztab, float2* P,
                               hipStream_t st) {
-  const int cells = a.n * a.n;
+  const int cells = a.np * a.np;
   hipLaunchKernelGGL(pupil_build_kernel, dim3((cells + 255) / 256), dim3(256), 0, st, a, Q, ztab, P);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
   using Cfg = CfgPupil;
-  const int tiles = ((a.n + Cfg::BM - 1) / Cfg::BM) * ((a.ny + Cfg::BN - 1) / Cfg::BN);
+  const int tiles = (a.np / Cfg::BM) * (a.nyp / Cfg::BN);
   const int nblocks = a.nstk * a.nzs * 3 * tiles;
   hipLaunchKernelGGL(gemm_pupil_kernel, dim3(nblocks), dim3(Cfg::NT), Cfg::LDS_BYTES, st, a);
   return hipGetLastError();
@@ -303,7 +295,7 @@ hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
 
 hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st) {
   using Cfg = CfgImage;
-  const int tiles = ((a.nx + Cfg::BM - 1) / Cfg::BM) * ((a.ny + Cfg::BN - 1) / Cfg::BN);
+  const int tiles = (a.nxp / Cfg::BM) * (a.nyp / Cfg::BN);
   const int nblocks = a.nstk * a.nzs * tiles;
   hipLaunchKernelGGL(gemm_image_kernel, dim3(nblocks), dim3(Cfg::NT), Cfg::LDS_BYTES, st, a);
   return hipGetLastError();

@@ -23,21 +23,21 @@ int bessel_plan_init(rwpsf_plan* p);
 
 static int fourier_plan_init(rwpsf_plan* p) {
   const int N = p->num.n_pupil, nx = p->grid.nx, ny = p->grid.ny;
+  const int np = round_up(N, kPadPupil), nxp = round_up(nx, kPadX), nyp = round_up(ny, kPadY);
+  p->np = np;
+  p->nxp = nxp;
+  p->nyp = nyp;
   const double s_max = p->s_max, k = p->k;
   const std::complex<double> ex(p->opt.ex_re, p->opt.ex_im), ey(p->opt.ey_re, p->opt.ey_im);
-  const size_t nn = (size_t)N * N;
-  std::vector<float2> Q(3 * nn);
-  std::vector<double> ksz(nn);
+  const size_t npp = (size_t)np * np;
+  std::vector<float2> Q(3 * npp, make_float2(0.f, 0.f));
+  std::vector<double> ksz(npp, 0.0);
   const double ds = 2.0 * s_max / N;
   for (int j = 0; j < N; ++j)
     for (int l = 0; l < N; ++l) {
       const long u = 2L * j + 1 - N, v = 2L * l + 1 - N;
-      const size_t cell = (size_t)j * N + l;
-      if (u * u + v * v > (long)N * N) {
-        for (int c = 0; c < 3; ++c) Q[c * nn + cell] = make_float2(0.f, 0.f);
-        ksz[cell] = 0.0;
-        continue;
-      }
+      if (u * u + v * v > (long)N * N) continue;
+      const size_t cell = (size_t)j * np + l;
       const double sx = u * s_max / N, sy = v * s_max / N;
       const double s2 = sx * sx + sy * sy;
       const double sin_t = std::sqrt(s2), cos_t = std::sqrt(1.0 - s2);
@@ -46,17 +46,17 @@ static int fourier_plan_init(rwpsf_plan* p) {
       far_field(ex, ey, cos_t, sin_t, cp, sp, e);
       const double w = ds * ds * amplitude(p->opt, cos_t, sin_t) / cos_t;
       for (int c = 0; c < 3; ++c)
-        Q[c * nn + cell] = make_float2((float)(w * e[c].real()), (float)(w * e[c].imag()));
+        Q[c * npp + cell] = make_float2((float)(w * e[c].real()), (float)(w * e[c].imag()));
       ksz[cell] = k * cos_t;
     }
-  std::vector<float2> AyT((size_t)N * ny), AxT((size_t)N * nx);
+  std::vector<float2> AyT((size_t)np * nyp, make_float2(0.f, 0.f)), AxT((size_t)np * nxp, make_float2(0.f, 0.f));
   const double pref = p->opt.focal_length * k / kTwoPi;  // C = -i pref
   for (int l = 0; l < N; ++l) {
     const double sy = (2.0 * l + 1.0 - N) * s_max / N;
     for (int n = 0; n < ny; ++n) {
       const double y = (double)(n - ny / 2) * p->grid.dy_nm;
       const double ph = k * sy * y;
-      AyT[(size_t)l * ny + n] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+      AyT[(size_t)l * nyp + n] = make_float2((float)std::cos(ph), (float)std::sin(ph));
     }
   }
   for (int j = 0; j < N; ++j) {
@@ -65,23 +65,23 @@ static int fourier_plan_init(rwpsf_plan* p) {
       const double x = (double)(m - nx / 2) * p->grid.dx_nm;
       const double ph = k * sx * x;
       // -i pref (cos + i sin) = pref (sin - i cos)
-      AxT[(size_t)j * nx + m] = make_float2((float)(pref * std::sin(ph)), (float)(-pref * std::cos(ph)));
+      AxT[(size_t)j * nxp + m] = make_float2((float)(pref * std::sin(ph)), (float)(-pref * std::cos(ph)));
     }
   }
   int st;
-  if ((st = dev_alloc(p, &p->d_Q, 3 * nn))) return st;
-  if ((st = dev_alloc(p, &p->d_ksz, nn))) return st;
-  if ((st = dev_alloc(p, &p->d_AyT, (size_t)N * ny))) return st;
-  if ((st = dev_alloc(p, &p->d_AxT, (size_t)N * nx))) return st;
-  if ((st = dev_alloc(p, &p->d_ztab, (size_t)RWPSF_MAX_ZERNIKE * nn))) return st;
+  if ((st = dev_alloc(p, &p->d_Q, 3 * npp))) return st;
+  if ((st = dev_alloc(p, &p->d_ksz, npp))) return st;
+  if ((st = dev_alloc(p, &p->d_AyT, (size_t)np * nyp))) return st;
+  if ((st = dev_alloc(p, &p->d_AxT, (size_t)np * nxp))) return st;
+  if ((st = dev_alloc(p, &p->d_ztab, (size_t)RWPSF_MAX_ZERNIKE * N * N))) return st;
   if ((st = dev_alloc(p, &p->d_z, (size_t)p->grid.nz))) return st;
   p->P_stacks = kPupilStacks;
-  if ((st = dev_alloc(p, &p->d_P, (size_t)p->P_stacks * 3 * nn))) return st;
+  if ((st = dev_alloc(p, &p->d_P, (size_t)p->P_stacks * 3 * npp))) return st;
   // plane workspace: whole chunk of stacks x planes, capped at 512 MiB
-  const size_t plane_bytes = 3 * (size_t)N * ny * sizeof(float2);
+  const size_t plane_bytes = 3 * (size_t)np * nyp * sizeof(float2);
   const size_t want = (size_t)kPupilStacks * p->grid.nz;
   p->T_planes = std::max<size_t>(1, std::min(want, (size_t)(512u << 20) / plane_bytes));
-  if ((st = dev_alloc(p, &p->d_T, p->T_planes * 3 * (size_t)N * ny))) return st;
+  if ((st = dev_alloc(p, &p->d_T, p->T_planes * 3 * (size_t)np * nyp))) return st;
 
   if ((st = hip_check(hipMemcpy(p->d_Q, Q.data(), Q.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
   if ((st = hip_check(hipMemcpy(p->d_ksz, ksz.data(), ksz.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
@@ -128,10 +128,12 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
   hipGetDevice(&cur);
   if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
   const int N = p->num.n_pupil, nz = p->grid.nz;
+  const size_t npp = (size_t)p->np * p->np;
   for (int b0 = 0; b0 < n; b0 += kPupilStacks) {
     const int nb = std::min(kPupilStacks, n - b0);
     PupilArgs pa{};
     pa.n = N;
+    pa.np = p->np;
     pa.nstk = nb;
     pa.gibson_lanni = p->opt.gibson_lanni;
     pa.s_max = p->s_max;
@@ -149,7 +151,9 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
       maxz = std::max(maxz, x.n_zernike);
     }
     pa.max_zernike = maxz;
+    int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
     int rc = hip_check(launch_pupil_build(pa, p->d_Q, p->d_ztab, p->d_P, st));
+    p->time_end(tr, st);
     if (rc) return rc;
     // slabs over (stack, plane): a slab is a run of planes of one or more stacks
     const size_t cap = p->T_planes;
@@ -158,24 +162,28 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
       for (int s0 = 0; s0 < nb; s0 += stk_per) {
         const int ns = std::min(stk_per, nb - s0);
         Gemm1Args g1{};
-        g1.P = p->d_P + (size_t)s0 * 3 * N * N;
+        g1.P = p->d_P + (size_t)s0 * 3 * npp;
         g1.ksz = p->d_ksz;
         g1.z = p->d_z;
         g1.AyT = p->d_AyT;
         g1.T = p->d_T;
         for (int i = 0; i < ns; ++i) g1.zoff[i] = s[b0 + s0 + i].z_offset_nm;
-        g1.n = N;
-        g1.ny = p->grid.ny;
+        g1.np = p->np;
+        g1.nyp = p->nyp;
         g1.nstk = ns;
         g1.z0 = 0;
         g1.nzs = nz;
+        tr = p->time_begin(RWPSF_KERNEL_GEMM_PUPIL, st);
         if ((rc = hip_check(launch_gemm_pupil(g1, st)))) return rc;
+        p->time_end(tr, st);
         Gemm2Args g2{};
         g2.AxT = p->d_AxT;
         g2.T = p->d_T;
         g2.E = E;
         g2.I = I;
-        g2.n = N;
+        g2.np = p->np;
+        g2.nxp = p->nxp;
+        g2.nyp = p->nyp;
         g2.nx = p->grid.nx;
         g2.ny = p->grid.ny;
         g2.nz = nz;
@@ -183,31 +191,37 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
         g2.s_base = b0 + s0;
         g2.z0 = 0;
         g2.nzs = nz;
+        tr = p->time_begin(RWPSF_KERNEL_GEMM_IMAGE, st);
         if ((rc = hip_check(launch_gemm_image(g2, st)))) return rc;
+        p->time_end(tr, st);
       }
     } else {
       for (int i = 0; i < nb; ++i)
         for (int z0 = 0; z0 < nz; z0 += (int)cap) {
           const int nzs = (int)std::min<size_t>(cap, nz - z0);
           Gemm1Args g1{};
-          g1.P = p->d_P + (size_t)i * 3 * N * N;
+          g1.P = p->d_P + (size_t)i * 3 * npp;
           g1.ksz = p->d_ksz;
           g1.z = p->d_z;
           g1.AyT = p->d_AyT;
           g1.T = p->d_T;
           g1.zoff[0] = s[b0 + i].z_offset_nm;
-          g1.n = N;
-          g1.ny = p->grid.ny;
+          g1.np = p->np;
+          g1.nyp = p->nyp;
           g1.nstk = 1;
           g1.z0 = z0;
           g1.nzs = nzs;
-          if ((rc = hip_check(launch_gemm_pupil(g1, st)))) return rc;
+          tr = p->time_begin(RWPSF_KERNEL_GEMM_PUPIL, st);
+        if ((rc = hip_check(launch_gemm_pupil(g1, st)))) return rc;
+        p->time_end(tr, st);
           Gemm2Args g2{};
           g2.AxT = p->d_AxT;
           g2.T = p->d_T;
           g2.E = E;
           g2.I = I;
-          g2.n = N;
+          g2.np = p->np;
+          g2.nxp = p->nxp;
+          g2.nyp = p->nyp;
           g2.nx = p->grid.nx;
           g2.ny = p->grid.ny;
           g2.nz = nz;
@@ -215,7 +229,9 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
           g2.s_base = b0 + i;
           g2.z0 = z0;
           g2.nzs = nzs;
-          if ((rc = hip_check(launch_gemm_image(g2, st)))) return rc;
+          tr = p->time_begin(RWPSF_KERNEL_GEMM_IMAGE, st);
+        if ((rc = hip_check(launch_gemm_image(g2, st)))) return rc;
+        p->time_end(tr, st);
         }
     }
   }

@@ -148,15 +148,16 @@ struct rwpsf_plan {
   size_t device_bytes = 0;
   std::vector<void*> allocations;
 
-  // Fourier form
+  // Fourier form (device operands zero-padded to whole GEMM tiles)
+  int np = 0, nxp = 0, nyp = 0; // padded pupil size and output widths
   double* d_z = nullptr;        // [nz]
-  double* d_ksz = nullptr;      // [N*N] k * s_z (0 outside the disk)
-  float2* d_Q = nullptr;        // [3][N][N] ds^2 a e_inf,c / s_z (0 outside)
-  float2* d_AyT = nullptr;      // [N][ny] exp(i k s_y[l] y_n)
-  float2* d_AxT = nullptr;      // [N][nx] C exp(i k s_x[j] x_m), C = -i f k / 2 pi
+  double* d_ksz = nullptr;      // [np][np] k * s_z (0 outside the disk)
+  float2* d_Q = nullptr;        // [3][np][np] ds^2 a e_inf,c / s_z (0 outside)
+  float2* d_AyT = nullptr;      // [np][nyp] exp(i k s_y[l] y_n)
+  float2* d_AxT = nullptr;      // [np][nxp] C exp(i k s_x[j] x_m), C = -i f k / 2 pi
   float* d_ztab = nullptr;      // [RWPSF_MAX_ZERNIKE][N][N] Noll basis on the pupil cells
-  float2* d_P = nullptr;        // workspace [chunk][3][N][N]
-  float2* d_T = nullptr;        // workspace [planes][3][N][ny]
+  float2* d_P = nullptr;        // workspace [chunk][3][np][np]
+  float2* d_T = nullptr;        // workspace [planes][3][np][nyp]
   size_t T_planes = 0;          // capacity of d_T in stack-planes
   int P_stacks = 0;             // capacity of d_P in stacks
 
@@ -169,6 +170,20 @@ struct rwpsf_plan {
   float2* d_In = nullptr;       // workspace [stacks][3][nz][R]
   int bessel_stacks = 0;        // capacity of the Bessel workspaces
   double drho = 0;              // radial sample pitch
+
+  // per-kernel timing (opt-in)
+  struct TimingRec {
+    int kernel;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<TimingRec> timing_recs;
+  std::vector<hipEvent_t> event_pool;
+  double timing_ms[RWPSF_KERNEL_COUNT] = {};
+  int64_t timing_launches[RWPSF_KERNEL_COUNT] = {};
+  int time_begin(int kernel, hipStream_t st);   // returns a record index or -1
+  void time_end(int rec, hipStream_t st);
+  void timing_flush();
 
   ~rwpsf_plan();
 };

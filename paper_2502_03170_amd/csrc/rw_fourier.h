@@ -14,29 +14,34 @@ struct PupilStack {
 };
 
 struct PupilArgs {
-  int n, nstk, max_zernike, gibson_lanni;
+  int n, np, nstk, max_zernike, gibson_lanni;   // n: pupil cells per axis, np: padded stride
   double s_max, k;
   GLParams gl;
   PupilStack s[kPupilStacks];
 };
 
+// Device operands are zero-padded: np = n rounded up to 64, nxp = nx rounded up
+// to 64, nyp = ny rounded up to 128.
 struct Gemm1Args {
-  const float2* P;     // [nstk][3][n][n]
-  const double* ksz;   // [n][n]
+  const float2* P;     // [nstk][3][np][np]
+  const double* ksz;   // [np][np]
   const double* z;     // plan planes
-  const float2* AyT;   // [n][ny]
-  float2* T;           // [nstk][nzs][3][n][ny]
+  const float2* AyT;   // [np][nyp]
+  float2* T;           // [nstk][nzs][3][np][nyp]
   double zoff[kPupilStacks];
-  int n, ny, nstk, z0, nzs;
+  int np, nyp, nstk, z0, nzs;
 };
 
 struct Gemm2Args {
-  const float2* AxT;   // [n][nx]
-  const float2* T;     // [nstk][nzs][3][n][ny]
+  const float2* AxT;   // [np][nxp]
+  const float2* T;     // [nstk][nzs][3][np][nyp]
   float2* E;           // [stacks][nz][3][nx][ny] or null
   float* I;            // [stacks][nz][nx][ny] or null
-  int n, nx, ny, nz, nstk, s_base, z0, nzs;
+  int np, nxp, nyp, nx, ny, nz, nstk, s_base, z0, nzs;
 };
+
+inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
+constexpr int kPadPupil = 64, kPadX = 64, kPadY = 128;
 
 hipError_t launch_zernike_table(float* out, int n, int nj, hipStream_t st);
 hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* ztab, float2* P,
