@@ -145,6 +145,63 @@ size_t rwpsf_plan_device_bytes(const rwpsf_plan* plan);
 int rwpsf_compute(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
                   void* E_out, float* I_out, void* stream);
 
+/* ---- batched emitters ----------------------------------------------------------
+   Thousands of emitters, each with its own sub-pixel position, axial position,
+   Zernike vector, crop size and plane count, evaluated by the Fourier form in one
+   persistent launch (optionally replayed from a captured hipGraph).  Optics as in
+   rwpsf_optics (the Gibson-Lanni layer is not supported here).  Emitter b gets
+   crop x crop pixels at pitch pixel_nm, pixel (i, j) at ((i - crop/2) p, (j - crop/2) p)
+   relative to the crop centre, and `planes` planes at z_d = (d - (planes-1)/2) *
+   plane_pitch_nm, d = 0..planes-1; its defocus is z_d - z_nm.  Outputs are packed in
+   input order: emitter b starts at voxel offset o_b = sum_{b'<b} planes_b' crop_b'^2
+   (rwpsf_batch_offsets) with layout I[o_b + (d crop + i) crop + j] (float) and
+   E[3 o_b + ((d 3 + c) crop + i) crop + j] (complex64). */
+#define RWPSF_BATCH_MAX_CROP 64
+#define RWPSF_BATCH_MAX_ZERNIKE 21
+
+typedef struct rwpsf_emitter {
+  double x0_nm, y0_nm;     /* lateral position relative to the crop centre, |x0|,|y0| <= 4 pixels */
+  double z_nm;             /* axial position of the emitter */
+  int crop;                /* 1..RWPSF_BATCH_MAX_CROP */
+  int planes;              /* 1..4096 */
+  double zernike_waves[RWPSF_BATCH_MAX_ZERNIKE];   /* Noll 1..21, waves */
+} rwpsf_emitter;
+
+typedef struct rwpsf_batch rwpsf_batch;
+
+/* Tables and workspace for up to max_emitters emitters on the current device.
+   n_pupil: 32..256 and a multiple of 32.  Synchronous. */
+int rwpsf_batch_create(const rwpsf_optics* optics, int n_pupil, double pixel_nm,
+                       double plane_pitch_nm, int max_emitters, rwpsf_batch** out);
+void rwpsf_batch_destroy(rwpsf_batch* batch);
+
+/* Host-only: packed voxel offsets (n+1 values, offsets[n] = total voxels). */
+int rwpsf_batch_offsets(int n, const rwpsf_emitter* emitters, int64_t* offsets);
+
+/* Evaluate n emitters (host array, validated and copied before return).  I_out:
+   device float [total voxels] or NULL; E_out: device complex64 [3 total voxels] or
+   NULL (not both NULL).  With graphs enabled the copy, phase GEMM and persistent
+   kernel are captured once per (n, outputs, configuration, stream) and replayed;
+   graph mode needs a created stream (not NULL).  Before the host staging area is
+   rewritten the call waits for the previous call's upload. */
+int rwpsf_batch_compute(rwpsf_batch* batch, int n, const rwpsf_emitter* emitters, float* I_out,
+                        void* E_out, void* stream);
+int rwpsf_batch_set_graph(rwpsf_batch* batch, int enable);
+
+/* Launch configuration: workgroups per CU of the persistent grid (1..4) and the
+   largest crop evaluated with 32-wide tiles (0 or 32; larger crops use 64). */
+typedef struct rwpsf_batch_config {
+  int wg_per_cu;
+  int small_tile_max_crop;
+} rwpsf_batch_config;
+int rwpsf_batch_set_config(rwpsf_batch* batch, const rwpsf_batch_config* cfg);
+int rwpsf_batch_get_config(const rwpsf_batch* batch, rwpsf_batch_config* cfg);
+
+/* Time each candidate configuration on these emitters (outputs written to I_out)
+   and keep the fastest.  Synchronises the stream.  best_ms may be NULL. */
+int rwpsf_batch_autotune(rwpsf_batch* batch, int n, const rwpsf_emitter* emitters, float* I_out,
+                         void* stream, rwpsf_batch_config* best, double* best_ms);
+
 /* ---- per-kernel timing, for benchmarking -------------------------------------
    When enabled, every kernel the plan launches is bracketed by HIP events on
    the call's stream.  rwpsf_plan_timing waits for the recorded events, folds them

@@ -65,6 +65,19 @@ class Stack(ctypes.Structure):
                 ("phase_map", c_void_p)]
 
 
+BATCH_MAX_CROP = 64
+BATCH_MAX_ZERNIKE = 21
+
+
+class Emitter(ctypes.Structure):
+    _fields_ = [("x0_nm", c_double), ("y0_nm", c_double), ("z_nm", c_double), ("crop", c_int),
+                ("planes", c_int), ("zernike_waves", c_double * BATCH_MAX_ZERNIKE)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("wg_per_cu", c_int), ("small_tile_max_crop", c_int)]
+
+
 _lib = None
 
 
@@ -92,6 +105,15 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "rwpsf_compute": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_void_p]),
         "rwpsf_plan_set_timing": (c_int, [c_void_p, c_int]),
         "rwpsf_plan_timing": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(ctypes.c_int64)]),
+        "rwpsf_batch_create": (c_int, [POINTER(Optics), c_int, c_double, c_double, c_int, POINTER(c_void_p)]),
+        "rwpsf_batch_destroy": (None, [c_void_p]),
+        "rwpsf_batch_offsets": (c_int, [c_int, POINTER(Emitter), POINTER(ctypes.c_int64)]),
+        "rwpsf_batch_compute": (c_int, [c_void_p, c_int, POINTER(Emitter), c_void_p, c_void_p, c_void_p]),
+        "rwpsf_batch_set_graph": (c_int, [c_void_p, c_int]),
+        "rwpsf_batch_set_config": (c_int, [c_void_p, POINTER(BatchConfig)]),
+        "rwpsf_batch_get_config": (c_int, [c_void_p, POINTER(BatchConfig)]),
+        "rwpsf_batch_autotune": (c_int, [c_void_p, c_int, POINTER(Emitter), c_void_p, c_void_p,
+                                         POINTER(BatchConfig), POINTER(c_double)]),
         "rwpsf_gauss_legendre": (c_int, [c_int, c_double, c_double, POINTER(c_double), POINTER(c_double)]),
         "rwpsf_bessel_j": (c_int, [c_int, c_int, POINTER(c_double), POINTER(c_double)]),
         "rwpsf_zernike": (c_int, [c_int, c_int, POINTER(c_double), POINTER(c_double), POINTER(c_double)]),
@@ -227,6 +249,77 @@ def compute(handle, stacks: list[dict], E=None, I=None, stream=None) -> None:
             raise ValueError("outputs must be contiguous CUDA tensors of complex64 (E) / float32 (I)")
     _check(load().rwpsf_compute(handle, len(stacks), arr, c_void_p(E.data_ptr() if E is not None else 0),
                                 c_void_p(I.data_ptr() if I is not None else 0), c_void_p(stream)))
+
+
+def make_emitters(x0, y0, z, crop, planes, zernike):
+    n = len(x0)
+    arr = (Emitter * n)()
+    for i in range(n):
+        arr[i].x0_nm, arr[i].y0_nm, arr[i].z_nm = float(x0[i]), float(y0[i]), float(z[i])
+        arr[i].crop, arr[i].planes = int(crop[i]), int(planes[i])
+        c = zernike[i]
+        for q in range(min(len(c), BATCH_MAX_ZERNIKE)):
+            arr[i].zernike_waves[q] = float(c[q])
+    return arr
+
+
+def batch_offsets(emitters) -> list:
+    n = len(emitters)
+    off = (ctypes.c_int64 * (n + 1))()
+    _check(load().rwpsf_batch_offsets(n, emitters, off))
+    return list(off)
+
+
+class Batch:
+    """Batched emitters (rwpsf_batch_*): one persistent launch for many small stacks."""
+
+    def __init__(self, *, na, wavelength, n_i, pixel, plane_pitch, max_emitters, n_pupil=128,
+                 e_inc=CIRCULAR, focal_length=1.0, apodization=True, s_env=0.0):
+        self.optics = make_optics(na, wavelength, n_i, e_inc, focal_length, apodization, s_env, None)
+        h = c_void_p()
+        _check(load().rwpsf_batch_create(byref(self.optics), n_pupil, pixel, plane_pitch, max_emitters,
+                                         byref(h)))
+        self.handle = h
+
+    def set_graph(self, enable: bool):
+        _check(load().rwpsf_batch_set_graph(self.handle, int(bool(enable))))
+
+    def set_config(self, wg_per_cu: int, small_tile_max_crop: int):
+        cfg = BatchConfig(wg_per_cu, small_tile_max_crop)
+        _check(load().rwpsf_batch_set_config(self.handle, byref(cfg)))
+
+    def get_config(self):
+        cfg = BatchConfig()
+        _check(load().rwpsf_batch_get_config(self.handle, byref(cfg)))
+        return cfg.wg_per_cu, cfg.small_tile_max_crop
+
+    def compute(self, emitters, I=None, E=None, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(load().rwpsf_batch_compute(self.handle, len(emitters), emitters,
+                                          c_void_p(I.data_ptr() if I is not None else 0),
+                                          c_void_p(E.data_ptr() if E is not None else 0), c_void_p(stream)))
+
+    def autotune(self, emitters, I, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        cfg, ms = BatchConfig(), c_double()
+        _check(load().rwpsf_batch_autotune(self.handle, len(emitters), emitters, c_void_p(I.data_ptr()),
+                                           c_void_p(stream), byref(cfg), byref(ms)))
+        return (cfg.wg_per_cu, cfg.small_tile_max_crop), ms.value
+
+    def close(self):
+        if self.handle:
+            load().rwpsf_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Plan:

@@ -99,8 +99,8 @@ constexpr int RSTAGE = RBK * RLDA + RBK * RLDB;
 
 __global__ void __launch_bounds__(256) bessel_contract_kernel(const float* __restrict__ A, int lda,
                                                                const float* __restrict__ B, int ldb,
-                                                               float* __restrict__ C, int M, int N,
-                                                               int K) {
+                                                               float* __restrict__ C, int ldc, int M,
+                                                               int N, int K) {
   __shared__ float lds[2 * RSTAGE];
   const int tiles_n = (N + RBN - 1) / RBN;
   const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
@@ -163,9 +163,19 @@ __global__ void __launch_bounds__(256) bessel_contract_kernel(const float* __res
     const int col = col0 + wcol + 32 * j + l32;
     for (int r = 0; r < 16; ++r) {
       const int row = row0 + wrow + (r >> 2) * 8 + h * 4 + (r & 3);
-      if (row < M && col < N) C[(size_t)row * N + col] = acc[j][r];
+      if (row < M && col < N) C[(size_t)row * ldc + col] = acc[j][r];
     }
   }
+}
+
+// C[M x N] (row stride ldc) = A^T B with A [K][lda], B [K][ldb]; also the batched
+// per-emitter phase GEMM.
+hipError_t launch_rgemm(const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M,
+                        int N, int K, hipStream_t st) {
+  const int blocks = ((M + RBM - 1) / RBM) * ((N + RBN - 1) / RBN);
+  hipLaunchKernelGGL(bessel_contract_kernel, dim3(blocks), dim3(256), 0, st, A, lda, B, ldb, C, ldc, M,
+                     N, K);
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------
@@ -362,7 +372,7 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
     const int blocks = ((M + RBM - 1) / RBM) * ((N + RBN - 1) / RBN);
     tr = p->time_begin(RWPSF_KERNEL_BESSEL_CONTRACT, st);
     hipLaunchKernelGGL(bessel_contract_kernel, dim3(blocks), dim3(256), 0, st, (const float*)p->d_phi,
-                       M, (const float*)p->d_btab, N, (float*)p->d_In, M, N, T);
+                       M, (const float*)p->d_btab, N, (float*)p->d_In, N, M, N, T);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
     EpiArgs ea{};

@@ -7,6 +7,9 @@
 
 namespace rw {
 
+int validate_plan(const rwpsf_optics* o, const rwpsf_grid* g, const rwpsf_numerics* nm);
+int validate_stacks(const rwpsf_optics* o, const rwpsf_grid* g, const rwpsf_numerics* nm, int n,
+                    const rwpsf_stack* s);
 int plan_init(rwpsf_plan* p, const rwpsf_optics& o, const rwpsf_grid& g, const rwpsf_numerics& nm);
 int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);
 int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);

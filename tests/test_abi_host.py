@@ -20,7 +20,8 @@ def declared_symbols():
     for f in os.listdir(inc):
         if f.endswith(".h"):
             text = open(os.path.join(inc, f)).read()
-            names |= set(re.findall(r"\b(rwpsf_[a-z_0-9]+)\s*\(", text))
+            names |= set(re.findall(r"^(?:int|void|size_t|const char\*|int64_t)\s+\*?(rwpsf_\w+)\s*\(",
+                                    text, flags=re.M))
     return sorted(names)
 
 
@@ -119,3 +120,8 @@ def test_plan_create_without_device_reports_no_device_or_works():
     with pytest.raises(rw.RwpsfError) as ei:
         rw.plan_create(o, g, nm)
     assert ei.value.status in (rw.ERR_NO_DEVICE, rw.ERR_HIP)
+
+
+def test_batch_offsets_are_packed_in_input_order():
+    em = rw.make_emitters([0.0] * 3, [0.0] * 3, [0.0] * 3, [24, 64, 1], [3, 1, 7], [[0.0]] * 3)
+    assert rw.batch_offsets(em) == [0, 3 * 24 * 24, 3 * 24 * 24 + 64 * 64, 3 * 24 * 24 + 64 * 64 + 7]
