@@ -145,6 +145,22 @@ size_t rwpsf_plan_device_bytes(const rwpsf_plan* plan);
 int rwpsf_compute(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
                   void* E_out, float* I_out, void* stream);
 
+/* Adjoint of the Fourier form (the paper differentiates through PyTorch autograd,
+   Sec. 4.1; this is the hand-written transposed chain).  Given the fields E_in
+   (device complex64 [n_stacks][nz][3][nx][ny], as written by rwpsf_compute for the
+   same plan and stacks) and dL_dI (device float [n_stacks][nz][nx][ny]) of a real
+   loss L(I), writes the gradient with respect to a phase perturbation shared by
+   all stacks:
+     dL_dc  : device float [n_zernike], dL/dc_q for Noll q = 1..n_zernike (waves)
+              (may be NULL when n_zernike = 0);
+     dL_dW0 : device float [n_pupil][n_pupil], dL/dW0 on the pupil cells (radians),
+              0 outside the disk; may be NULL.
+   Outputs are overwritten, never accumulated.  Fourier form with nx, ny multiples
+   of 16 (RWPSF_ERR_UNSUPPORTED otherwise).  Every reduction runs in a fixed order,
+   so repeated calls give bitwise-identical results. */
+int rwpsf_adjoint(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, const void* E_in,
+                  const float* dL_dI, int n_zernike, float* dL_dc, float* dL_dW0, void* stream);
+
 /* ---- batched emitters ----------------------------------------------------------
    Thousands of emitters, each with its own sub-pixel position, axial position,
    Zernike vector, crop size and plane count, evaluated by the Fourier form in one
@@ -214,6 +230,9 @@ enum rwpsf_kernel_id {
   RWPSF_KERNEL_BESSEL_PHI = 3,        /* Bessel: pupil x defocus on the theta nodes */
   RWPSF_KERNEL_BESSEL_CONTRACT = 4,   /* Bessel: theta contraction on the matrix cores */
   RWPSF_KERNEL_BESSEL_EPILOGUE = 5,   /* Bessel: radial interpolation, fields and |E|^2 */
+  RWPSF_KERNEL_ADJ_H = 6,             /* adjoint: (2 dL/dI E) conj(Ay) */
+  RWPSF_KERNEL_ADJ_G = 7,             /* adjoint: Ax'^H H with Im(G conj(P~)) accumulation */
+  RWPSF_KERNEL_ADJ_REDUCE = 8,        /* adjoint: fixed-order reductions to dL/dW0, dL/dc */
   RWPSF_KERNEL_COUNT = 16
 };
 int rwpsf_plan_set_timing(rwpsf_plan* plan, int enable);   /* also resets the totals */

@@ -31,6 +31,9 @@ KERNEL_GEMM_IMAGE = 2
 KERNEL_BESSEL_PHI = 3
 KERNEL_BESSEL_CONTRACT = 4
 KERNEL_BESSEL_EPILOGUE = 5
+KERNEL_ADJ_H = 6
+KERNEL_ADJ_G = 7
+KERNEL_ADJ_REDUCE = 8
 MAX_ZERNIKE = 36
 CIRCULAR = (1 / math.sqrt(2), 1j / math.sqrt(2))
 
@@ -105,6 +108,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "rwpsf_compute": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_void_p]),
         "rwpsf_plan_set_timing": (c_int, [c_void_p, c_int]),
         "rwpsf_plan_timing": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(ctypes.c_int64)]),
+        "rwpsf_adjoint": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_int, c_void_p,
+                                  c_void_p, c_void_p]),
         "rwpsf_batch_create": (c_int, [POINTER(Optics), c_int, c_double, c_double, c_int, POINTER(c_void_p)]),
         "rwpsf_batch_destroy": (None, [c_void_p]),
         "rwpsf_batch_offsets": (c_int, [c_int, POINTER(Emitter), POINTER(ctypes.c_int64)]),
@@ -251,6 +256,61 @@ def compute(handle, stacks: list[dict], E=None, I=None, stream=None) -> None:
                                 c_void_p(I.data_ptr() if I is not None else 0), c_void_p(stream)))
 
 
+def adjoint(handle, stacks: list[dict], E, dL_dI, n_zernike: int, dL_dc=None, dL_dW0=None, stream=None):
+    """Enqueue rwpsf_adjoint (E complex64, dL_dI float32, outputs float32; CUDA tensors)."""
+    import torch
+    arr, _keep = make_stacks(stacks)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    for t in (E, dL_dI, dL_dc, dL_dW0):
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("adjoint tensors must be contiguous CUDA tensors")
+    _check(load().rwpsf_adjoint(handle, len(stacks), arr, c_void_p(E.data_ptr()), c_void_p(dL_dI.data_ptr()),
+                                n_zernike, c_void_p(dL_dc.data_ptr() if dL_dc is not None else 0),
+                                c_void_p(dL_dW0.data_ptr() if dL_dW0 is not None else 0), c_void_p(stream)))
+
+
+def _psf_function():
+    import torch
+
+    class PSFFunction(torch.autograd.Function):
+        """I = PSF(c, W0): intensity stacks of a Fourier plan as a differentiable function of
+        Zernike coefficients c (CPU float64, Noll 1..K, waves) and a pupil phase map W0
+        (CUDA float32 [N][N], radians) shared by all stacks.  The backward is rwpsf_adjoint."""
+
+        @staticmethod
+        def forward(ctx, c, w0, plan, stacks):
+            st = [dict(s, zernike=c.detach().cpu().double().numpy(), phase_map=w0.detach().contiguous())
+                  for s in stacks]
+            E, I = plan.compute(st)
+            ctx.save_for_backward(E)
+            ctx.plan, ctx.stacks, ctx.nz = plan, st, c.numel()
+            ctx.c_device, ctx.c_dtype = c.device, c.dtype
+            return I
+
+        @staticmethod
+        def backward(ctx, grad_I):
+            (E,) = ctx.saved_tensors
+            n = ctx.nz
+            dc = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+            dw = torch.empty_like(ctx.stacks[0]["phase_map"])
+            adjoint(ctx.plan.handle, ctx.stacks, E, grad_I.contiguous().float(), n, dc, dw)
+            return dc[:n].to(ctx.c_device, ctx.c_dtype), dw, None, None
+
+    return PSFFunction
+
+
+_PSF = None
+
+
+def psf_function():
+    """The torch.autograd.Function class (created on first use, torch imported lazily)."""
+    global _PSF
+    if _PSF is None:
+        _PSF = _psf_function()
+    return _PSF
+
+
 def make_emitters(x0, y0, z, crop, planes, zernike):
     n = len(x0)
     arr = (Emitter * n)()
@@ -355,6 +415,14 @@ class Plan:
             I = torch.empty((b, self.nz, self.nx, self.ny), dtype=torch.float32, device="cuda")
         compute(self.handle, stacks, E if fields else None, I if intensity else None, stream)
         return E, I
+
+    def adjoint(self, stacks: list[dict], E, dL_dI, n_zernike: int, stream=None):
+        """(dL/dc [n_zernike], dL/dW0 [N][N]) for a loss with per-voxel dL/dI."""
+        import torch
+        dc = torch.empty(max(n_zernike, 1), dtype=torch.float32, device="cuda")
+        dw = torch.empty((self.num.n_pupil, self.num.n_pupil), dtype=torch.float32, device="cuda")
+        adjoint(self.handle, stacks, E, dL_dI, n_zernike, dc, dw, stream)
+        return dc[:n_zernike], dw
 
     def close(self):
         if self.handle:

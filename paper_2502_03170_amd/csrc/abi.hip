@@ -284,4 +284,17 @@ int rwpsf_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, void* E, float* I,
   return rw::bessel_compute(p, n, s, (float2*)E, I, (hipStream_t)stream);
 }
 
+int rwpsf_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const void* E, const float* dLdI,
+                  int n_zernike, float* dc, float* dW0, void* stream) {
+  if (!p || !E || !dLdI) return RWPSF_ERR_INVALID_ARG;
+  if (n_zernike < 0 || n_zernike > RWPSF_MAX_ZERNIKE || (n_zernike > 0 && !dc)) return RWPSF_ERR_INVALID_ARG;
+  if (p->num.form != RWPSF_FORM_FOURIER) return RWPSF_ERR_UNSUPPORTED;
+  int st = rw::validate_stacks(&p->opt, &p->grid, &p->num, n, s);
+  if (st != RWPSF_OK) return st;
+  int cur = -1;
+  hipGetDevice(&cur);
+  if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
+  return rw::fourier_adjoint(p, n, s, (const float2*)E, dLdI, n_zernike, dc, dW0, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -119,6 +119,34 @@ int plan_init(rwpsf_plan* p, const rwpsf_optics& o, const rwpsf_grid& g, const r
   return bessel_plan_init(p);
 }
 
+// Base pupils P_{b,c} of up to 8 stacks into the plan's pupil workspace.
+int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st) {
+  PupilArgs pa{};
+  pa.n = p->num.n_pupil;
+  pa.np = p->np;
+  pa.nstk = nb;
+  pa.gibson_lanni = p->opt.gibson_lanni;
+  pa.s_max = p->s_max;
+  pa.k = p->k;
+  pa.gl = p->gl;
+  int maxz = 0;
+  for (int i = 0; i < nb; ++i) {
+    const rwpsf_stack& x = s[i];
+    PupilStack& d = pa.s[i];
+    d.t_s = x.t_s_nm;
+    d.x0 = x.x0_nm;
+    d.y0 = x.y0_nm;
+    for (int q = 0; q < RWPSF_MAX_ZERNIKE; ++q) d.coef[q] = q < x.n_zernike ? x.zernike_waves[q] : 0.0;
+    d.w0 = x.phase_map;
+    maxz = std::max(maxz, x.n_zernike);
+  }
+  pa.max_zernike = maxz;
+  const int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
+  const int rc = hip_check(launch_pupil_build(pa, p->d_Q, p->d_ztab, p->d_P, st));
+  p->time_end(tr, st);
+  return rc;
+}
+
 // --------------------------------------------------------------------------
 // Fourier dispatch: chunks of up to 8 stacks (pupil build), then slabs of
 // stack-planes through the two GEMM kernels.
@@ -131,30 +159,9 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
   const size_t npp = (size_t)p->np * p->np;
   for (int b0 = 0; b0 < n; b0 += kPupilStacks) {
     const int nb = std::min(kPupilStacks, n - b0);
-    PupilArgs pa{};
-    pa.n = N;
-    pa.np = p->np;
-    pa.nstk = nb;
-    pa.gibson_lanni = p->opt.gibson_lanni;
-    pa.s_max = p->s_max;
-    pa.k = p->k;
-    pa.gl = p->gl;
-    int maxz = 0;
-    for (int i = 0; i < nb; ++i) {
-      const rwpsf_stack& x = s[b0 + i];
-      PupilStack& d = pa.s[i];
-      d.t_s = x.t_s_nm;
-      d.x0 = x.x0_nm;
-      d.y0 = x.y0_nm;
-      for (int q = 0; q < RWPSF_MAX_ZERNIKE; ++q) d.coef[q] = q < x.n_zernike ? x.zernike_waves[q] : 0.0;
-      d.w0 = x.phase_map;
-      maxz = std::max(maxz, x.n_zernike);
-    }
-    pa.max_zernike = maxz;
-    int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
-    int rc = hip_check(launch_pupil_build(pa, p->d_Q, p->d_ztab, p->d_P, st));
-    p->time_end(tr, st);
+    int rc = fourier_build_pupils(p, s + b0, nb, st);
     if (rc) return rc;
+    int tr = -1;
     // slabs over (stack, plane): a slab is a run of planes of one or more stacks
     const size_t cap = p->T_planes;
     if ((size_t)nz <= cap) {
