@@ -218,6 +218,41 @@ int rwpsf_batch_get_config(const rwpsf_batch* batch, rwpsf_batch_config* cfg);
 int rwpsf_batch_autotune(rwpsf_batch* batch, int n, const rwpsf_emitter* emitters, float* I_out,
                          void* stream, rwpsf_batch_config* best, double* best_ms);
 
+/* ---- learned surrogate ----------------------------------------------------------
+   A network (~2.4M parameters) from 21 Noll coefficients (waves) and a defocus z (nm)
+   to a 64 x 64 intensity crop, trained on crops this engine generates (the paper
+   motivates PSF models as generators of training data for networks, Sec. 6):
+     x = (c / 0.05, z / 1000); three dense layers 22 -> 256 -> 1024 -> 2048 with relu;
+     2048 read as 32 x 8 x 8; three stride-2 transposed convolutions (4 x 4 kernel,
+     padding 1) 32 -> 16 -> 8 -> 1 channels, relu after the first two.
+   Parameters are one flat FP32 array in the order W1 [22][256], b1, W2 [256][1024], b2,
+   W3 [1024][2048], b3, K1 [32][16][4][4], c1, K2 [16][8][4][4], c2, K3 [8][1][4][4], c3
+   (rwpsf_sg_param_count values).  Dense layers run on the BF16 matrix cores; with
+   RWPSF_SG_BF16X3 each operand is split into two BF16 parts (FP32-level accuracy),
+   with RWPSF_SG_BF16 only the leading parts are multiplied.  All device arrays are
+   caller-owned except the parameters, gradients and Adam moments, which the handle
+   owns.  Gradient reductions run in a fixed order. */
+enum rwpsf_sg_precision { RWPSF_SG_BF16X3 = 0, RWPSF_SG_BF16 = 1 };
+typedef struct rwpsf_sg rwpsf_sg;
+size_t rwpsf_sg_param_count(void);
+/* Workspace for batches up to max_batch; parameters and moments start at zero. */
+int rwpsf_sg_create(int max_batch, rwpsf_sg** out);
+void rwpsf_sg_destroy(rwpsf_sg* sg);
+/* Host arrays of rwpsf_sg_param_count floats; m, v may be NULL (left unchanged / not read). */
+int rwpsf_sg_set_state(rwpsf_sg* sg, const float* params, const float* adam_m, const float* adam_v,
+                       int64_t step);
+int rwpsf_sg_get_state(const rwpsf_sg* sg, float* params, float* adam_m, float* adam_v, float* grads,
+                       int64_t* step);
+/* out = net(coef, z): coef device float [B][21], z device float [B], out device float [B][64][64]. */
+int rwpsf_sg_forward(rwpsf_sg* sg, int B, const float* coef, const float* z, float* out, int precision,
+                     void* stream);
+/* Gradient of the mean squared error to target (device float [B][64][64]) into the handle's
+   gradient buffer (accurate precision); loss: device float [1] or NULL. */
+int rwpsf_sg_gradient(rwpsf_sg* sg, int B, const float* coef, const float* z, const float* target,
+                      float* loss, void* stream);
+/* One Adam step (Kingma & Ba, bias-corrected) on the FP32 parameters with the stored gradient. */
+int rwpsf_sg_adam(rwpsf_sg* sg, float lr, float beta1, float beta2, float eps, void* stream);
+
 /* ---- per-kernel timing, for benchmarking -------------------------------------
    When enabled, every kernel the plan launches is bracketed by HIP events on
    the call's stream.  rwpsf_plan_timing waits for the recorded events, folds them

@@ -110,6 +110,16 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "rwpsf_plan_timing": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(ctypes.c_int64)]),
         "rwpsf_adjoint": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_int, c_void_p,
                                   c_void_p, c_void_p]),
+        "rwpsf_sg_param_count": (c_size_t, []),
+        "rwpsf_sg_create": (c_int, [c_int, POINTER(c_void_p)]),
+        "rwpsf_sg_destroy": (None, [c_void_p]),
+        "rwpsf_sg_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_int64]),
+        "rwpsf_sg_get_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                                       POINTER(ctypes.c_int64)]),
+        "rwpsf_sg_forward": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_int, c_void_p]),
+        "rwpsf_sg_gradient": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+        "rwpsf_sg_adam": (c_int, [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  c_void_p]),
         "rwpsf_batch_create": (c_int, [POINTER(Optics), c_int, c_double, c_double, c_int, POINTER(c_void_p)]),
         "rwpsf_batch_destroy": (None, [c_void_p]),
         "rwpsf_batch_offsets": (c_int, [c_int, POINTER(Emitter), POINTER(ctypes.c_int64)]),
@@ -373,6 +383,70 @@ class Batch:
     def close(self):
         if self.handle:
             load().rwpsf_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+SG_BF16X3 = 0
+SG_BF16 = 1
+
+
+class Surrogate:
+    """The learned surrogate (rwpsf_sg_*): parameters and Adam state live on the device."""
+
+    def __init__(self, max_batch: int):
+        h = c_void_p()
+        _check(load().rwpsf_sg_create(max_batch, byref(h)))
+        self.handle = h
+        self.max_batch = max_batch
+        self.n_params = load().rwpsf_sg_param_count()
+
+    def set_state(self, params, m=None, v=None, step: int = 0):
+        import numpy as np
+        arrs = [None if a is None else np.ascontiguousarray(a, dtype=np.float32) for a in (params, m, v)]
+        ptr = [c_void_p(a.ctypes.data) if a is not None else c_void_p(0) for a in arrs]
+        _check(load().rwpsf_sg_set_state(self.handle, *ptr, step))
+
+    def get_state(self):
+        import numpy as np
+        w, m, v, g = (np.empty(self.n_params, dtype=np.float32) for _ in range(4))
+        step = ctypes.c_int64()
+        _check(load().rwpsf_sg_get_state(self.handle, c_void_p(w.ctypes.data), c_void_p(m.ctypes.data),
+                                         c_void_p(v.ctypes.data), c_void_p(g.ctypes.data), byref(step)))
+        return dict(params=w, adam_m=m, adam_v=v, grads=g, step=step.value)
+
+    def forward(self, coef, z, out=None, precision=SG_BF16X3, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty((coef.shape[0], 64, 64), dtype=torch.float32, device="cuda")
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(load().rwpsf_sg_forward(self.handle, coef.shape[0], c_void_p(coef.data_ptr()), c_void_p(z.data_ptr()),
+                                       c_void_p(out.data_ptr()), precision, c_void_p(stream)))
+        return out
+
+    def gradient(self, coef, z, target, loss=None, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(load().rwpsf_sg_gradient(self.handle, coef.shape[0], c_void_p(coef.data_ptr()),
+                                        c_void_p(z.data_ptr()), c_void_p(target.data_ptr()),
+                                        c_void_p(loss.data_ptr() if loss is not None else 0), c_void_p(stream)))
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        _check(load().rwpsf_sg_adam(self.handle, lr, beta1, beta2, eps, c_void_p(stream)))
+
+    def close(self):
+        if self.handle:
+            load().rwpsf_sg_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

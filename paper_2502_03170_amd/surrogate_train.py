@@ -1,0 +1,134 @@
+"""Training, judging and serving of the learned surrogate (orchestration of librwpsf calls).
+
+* ``CropEngine``  -- 64 x 64 intensity crops (100 nm pixels, 128 x 128 pupil, NA 1.4,
+  600 nm, circular polarisation) from the batched-emitter path, normalised by the
+  peak of the unaberrated in-focus PSF; this is both the training-data generator
+  and the judge / fallback of the surrogate.
+* ``train``       -- Adam on mini-batches drawn with a seeded device generator; every
+  forward/backward/update is a librwpsf kernel.
+* ``judge``       -- rel-L2 of the surrogate against the plain path, per crop.
+* ``predict``     -- surrogate for in-distribution inputs, plain path for the rest
+  (any |c_q| > 4 x 0.05 waves or |z| > 1 um).
+* ``save`` / ``load`` -- checkpoint with parameters, Adam moments and step.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+import paper_2502_03170_amd as rw
+
+CROP = 64
+SIGMA_C = 0.05
+Z_MAX = 1000.0
+OOD_SIGMAS = 4.0
+
+
+class CropEngine:
+    def __init__(self, max_emitters: int = 4096, n_pupil: int = 128, pixel: float = 100.0):
+        import torch
+        self.batch = rw.Batch(na=1.4, wavelength=600.0, n_i=1.518, pixel=pixel, plane_pitch=0.0,
+                              max_emitters=max_emitters, n_pupil=n_pupil)
+        self.max = max_emitters
+        z0 = torch.zeros(1, device="cuda")
+        c0 = torch.zeros(1, 21, device="cuda")
+        self.norm = 1.0
+        self.norm = float(self.crops(c0, z0).max().item())
+
+    def crops(self, coef, z):
+        """coef [B][21], z [B] (any device) -> [B][64][64] float32 on the GPU."""
+        import torch
+        c = coef.detach().double().cpu().numpy()
+        zz = z.detach().double().cpu().numpy()
+        B = c.shape[0]
+        out = torch.empty((B, CROP, CROP), dtype=torch.float32, device="cuda")
+        for a in range(0, B, self.max):
+            b = min(B, a + self.max)
+            n = b - a
+            em = rw.make_emitters(np.zeros(n), np.zeros(n), -zz[a:b], [CROP] * n, [1] * n, c[a:b])
+            self.batch.compute(em, I=out[a:b].view(-1))
+        return out / self.norm
+
+
+def make_dataset(eng: CropEngine, n: int, seed: int):
+    import torch
+    import workloads as W
+    w = W.surrogate(n, seed, sigma=SIGMA_C, z_half=Z_MAX)
+    coef = torch.tensor(w["zernike"], dtype=torch.float32, device="cuda").contiguous()
+    z = torch.tensor(w["z"], dtype=torch.float32, device="cuda").contiguous()
+    return dict(coef=coef, z=z, target=eng.crops(coef, z).contiguous())
+
+
+def init_params(seed: int) -> np.ndarray:
+    """He-normal weights, zero biases, flat in the library's parameter order."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for a, b in ((22, 256), (256, 1024), (1024, 2048)):
+        parts += [rng.normal(0, math.sqrt(2.0 / a), a * b), np.zeros(b)]
+    for a, b in ((32, 16), (16, 8), (8, 1)):
+        parts += [rng.normal(0, math.sqrt(2.0 / (a * 4)), a * b * 16), np.zeros(b)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def train(sg: rw.Surrogate, data: dict, steps: int, batch: int, lr: float, seed: int, log_every: int = 50):
+    import torch
+    n = data["coef"].shape[0]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hist = []
+    for step in range(steps):
+        idx = torch.randint(0, n, (batch,), device="cuda", generator=gen)
+        sg.gradient(data["coef"][idx].contiguous(), data["z"][idx].contiguous(),
+                    data["target"][idx].contiguous(), loss=loss)
+        sg.adam(lr)
+        if step % log_every == 0 or step == steps - 1:
+            hist.append(float(loss.item()))
+    return hist
+
+
+def rel_l2_per_crop(pred, ref):
+    d = (pred - ref).flatten(1).norm(dim=1)
+    return d / ref.flatten(1).norm(dim=1)
+
+
+def judge(sg: rw.Surrogate, eng: CropEngine, data: dict, precision: int = rw.SG_BF16X3):
+    import torch
+    B = data["coef"].shape[0]
+    pred = torch.empty_like(data["target"])
+    for a in range(0, B, sg.max_batch):
+        b = min(B, a + sg.max_batch)
+        sg.forward(data["coef"][a:b], data["z"][a:b], out=pred[a:b], precision=precision)
+    e = rel_l2_per_crop(pred, data["target"]).cpu().numpy()
+    return dict(median_rel_l2=float(np.median(e)), p95_rel_l2=float(np.percentile(e, 95)),
+                max_rel_l2=float(e.max()), n=int(B))
+
+
+def out_of_distribution(coef, z):
+    return (coef.abs() > OOD_SIGMAS * SIGMA_C).any(dim=1) | (z.abs() > Z_MAX)
+
+
+def predict(sg: rw.Surrogate, eng: CropEngine, coef, z, precision: int = rw.SG_BF16X3):
+    """Surrogate crops, with the plain path for out-of-distribution inputs."""
+    import torch
+    ood = out_of_distribution(coef, z)
+    out = torch.empty((coef.shape[0], CROP, CROP), dtype=torch.float32, device="cuda")
+    ok = (~ood).nonzero().flatten()
+    bad = ood.nonzero().flatten()
+    for a in range(0, ok.numel(), sg.max_batch):
+        sel = ok[a:a + sg.max_batch]
+        out[sel] = sg.forward(coef[sel].contiguous(), z[sel].contiguous(), precision=precision)
+    if bad.numel():
+        out[bad] = eng.crops(coef[bad], z[bad])
+    return out, ood
+
+
+def save(sg: rw.Surrogate, path: str):
+    st = sg.get_state()
+    np.savez(path, params=st["params"], adam_m=st["adam_m"], adam_v=st["adam_v"], step=st["step"])
+
+
+def load(sg: rw.Surrogate, path: str):
+    d = np.load(path)
+    sg.set_state(d["params"], d["adam_m"], d["adam_v"], int(d["step"]))

@@ -1,0 +1,130 @@
+"""Surrogate kernels against the FP64 network oracle (same weights), and a short training run
+on crops the engine generates, judged by the plain path."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import surrogate as OS
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _flat(p):
+    return np.concatenate([p[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3", "K1", "c1", "K2", "c2", "K3", "c3")])
+
+
+def _unflat(w, like):
+    out, o = {}, 0
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3", "K1", "c1", "K2", "c2", "K3", "c3"):
+        n = like[k].size
+        out[k] = w[o:o + n].reshape(like[k].shape).astype(np.float64)
+        o += n
+    return out
+
+
+def _random_params(seed):
+    p = OS.init_params(seed)
+    rng = np.random.default_rng(seed + 1)
+    for k in p:
+        if k[0] in "bc":
+            p[k] = rng.normal(0, 0.05, p[k].shape)
+    # round to FP32: the device holds FP32 parameters
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
+def _inputs(torch, B, seed):
+    w = W.surrogate(B, seed)
+    coef = torch.tensor(w["zernike"], dtype=torch.float32, device="cuda").contiguous()
+    z = torch.tensor(w["z"], dtype=torch.float32, device="cuda").contiguous()
+    x = OS.features(coef.cpu().numpy().astype(np.float64), z.cpu().numpy().astype(np.float64))
+    return coef, z, x
+
+
+def test_surrogate_forward_matches_fp64_network(lib):
+    import torch
+    rw = lib
+    p = _random_params(11)
+    sg = rw.Surrogate(max_batch=64)
+    assert sg.n_params == _flat(p).size
+    sg.set_state(_flat(p))
+    coef, z, x = _inputs(torch, 37, 12)
+    ref, _ = OS.forward(p, x)
+    y3 = sg.forward(coef, z, precision=rw.SG_BF16X3)
+    y1 = sg.forward(coef, z, precision=rw.SG_BF16)
+    torch.cuda.synchronize()
+    e3 = rel_l2(y3.cpu().numpy(), ref)
+    e1 = rel_l2(y1.cpu().numpy(), ref)
+    assert e3 < 1e-5, e3
+    assert e1 < 1e-2, e1   # BF16 operands in the dense layers: ~2^-8 per rounding
+
+
+def test_surrogate_gradient_and_adam_match_fp64(lib):
+    import torch
+    rw = lib
+    p = _random_params(21)
+    sg = rw.Surrogate(max_batch=64)
+    sg.set_state(_flat(p))
+    coef, z, x = _inputs(torch, 40, 22)
+    target = np.random.default_rng(23).normal(0, 0.3, (40, 64, 64)).astype(np.float32)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    sg.gradient(coef, z, torch.tensor(target, device="cuda"), loss=loss)
+    torch.cuda.synchronize()
+    ref_loss, ref_g = OS.loss_and_grads(p, x, target.astype(np.float64))
+    st = sg.get_state()
+    g = _unflat(st["grads"], p)
+    assert abs(loss.item() - ref_loss) < 1e-5 * ref_loss
+    for k in p:
+        assert rel_l2(g[k], ref_g[k]) < 1e-4, (k, rel_l2(g[k], ref_g[k]))
+    # one Adam step on the device vs the FP64 update from the same gradient
+    sg.adam(1e-3)
+    torch.cuda.synchronize()
+    st2 = sg.get_state()
+    pp = {k: v.copy() for k, v in p.items()}
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(v) for k, v in p.items()}
+    OS.adam_step(pp, g, m, v, 1, 1e-3)
+    w2 = _unflat(st2["params"], p)
+    for k in p:
+        np.testing.assert_allclose(w2[k], pp[k], rtol=0, atol=2e-6 * max(1.0, np.abs(pp[k]).max()))
+    assert st2["step"] == 1
+
+
+def test_surrogate_gradient_is_deterministic(lib):
+    import torch
+    rw = lib
+    sg = rw.Surrogate(max_batch=64)
+    sg.set_state(_flat(_random_params(31)))
+    coef, z, _ = _inputs(torch, 48, 32)
+    t = torch.randn(48, 64, 64, device="cuda")
+    sg.gradient(coef, z, t)
+    g1 = sg.get_state()["grads"]
+    sg.gradient(coef, z, t)
+    g2 = sg.get_state()["grads"]
+    np.testing.assert_array_equal(g1, g2)
+
+
+def test_surrogate_training_reduces_error_and_judge(lib):
+    """Train briefly on engine-generated crops; the loss falls and the judge/fallback work."""
+    import torch
+    from paper_2502_03170_amd import surrogate_train as ST
+    rw = lib
+    eng = ST.CropEngine(max_emitters=4096)
+    train = ST.make_dataset(eng, 8192, seed=505)
+    test = ST.make_dataset(eng, 512, seed=506)
+    sg = rw.Surrogate(max_batch=256)
+    sg.set_state(ST.init_params(0))
+    hist = ST.train(sg, train, steps=600, batch=256, lr=1e-3, seed=0)
+    assert hist[-1] < 0.5 * hist[0], (hist[0], hist[-1])
+    rep = ST.judge(sg, eng, test)
+    assert rep["median_rel_l2"] < 0.6 and np.isfinite(rep["p95_rel_l2"])
+    # out-of-distribution inputs go to the plain path and match it exactly
+    coef = test["coef"][:4].clone()
+    coef[0, 5] = 1.0                 # 20 sigma
+    z = test["z"][:4].clone()
+    z[1] = 3000.0                    # outside the trained defocus range
+    out, used_fallback = ST.predict(sg, eng, coef, z)
+    assert used_fallback.tolist() == [True, True, False, False]
+    plain = eng.crops(coef[:2], z[:2])
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(out[:2].cpu().numpy(), plain.cpu().numpy())
