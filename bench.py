@@ -136,6 +136,140 @@ def bench_bessel(rw, torch, steps, warmup, n_stacks=256):
                               traffic=None, bytes_per_launch=bytes_per_launch))
 
 
+def _cuda_time(torch, fn, reps):
+    """Mean milliseconds of fn() over reps calls, HIP events on the current stream."""
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def bench_batched(rw, torch, steps, warmup):
+    import workloads as W
+    w = W.batched()
+    o = w["optics"]
+    em = rw.make_emitters(w["x0"], w["y0"], w["z_e"], w["S"], w["D"], w["zernike"])
+    off = rw.batch_offsets(em)
+    b = rw.Batch(na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], pixel=w["dx"], plane_pitch=w["dz"],
+                 max_emitters=len(w["S"]), n_pupil=w["n_pupil"], e_inc=w["e_inc"])
+    I = torch.zeros(off[-1], dtype=torch.float32, device="cuda")
+    cfg, tune_ms = b.autotune(em, I)
+    s = torch.cuda.Stream()
+    b.set_graph(True)
+    with torch.cuda.stream(s):
+        for _ in range(max(1, warmup)):
+            b.compute(em, I=I, stream=s.cuda_stream)
+        ms = _cuda_time(torch, lambda: b.compute(em, I=I, stream=s.cuda_stream), max(3, steps // 4))
+    b.set_graph(False)
+    b.close()
+    S = w["S"].astype(np.float64)
+    D = w["D"].astype(np.float64)
+    n = w["n_pupil"]
+    flops = float(np.sum(D * 3 * 8.0 * S * n * (n + S)))     # U = Ax_S P~, E = U Ay_S^T per plane
+    ach = flops / (ms * 1e-3) / 1e12
+    return dict(workload="batched: 4096 emitters, crops U{24..64}, planes U{1..41}, 128x128 pupil, "
+                         "Noll 4-21 N(0,0.04), sub-pixel x0/y0, intensity only, one persistent launch "
+                         "replayed from a hipGraph, autotuned",
+                value=off[-1] / (ms * 1e-3), unit="voxels/s", ms_per_launch=ms, voxels=off[-1],
+                autotuned_config=dict(wg_per_cu=cfg[0], small_tile_max_crop=cfg[1]),
+                roofline=dict(kernel="batch_planes_kernel (+ phase GEMM)", bound="mfma",
+                              achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+                              frac=round(ach / PEAK_FP32_TFLOPS, 4), traffic=None, flops_per_launch=flops))
+
+
+def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
+    import workloads as W
+    w = W.adjoint(n_stacks=n_stacks)
+    o = w["optics"]
+    n, nx, nz = w["n_pupil"], w["nx"], len(w["z"])
+    plan = rw.Plan(form=rw.FORM_FOURIER, na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], nx=nx, ny=nx,
+                   dx=w["dx"], dy=w["dy"], z=w["z"], e_inc=w["e_inc"], n_pupil=n)
+    rng = np.random.default_rng(404)
+    w0 = torch.tensor(w["w0_eval"], dtype=torch.float32, device="cuda")
+    st = [dict(x0=rng.uniform(-50, 50), y0=rng.uniform(-50, 50), z_offset=rng.uniform(-200, 200),
+               zernike=w["c_eval"], phase_map=w0) for _ in range(n_stacks)]
+    E = torch.empty((n_stacks, nz, 3, nx, nx), dtype=torch.complex64, device="cuda")
+    I = torch.empty((n_stacks, nz, nx, nx), dtype=torch.float32, device="cuda")
+    Y = torch.rand_like(I)
+    dc = torch.empty(21, dtype=torch.float32, device="cuda")
+    dw = torch.empty((n, n), dtype=torch.float32, device="cuda")
+
+    def step():
+        plan.compute(st, E=E, I=I)
+        rw.adjoint(plan.handle, st, E, (2.0 / I.numel()) * (I - Y), 21, dc, dw)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    ms = _cuda_time(torch, step, max(3, steps // 4))
+    kt = {k: plan.timing(v) for k, v in (("gemm_pupil", rw.KERNEL_GEMM_PUPIL), ("gemm_image", rw.KERNEL_GEMM_IMAGE),
+                                          ("adj_h", rw.KERNEL_ADJ_H), ("adj_g", rw.KERNEL_ADJ_G),
+                                          ("adj_reduce", rw.KERNEL_ADJ_REDUCE))}
+    plan.close()
+    comp = n_stacks * nz * 3
+    fwd = comp * 8.0 * (n * n * nx + nx * n * nx)
+    adj = comp * 8.0 * (nx * nx * n + n * nx * n)
+    ach = (fwd + adj) / (ms * 1e-3) / 1e12
+    vox = n_stacks * nz * nx * nx
+    return dict(workload=f"adjoint: {n_stacks} stacks of {nx}x{nx}x{nz} at 100 nm, 256x256 pupil, shared Noll "
+                         "1-21 + free 256x256 phase map; step = forward (fields) + adjoint (dL/dc, dL/dW0)",
+                value=vox / (ms * 1e-3), unit="voxels/s (forward+adjoint)", ms_per_step=ms,
+                gradient_steps_per_s=1e3 / ms,
+                kernels={k: dict(total_ms=v[0], launches=v[1], avg_us=(v[0] / v[1] * 1e3 if v[1] else None))
+                         for k, v in kt.items()},
+                roofline=dict(kernel="whole step", bound="mfma", achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS,
+                              unit="TFLOP/s", frac=round(ach / PEAK_FP32_TFLOPS, 4), traffic=None,
+                              flops_per_step=fwd + adj))
+
+
+def bench_surrogate(rw, torch, train_seconds):
+    from paper_2502_03170_amd import surrogate_train as ST
+    eng = ST.CropEngine(max_emitters=4096)
+    train = ST.make_dataset(eng, 65536, seed=505)
+    test = ST.make_dataset(eng, 2048, seed=506)
+    sg = rw.Surrogate(max_batch=65536)
+    sg.set_state(ST.init_params(0))
+    t0 = time.perf_counter()
+    steps = 0
+    lr = 1e-3
+    while time.perf_counter() - t0 < train_seconds:
+        ST.train(sg, train, steps=250, batch=256, lr=lr, seed=steps, log_every=250)
+        steps += 250
+        if steps % 2000 == 0:
+            lr *= 0.5
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    acc = {p: ST.judge(sg, eng, test, precision=p) for p in (rw.SG_BF16X3, rw.SG_BF16)}
+    B = 65536
+    coef, z = train["coef"][:B].contiguous(), train["z"][:B].contiguous()
+    out = torch.empty((B, 64, 64), dtype=torch.float32, device="cuda")
+    res = {}
+    for name, p in (("bf16x3", rw.SG_BF16X3), ("bf16", rw.SG_BF16)):
+        sg.forward(coef, z, out=out, precision=p)
+        ms = _cuda_time(torch, lambda: sg.forward(coef, z, out=out, precision=p), 3)
+        res[name] = dict(ms_per_batch=ms, crops_per_s=B / (ms * 1e-3), px_per_s=B * 4096 / (ms * 1e-3))
+    em = rw.make_emitters(np.zeros(4096), np.zeros(4096), -z[:4096].double().cpu().numpy(), [64] * 4096,
+                          [1] * 4096, coef[:4096].double().cpu().numpy())
+    I = torch.empty(4096 * 4096, dtype=torch.float32, device="cuda")
+    eng.batch.compute(em, I=I)
+    ms_plain = _cuda_time(torch, lambda: eng.batch.compute(em, I=I), 3) * (B / 4096)
+    sg.close()
+    return dict(workload="surrogate: (Noll 1-21, z) -> 64x64 crop, 2.38M parameters, trained on 65536 engine "
+                         "crops (Noll 4-21 N(0,0.05), z U(+-1 um), 128x128 pupil, 100 nm pixels) for "
+                         f"{steps} Adam steps of 256 ({train_s:.0f} s); inference batch 65536",
+                value=res["bf16"]["px_per_s"], unit="px/s (inference, bf16)", inference=res,
+                plain_path=dict(ms_per_batch=ms_plain, crops_per_s=B / (ms_plain * 1e-3),
+                                px_per_s=B * 4096 / (ms_plain * 1e-3)),
+                speedup_vs_plain=dict(bf16=ms_plain / res["bf16"]["ms_per_batch"],
+                                      bf16x3=ms_plain / res["bf16x3"]["ms_per_batch"]),
+                accuracy_vs_plain=dict(bf16x3=acc[rw.SG_BF16X3], bf16=acc[rw.SG_BF16]),
+                train_steps=steps)
+
+
 def cpu_baseline(seconds: float):
     """The FP64 oracle (pupil build + separable evaluation) on whole stacks for about `seconds`."""
     from oracle import fourier as OF
@@ -174,7 +308,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="bessel", help="comma list of extra forms, or 'none'")
+    ap.add_argument("--forms", default="bessel,batched,adjoint,surrogate",
+                    help="comma list of extra forms, or 'none'")
+    ap.add_argument("--train-seconds", type=float, default=20.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -194,6 +330,15 @@ def main():
     if "bessel" in args.forms.split(","):
         forms["bessel"] = bench_bessel(rw, torch, args.steps, args.warmup)
         print(f"# bessel: {forms['bessel']['value']:.3e} voxels/s", file=sys.stderr, flush=True)
+    if "batched" in args.forms.split(","):
+        forms["batched"] = bench_batched(rw, torch, args.steps, args.warmup)
+        print(f"# batched: {forms['batched']['value']:.3e} voxels/s", file=sys.stderr, flush=True)
+    if "adjoint" in args.forms.split(","):
+        forms["adjoint"] = bench_adjoint(rw, torch, args.steps, args.warmup)
+        print(f"# adjoint: {forms['adjoint']['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    if "surrogate" in args.forms.split(","):
+        forms["surrogate"] = bench_surrogate(rw, torch, args.train_seconds)
+        print(f"# surrogate: {forms['surrogate']['speedup_vs_plain']}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)

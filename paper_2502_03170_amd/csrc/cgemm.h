@@ -131,15 +131,26 @@ __device__ __forceinline__ void cg_stage_mma(CgAcc<Cfg>& acc, const float* a_re,
   }
 }
 
-// Full K loop: acc += A[rows, 0:K] * B[0:K, cols] with double-buffered LDS (K a multiple of BK).
+// K loop over [k_begin, k_end): acc += A[rows, k] * B[k, cols] with double-buffered LDS
+// (both bounds multiples of BK, k_end > k_begin).
+template <class Cfg, class ALoader, class BLoader>
+__device__ __forceinline__ void cg_mainloop(CgAcc<Cfg>& acc, ALoader& la, BLoader& lb, int k_begin,
+                                            int k_end, float* lds, int tid, int wrow, int wcol, int lane);
+
 template <class Cfg, class ALoader, class BLoader>
 __device__ __forceinline__ void cg_mainloop(CgAcc<Cfg>& acc, ALoader& la, BLoader& lb, int K,
                                             float* lds, int tid, int wrow, int wcol, int lane) {
+  cg_mainloop<Cfg>(acc, la, lb, 0, K, lds, tid, wrow, wcol, lane);
+}
+
+template <class Cfg, class ALoader, class BLoader>
+__device__ __forceinline__ void cg_mainloop(CgAcc<Cfg>& acc, ALoader& la, BLoader& lb, int k_begin,
+                                            int k_end, float* lds, int tid, int wrow, int wcol, int lane) {
   // stage pointers by arithmetic on the __shared__ base: a pointer picked from a
   // local array loses its address space and turns the LDS reads into flat loads
-  const int KT = K / Cfg::BK;
-  la.load(0, tid);
-  lb.load(0, tid);
+  const int KT = (k_end - k_begin) / Cfg::BK;
+  la.load(k_begin, tid);
+  lb.load(k_begin, tid);
   la.store(lds, lds + Cfg::BK * Cfg::LDA, Cfg::LDA, tid);
   lb.store(lds + Cfg::A_FLOATS, lds + Cfg::A_FLOATS + Cfg::BK * Cfg::LDB, Cfg::LDB, tid);
   __syncthreads();
@@ -148,8 +159,8 @@ __device__ __forceinline__ void cg_mainloop(CgAcc<Cfg>& acc, ALoader& la, BLoade
     float* nxt = lds + ((kt + 1) & 1) * Cfg::STAGE_FLOATS;
     const bool more = kt + 1 < KT;
     if (more) {
-      la.load((kt + 1) * Cfg::BK, tid);
-      lb.load((kt + 1) * Cfg::BK, tid);
+      la.load(k_begin + (kt + 1) * Cfg::BK, tid);
+      lb.load(k_begin + (kt + 1) * Cfg::BK, tid);
     }
     cg_stage_mma<Cfg>(acc, cur, cur + Cfg::BK * Cfg::LDA, cur + Cfg::A_FLOATS,
                       cur + Cfg::A_FLOATS + Cfg::BK * Cfg::LDB, wrow, wcol, lane);

@@ -181,9 +181,26 @@ __global__ void __launch_bounds__(CfgPupil::NT, RW_PUPIL_OCC) gemm_pupil_kernel(
   lb.src = a.AyT + col0;
   lb.ld = a.nyp;
 
+  // The pupil is zero outside the disk (2j+1-n)^2 + (2l+1-n)^2 <= n^2: this row block only
+  // needs the columns l that its row nearest the centre reaches.
+  int k_begin = 0, k_end = a.np;
+  {
+    const int n = a.n;
+    const int r_lo = row0, r_hi = min(row0 + Cfg::BM, n) - 1;
+    if (r_lo >= n) {
+      k_end = Cfg::BK;   // padding rows only: one (zero) stage
+    } else {
+      const int u_lo = 2 * r_lo + 1 - n, u_hi = 2 * r_hi + 1 - n;
+      const int umin = (u_lo <= 0 && u_hi >= 0) ? 0 : min(abs(u_lo), abs(u_hi));
+      const int vmax = (int)floorf(sqrtf((float)n * n - (float)umin * umin)) + 1;   // generous
+      const int l_lo = max(0, (n - 1 - vmax) / 2), l_hi = min(n - 1, (n - 1 + vmax) / 2 + 1);
+      k_begin = (l_lo / Cfg::BK) * Cfg::BK;
+      k_end = min(a.np, (l_hi / Cfg::BK + 1) * Cfg::BK);
+    }
+  }
   CgAcc<Cfg> acc;
   acc.zero();
-  cg_mainloop<Cfg>(acc, la, lb, a.np, lds, tid, wrow, wcol, lane);
+  cg_mainloop<Cfg>(acc, la, lb, k_begin, k_end, lds, tid, wrow, wcol, lane);
 
   float2* T = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)a.np * a.nyp;
 #pragma unroll

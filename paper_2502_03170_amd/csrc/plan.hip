@@ -175,6 +175,7 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
         g1.AyT = p->d_AyT;
         g1.T = p->d_T;
         for (int i = 0; i < ns; ++i) g1.zoff[i] = s[b0 + s0 + i].z_offset_nm;
+        g1.n = N;
         g1.np = p->np;
         g1.nyp = p->nyp;
         g1.nstk = ns;
@@ -213,6 +214,7 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
           g1.AyT = p->d_AyT;
           g1.T = p->d_T;
           g1.zoff[0] = s[b0 + i].z_offset_nm;
+          g1.n = N;
           g1.np = p->np;
           g1.nyp = p->nyp;
           g1.nstk = 1;

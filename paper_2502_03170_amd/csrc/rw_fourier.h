@@ -29,7 +29,7 @@ struct Gemm1Args {
   const float2* AyT;   // [np][nyp]
   float2* T;           // [nstk][nzs][3][np][nyp]
   double zoff[kPupilStacks];
-  int np, nyp, nstk, z0, nzs;
+  int n, np, nyp, nstk, z0, nzs;   // n: pupil cells per axis
 };
 
 struct Gemm2Args {

@@ -60,18 +60,23 @@ def make_dataset(eng: CropEngine, n: int, seed: int):
     return dict(coef=coef, z=z, target=eng.crops(coef, z).contiguous())
 
 
-def init_params(seed: int) -> np.ndarray:
-    """He-normal weights, zero biases, flat in the library's parameter order."""
+def init_params(seed: int, out_scale: float = 0.05, bias: float = 0.01) -> np.ndarray:
+    """He-normal weights, slightly positive biases (live relus) and a small output layer
+    (the targets are O(1e-2) per pixel), flat in the library's parameter order."""
     rng = np.random.default_rng(seed)
     parts = []
     for a, b in ((22, 256), (256, 1024), (1024, 2048)):
-        parts += [rng.normal(0, math.sqrt(2.0 / a), a * b), np.zeros(b)]
-    for a, b in ((32, 16), (16, 8), (8, 1)):
-        parts += [rng.normal(0, math.sqrt(2.0 / (a * 4)), a * b * 16), np.zeros(b)]
+        parts += [rng.normal(0, math.sqrt(2.0 / a), a * b), np.full(b, bias)]
+    for i, (a, b) in enumerate(((32, 16), (16, 8), (8, 1))):
+        w = rng.normal(0, math.sqrt(2.0 / (a * 4)), a * b * 16)
+        if i == 2:
+            w *= out_scale
+        parts += [w, np.full(b, bias if i < 2 else 0.0)]
     return np.concatenate(parts).astype(np.float32)
 
 
-def train(sg: rw.Surrogate, data: dict, steps: int, batch: int, lr: float, seed: int, log_every: int = 50):
+def train(sg: rw.Surrogate, data: dict, steps: int, batch: int, lr: float, seed: int, log_every: int = 50,
+          eps: float = 1e-10):
     import torch
     n = data["coef"].shape[0]
     gen = torch.Generator(device="cuda")
@@ -82,7 +87,7 @@ def train(sg: rw.Surrogate, data: dict, steps: int, batch: int, lr: float, seed:
         idx = torch.randint(0, n, (batch,), device="cuda", generator=gen)
         sg.gradient(data["coef"][idx].contiguous(), data["z"][idx].contiguous(),
                     data["target"][idx].contiguous(), loss=loss)
-        sg.adam(lr)
+        sg.adam(lr, eps=eps)
         if step % log_every == 0 or step == steps - 1:
             hist.append(float(loss.item()))
     return hist

@@ -33,6 +33,31 @@ def _random_params(seed):
     return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
 
 
+def _decisive_params(seed, x):
+    """Weights whose pre-activations stay at least 1.5 from zero on the inputs x: biases
+    are +-3 and each layer's weights are scaled so that |pre - bias| <= 1.5.  Relu masks
+    are then the same in FP32 and FP64 (a relu decision within rounding of zero would
+    flip between the two precisions and move the gradient by a whole term)."""
+    p = OS.init_params(seed)
+    rng = np.random.default_rng(seed + 2)
+    h = x
+    for i in range(1, 4):
+        p[f"b{i}"] = 3.0 * rng.choice([-1.0, 1.0], p[f"b{i}"].shape)
+        raw = h @ p[f"W{i}"]
+        p[f"W{i}"] *= 1.5 / np.abs(raw).max()
+        p[f"W{i}"] = p[f"W{i}"].astype(np.float32).astype(np.float64)
+        h = np.maximum(h @ p[f"W{i}"] + p[f"b{i}"], 0.0)
+    d = h.reshape(-1, 32, 8, 8)
+    for i in range(1, 4):
+        p[f"c{i}"] = 3.0 * rng.choice([-1.0, 1.0], p[f"c{i}"].shape)
+        raw = OS.deconv(d, p[f"K{i}"], np.zeros_like(p[f"c{i}"]))
+        p[f"K{i}"] *= 1.5 / np.abs(raw).max()
+        p[f"K{i}"] = p[f"K{i}"].astype(np.float32).astype(np.float64)
+        pre = OS.deconv(d, p[f"K{i}"], p[f"c{i}"])
+        d = np.maximum(pre, 0.0) if i < 3 else pre
+    return {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+
+
 def _inputs(torch, B, seed):
     w = W.surrogate(B, seed)
     coef = torch.tensor(w["zernike"], dtype=torch.float32, device="cuda").contiguous()
@@ -62,10 +87,10 @@ def test_surrogate_forward_matches_fp64_network(lib):
 def test_surrogate_gradient_and_adam_match_fp64(lib):
     import torch
     rw = lib
-    p = _random_params(21)
+    coef, z, x = _inputs(torch, 40, 22)
+    p = _decisive_params(21, x)
     sg = rw.Surrogate(max_batch=64)
     sg.set_state(_flat(p))
-    coef, z, x = _inputs(torch, 40, 22)
     target = np.random.default_rng(23).normal(0, 0.3, (40, 64, 64)).astype(np.float32)
     loss = torch.zeros(1, dtype=torch.float32, device="cuda")
     sg.gradient(coef, z, torch.tensor(target, device="cuda"), loss=loss)
