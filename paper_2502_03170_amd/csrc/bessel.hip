@@ -48,11 +48,15 @@ __global__ void bessel_table_kernel(float* __restrict__ out, const double* __res
 // --------------------------------------------------------------------------
 // Per call: pupil x defocus on the theta nodes, Phi[q][s * nz + z] (complex64).
 // --------------------------------------------------------------------------
+// Only the axisymmetric Noll terms reach the Bessel form (validated): j = 1, 4, 11, 22
+// (radial orders 0, 2, 4, 6) within RWPSF_MAX_ZERNIKE.
+constexpr int kAxiTerms = 4;
+constexpr int kAxiNoll[kAxiTerms] = {1, 4, 11, 22};
 struct PhiStack {
   double t_s, zoff;
-  double coef[RWPSF_MAX_ZERNIKE];  // only m = 0 terms are non-zero (validated)
+  double coef[kAxiTerms];
 };
-constexpr int kPhiStacks = 8;
+constexpr int kPhiStacks = 64;
 struct PhiArgs {
   int T, nz, nstk, s_base_unused, max_zernike, gibson_lanni, apod;
   double k, s_max, s_env;
@@ -77,8 +81,8 @@ __global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
   double w_re = 0.0, w_im = 0.0;
   if (a.gibson_lanni) gl_opd(a.gl, st.t_s, sin_t, &w_re, &w_im);
   const double r = sin_t / a.s_max;
-  for (int j = 0; j < a.max_zernike; ++j)
-    if (st.coef[j] != 0.0) w_re += kTwoPi * st.coef[j] * zernike_noll(j + 1, r, 1.0, 0.0);
+  for (int j = 0; j < kAxiTerms; ++j)
+    if (st.coef[j] != 0.0) w_re += kTwoPi * st.coef[j] * zernike_noll(kAxiNoll[j], r, 1.0, 0.0);
   const double ph = w_re + a.k * (z[zi] + st.zoff) * cos_t;
   float sn, cs;
   sincosf((float)reduce_2pi(ph), &sn, &cs);
@@ -356,7 +360,8 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
       const rwpsf_stack& x = s[b0 + i];
       pa.s[i].t_s = x.t_s_nm;
       pa.s[i].zoff = x.z_offset_nm;
-      for (int q = 0; q < RWPSF_MAX_ZERNIKE; ++q) pa.s[i].coef[q] = q < x.n_zernike ? x.zernike_waves[q] : 0.0;
+      for (int q = 0; q < kAxiTerms; ++q)
+        pa.s[i].coef[q] = kAxiNoll[q] <= x.n_zernike ? x.zernike_waves[kAxiNoll[q] - 1] : 0.0;
       maxz = std::max(maxz, x.n_zernike);
     }
     pa.max_zernike = maxz;
