@@ -229,18 +229,19 @@ def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
 def bench_surrogate(rw, torch, train_seconds):
     from paper_2502_03170_amd import surrogate_train as ST
     eng = ST.CropEngine(max_emitters=4096)
-    train = ST.make_dataset(eng, 65536, seed=505)
+    train = ST.make_dataset(eng, 200_000, seed=505)
     test = ST.make_dataset(eng, 2048, seed=506)
     sg = rw.Surrogate(max_batch=65536)
     sg.set_state(ST.init_params(0))
+    # time a short run to size the schedule to the budget, then one cosine schedule
     t0 = time.perf_counter()
-    steps = 0
-    lr = 1e-3
-    while time.perf_counter() - t0 < train_seconds:
-        ST.train(sg, train, steps=250, batch=256, lr=lr, seed=steps, log_every=250)
-        steps += 250
-        if steps % 2000 == 0:
-            lr *= 0.5
+    ST.train(sg, train, steps=50, batch=256, lr=2e-3, seed=0, log_every=50)
+    torch.cuda.synchronize()
+    per_step = (time.perf_counter() - t0) / 50
+    steps = max(100, int(train_seconds / per_step))
+    sg.set_state(ST.init_params(0))
+    t0 = time.perf_counter()
+    ST.train(sg, train, steps=steps, batch=256, lr=2e-3, lr_end=1e-4, seed=1, log_every=max(1, steps // 4))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     acc = {p: ST.judge(sg, eng, test, precision=p) for p in (rw.SG_BF16X3, rw.SG_BF16)}
@@ -258,7 +259,7 @@ def bench_surrogate(rw, torch, train_seconds):
     eng.batch.compute(em, I=I)
     ms_plain = _cuda_time(torch, lambda: eng.batch.compute(em, I=I), 3) * (B / 4096)
     sg.close()
-    return dict(workload="surrogate: (Noll 1-21, z) -> 64x64 crop, 2.38M parameters, trained on 65536 engine "
+    return dict(workload="surrogate: (Noll 1-21, z) -> 64x64 crop, 2.38M parameters, trained on 200000 engine "
                          "crops (Noll 4-21 N(0,0.05), z U(+-1 um), 128x128 pupil, 100 nm pixels) for "
                          f"{steps} Adam steps of 256 ({train_s:.0f} s); inference batch 65536",
                 value=res["bf16"]["px_per_s"], unit="px/s (inference, bf16)", inference=res,
@@ -311,6 +312,8 @@ def main():
     ap.add_argument("--forms", default="bessel,batched,adjoint,surrogate",
                     help="comma list of extra forms, or 'none'")
     ap.add_argument("--train-seconds", type=float, default=20.0)
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="also run a 256 MiB device-to-device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -323,6 +326,12 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.synchronize()
+    if args.copy_reference:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     res = bench_fourier(rw, torch, args.steps, args.warmup)
     print(f"# fourier: {res['ms_per_step']:.3f} ms/step, {res['value']:.3e} voxels/s", file=sys.stderr,
           flush=True)

@@ -76,7 +76,9 @@ def init_params(seed: int, out_scale: float = 0.05, bias: float = 0.01) -> np.nd
 
 
 def train(sg: rw.Surrogate, data: dict, steps: int, batch: int, lr: float, seed: int, log_every: int = 50,
-          eps: float = 1e-10):
+          eps: float = 1e-10, lr_end: float | None = None):
+    """Adam steps on random mini-batches; the learning rate follows a cosine from lr to
+    lr_end (constant when lr_end is None).  Returns the logged losses."""
     import torch
     n = data["coef"].shape[0]
     gen = torch.Generator(device="cuda")
@@ -87,7 +89,8 @@ def train(sg: rw.Surrogate, data: dict, steps: int, batch: int, lr: float, seed:
         idx = torch.randint(0, n, (batch,), device="cuda", generator=gen)
         sg.gradient(data["coef"][idx].contiguous(), data["z"][idx].contiguous(),
                     data["target"][idx].contiguous(), loss=loss)
-        sg.adam(lr, eps=eps)
+        rate = lr if lr_end is None else lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * step / steps))
+        sg.adam(rate, eps=eps)
         if step % log_every == 0 or step == steps - 1:
             hist.append(float(loss.item()))
     return hist
