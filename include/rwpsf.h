@@ -214,7 +214,11 @@ int rwpsf_batch_set_config(rwpsf_batch* batch, const rwpsf_batch_config* cfg);
 int rwpsf_batch_get_config(const rwpsf_batch* batch, rwpsf_batch_config* cfg);
 
 /* Time each candidate configuration on these emitters (outputs written to I_out)
-   and keep the fastest.  Synchronises the stream.  best_ms may be NULL. */
+   and keep the fastest.  Synchronises the stream.  best_ms may be NULL.  If the
+   environment variable RWPSF_AUTOTUNE_CACHE names a file, a configuration stored there
+   for the same key (pupil size, batch-size bucket, crop mix, mean plane count, CU
+   count) is used without timing, and new results are added to it; a file that does
+   not parse is ignored and rewritten. */
 int rwpsf_batch_autotune(rwpsf_batch* batch, int n, const rwpsf_emitter* emitters, float* I_out,
                          void* stream, rwpsf_batch_config* best, double* best_ms);
 

@@ -17,8 +17,12 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <numeric>
 #include <vector>
 
@@ -538,12 +542,97 @@ int rwpsf_batch_compute(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I,
   return RWPSF_OK;
 }
 
+}  // extern "C"
+
+namespace rw {
+
+// Autotune cache: a flat JSON object {"key": [wg_per_cu, small_tile_max_crop, ms], ...}
+// in the file named by RWPSF_AUTOTUNE_CACHE.  Anything that does not parse is ignored
+// (and replaced on the next write).
+static std::string tune_key(const rwpsf_batch* b, int n, const rwpsf_emitter* e) {
+  int small = 0, large = 0;
+  long long planes = 0;
+  for (int i = 0; i < n; ++i) {
+    (e[i].crop <= 32 ? small : large) += 1;
+    planes += e[i].planes;
+  }
+  int nb = 1;
+  while (nb < n) nb <<= 1;
+  char buf[160];
+  snprintf(buf, sizeof buf, "N%d_n%d_small%d_large%d_meanD%lld_cus%d", b->N, nb, (int)(16.0 * small / n),
+           (int)(16.0 * large / n), planes / n, b->num_cus);
+  return buf;
+}
+
+static std::map<std::string, std::pair<rwpsf_batch_config, double>> cache_read(const char* path) {
+  std::map<std::string, std::pair<rwpsf_batch_config, double>> m;
+  FILE* f = fopen(path, "r");
+  if (!f) return m;
+  std::string text;
+  char chunk[4096];
+  size_t got;
+  while ((got = fread(chunk, 1, sizeof chunk, f)) > 0) text.append(chunk, got);
+  fclose(f);
+  size_t pos = text.find('{');
+  if (pos == std::string::npos) return {};
+  while (true) {
+    const size_t k0 = text.find('"', pos);
+    if (k0 == std::string::npos) break;
+    const size_t k1 = text.find('"', k0 + 1);
+    if (k1 == std::string::npos) return {};
+    const size_t b0 = text.find('[', k1);
+    const size_t b1 = text.find(']', b0 == std::string::npos ? k1 : b0);
+    if (b0 == std::string::npos || b1 == std::string::npos) return {};
+    int wg = 0, sm = 0;
+    double ms = 0;
+    if (sscanf(text.c_str() + b0, "[%d ,%d ,%lf]", &wg, &sm, &ms) != 3 &&
+        sscanf(text.c_str() + b0, "[%d, %d, %lf]", &wg, &sm, &ms) != 3)
+      return {};
+    if (wg < 1 || wg > 4 || (sm != 0 && sm != 32)) return {};
+    m[text.substr(k0 + 1, k1 - k0 - 1)] = {rwpsf_batch_config{wg, sm}, ms};
+    pos = b1 + 1;
+  }
+  return m;
+}
+
+static void cache_write(const char* path, const std::map<std::string, std::pair<rwpsf_batch_config, double>>& m) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = fopen(tmp.c_str(), "w");
+  if (!f) return;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (const auto& kv : m)
+    fprintf(f, "  \"%s\": [%d, %d, %.6f]%s\n", kv.first.c_str(), kv.second.first.wg_per_cu,
+            kv.second.first.small_tile_max_crop, kv.second.second, ++i < m.size() ? "," : "");
+  fprintf(f, "}\n");
+  fclose(f);
+  rename(tmp.c_str(), path);
+}
+
+}  // namespace rw
+
+extern "C" {
+
 int rwpsf_batch_autotune(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I, void* stream,
                          rwpsf_batch_config* best_out, double* best_ms) {
   using namespace rw;
   int rc = batch_validate(b, n, e);
   if (rc) return rc;
   if (!I) return RWPSF_ERR_INVALID_ARG;
+  const char* cache_path = getenv("RWPSF_AUTOTUNE_CACHE");
+  std::string key;
+  std::map<std::string, std::pair<rwpsf_batch_config, double>> cache;
+  if (cache_path && *cache_path) {
+    key = tune_key(b, n, e);
+    cache = cache_read(cache_path);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+      b->cfg = it->second.first;
+      if (best_out) *best_out = it->second.first;
+      if (best_ms) *best_ms = it->second.second;
+      return RWPSF_OK;
+    }
+  }
   hipStream_t st = (hipStream_t)stream;
   const rwpsf_batch_config saved = b->cfg;
   const bool saved_graph = b->use_graph;
@@ -579,6 +668,10 @@ int rwpsf_batch_autotune(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I
   if (rc) return rc;
   if (best_out) *best_out = best;
   if (best_ms) *best_ms = best_t;
+  if (cache_path && *cache_path) {
+    cache[key] = {best, best_t};
+    cache_write(cache_path, cache);
+  }
   return RWPSF_OK;
 }
 

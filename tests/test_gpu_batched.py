@@ -179,3 +179,22 @@ def test_batched_validation(lib):
         b.compute(_emitters(rw, w, np.arange(1), crop=[65]), I=I)  # crop too large
     with pytest.raises(rw.RwpsfError):
         b.compute(_emitters(rw, w, np.arange(1), planes=[0]), I=I)
+
+
+def test_batched_autotune_cache(lib, tmp_path, monkeypatch):
+    import torch
+    rw = lib
+    path = tmp_path / "tune.json"
+    path.write_text("{ this is not json")             # corrupt cache: ignored, then rewritten
+    monkeypatch.setenv("RWPSF_AUTOTUNE_CACHE", str(path))
+    w = W.batched(n_emitters=64, seed=38)
+    em = _emitters(rw, w, np.arange(64))
+    off = rw.batch_offsets(em)
+    b = _batch(rw, w, 64)
+    I = torch.zeros(off[-1], dtype=torch.float32, device="cuda")
+    cfg1, ms1 = b.autotune(em, I)
+    text = path.read_text()
+    assert text.strip().startswith("{") and str(list(cfg1))[1:-1].replace(" ", "") in text.replace(" ", "")
+    b2 = _batch(rw, w, 64)
+    cfg2, ms2 = b2.autotune(em, I)                    # served from the cache, no timing
+    assert cfg2 == cfg1 and abs(ms2 - ms1) < 1e-3
