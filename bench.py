@@ -64,9 +64,11 @@ def bench_fourier(rw, torch, steps, warmup):
                                                ("gemm_image", rw.KERNEL_GEMM_IMAGE))}
     plan.set_timing(False)
     voxels = B * nz * nx * nx
-    # algorithmic work of the separable matrix DFT, per component-plane
-    f1 = 8.0 * n * n * nx            # T = P~ Ay^T
-    f2 = 8.0 * nx * n * nx           # E = Ax T
+    # algorithmic work of the mirror-folded separable transform, per component-plane:
+    # two real GEMMs, [2n x n] x [n x ny] and [nx x n] x [n x 2ny] (half the flops of the
+    # complex matrix DFT, 8 n ny (n + nx))
+    f1 = 4.0 * n * n * nx            # T = Pf~ B1
+    f2 = 4.0 * nx * n * nx           # E' = A2 T
     comp_planes = B * nz * 3
     g1_ms, g1_n = kt["gemm_pupil"]
     g2_ms, g2_n = kt["gemm_image"]

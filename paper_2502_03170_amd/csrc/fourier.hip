@@ -2,18 +2,21 @@
 //
 // Sec. 3.3 eq. "cartesian vectorial" with the correction factors of Sec. 3.4:
 // each z-plane of each field component is the 2-D transform of the pupil
-//   P~_c[j,l] = P_c[j,l] exp(i k s_z[j,l] z),  P_c = ds^2 a exp(iW) e_inf,c / s_z
-// to the pixel grid.  It is evaluated as the separable matrix DFT
-//   E_c = Ax P~_c Ay^T,  Ax[m,j] = C exp(i k s_x[j] x_m),  Ay[n,l] = exp(i k s_y[l] y_n)
-// (C = -i f k / 2 pi), i.e. two complex GEMMs per component-plane on the FP32
-// matrix cores:
-//   K1 pupil_build   P_c for up to 8 stacks (FP64 phase: Gibson-Lanni, Zernike,
-//                    free phase map, lateral emitter shift), complex64 [s][c][j][l]
-//   K2 gemm_pupil    T = P~ Ay^T; the defocus factor is formed while the pupil
-//                    tile is staged (FP64 phase, reduced mod 2 pi, FP32 sincos)
-//   K3 gemm_image    E_c = Ax T_c for c = x, y, z in one workgroup, writing E and
-//                    I = sum_c |E_c|^2 from registers.
+//   P~_c[j,l] = P_c[j,l] exp(i k s_z z),  P_c = ds^2 a exp(iW) e_inf,c / s_z
+// to the pixel grid, E_c = C sum_{j,l} P~_c[j,l] e^{i k (s_x[j] x + s_y[l] y)},
+// C = -i f k / 2 pi.  The sample grid is symmetric (s[n-1-j] = -s[j]), so each 1-D
+// transform folds into even and odd parts with real coefficients cos / sin, and the
+// separable transform becomes two real GEMMs on the FP32 matrix cores with half the
+// flops of the complex matrix DFT:
+//   K1  pupil_build   P_c for up to 8 stacks (FP64 phase: Gibson-Lanni, Zernike,
+//                     free phase map, lateral emitter shift), complex64 [s][c][j][l]
+//   K1b pupil_fold    mirror-folded pupils Pf (four parities per folded cell)
+//   K2  gemm_pupil    T = Pf~ B1 (fold along y); the defocus factor is formed while the
+//                     pupil tile is staged (FP64 phase, reduced mod 2 pi, FP32 sincos)
+//   K3  gemm_image    E'_c = A2 T_c (fold along x) for c = x, y, z in one workgroup,
+//                     writing E = -i E' and I = sum_c |E_c|^2 from registers.
 #include "cgemm.h"
+#include "rgemm.h"
 #include "rw_common.h"
 #include "rw_fourier.h"
 
@@ -96,69 +99,155 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
 }
 
 // --------------------------------------------------------------------------
-// A operand of K2: pupil rows j, contraction index l, with the defocus factor
-// exp(i k s_z z) applied on the way into LDS.  The phase k s_z z is formed and
-// reduced in FP64; only the reduced angle goes through FP32 sincos.
+// K1b: mirror fold of the base pupils.
+//
+// The cell-centred grid is symmetric, s[n-1-j] = -s[j], so with jf < nh = ceil(n/2)
+// and its mirror j' = n-1-jf each 1-D transform splits into even and odd parts:
+//   sum_j p_j e^{i k s_j x} = sum_jf cos(k s_jf x) (p_jf + p_j') + sin(k s_jf x) i (p_jf - p_j')
+// Folding both pupil axes gives, per folded cell (jf, lf) and parities (pj, pl),
+//   Pf_{pj,pl} = i^(pj+pl) sum_{a,b in {0,1}} (-1)^(a pj + b pl) P[mir_a(jf), mir_b(lf)]
+// (a mirror equal to the cell itself -- the middle row of an odd n -- is counted once
+// and has no odd part).  Both transforms then have real coefficients (cos, sin), so
+// each is one real GEMM with half the flops of the complex one.  The defocus factor
+// depends on s_x^2 + s_y^2 only and is the same for all four mirrors.
+// Layout: Pf[s][c][q = 2 jf + pj][kk = 2 lf + pl], complex, (2 nhp) x (2 nhp).
+// --------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) pupil_fold_kernel(FoldArgs a) {
+  const int nhp = a.nhp, n = a.n, nh = (a.n + 1) / 2;
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= nhp * nhp) return;
+  const int jf = cell / nhp, lf = cell % nhp;
+  const size_t npp = (size_t)a.np * a.np, fpp = (size_t)4 * nhp * nhp;
+  const int w = 2 * nhp;
+  const size_t o00 = (size_t)(2 * jf) * w + 2 * lf;   // (pj, pl) = (0, 0); (0,1) = +1; (1,0) = +w
+  const float2 zero = make_float2(0.f, 0.f);
+  for (int s = 0; s < a.nstk; ++s)
+    for (int c = 0; c < 3; ++c) {
+      float2* out = a.Pf + ((size_t)s * 3 + c) * fpp + o00;
+      if (jf >= nh || lf >= nh) {
+        out[0] = zero;
+        out[1] = zero;
+        out[w] = zero;
+        out[w + 1] = zero;
+        continue;
+      }
+      const float2* P = a.P + ((size_t)s * 3 + c) * npp;
+      const int j1 = n - 1 - jf, l1 = n - 1 - lf;
+      const bool dj = j1 != jf, dl = l1 != lf;
+      const float2 p00 = P[(size_t)jf * a.np + lf];
+      const float2 p01 = dl ? P[(size_t)jf * a.np + l1] : zero;
+      const float2 p10 = dj ? P[(size_t)j1 * a.np + lf] : zero;
+      const float2 p11 = (dj && dl) ? P[(size_t)j1 * a.np + l1] : zero;
+      // even/odd in l for each j mirror, then in j
+      const float2 e0 = make_float2(p00.x + p01.x, p00.y + p01.y), o0 = make_float2(p00.x - p01.x, p00.y - p01.y);
+      const float2 e1 = make_float2(p10.x + p11.x, p10.y + p11.y), o1 = make_float2(p10.x - p11.x, p10.y - p11.y);
+      const float2 ee = make_float2(e0.x + e1.x, e0.y + e1.y);
+      const float2 eo = dl ? make_float2(o0.x + o1.x, o0.y + o1.y) : zero;            // odd in l
+      const float2 oe = dj ? make_float2(e0.x - e1.x, e0.y - e1.y) : zero;            // odd in j
+      const float2 oo = (dj && dl) ? make_float2(o0.x - o1.x, o0.y - o1.y) : zero;
+      out[0] = ee;
+      out[1] = make_float2(-eo.y, eo.x);        // i * eo
+      out[w] = make_float2(-oe.y, oe.x);        // i * oe
+      out[w + 1] = make_float2(-oo.x, -oo.y);   // i^2 * oo
+    }
+}
+
+// --------------------------------------------------------------------------
+// A operand of K2: rows 2q + ri (q = 2 jf + pj, ri = re/im) and contraction index
+// kk = 2 lf + pl of the folded pupil, with the defocus factor exp(i k s_z z) applied
+// on the way into LDS.  One thread takes one folded cell (jf, lf): its four values
+// share one defocus factor, formed in FP64 and reduced mod 2 pi before the FP32 sincos.
 // --------------------------------------------------------------------------
 template <class Cfg>
-struct DefocusLoader {
-  static constexpr int PAIRS = Cfg::BK / 2;
-  static constexpr int PER_THREAD = Cfg::BM * PAIRS / Cfg::NT;
-  static_assert(Cfg::BM * PAIRS % Cfg::NT == 0, "loader shape");
-  const float2* P;    // [np][np] of this stack and component, rows from row0
-  const double* ksz;  // [np][np], rows from row0
+struct FoldDefocusLoader {
+  static constexpr int JF = Cfg::BM / 4, LF = Cfg::BK / 2;
+  static constexpr int PER_THREAD = JF * LF / Cfg::NT;
+  static_assert(JF * LF % Cfg::NT == 0, "loader shape");
+  const float2* Pf;    // [2 nhp][2 nhp] of this stack and component, from folded row jf0
+  const double* kszf;  // [nhp][nhp], from row jf0
   double z;
-  int ld;
-  float4 v[PER_THREAD];
-  double2 kz[PER_THREAD];
+  int w, nhp;          // w = 2 nhp
+  float4 v0[PER_THREAD], v1[PER_THREAD];
+  double kz[PER_THREAD];
 
   __device__ void load(int k0, int tid) {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
-      const int row = idx / PAIRS, kk = 2 * (idx % PAIRS);
-      const size_t off = (size_t)row * ld + k0 + kk;
-      v[i] = *reinterpret_cast<const float4*>(P + off);
-      kz[i] = *reinterpret_cast<const double2*>(ksz + off);
+      const int jl = idx / LF, ll = idx % LF;
+      const size_t off = (size_t)(2 * jl) * w + k0 + 2 * ll;
+      v0[i] = *reinterpret_cast<const float4*>(Pf + off);       // pj = 0, pl = 0, 1
+      v1[i] = *reinterpret_cast<const float4*>(Pf + off + w);   // pj = 1
+      kz[i] = kszf[(size_t)jl * nhp + k0 / 2 + ll];
     }
   }
-  __device__ void store(float* re, float* im, int ldl, int tid) const {
+  __device__ void store(float* dst, int ldl, int tid) const {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
-      const int row = idx / PAIRS, kk = 2 * (idx % PAIRS);
-      float s0, c0, s1, c1;
-      sincosf((float)reduce_2pi(kz[i].x * z), &s0, &c0);
-      sincosf((float)reduce_2pi(kz[i].y * z), &s1, &c1);
-      re[kk * ldl + row] = v[i].x * c0 - v[i].y * s0;
-      im[kk * ldl + row] = v[i].x * s0 + v[i].y * c0;
-      re[(kk + 1) * ldl + row] = v[i].z * c1 - v[i].w * s1;
-      im[(kk + 1) * ldl + row] = v[i].z * s1 + v[i].w * c1;
+      const int jl = idx / LF, ll = idx % LF;
+      float sn, cs;
+      sincosf((float)reduce_2pi(kz[i] * z), &sn, &cs);
+      *reinterpret_cast<float4*>(dst + (2 * ll) * ldl + 4 * jl) =
+          make_float4(v0[i].x * cs - v0[i].y * sn, v0[i].x * sn + v0[i].y * cs, v1[i].x * cs - v1[i].y * sn,
+                      v1[i].x * sn + v1[i].y * cs);
+      *reinterpret_cast<float4*>(dst + (2 * ll + 1) * ldl + 4 * jl) =
+          make_float4(v0[i].z * cs - v0[i].w * sn, v0[i].z * sn + v0[i].w * cs, v1[i].z * cs - v1[i].w * sn,
+                      v1[i].z * sn + v1[i].w * cs);
     }
   }
 };
 
-#ifndef RW_PUPIL_BK
-#define RW_PUPIL_BK 16
+#ifndef RW_F1_BM
+#define RW_F1_BM 128
 #endif
-#ifndef RW_IMAGE_BK
-#define RW_IMAGE_BK 8
+#ifndef RW_F1_BN
+#define RW_F1_BN 128
 #endif
-#ifndef RW_PUPIL_OCC
-#define RW_PUPIL_OCC 2
+#ifndef RW_F1_BK
+#define RW_F1_BK 32
 #endif
-#ifndef RW_IMAGE_OCC
-#define RW_IMAGE_OCC 2
+#ifndef RW_F1_WM
+#define RW_F1_WM 64
 #endif
-static_assert(kPadPupil % 64 == 0 && kPadY % 128 == 0 && kPadX % 64 == 0, "tile padding");
-using CfgPupil = CgCfg<64, 128, RW_PUPIL_BK, 64, 32>;
-using CfgImage = CgCfg<64, 128, RW_IMAGE_BK, 64, 32>;
+#ifndef RW_F1_WN
+#define RW_F1_WN 64
+#endif
+#ifndef RW_F1_OCC
+#define RW_F1_OCC 2
+#endif
+#ifndef RW_F2_BM
+#define RW_F2_BM 64
+#endif
+#ifndef RW_F2_BN
+#define RW_F2_BN 128
+#endif
+#ifndef RW_F2_BK
+#define RW_F2_BK 32
+#endif
+#ifndef RW_F2_WM
+#define RW_F2_WM 32
+#endif
+#ifndef RW_F2_WN
+#define RW_F2_WN 64
+#endif
+#ifndef RW_F2_OCC
+#define RW_F2_OCC 3
+#endif
+using CfgPupil = RgCfg<RW_F1_BM, RW_F1_BN, RW_F1_BK, RW_F1_WM, RW_F1_WN>;
+using CfgImage = RgCfg<RW_F2_BM, RW_F2_BN, RW_F2_BK, RW_F2_WM, RW_F2_WN>;
+static_assert((4 * kFoldPad) % CfgPupil::BM == 0 && (2 * kFoldPad) % CfgPupil::BK == 0, "pupil GEMM padding");
+static_assert(kPadY % CfgPupil::BN == 0 && kPadX % CfgImage::BM == 0 && (2 * kPadY) % CfgImage::BN == 0 &&
+                  (2 * kFoldPad) % CfgImage::BK == 0,
+              "image GEMM padding");
 
-// K2: T[s][z][c] = P~[s][c](z) * Ay^T   ([n x n] * [n x ny])
-__global__ void __launch_bounds__(CfgPupil::NT, RW_PUPIL_OCC) gemm_pupil_kernel(Gemm1Args a) {
+// K2: T[s][z][c] = (Pf~ B1) with rows 2q + ri, i.e. the complex [2 nhp] x [nyp] matrix
+// T[q][n] = sum_kk Pf~[q][kk] B1[kk][n], B1[2lf][n] = cos(k s_lf y_n), B1[2lf+1][n] = sin(...)
+__global__ void __launch_bounds__(CfgPupil::NT, RW_F1_OCC) gemm_pupil_kernel(Gemm1Args a) {
   using Cfg = CfgPupil;
   extern __shared__ float lds[];
-  const int tiles_m = a.np / Cfg::BM;
+  const int w = 2 * a.nhp;
+  const int tiles_m = 2 * w / Cfg::BM;
   const int tiles_n = a.nyp / Cfg::BN;
   const int nblocks = a.nstk * a.nzs * 3 * tiles_m * tiles_n;
   int id = xcd_remap(blockIdx.x, nblocks);
@@ -169,59 +258,63 @@ __global__ void __launch_bounds__(CfgPupil::NT, RW_PUPIL_OCC) gemm_pupil_kernel(
   const int s = id;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wrow = (wave / Cfg::WAVES_N) * Cfg::WM, wcol = (wave % Cfg::WAVES_N) * Cfg::WN;
-  const size_t npp = (size_t)a.np * a.np;
+  const size_t fpp = (size_t)w * w;
   const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
+  const int jf0 = row0 / 4;
 
-  DefocusLoader<Cfg> la;
-  la.P = a.P + ((size_t)s * 3 + c) * npp + (size_t)row0 * a.np;
-  la.ksz = a.ksz + (size_t)row0 * a.np;
+  FoldDefocusLoader<Cfg> la;
+  la.Pf = a.Pf + ((size_t)s * 3 + c) * fpp + (size_t)(2 * jf0) * w;
+  la.kszf = a.kszf + (size_t)jf0 * a.nhp;
   la.z = a.z[a.z0 + zi] + a.zoff[s];
-  la.ld = a.np;
-  KMajorLoader<Cfg, Cfg::BN> lb;
-  lb.src = a.AyT + col0;
+  la.w = w;
+  la.nhp = a.nhp;
+  RKMajorLoader<Cfg, Cfg::BN> lb;
+  lb.src = a.B1 + col0;
   lb.ld = a.nyp;
 
-  // The pupil is zero outside the disk (2j+1-n)^2 + (2l+1-n)^2 <= n^2: this row block only
-  // needs the columns l that its row nearest the centre reaches.
-  int k_begin = 0, k_end = a.np;
+  // The pupil is zero outside the disk (2j+1-n)^2 + (2l+1-n)^2 <= n^2: this row block
+  // needs the folded columns lf that its row nearest the centre (largest jf) reaches.
+  int k_begin = 0, k_end = w;
   {
-    const int n = a.n;
-    const int r_lo = row0, r_hi = min(row0 + Cfg::BM, n) - 1;
-    if (r_lo >= n) {
+    const int n = a.n, nh = (a.n + 1) / 2;
+    const int jf_hi = min(jf0 + Cfg::BM / 4, nh) - 1;
+    if (jf_hi < jf0) {
       k_end = Cfg::BK;   // padding rows only: one (zero) stage
     } else {
-      const int u_lo = 2 * r_lo + 1 - n, u_hi = 2 * r_hi + 1 - n;
-      const int umin = (u_lo <= 0 && u_hi >= 0) ? 0 : min(abs(u_lo), abs(u_hi));
+      const int umin = abs(2 * jf_hi + 1 - n);
       const int vmax = (int)floorf(sqrtf((float)n * n - (float)umin * umin)) + 1;   // generous
-      const int l_lo = max(0, (n - 1 - vmax) / 2), l_hi = min(n - 1, (n - 1 + vmax) / 2 + 1);
-      k_begin = (l_lo / Cfg::BK) * Cfg::BK;
-      k_end = min(a.np, (l_hi / Cfg::BK + 1) * Cfg::BK);
+      const int lf_lo = max(0, (n - 1 - vmax) / 2);
+      k_begin = (2 * lf_lo / Cfg::BK) * Cfg::BK;
     }
   }
-  CgAcc<Cfg> acc;
+  RgAcc<Cfg> acc;
   acc.zero();
-  cg_mainloop<Cfg>(acc, la, lb, k_begin, k_end, lds, tid, wrow, wcol, lane);
+  rg_mainloop<Cfg>(acc, la, lb, k_begin, k_end, lds, tid, wrow, wcol, lane);
 
-  float2* T = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)a.np * a.nyp;
+  // rows 2q + ri: registers r and r + 1 (r even) are the re/im parts of one T[q][n]
+  float2* T = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)w * a.nyp;
 #pragma unroll
   for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
     for (int jj = 0; jj < Cfg::TN; ++jj) {
-      const int col = col0 + cg_col(wcol, jj, lane);
+      const int col = col0 + rg_col(wcol, jj, lane);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = row0 + cg_row(wrow, i, r, lane);
-        T[(size_t)row * a.nyp + col] = make_float2(acc.re[i][jj][r], acc.im[i][jj][r]);
+      for (int r = 0; r < 16; r += 2) {
+        const int q = (row0 + rg_row(wrow, i, r, lane)) >> 1;
+        T[(size_t)q * a.nyp + col] = make_float2(acc.c[i][jj][r], acc.c[i][jj][r + 1]);
       }
     }
 }
 
-// K3: E[s][z][c] = Ax T[s][z][c] for c = 0..2 and I = sum_c |E_c|^2
-__global__ void __launch_bounds__(CfgImage::NT, RW_IMAGE_OCC) gemm_image_kernel(Gemm2Args a) {
+// K3: E'[m][(n, ri)] = sum_kk A2[m][kk] T[kk][(n, ri)] with A2[m][2jf] = pref cos(k s_jf x_m),
+// A2[m][2jf+1] = pref sin(...) for c = x, y, z in one workgroup; E = -i E' and
+// I = sum_c |E_c|^2 are written from registers.
+__global__ void __launch_bounds__(CfgImage::NT, RW_F2_OCC) gemm_image_kernel(Gemm2Args a) {
   using Cfg = CfgImage;
   extern __shared__ float lds[];
+  const int w = 2 * a.nhp;
   const int tiles_m = a.nxp / Cfg::BM;
-  const int tiles_n = a.nyp / Cfg::BN;
+  const int tiles_n = 2 * a.nyp / Cfg::BN;
   const int nblocks = a.nstk * a.nzs * tiles_m * tiles_n;
   int id = xcd_remap(blockIdx.x, nblocks);
   const int tn = id % tiles_n; id /= tiles_n;
@@ -233,6 +326,7 @@ __global__ void __launch_bounds__(CfgImage::NT, RW_IMAGE_OCC) gemm_image_kernel(
   const size_t plane = (size_t)a.nx * a.ny;
   const size_t gstk = (size_t)(a.s_base + s), gz = (size_t)(a.z0 + zi);
   const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
+  const int ri = lane & 1;   // columns alternate re/im with the lane index
 
   float isum[Cfg::TM][Cfg::TN][16];
 #pragma unroll
@@ -244,28 +338,30 @@ __global__ void __launch_bounds__(CfgImage::NT, RW_IMAGE_OCC) gemm_image_kernel(
 
 #pragma unroll 1
   for (int c = 0; c < 3; ++c) {
-    KMajorLoader<Cfg, Cfg::BM> la;
-    la.src = a.AxT + row0;
+    RKMajorLoader<Cfg, Cfg::BM> la;
+    la.src = a.A2T + row0;
     la.ld = a.nxp;
-    KMajorLoader<Cfg, Cfg::BN> lb;
-    lb.src = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)a.np * a.nyp + col0;
-    lb.ld = a.nyp;
-    CgAcc<Cfg> acc;
+    RKMajorLoader<Cfg, Cfg::BN> lb;
+    lb.src = reinterpret_cast<const float*>(a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)w * a.nyp) + col0;
+    lb.ld = 2 * a.nyp;
+    RgAcc<Cfg> acc;
     acc.zero();
-    cg_mainloop<Cfg>(acc, la, lb, a.np, lds, tid, wrow, wcol, lane);
+    rg_mainloop<Cfg>(acc, la, lb, 0, w, lds, tid, wrow, wcol, lane);
 
-    float2* E = a.E ? a.E + ((gstk * a.nz + gz) * 3 + c) * plane : nullptr;
+    // E = -i E': the lane holding Re E' writes -Re E' as Im E, the lane holding Im E'
+    // writes it as Re E (32 lanes cover 16 consecutive complex values of a row)
+    float* E = a.E ? reinterpret_cast<float*>(a.E + ((gstk * a.nz + gz) * 3 + c) * plane) : nullptr;
 #pragma unroll
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
       for (int jj = 0; jj < Cfg::TN; ++jj) {
-        const int col = col0 + cg_col(wcol, jj, lane);
+        const int n = (col0 + rg_col(wcol, jj, lane)) >> 1;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int row = row0 + cg_row(wrow, i, r, lane);
-          const float er = acc.re[i][jj][r], ei = acc.im[i][jj][r];
-          isum[i][jj][r] += er * er + ei * ei;
-          if (E && row < a.nx && col < a.ny) E[(size_t)row * a.ny + col] = make_float2(er, ei);
+          const int m = row0 + rg_row(wrow, i, r, lane);
+          const float v = acc.c[i][jj][r];
+          isum[i][jj][r] += v * v;
+          if (E && m < a.nx && n < a.ny) E[2 * ((size_t)m * a.ny + n) + (1 - ri)] = ri ? v : -v;
         }
       }
   }
@@ -275,11 +371,12 @@ __global__ void __launch_bounds__(CfgImage::NT, RW_IMAGE_OCC) gemm_image_kernel(
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
       for (int jj = 0; jj < Cfg::TN; ++jj) {
-        const int col = col0 + cg_col(wcol, jj, lane);
+        const int n = (col0 + rg_col(wcol, jj, lane)) >> 1;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int row = row0 + cg_row(wrow, i, r, lane);
-          if (row < a.nx && col < a.ny) I[(size_t)row * a.ny + col] = isum[i][jj][r];
+          const float tot = isum[i][jj][r] + __shfl_xor(isum[i][jj][r], 1);
+          const int m = row0 + rg_row(wrow, i, r, lane);
+          if (!ri && m < a.nx && n < a.ny) I[(size_t)m * a.ny + n] = tot;
         }
       }
   }
@@ -302,9 +399,15 @@ hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* 
   return hipGetLastError();
 }
 
+hipError_t launch_pupil_fold(const FoldArgs& a, hipStream_t st) {
+  const int cells = a.nhp * a.nhp;
+  hipLaunchKernelGGL(pupil_fold_kernel, dim3((cells + 255) / 256), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
   using Cfg = CfgPupil;
-  const int tiles = (a.np / Cfg::BM) * (a.nyp / Cfg::BN);
+  const int tiles = (4 * a.nhp / Cfg::BM) * (a.nyp / Cfg::BN);
   const int nblocks = a.nstk * a.nzs * 3 * tiles;
   hipLaunchKernelGGL(gemm_pupil_kernel, dim3(nblocks), dim3(Cfg::NT), Cfg::LDS_BYTES, st, a);
   return hipGetLastError();
@@ -312,7 +415,7 @@ hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
 
 hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st) {
   using Cfg = CfgImage;
-  const int tiles = (a.nxp / Cfg::BM) * (a.nyp / Cfg::BN);
+  const int tiles = (a.nxp / Cfg::BM) * (2 * a.nyp / Cfg::BN);
   const int nblocks = a.nstk * a.nzs * tiles;
   hipLaunchKernelGGL(gemm_image_kernel, dim3(nblocks), dim3(Cfg::NT), Cfg::LDS_BYTES, st, a);
   return hipGetLastError();

@@ -5,8 +5,10 @@
 // disk mask (2j+1-N)^2 + (2l+1-N)^2 <= N^2 decided in integers:
 //   Q_c[j,l]  = ds^2 a(s) e_inf,c(s) / s_z          (complex64, 0 outside the disk)
 //   ksz[j,l]  = k s_z                                (FP64, for the defocus phase)
-//   AyT[l,n]  = exp(i k s_y[l] y_n)                  (complex64)
-//   AxT[j,m]  = -(i f k / 2 pi) exp(i k s_x[j] x_m)  (complex64, prefactor folded in)
+// and of the folded transforms (jf, lf < nh = ceil(N/2), the mirror-symmetric half):
+//   kszf[jf,lf]   = k s_z                            (FP64)
+//   B1[2lf][n]    = cos(k s_y[lf] y_n),  B1[2lf+1][n] = sin(k s_y[lf] y_n)
+//   A2T[2jf][m]   = pref cos(k s_x[jf] x_m),  A2T[2jf+1][m] = pref sin(...),  pref = f k / 2 pi
 // with x_m = (m - nx/2) dx, y_n = (n - ny/2) dy.
 #include <algorithm>
 #include <cmath>
@@ -49,44 +51,51 @@ static int fourier_plan_init(rwpsf_plan* p) {
         Q[c * npp + cell] = make_float2((float)(w * e[c].real()), (float)(w * e[c].imag()));
       ksz[cell] = k * cos_t;
     }
-  std::vector<float2> AyT((size_t)np * nyp, make_float2(0.f, 0.f)), AxT((size_t)np * nxp, make_float2(0.f, 0.f));
+  const int nh = (N + 1) / 2, nhp = round_up(nh, kFoldPad), w = 2 * nhp;
+  p->nhp = nhp;
+  std::vector<double> kszf((size_t)nhp * nhp, 0.0);
+  for (int jf = 0; jf < nh; ++jf)
+    for (int lf = 0; lf < nh; ++lf) kszf[(size_t)jf * nhp + lf] = ksz[(size_t)jf * np + lf];
+  std::vector<float> B1((size_t)w * nyp, 0.f), A2T((size_t)w * nxp, 0.f);
   const double pref = p->opt.focal_length * k / kTwoPi;  // C = -i pref
-  for (int l = 0; l < N; ++l) {
-    const double sy = (2.0 * l + 1.0 - N) * s_max / N;
+  for (int lf = 0; lf < nh; ++lf) {
+    const double sy = (2.0 * lf + 1.0 - N) * s_max / N;
     for (int n = 0; n < ny; ++n) {
-      const double y = (double)(n - ny / 2) * p->grid.dy_nm;
-      const double ph = k * sy * y;
-      AyT[(size_t)l * nyp + n] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+      const double ph = k * sy * (double)(n - ny / 2) * p->grid.dy_nm;
+      B1[(size_t)(2 * lf) * nyp + n] = (float)std::cos(ph);
+      B1[(size_t)(2 * lf + 1) * nyp + n] = (float)std::sin(ph);
     }
   }
-  for (int j = 0; j < N; ++j) {
-    const double sx = (2.0 * j + 1.0 - N) * s_max / N;
+  for (int jf = 0; jf < nh; ++jf) {
+    const double sx = (2.0 * jf + 1.0 - N) * s_max / N;
     for (int m = 0; m < nx; ++m) {
-      const double x = (double)(m - nx / 2) * p->grid.dx_nm;
-      const double ph = k * sx * x;
-      // -i pref (cos + i sin) = pref (sin - i cos)
-      AxT[(size_t)j * nxp + m] = make_float2((float)(pref * std::sin(ph)), (float)(-pref * std::cos(ph)));
+      const double ph = k * sx * (double)(m - nx / 2) * p->grid.dx_nm;
+      A2T[(size_t)(2 * jf) * nxp + m] = (float)(pref * std::cos(ph));
+      A2T[(size_t)(2 * jf + 1) * nxp + m] = (float)(pref * std::sin(ph));
     }
   }
   int st;
   if ((st = dev_alloc(p, &p->d_Q, 3 * npp))) return st;
   if ((st = dev_alloc(p, &p->d_ksz, npp))) return st;
-  if ((st = dev_alloc(p, &p->d_AyT, (size_t)np * nyp))) return st;
-  if ((st = dev_alloc(p, &p->d_AxT, (size_t)np * nxp))) return st;
+  if ((st = dev_alloc(p, &p->d_kszf, kszf.size()))) return st;
+  if ((st = dev_alloc(p, &p->d_B1, B1.size()))) return st;
+  if ((st = dev_alloc(p, &p->d_A2T, A2T.size()))) return st;
   if ((st = dev_alloc(p, &p->d_ztab, (size_t)RWPSF_MAX_ZERNIKE * N * N))) return st;
   if ((st = dev_alloc(p, &p->d_z, (size_t)p->grid.nz))) return st;
   p->P_stacks = kPupilStacks;
   if ((st = dev_alloc(p, &p->d_P, (size_t)p->P_stacks * 3 * npp))) return st;
+  if ((st = dev_alloc(p, &p->d_Pf, (size_t)p->P_stacks * 3 * w * w))) return st;
   // plane workspace: whole chunk of stacks x planes, capped at 512 MiB
-  const size_t plane_bytes = 3 * (size_t)np * nyp * sizeof(float2);
+  const size_t plane_bytes = 3 * (size_t)w * nyp * sizeof(float2);
   const size_t want = (size_t)kPupilStacks * p->grid.nz;
   p->T_planes = std::max<size_t>(1, std::min(want, (size_t)(512u << 20) / plane_bytes));
-  if ((st = dev_alloc(p, &p->d_T, p->T_planes * 3 * (size_t)np * nyp))) return st;
+  if ((st = dev_alloc(p, &p->d_T, p->T_planes * 3 * (size_t)w * nyp))) return st;
 
   if ((st = hip_check(hipMemcpy(p->d_Q, Q.data(), Q.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
   if ((st = hip_check(hipMemcpy(p->d_ksz, ksz.data(), ksz.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
-  if ((st = hip_check(hipMemcpy(p->d_AyT, AyT.data(), AyT.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
-  if ((st = hip_check(hipMemcpy(p->d_AxT, AxT.data(), AxT.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_kszf, kszf.data(), kszf.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_B1, B1.data(), B1.size() * sizeof(float), hipMemcpyHostToDevice)))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_A2T, A2T.data(), A2T.size() * sizeof(float), hipMemcpyHostToDevice)))) return st;
   if ((st = hip_check(hipMemcpy(p->d_z, p->z.data(), p->z.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
   if ((st = hip_check(launch_zernike_table(p->d_ztab, N, RWPSF_MAX_ZERNIKE, 0)))) return st;
   if ((st = hip_check(fourier_kernel_attributes()))) return st;
@@ -148,99 +157,78 @@ int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_
 }
 
 // --------------------------------------------------------------------------
-// Fourier dispatch: chunks of up to 8 stacks (pupil build), then slabs of
+// Fourier dispatch: chunks of up to 8 stacks (pupil build + fold), then slabs of
 // stack-planes through the two GEMM kernels.
 // --------------------------------------------------------------------------
+static int fourier_gemms(rwpsf_plan* p, int s_local, int ns, const double* zoff, int s_global, int z0, int nzs,
+                         float2* E, float* I, hipStream_t st) {
+  const int w = 2 * p->nhp;
+  Gemm1Args g1{};
+  g1.Pf = p->d_Pf + (size_t)s_local * 3 * w * w;
+  g1.kszf = p->d_kszf;
+  g1.z = p->d_z;
+  g1.B1 = p->d_B1;
+  g1.T = p->d_T;
+  for (int i = 0; i < ns; ++i) g1.zoff[i] = zoff[i];
+  g1.n = p->num.n_pupil;
+  g1.nhp = p->nhp;
+  g1.nyp = p->nyp;
+  g1.nstk = ns;
+  g1.z0 = z0;
+  g1.nzs = nzs;
+  int tr = p->time_begin(RWPSF_KERNEL_GEMM_PUPIL, st);
+  int rc = hip_check(launch_gemm_pupil(g1, st));
+  if (rc) return rc;
+  p->time_end(tr, st);
+  Gemm2Args g2{};
+  g2.A2T = p->d_A2T;
+  g2.T = p->d_T;
+  g2.E = E;
+  g2.I = I;
+  g2.nhp = p->nhp;
+  g2.nxp = p->nxp;
+  g2.nyp = p->nyp;
+  g2.nx = p->grid.nx;
+  g2.ny = p->grid.ny;
+  g2.nz = p->grid.nz;
+  g2.nstk = ns;
+  g2.s_base = s_global;
+  g2.z0 = z0;
+  g2.nzs = nzs;
+  tr = p->time_begin(RWPSF_KERNEL_GEMM_IMAGE, st);
+  if ((rc = hip_check(launch_gemm_image(g2, st)))) return rc;
+  p->time_end(tr, st);
+  return RWPSF_OK;
+}
+
 int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
   int cur = -1;
   hipGetDevice(&cur);
   if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
-  const int N = p->num.n_pupil, nz = p->grid.nz;
-  const size_t npp = (size_t)p->np * p->np;
+  const int nz = p->grid.nz;
   for (int b0 = 0; b0 < n; b0 += kPupilStacks) {
     const int nb = std::min(kPupilStacks, n - b0);
     int rc = fourier_build_pupils(p, s + b0, nb, st);
     if (rc) return rc;
-    int tr = -1;
+    FoldArgs fa{p->d_P, p->d_Pf, p->num.n_pupil, p->np, p->nhp, nb};
+    int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
+    if ((rc = hip_check(launch_pupil_fold(fa, st)))) return rc;
+    p->time_end(tr, st);
+    double zoff[kPupilStacks];
+    for (int i = 0; i < nb; ++i) zoff[i] = s[b0 + i].z_offset_nm;
     // slabs over (stack, plane): a slab is a run of planes of one or more stacks
     const size_t cap = p->T_planes;
     if ((size_t)nz <= cap) {
       const int stk_per = (int)std::min<size_t>(nb, cap / nz);
       for (int s0 = 0; s0 < nb; s0 += stk_per) {
         const int ns = std::min(stk_per, nb - s0);
-        Gemm1Args g1{};
-        g1.P = p->d_P + (size_t)s0 * 3 * npp;
-        g1.ksz = p->d_ksz;
-        g1.z = p->d_z;
-        g1.AyT = p->d_AyT;
-        g1.T = p->d_T;
-        for (int i = 0; i < ns; ++i) g1.zoff[i] = s[b0 + s0 + i].z_offset_nm;
-        g1.n = N;
-        g1.np = p->np;
-        g1.nyp = p->nyp;
-        g1.nstk = ns;
-        g1.z0 = 0;
-        g1.nzs = nz;
-        tr = p->time_begin(RWPSF_KERNEL_GEMM_PUPIL, st);
-        if ((rc = hip_check(launch_gemm_pupil(g1, st)))) return rc;
-        p->time_end(tr, st);
-        Gemm2Args g2{};
-        g2.AxT = p->d_AxT;
-        g2.T = p->d_T;
-        g2.E = E;
-        g2.I = I;
-        g2.np = p->np;
-        g2.nxp = p->nxp;
-        g2.nyp = p->nyp;
-        g2.nx = p->grid.nx;
-        g2.ny = p->grid.ny;
-        g2.nz = nz;
-        g2.nstk = ns;
-        g2.s_base = b0 + s0;
-        g2.z0 = 0;
-        g2.nzs = nz;
-        tr = p->time_begin(RWPSF_KERNEL_GEMM_IMAGE, st);
-        if ((rc = hip_check(launch_gemm_image(g2, st)))) return rc;
-        p->time_end(tr, st);
+        if ((rc = fourier_gemms(p, s0, ns, zoff + s0, b0 + s0, 0, nz, E, I, st))) return rc;
       }
     } else {
       for (int i = 0; i < nb; ++i)
         for (int z0 = 0; z0 < nz; z0 += (int)cap) {
           const int nzs = (int)std::min<size_t>(cap, nz - z0);
-          Gemm1Args g1{};
-          g1.P = p->d_P + (size_t)i * 3 * npp;
-          g1.ksz = p->d_ksz;
-          g1.z = p->d_z;
-          g1.AyT = p->d_AyT;
-          g1.T = p->d_T;
-          g1.zoff[0] = s[b0 + i].z_offset_nm;
-          g1.n = N;
-          g1.np = p->np;
-          g1.nyp = p->nyp;
-          g1.nstk = 1;
-          g1.z0 = z0;
-          g1.nzs = nzs;
-          tr = p->time_begin(RWPSF_KERNEL_GEMM_PUPIL, st);
-        if ((rc = hip_check(launch_gemm_pupil(g1, st)))) return rc;
-        p->time_end(tr, st);
-          Gemm2Args g2{};
-          g2.AxT = p->d_AxT;
-          g2.T = p->d_T;
-          g2.E = E;
-          g2.I = I;
-          g2.np = p->np;
-          g2.nxp = p->nxp;
-          g2.nyp = p->nyp;
-          g2.nx = p->grid.nx;
-          g2.ny = p->grid.ny;
-          g2.nz = nz;
-          g2.nstk = 1;
-          g2.s_base = b0 + i;
-          g2.z0 = z0;
-          g2.nzs = nzs;
-          tr = p->time_begin(RWPSF_KERNEL_GEMM_IMAGE, st);
-        if ((rc = hip_check(launch_gemm_image(g2, st)))) return rc;
-        p->time_end(tr, st);
+          if ((rc = fourier_gemms(p, i, 1, zoff + i, b0 + i, z0, nzs, E, I, st))) return rc;
         }
     }
   }

@@ -153,11 +153,14 @@ struct rwpsf_plan {
   double* d_z = nullptr;        // [nz]
   double* d_ksz = nullptr;      // [np][np] k * s_z (0 outside the disk)
   float2* d_Q = nullptr;        // [3][np][np] ds^2 a e_inf,c / s_z (0 outside)
-  float2* d_AyT = nullptr;      // [np][nyp] exp(i k s_y[l] y_n)
-  float2* d_AxT = nullptr;      // [np][nxp] C exp(i k s_x[j] x_m), C = -i f k / 2 pi
+  int nhp = 0;                  // folded pupil cells per axis, padded (2 nhp = np)
+  double* d_kszf = nullptr;     // [nhp][nhp] k * s_z on the folded cells
+  float* d_B1 = nullptr;        // [2 nhp][nyp] cos / sin (k s_y[lf] y_n)
+  float* d_A2T = nullptr;       // [2 nhp][nxp] pref cos / sin (k s_x[jf] x_m), pref = f k / 2 pi
   float* d_ztab = nullptr;      // [RWPSF_MAX_ZERNIKE][N][N] Noll basis on the pupil cells
   float2* d_P = nullptr;        // workspace [chunk][3][np][np]
-  float2* d_T = nullptr;        // workspace [planes][3][np][nyp]
+  float2* d_Pf = nullptr;       // workspace [chunk][3][2 nhp][2 nhp] folded pupils
+  float2* d_T = nullptr;        // workspace [planes][3][2 nhp][nyp]
   size_t T_planes = 0;          // capacity of d_T in stack-planes
   // adjoint (built on first use)
   float2* d_AxH = nullptr;      // [nxp][np] conj of the prefactor-scaled x DFT, k-major in x

@@ -21,31 +21,39 @@ struct PupilArgs {
 };
 
 // Device operands are zero-padded: np = n rounded up to 64, nxp = nx rounded up
-// to 64, nyp = ny rounded up to 128.
+// to 64, nyp = ny rounded up to 128, and the folded pupil axis nh = ceil(n/2) to
+// nhp = nh rounded up to 32 (so 2 nhp = np).
+struct FoldArgs {
+  const float2* P;     // [nstk][3][np][np] base pupils
+  float2* Pf;          // [nstk][3][2 nhp][2 nhp] folded pupils
+  int n, np, nhp, nstk;
+};
+
 struct Gemm1Args {
-  const float2* P;     // [nstk][3][np][np]
-  const double* ksz;   // [np][np]
+  const float2* Pf;    // [nstk][3][2 nhp][2 nhp]
+  const double* kszf;  // [nhp][nhp] k s_z on the folded cells
   const double* z;     // plan planes
-  const float2* AyT;   // [np][nyp]
-  float2* T;           // [nstk][nzs][3][np][nyp]
+  const float* B1;     // [2 nhp][nyp] cos / sin (k s_y[lf] y_n)
+  float2* T;           // [nstk][nzs][3][2 nhp][nyp]
   double zoff[kPupilStacks];
-  int n, np, nyp, nstk, z0, nzs;   // n: pupil cells per axis
+  int n, nhp, nyp, nstk, z0, nzs;   // n: pupil cells per axis
 };
 
 struct Gemm2Args {
-  const float2* AxT;   // [np][nxp]
-  const float2* T;     // [nstk][nzs][3][np][nyp]
+  const float* A2T;    // [2 nhp][nxp] pref cos / sin (k s_x[jf] x_m)
+  const float2* T;     // [nstk][nzs][3][2 nhp][nyp]
   float2* E;           // [stacks][nz][3][nx][ny] or null
   float* I;            // [stacks][nz][nx][ny] or null
-  int np, nxp, nyp, nx, ny, nz, nstk, s_base, z0, nzs;
+  int nhp, nxp, nyp, nx, ny, nz, nstk, s_base, z0, nzs;
 };
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
-constexpr int kPadPupil = 64, kPadX = 64, kPadY = 128;
+constexpr int kPadPupil = 64, kPadX = 64, kPadY = 128, kFoldPad = 32;
 
 hipError_t launch_zernike_table(float* out, int n, int nj, hipStream_t st);
 hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* ztab, float2* P,
                               hipStream_t st);
+hipError_t launch_pupil_fold(const FoldArgs& a, hipStream_t st);
 hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st);
 hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st);
 hipError_t fourier_kernel_attributes();
