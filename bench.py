@@ -247,6 +247,7 @@ def bench_surrogate(rw, torch, train_seconds):
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     acc = {p: ST.judge(sg, eng, test, precision=p) for p in (rw.SG_BF16X3, rw.SG_BF16)}
+    base = ST.mean_crop_baseline(train, test)
     B = 65536
     coef, z = train["coef"][:B].contiguous(), train["z"][:B].contiguous()
     out = torch.empty((B, 64, 64), dtype=torch.float32, device="cuda")
@@ -270,6 +271,7 @@ def bench_surrogate(rw, torch, train_seconds):
                 speedup_vs_plain=dict(bf16=ms_plain / res["bf16"]["ms_per_batch"],
                                       bf16x3=ms_plain / res["bf16x3"]["ms_per_batch"]),
                 accuracy_vs_plain=dict(bf16x3=acc[rw.SG_BF16X3], bf16=acc[rw.SG_BF16]),
+                mean_crop_predictor=base, train_ms_per_step=train_s * 1e3 / steps,
                 train_steps=steps)
 
 

@@ -205,7 +205,7 @@ struct FoldDefocusLoader {
 #define RW_F1_BN 128
 #endif
 #ifndef RW_F1_BK
-#define RW_F1_BK 32
+#define RW_F1_BK 16
 #endif
 #ifndef RW_F1_WM
 #define RW_F1_WM 64
@@ -214,22 +214,22 @@ struct FoldDefocusLoader {
 #define RW_F1_WN 64
 #endif
 #ifndef RW_F1_OCC
-#define RW_F1_OCC 2
+#define RW_F1_OCC 4
 #endif
 #ifndef RW_F2_BM
-#define RW_F2_BM 64
+#define RW_F2_BM 128
 #endif
 #ifndef RW_F2_BN
-#define RW_F2_BN 128
+#define RW_F2_BN 64
 #endif
 #ifndef RW_F2_BK
 #define RW_F2_BK 32
 #endif
 #ifndef RW_F2_WM
-#define RW_F2_WM 32
+#define RW_F2_WM 64
 #endif
 #ifndef RW_F2_WN
-#define RW_F2_WN 64
+#define RW_F2_WN 32
 #endif
 #ifndef RW_F2_OCC
 #define RW_F2_OCC 3
@@ -348,9 +348,13 @@ __global__ void __launch_bounds__(CfgImage::NT, RW_F2_OCC) gemm_image_kernel(Gem
     acc.zero();
     rg_mainloop<Cfg>(acc, la, lb, 0, w, lds, tid, wrow, wcol, lane);
 
-    // E = -i E': the lane holding Re E' writes -Re E' as Im E, the lane holding Im E'
-    // writes it as Re E (32 lanes cover 16 consecutive complex values of a row)
-    float* E = a.E ? reinterpret_cast<float*>(a.E + ((gstk * a.nz + gz) * 3 + c) * plane) : nullptr;
+    // Lanes 2t and 2t+1 hold Re E' and Im E' of one pixel; a DPP swap within lane pairs
+    // gives the even lane both, and it writes E = -i E' = (Im E', -Re E') as one float2.
+    float2* E = a.E ? a.E + ((gstk * a.nz + gz) * 3 + c) * plane : nullptr;
+    // the store offsets are the same for every component; keeping them opaque here stops
+    // them from being hoisted out of the component loop (32 live offsets would spill)
+    int mbase = row0 + rg_row(wrow, 0, 0, lane);
+    asm volatile("" : "+v"(mbase));
 #pragma unroll
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
@@ -358,10 +362,11 @@ __global__ void __launch_bounds__(CfgImage::NT, RW_F2_OCC) gemm_image_kernel(Gem
         const int n = (col0 + rg_col(wcol, jj, lane)) >> 1;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int m = row0 + rg_row(wrow, i, r, lane);
+          const int m = mbase + 32 * i + (r >> 2) * 8 + (r & 3);
           const float v = acc.c[i][jj][r];
-          isum[i][jj][r] += v * v;
-          if (E && m < a.nx && n < a.ny) E[2 * ((size_t)m * a.ny + n) + (1 - ri)] = ri ? v : -v;
+          const float u = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+          isum[i][jj][r] += v * v + u * u;
+          if (E && !ri && m < a.nx && n < a.ny) E[m * a.ny + n] = make_float2(u, -v);
         }
       }
   }
@@ -374,9 +379,8 @@ __global__ void __launch_bounds__(CfgImage::NT, RW_F2_OCC) gemm_image_kernel(Gem
         const int n = (col0 + rg_col(wcol, jj, lane)) >> 1;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const float tot = isum[i][jj][r] + __shfl_xor(isum[i][jj][r], 1);
           const int m = row0 + rg_row(wrow, i, r, lane);
-          if (!ri && m < a.nx && n < a.ny) I[(size_t)m * a.ny + n] = tot;
+          if (!ri && m < a.nx && n < a.ny) I[m * a.ny + n] = isum[i][jj][r];
         }
       }
   }

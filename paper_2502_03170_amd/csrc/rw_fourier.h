@@ -21,7 +21,7 @@ struct PupilArgs {
 };
 
 // Device operands are zero-padded: np = n rounded up to 64, nxp = nx rounded up
-// to 64, nyp = ny rounded up to 128, and the folded pupil axis nh = ceil(n/2) to
+// to 128, nyp = ny rounded up to 128, and the folded pupil axis nh = ceil(n/2) to
 // nhp = nh rounded up to 32 (so 2 nhp = np).
 struct FoldArgs {
   const float2* P;     // [nstk][3][np][np] base pupils
@@ -48,7 +48,7 @@ struct Gemm2Args {
 };
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
-constexpr int kPadPupil = 64, kPadX = 64, kPadY = 128, kFoldPad = 32;
+constexpr int kPadPupil = 64, kPadX = 128, kPadY = 128, kFoldPad = 32;
 
 hipError_t launch_zernike_table(float* out, int n, int nj, hipStream_t st);
 hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* ztab, float2* P,

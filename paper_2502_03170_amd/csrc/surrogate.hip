@@ -238,40 +238,51 @@ __global__ void __launch_bounds__(256) sg_deconv_bwd_data_kernel(const float* __
   }
 }
 
-// Per chunk of samples: partial dK[ci, co, ky, kx] and dbias[co] (fixed order inside the chunk).
+// Per chunk of samples: partial dK[ci, co, ky, kx] and dbias[co], summed over the chunk's
+// samples in order.  Each sample's input and output gradient are staged in LDS; every
+// thread owns a fixed set of parameters and keeps their sums in LDS.
 __global__ void __launch_bounds__(256) sg_deconv_bwd_weight_kernel(const float* __restrict__ in,
                                                                     const float* __restrict__ dout, int B,
                                                                     int chunk, int Ci, int Co, int H,
                                                                     float* __restrict__ partial) {
-  const int HO = 2 * H, np = Ci * Co * 16;
+  extern __shared__ float sh[];
+  const int HO = 2 * H, np = Ci * Co * 16, nin = Ci * H * H, nout = Co * HO * HO;
+  float* xs = sh;                  // [Ci][H][H]
+  float* gs = sh + nin;            // [Co][HO][HO]
+  float* accs = gs + nout;         // [np + Co]
   const int b0 = blockIdx.x * chunk, b1 = min(B, b0 + chunk);
-  float* dst = partial + (size_t)blockIdx.x * (np + Co);
-  for (int p = threadIdx.x; p < np + Co; p += 256) {
-    double s = 0.0;
-    if (p < np) {
-      const int ci = p / (Co * 16), co = (p / 16) % Co, ky = (p / 4) % 4, kx = p % 4;
-      for (int b = b0; b < b1; ++b) {
-        const float* x = in + ((size_t)b * Ci + ci) * H * H;
-        const float* g = dout + ((size_t)b * Co + co) * HO * HO;
-        for (int iy = 0; iy < H; ++iy) {
-          const int oy = 2 * iy - 1 + ky;
-          if (oy < 0 || oy >= HO) continue;
-          for (int ix = 0; ix < H; ++ix) {
-            const int ox = 2 * ix - 1 + kx;
-            if (ox < 0 || ox >= HO) continue;
-            s += (double)x[iy * H + ix] * g[oy * HO + ox];
-          }
+  for (int p = threadIdx.x; p < np + Co; p += 256) accs[p] = 0.f;
+  for (int b = b0; b < b1; ++b) {
+    __syncthreads();
+    const float* xsrc = in + (size_t)b * nin;
+    const float* gsrc = dout + (size_t)b * nout;
+    for (int i = threadIdx.x; i < nin; i += 256) xs[i] = xsrc[i];
+    for (int i = threadIdx.x; i < nout; i += 256) gs[i] = gsrc[i];
+    __syncthreads();
+    for (int p = threadIdx.x; p < np + Co; p += 256) {
+      float s = 0.f;
+      if (p < np) {
+        const int ci = p / (Co * 16), co = (p / 16) % Co, ky = (p / 4) % 4, kx = p % 4;
+        const float* x = xs + ci * H * H;
+        const float* g = gs + co * HO * HO;
+        // output rows oy = 2 iy - 1 + ky inside [0, HO): iy from (1 - ky + 1) / 2 when ky = 0
+        const int iy0 = ky == 0 ? 1 : 0, iy1 = ky == 3 ? H - 1 : H;
+        const int ix0 = kx == 0 ? 1 : 0, ix1 = kx == 3 ? H - 1 : H;
+        for (int iy = iy0; iy < iy1; ++iy) {
+          const float* xr = x + iy * H;
+          const float* gr = g + (2 * iy - 1 + ky) * HO - 1 + kx;
+          for (int ix = ix0; ix < ix1; ++ix) s += xr[ix] * gr[2 * ix];
         }
-      }
-    } else {
-      const int co = p - np;
-      for (int b = b0; b < b1; ++b) {
-        const float* g = dout + ((size_t)b * Co + co) * HO * HO;
+      } else {
+        const float* g = gs + (p - np) * HO * HO;
         for (int i = 0; i < HO * HO; ++i) s += g[i];
       }
+      accs[p] += s;
     }
-    dst[p] = (float)s;
   }
+  __syncthreads();
+  float* dst = partial + (size_t)blockIdx.x * (np + Co);
+  for (int p = threadIdx.x; p < np + Co; p += 256) dst[p] = accs[p];
 }
 
 // sum partials [chunks][n] in chunk order
@@ -317,7 +328,7 @@ Layout layout() {
   L.total = o;
   return L;
 }
-constexpr int kChunk = 16;   // samples per partial sum of the convolution weight gradients
+constexpr int kMaxChunks = 256;   // partial sums of the convolution weight gradients per step
 }  // namespace
 
 struct rwpsf_sg {
@@ -381,14 +392,16 @@ static int sg_backward_impl(rwpsf_sg* s, int B, const float* target, float* loss
     hipLaunchKernelGGL(sg_sum_kernel, dim3(1), dim3(64), 0, st, s->loss_partial, lb, 1.0 / (double)ny, loss);
     if ((rc = hip_check(hipGetLastError()))) return rc;
   }
-  const int chunks = (B + kChunk - 1) / kChunk;
+  const int chunk = (B + kMaxChunks - 1) / kMaxChunks;   // samples per partial sum
+  const int chunks = (B + chunk - 1) / chunk;
   struct Conv { float *in, *gin, *gout; int Ci, Co, H; size_t K, c; bool relu_in; };
   const Conv convs[3] = {{s->d2, s->gd2, s->gy, 8, 1, 32, L.K3, L.c3, true},
                          {s->d1, s->gd1, s->gd2, 16, 8, 16, L.K2, L.c2, true},
                          {s->h3, s->g3, s->gd1, 32, 16, 8, L.K1, L.c1, true}};
   for (const Conv& c : convs) {
     const int np = c.Ci * c.Co * 16;
-    hipLaunchKernelGGL(sg_deconv_bwd_weight_kernel, dim3(chunks), dim3(256), 0, st, c.in, c.gout, B, kChunk, c.Ci,
+    const int lds = (c.Ci * c.H * c.H + c.Co * 4 * c.H * c.H + np + c.Co) * 4;
+    hipLaunchKernelGGL(sg_deconv_bwd_weight_kernel, dim3(chunks), dim3(256), lds, st, c.in, c.gout, B, chunk, c.Ci,
                        c.Co, c.H, s->partial);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     hipLaunchKernelGGL(sg_reduce_partials_kernel, dim3((np + c.Co + 255) / 256), dim3(256), 0, st, s->partial, chunks,
@@ -440,7 +453,7 @@ int rwpsf_sg_create(int max_batch, rwpsf_sg** out) {
   s->max_batch = max_batch;
   s->L = layout();
   const size_t P = s->L.total, B = (size_t)max_batch;
-  const int chunks = (max_batch + kChunk - 1) / kChunk;
+  const int chunks = std::min(max_batch, kMaxChunks);
   int rc;
   if ((rc = sg_alloc(s, &s->w, P)) || (rc = sg_alloc(s, &s->g, P)) || (rc = sg_alloc(s, &s->m, P)) ||
       (rc = sg_alloc(s, &s->v, P)) || (rc = sg_alloc(s, &s->x, B * 22)) || (rc = sg_alloc(s, &s->h1, B * 256)) ||

@@ -60,9 +60,10 @@ def make_dataset(eng: CropEngine, n: int, seed: int):
     return dict(coef=coef, z=z, target=eng.crops(coef, z).contiguous())
 
 
-def init_params(seed: int, out_scale: float = 0.05, bias: float = 0.01) -> np.ndarray:
-    """He-normal weights, slightly positive biases (live relus) and a small output layer
-    (the targets are O(1e-2) per pixel), flat in the library's parameter order."""
+def init_params(seed: int, out_scale: float = 0.01, bias: float = 0.1) -> np.ndarray:
+    """He-normal weights, positive biases (live relus) and a small output layer (the
+    targets are O(1e-2) per pixel; a larger first output makes the first Adam steps
+    drive the decoder relus dead for some seeds), flat in the library's parameter order."""
     rng = np.random.default_rng(seed)
     parts = []
     for a, b in ((22, 256), (256, 1024), (1024, 2048)):
@@ -76,9 +77,10 @@ def init_params(seed: int, out_scale: float = 0.05, bias: float = 0.01) -> np.nd
 
 
 def train(sg: rw.Surrogate, data: dict, steps: int, batch: int, lr: float, seed: int, log_every: int = 50,
-          eps: float = 1e-10, lr_end: float | None = None):
-    """Adam steps on random mini-batches; the learning rate follows a cosine from lr to
-    lr_end (constant when lr_end is None).  Returns the logged losses."""
+          eps: float = 1e-10, lr_end: float | None = None, warmup: int = 100):
+    """Adam steps on random mini-batches; the learning rate ramps up linearly over the
+    first ``warmup`` steps and follows a cosine from lr to lr_end (constant when lr_end
+    is None).  Returns the logged losses."""
     import torch
     n = data["coef"].shape[0]
     gen = torch.Generator(device="cuda")
@@ -90,6 +92,8 @@ def train(sg: rw.Surrogate, data: dict, steps: int, batch: int, lr: float, seed:
         sg.gradient(data["coef"][idx].contiguous(), data["z"][idx].contiguous(),
                     data["target"][idx].contiguous(), loss=loss)
         rate = lr if lr_end is None else lr_end + 0.5 * (lr - lr_end) * (1 + math.cos(math.pi * step / steps))
+        if step < warmup:
+            rate *= (step + 1) / warmup
         sg.adam(rate, eps=eps)
         if step % log_every == 0 or step == steps - 1:
             hist.append(float(loss.item()))
@@ -111,6 +115,14 @@ def judge(sg: rw.Surrogate, eng: CropEngine, data: dict, precision: int = rw.SG_
     e = rel_l2_per_crop(pred, data["target"]).cpu().numpy()
     return dict(median_rel_l2=float(np.median(e)), p95_rel_l2=float(np.percentile(e, 95)),
                 max_rel_l2=float(e.max()), n=int(B))
+
+
+def mean_crop_baseline(train: dict, test: dict):
+    """rel-L2 on the test crops of the best input-independent prediction (the mean
+    training crop): the level a network that ignores its inputs would reach."""
+    mean = train["target"].mean(0, keepdim=True)
+    e = rel_l2_per_crop(mean.expand_as(test["target"]), test["target"]).cpu().numpy()
+    return dict(median_rel_l2=float(np.median(e)), p95_rel_l2=float(np.percentile(e, 95)))
 
 
 def out_of_distribution(coef, z):

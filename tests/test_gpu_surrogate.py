@@ -143,9 +143,12 @@ def test_surrogate_training_reduces_error_and_judge(lib):
     hist = ST.train(sg, train, steps=1500, batch=256, lr=2e-3, lr_end=1e-4, seed=0)
     assert hist[-1] < 0.5 * hist[0], (hist[0], hist[-1])
     rep = ST.judge(sg, eng, test)
-    # a learned approximation: the bar is that training removes most of the error of the
-    # untrained network (the absolute accuracy is reported by the benchmark, not pinned)
-    assert rep["median_rel_l2"] < 0.8 and rep["median_rel_l2"] < 0.8 * before["median_rel_l2"], (before, rep)
+    base = ST.mean_crop_baseline(train, test)
+    # a learned approximation: the bar is that the trained network uses its inputs -- it
+    # beats the best input-independent prediction (the mean training crop) by a clear
+    # margin (the absolute accuracy after a longer run is reported by the benchmark)
+    assert rep["median_rel_l2"] < 0.85 * base["median_rel_l2"], (before, rep, base)
+    assert rep["median_rel_l2"] < 0.5 * before["median_rel_l2"], (before, rep)
     # out-of-distribution inputs go to the plain path and match it exactly
     coef = test["coef"][:4].clone()
     coef[0, 5] = 1.0                 # 20 sigma
