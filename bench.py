@@ -98,7 +98,7 @@ def bench_bessel(rw, torch, steps, warmup, n_stacks=256):
     o = w["optics"]
     plan = rw.Plan(form=rw.FORM_BESSEL, na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], nx=65,
                    ny=65, dx=20.0, dy=20.0, z=w["z"], e_inc=w["e_inc"], n_theta=200, n_rho=256)
-    stacks = [dict(z_offset=float(v)) for v in w["z_offsets"]]
+    stacks = rw.Stacks([dict(z_offset=float(v)) for v in w["z_offsets"]])   # marshalled once
     nz = len(w["z"])
     E = torch.empty((n_stacks, nz, 3, 65, 65), dtype=torch.complex64, device="cuda")
     I = torch.empty((n_stacks, nz, 65, 65), dtype=torch.float32, device="cuda")
@@ -191,8 +191,8 @@ def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
                    dx=w["dx"], dy=w["dy"], z=w["z"], e_inc=w["e_inc"], n_pupil=n)
     rng = np.random.default_rng(404)
     w0 = torch.tensor(w["w0_eval"], dtype=torch.float32, device="cuda")
-    st = [dict(x0=rng.uniform(-50, 50), y0=rng.uniform(-50, 50), z_offset=rng.uniform(-200, 200),
-               zernike=w["c_eval"], phase_map=w0) for _ in range(n_stacks)]
+    st = rw.Stacks([dict(x0=rng.uniform(-50, 50), y0=rng.uniform(-50, 50), z_offset=rng.uniform(-200, 200),
+                         zernike=w["c_eval"], phase_map=w0) for _ in range(n_stacks)])
     E = torch.empty((n_stacks, nz, 3, nx, nx), dtype=torch.complex64, device="cuda")
     I = torch.empty((n_stacks, nz, nx, nx), dtype=torch.float32, device="cuda")
     Y = torch.rand_like(I)
@@ -213,8 +213,8 @@ def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
                                           ("adj_reduce", rw.KERNEL_ADJ_REDUCE))}
     plan.close()
     comp = n_stacks * nz * 3
-    fwd = comp * 8.0 * (n * n * nx + nx * n * nx)
-    adj = comp * 8.0 * (nx * nx * n + n * nx * n)
+    fwd = comp * 4.0 * (n * n * nx + nx * n * nx)     # folded real GEMMs
+    adj = comp * 8.0 * (nx * nx * n + n * nx * n)     # complex GEMMs of the adjoint
     ach = (fwd + adj) / (ms * 1e-3) / 1e12
     vox = n_stacks * nz * nx * nx
     return dict(workload=f"adjoint: {n_stacks} stacks of {nx}x{nx}x{nz} at 100 nm, 256x256 pupil, shared Noll "

@@ -202,6 +202,24 @@ def make_stacks(stacks: list[dict]):
     return arr, keep
 
 
+class Stacks:
+    """A list of stack dicts marshalled once into an rwpsf_stack array, for calls that
+    repeat with the same stacks (the marshalling of many stacks costs host time)."""
+
+    def __init__(self, stacks: list[dict]):
+        self.arr, self.keep = make_stacks(stacks)
+        self.n = len(stacks)
+
+    def __len__(self):
+        return self.n
+
+
+def _marshal(stacks):
+    if isinstance(stacks, Stacks):
+        return stacks.arr, stacks.keep
+    return make_stacks(stacks)
+
+
 # ---------------------------------------------------------------- ABI mirrors
 def validate(optics: Optics, grid: Grid, num: Numerics) -> int:
     return load().rwpsf_validate(byref(optics), byref(grid), byref(num))
@@ -254,9 +272,10 @@ def plan_timing(handle, kernel: int):
 
 
 def compute(handle, stacks: list[dict], E=None, I=None, stream=None) -> None:
-    """Enqueue rwpsf_compute; E (complex64) and I (float32) are CUDA tensors or None."""
+    """Enqueue rwpsf_compute; E (complex64) and I (float32) are CUDA tensors or None.
+    ``stacks`` is a list of dicts or a ``Stacks``."""
     import torch
-    arr, _keep = make_stacks(stacks)
+    arr, _keep = _marshal(stacks)
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     for t, dt in ((E, torch.complex64), (I, torch.float32)):
@@ -267,9 +286,10 @@ def compute(handle, stacks: list[dict], E=None, I=None, stream=None) -> None:
 
 
 def adjoint(handle, stacks: list[dict], E, dL_dI, n_zernike: int, dL_dc=None, dL_dW0=None, stream=None):
-    """Enqueue rwpsf_adjoint (E complex64, dL_dI float32, outputs float32; CUDA tensors)."""
+    """Enqueue rwpsf_adjoint (E complex64, dL_dI float32, outputs float32; CUDA tensors).
+    ``stacks`` is a list of dicts or a ``Stacks``."""
     import torch
-    arr, _keep = make_stacks(stacks)
+    arr, _keep = _marshal(stacks)
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
     for t in (E, dL_dI, dL_dc, dL_dW0):
