@@ -170,7 +170,7 @@ def bench_batched(rw, torch, steps, warmup):
     S = w["S"].astype(np.float64)
     D = w["D"].astype(np.float64)
     n = w["n_pupil"]
-    flops = float(np.sum(D * 3 * 8.0 * S * n * (n + S)))     # U = Ax_S P~, E = U Ay_S^T per plane
+    flops = float(np.sum(D * 3 * 4.0 * S * n * (n + S)))     # folded: U = A2_S Pf~, E' = U B1_S per plane
     ach = flops / (ms * 1e-3) / 1e12
     return dict(workload="batched: 4096 emitters, crops U{24..64}, planes U{1..41}, 128x128 pupil, "
                          "Noll 4-21 N(0,0.04), sub-pixel x0/y0, intensity only, one persistent launch "

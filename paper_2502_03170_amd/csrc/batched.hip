@@ -7,13 +7,16 @@
 //   Phi_b[j,l] = 2 pi sum_q c_bq Z_q(s) - k (s_x x0_b + s_y y0_b)
 // formed for all emitters at once by one real GEMM on the matrix cores,
 //   Phi[b][cell] = sum_k coef[k][b] basis[k][cell],  basis = (2 pi Z_1..Z_21, s_x, s_y).
-// Each plane d of each field component c is then, with P~ = Q_c exp(i (Phi_b + k s_z z)),
-//   U = Ax_S P~          (S x N, P~ generated in registers as the MFMA B operand)
-//   E = U Ay_S^T         (S x S, U staged in LDS as the A operand)
-// and I = sum_c |E_c|^2.  Ax_S / Ay_S are the rows of one 96-row DFT table that
-// cover the crop (pixel i of an S-crop is table row i - S/2 + 32).  A workgroup
-// takes whole emitters from an atomic counter over a cost-sorted (longest first)
-// list until the list is exhausted; every workgroup exits when the counter passes n.
+// The cell-centred grids are mirror-symmetric, so each emitter's pupil is folded once
+// (four parities per folded cell, written to the workgroup's scratch slot) and each
+// plane d of each field component c is two real-coefficient GEMMs on the matrix cores,
+//   U  = A2_S (Dz o Pf_c)   (S x N; the defocus Dz of the plane is shared by the three
+//                            components and the four mirror cells)
+//   E' = U B1_S             (S x S, U staged in LDS as the A operand),  E = -i E'
+// and I = sum_c |E_c|^2.  A2_S / B1_S are the rows of one 96-row table that cover the
+// crop (pixel i of an S-crop is table row i - S/2 + 32).  A workgroup takes whole
+// emitters from an atomic counter over a cost-sorted (longest first) list until the
+// list is exhausted; every workgroup exits when the counter passes n.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -38,6 +41,10 @@ typedef float f16v_t __attribute__((ext_vector_type(16)));
 
 constexpr int kTabRows = 96;    // DFT table rows: x_r = (r - 32) * pixel
 constexpr int kBasisRows = 32;  // 21 Zernike + s_x + s_y, zero-padded
+constexpr int kMaxWgPerCu = 4;  // workgroups per CU of the persistent launch (configuration bound)
+constexpr int kBK = 16;                       // k-stage of the staged pupil GEMM
+constexpr int kLdaU = 64 + 4, kLdbU = 128 + 4;  // LDS row strides of its A (crop rows) and B (columns)
+constexpr int kStageU = kBK * (kLdaU + 2 * kLdbU);
 
 struct BatchParam {
   double zoff;      // -z_e
@@ -46,179 +53,306 @@ struct BatchParam {
 };
 
 struct BatchArgs {
-  const BatchParam* params;  // [n] cost-sorted
+  const BatchParam* params;  // [n] cost-sorted (slot order)
   const float2* Q;           // [3][N][N]
   const double* ksz;         // [N][N]
   const float* phi;          // [n][N*N], slot order
-  const float2* AxT;         // [N][96]
-  const float2* AyT;         // [N][96]
+  const float* A2T;          // [N][96] rows 2jf + pj: pref cos / sin (k s_x[jf] x_r)
+  const float* B1T;          // [N][96] rows 2lf + pl: cos / sin (k s_y[lf] y_r)
+  float2* Pf;                // [n][3][N][N] folded pupils, slot order
+  float2* Dz;                // per workgroup [N/2][N/2] defocus factors of its current plane
+  const int* list;           // [n] slots grouped by XCD queue
+  const long long* pre;      // [n + 1] plane prefix sums over list
+  const int* qoff;           // [9] queue x owns list[qoff[x] .. qoff[x+1])
+  unsigned long long* counter;   // [8] next item of each queue
   float* I;
   float2* E;
-  int* counter;
   int n, N;
   double pitch;
 };
 
-__global__ void batch_reset_kernel(int* counter) { *counter = 0; }
+// Each queue's counter starts at its first item (a kernel, not a memset, so that the
+// launch sequence can be captured in a graph).
+__global__ void batch_reset_kernel(unsigned long long* counter, const long long* pre, const int* qoff) {
+  const int x = threadIdx.x;
+  if (x < 8) counter[x] = (unsigned long long)pre[qoff[x]];
+}
+
+// Folded pupil of every emitter (one workgroup per emitter).  The pupil and pixel grids
+// are mirror-symmetric (s[N-1-j] = -s[j]); with P = Q_c exp(i Phi) at the four mirror
+// cells of (jf, lf),
+//   Pf_{pj,pl}[jf][lf] = i^(pj+pl) sum_{a,b} (-1)^(a pj + b pl) P[mir_a(jf)][mir_b(lf)],
+// stored at Pf[c][2jf + pj][2lf + pl].
+__global__ void __launch_bounds__(256) batch_fold_kernel(BatchArgs a) {
+  const int slot = blockIdx.x;
+  const int N = a.N, NN = N * N, nh = N / 2;
+  const float* phi = a.phi + (size_t)slot * NN;
+  float2* Pf = a.Pf + (size_t)slot * 3 * NN;
+  for (int cell = threadIdx.x; cell < nh * nh; cell += 256) {
+    const int jf = cell / nh, lf = cell % nh, j1 = N - 1 - jf, l1 = N - 1 - lf;
+    const int idx[4] = {jf * N + lf, jf * N + l1, j1 * N + lf, j1 * N + l1};
+    float er[4], ei[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sincosf(phi[idx[q]], &ei[q], &er[q]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float pr[4], pi[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float2 v = a.Q[(size_t)c * NN + idx[q]];
+        pr[q] = v.x * er[q] - v.y * ei[q];
+        pi[q] = v.x * ei[q] + v.y * er[q];
+      }
+      float2* o = Pf + (size_t)c * NN + (size_t)(2 * jf) * N + 2 * lf;
+      // (pj, pl) = (0,0): +,+,+,+   (0,1): i(+,-,+,-)   (1,0): i(+,+,-,-)   (1,1): -(+,-,-,+)
+      o[0] = make_float2(pr[0] + pr[1] + pr[2] + pr[3], pi[0] + pi[1] + pi[2] + pi[3]);
+      o[1] = make_float2(-(pi[0] - pi[1] + pi[2] - pi[3]), pr[0] - pr[1] + pr[2] - pr[3]);
+      o[N] = make_float2(-(pi[0] + pi[1] - pi[2] - pi[3]), pr[0] + pr[1] - pr[2] - pr[3]);
+      o[N + 1] = make_float2(-(pr[0] - pr[1] - pr[2] + pr[3]), -(pi[0] - pi[1] - pi[2] + pi[3]));
+    }
+  }
+}
 
 // MFMA 32x32x2 f32: A lane l -> A[l%32][l/32], B lane l -> B[l/32][l%32],
 // C register r of lane l -> C[8(r/4) + 4(l/32) + r%4][l%32].
+//
+// Plane d of emitter `slot`:  U = A2 (Dz o Pf_c)  (real x complex),  E' = U B1
+// (complex x real),  E = -i E',  I = sum_c |E_c|^2, with the defocus Dz[jf][lf] =
+// exp(i k s_z z) shared by the three components and the four mirror cells.
 template <int SP>
-__device__ __forceinline__ void batch_emitter(const BatchArgs& a, const BatchParam& bp, int slot,
-                                              float* lds, int tid) {
+__device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam& bp, int slot, int d,
+                                            float* lds, int tid, float2* __restrict__ Dz) {
   constexpr int TI = SP / 32;
   constexpr int LDU = SP + 1;
   const int lane = tid & 63, w = tid >> 6, h = lane >> 5, l32 = lane & 31;
-  const int N = a.N, NN = N * N, S = bp.S;
+  const int N = a.N, NN = N * N, nh = N / 2, S = bp.S;
   const int r0 = 32 - S / 2;
-  const float* phi = a.phi + (size_t)slot * NN;
+  const float2* Pf = a.Pf + (size_t)slot * 3 * NN;
   float* Ure = lds;
   float* Uim = lds + N * LDU;
-  for (int d = 0; d < bp.D; ++d) {
-    const double z = (d - 0.5 * (bp.D - 1)) * a.pitch + bp.zoff;
-    float isum64[16];   // SP = 64: this wave's 32x32 block of E, MFMA C layout
-    float isum32[4];    // SP = 32: elements tid + 256 q of the 32x32 image
+  const double z = (d - 0.5 * (bp.D - 1)) * a.pitch + bp.zoff;
+  // ---- defocus of this plane on the folded cells (FP64 phase, reduced mod 2 pi)
+  for (int cell = tid; cell < nh * nh; cell += 256) {
+    const int jf = cell / nh, lf = cell % nh;
+    float sn, cs;
+    sincosf((float)reduce_2pi(a.ksz[jf * N + lf] * z), &sn, &cs);
+    Dz[cell] = make_float2(cs, sn);
+  }
+  // the defocus table was written by other waves of this workgroup
+  __threadfence();
+  __syncthreads();
+  float isum64[16];   // SP = 64: this wave's 32x32 block of E, MFMA C layout
+  float isum32[4];    // SP = 32: elements tid + 256 q of the 32x32 image
 #pragma unroll
-    for (int r = 0; r < 16; ++r) isum64[r] = 0.f;
+  for (int r = 0; r < 16; ++r) isum64[r] = 0.f;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) isum32[q] = 0.f;
-    for (int c = 0; c < 3; ++c) {
-      const float2* Qc = a.Q + (size_t)c * NN;
-      // ---- U[m][l] = sum_j Ax[r0 + m][j] P~[j][l], this wave's 32-column blocks of l
-      for (int lb = w; lb < N / 32; lb += 4) {
-        f16v_t ur[TI], ui[TI];
+  for (int q = 0; q < 4; ++q) isum32[q] = 0.f;
+  for (int c = 0; c < 3; ++c) {
+    const float2* Pc = Pf + (size_t)c * NN;
+    // ---- U[m][col] = sum_k A2[r0 + m][k] (Dz o Pf)[k][col]: k-stages of A2 rows and of the
+    // defocused folded pupil (re / im planes) staged in LDS, double-buffered; wave w owns
+    // columns 32 w .. 32 w + 31
+    {
+      float ra[4];      // A prefetch: BK x SP floats, up to 4 per thread
+      float4 rp[4];     // B prefetch: BK x N/2 float4, up to 4 per thread
+      float2 rd[4];
+      const int na = kBK * SP / 256, nb = kBK * (N / 2) / 256;
+      auto load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-          for (int r = 0; r < 16; ++r) {
-            ur[i][r] = 0.f;
-            ui[i][r] = 0.f;
+        for (int i = 0; i < 4; ++i)
+          if (i < na) {
+            const int idx = tid + 256 * i, kk = idx / SP, m = idx % SP;
+            ra[i] = a.A2T[(k0 + kk) * kTabRows + r0 + m];
           }
-        const int l = 32 * lb + l32;
-#pragma unroll 4
-        for (int kp = 0; kp < N / 2; ++kp) {
-          const int j = 2 * kp + h;
-          const int cell = j * N + l;
-          const float2 q = Qc[cell];
-          float sn, cs;
-          sincosf(phi[cell] + (float)reduce_2pi(a.ksz[cell] * z), &sn, &cs);
-          const float br = q.x * cs - q.y * sn, bi = q.x * sn + q.y * cs;
 #pragma unroll
-          for (int i = 0; i < TI; ++i) {
-            const float2 av = a.AxT[j * kTabRows + r0 + 32 * i + l32];
-            ur[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, br, ur[i], 0, 0, 0);
-            ui[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.x, bi, ui[i], 0, 0, 0);
+        for (int i = 0; i < 4; ++i)
+          if (i < nb) {
+            const int idx = tid + 256 * i, kk = idx / (N / 2), c2 = idx % (N / 2);
+            rp[i] = *reinterpret_cast<const float4*>(Pc + (size_t)(k0 + kk) * N + 2 * c2);
+            rd[i] = Dz[((k0 + kk) >> 1) * nh + c2];
+          }
+      };
+      auto store = [&](float* st) {
+        float* sa = st;
+        float* sr = st + kBK * kLdaU;
+        float* si = sr + kBK * kLdbU;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (i < na) {
+            const int idx = tid + 256 * i, kk = idx / SP, m = idx % SP;
+            sa[kk * kLdaU + m] = ra[i];
           }
 #pragma unroll
-          for (int i = 0; i < TI; ++i) {
-            const float2 av = a.AxT[j * kTabRows + r0 + 32 * i + l32];
-            ur[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(-av.y, bi, ur[i], 0, 0, 0);
-            ui[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(av.y, br, ui[i], 0, 0, 0);
+        for (int i = 0; i < 4; ++i)
+          if (i < nb) {
+            const int idx = tid + 256 * i, kk = idx / (N / 2), c2 = idx % (N / 2);
+            const float2 dz = rd[i];
+            *reinterpret_cast<float2*>(sr + kk * kLdbU + 2 * c2) =
+                make_float2(rp[i].x * dz.x - rp[i].y * dz.y, rp[i].z * dz.x - rp[i].w * dz.y);
+            *reinterpret_cast<float2*>(si + kk * kLdbU + 2 * c2) =
+                make_float2(rp[i].x * dz.y + rp[i].y * dz.x, rp[i].z * dz.y + rp[i].w * dz.x);
+          }
+      };
+      f16v_t ur[TI], ui[TI];
+#pragma unroll
+      for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          ur[i][r] = 0.f;
+          ui[i][r] = 0.f;
+        }
+      const bool has_cols = 32 * w < N;
+      const int KT = N / kBK;
+      load(0);
+      store(lds);
+      __syncthreads();
+      for (int kt = 0; kt < KT; ++kt) {
+        float* cur = lds + (kt & 1) * kStageU;
+        float* nxt = lds + ((kt + 1) & 1) * kStageU;
+        const bool more = kt + 1 < KT;
+        if (more) load((kt + 1) * kBK);
+        if (has_cols) {
+          const float* sa = cur;
+          const float* sr = cur + kBK * kLdaU;
+          const float* si = sr + kBK * kLdbU;
+#pragma unroll
+          for (int kp = 0; kp < kBK / 2; ++kp) {
+            const int kk = 2 * kp + h;
+            const float br = sr[kk * kLdbU + 32 * w + l32], bi = si[kk * kLdbU + 32 * w + l32];
+#pragma unroll
+            for (int i = 0; i < TI; ++i) {
+              const float av = sa[kk * kLdaU + 32 * i + l32];
+              ur[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, br, ur[i], 0, 0, 0);
+              ui[i] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bi, ui[i], 0, 0, 0);
+            }
           }
         }
+        if (more) store(nxt);
+        __syncthreads();
+      }
+      // U overwrites the stage buffers: every wave has passed the last barrier above
+      if (has_cols) {
+        const int col = 32 * w + l32;
 #pragma unroll
         for (int i = 0; i < TI; ++i)
 #pragma unroll
           for (int r = 0; r < 16; ++r) {
             const int m = 32 * i + 8 * (r >> 2) + 4 * h + (r & 3);
-            Ure[l * LDU + m] = ur[i][r];
-            Uim[l * LDU + m] = ui[i][r];
+            Ure[col * LDU + m] = ur[i][r];
+            Uim[col * LDU + m] = ui[i][r];
           }
-      }
-      __syncthreads();
-      // ---- E[m][n] = sum_l U[m][l] Ay[r0 + n][l]
-      f16v_t er, ei;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        er[r] = 0.f;
-        ei[r] = 0.f;
-      }
-      const int mi = (SP == 64) ? (w >> 1) : 0, ni = (SP == 64) ? (w & 1) : 0;
-      const int kp0 = (SP == 64) ? 0 : w * 16;               // SP = 32: K split over the waves
-      const int kp1 = (SP == 64) ? N / 2 : min(N / 2, w * 16 + 16);
-#pragma unroll 4
-      for (int kp = kp0; kp < kp1; ++kp) {
-        const int l = 2 * kp + h;
-        const float ar = Ure[l * LDU + 32 * mi + l32], ai = Uim[l * LDU + 32 * mi + l32];
-        const float2 b = a.AyT[l * kTabRows + r0 + 32 * ni + l32];
-        er = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b.x, er, 0, 0, 0);
-        ei = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b.y, ei, 0, 0, 0);
-        er = __builtin_amdgcn_mfma_f32_32x32x2f32(-ai, b.y, er, 0, 0, 0);
-        ei = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b.x, ei, 0, 0, 0);
-      }
-      __syncthreads();   // U is consumed
-      if (SP == 64) {
-        float2* Ec = a.E ? a.E + 3 * bp.off + ((size_t)(d * 3 + c) * S) * S : nullptr;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = 32 * mi + 8 * (r >> 2) + 4 * h + (r & 3), n = 32 * ni + l32;
-          isum64[r] += er[r] * er[r] + ei[r] * ei[r];
-          if (Ec && m < S && n < S) Ec[m * S + n] = make_float2(er[r], ei[r]);
-        }
-      } else {
-        // reduce the four K-partials through LDS (the U area is free now)
-        float* pre = lds + w * 2 * 32 * 33;
-        float* pim = pre + 32 * 33;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = 8 * (r >> 2) + 4 * h + (r & 3);
-          pre[m * 33 + l32] = er[r];
-          pim[m * 33 + l32] = ei[r];
-        }
-        __syncthreads();
-        float2* Ec = a.E ? a.E + 3 * bp.off + ((size_t)(d * 3 + c) * S) * S : nullptr;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = tid + 256 * q, m = e >> 5, n = e & 31;
-          float sr = 0.f, si = 0.f;
-#pragma unroll
-          for (int ww = 0; ww < 4; ++ww) {
-            sr += lds[ww * 2 * 32 * 33 + m * 33 + n];
-            si += lds[ww * 2 * 32 * 33 + 32 * 33 + m * 33 + n];
-          }
-          isum32[q] += sr * sr + si * si;
-          if (Ec && m < S && n < S) Ec[m * S + n] = make_float2(sr, si);
-        }
-        __syncthreads();
       }
     }
-    if (a.I) {
-      float* Ip = a.I + bp.off + (size_t)d * S * S;
-      if (SP == 64) {
-        const int mi = w >> 1, ni = w & 1;
+    __syncthreads();
+    // ---- E'[m][n] = sum_col U[m][col] B1[col][r0 + n]
+    f16v_t er, ei;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = 32 * mi + 8 * (r >> 2) + 4 * h + (r & 3), n = 32 * ni + l32;
-          if (m < S && n < S) Ip[m * S + n] = isum64[r];
-        }
-      } else {
+    for (int r = 0; r < 16; ++r) {
+      er[r] = 0.f;
+      ei[r] = 0.f;
+    }
+    const int mi = (SP == 64) ? (w >> 1) : 0, ni = (SP == 64) ? (w & 1) : 0;
+    const int kp1a = (SP == 64) ? 0 : w * (N / 8);               // SP = 32: K split over the waves
+    const int kp1b = (SP == 64) ? N / 2 : (w + 1) * (N / 8);
+#pragma unroll 4
+    for (int kp = kp1a; kp < kp1b; ++kp) {
+      const int kk = 2 * kp + h;
+      const float ar = Ure[kk * LDU + 32 * mi + l32], ai = Uim[kk * LDU + 32 * mi + l32];
+      const float b = a.B1T[kk * kTabRows + r0 + 32 * ni + l32];
+      er = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b, er, 0, 0, 0);
+      ei = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b, ei, 0, 0, 0);
+    }
+    __syncthreads();   // U is consumed
+    // E = -i E' = (Im E', -Re E')
+    if (SP == 64) {
+      float2* Ec = a.E ? a.E + 3 * bp.off + ((size_t)(d * 3 + c) * S) * S : nullptr;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = tid + 256 * q, m = e >> 5, n = e & 31;
-          if (m < S && n < S) Ip[m * S + n] = isum32[q];
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * mi + 8 * (r >> 2) + 4 * h + (r & 3), n = 32 * ni + l32;
+        isum64[r] += er[r] * er[r] + ei[r] * ei[r];
+        if (Ec && m < S && n < S) Ec[m * S + n] = make_float2(ei[r], -er[r]);
+      }
+    } else {
+      // reduce the four K-partials through LDS (the U area is free now)
+      float* pre = lds + w * 2 * 32 * 33;
+      float* pim = pre + 32 * 33;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 8 * (r >> 2) + 4 * h + (r & 3);
+        pre[m * 33 + l32] = er[r];
+        pim[m * 33 + l32] = ei[r];
+      }
+      __syncthreads();
+      float2* Ec = a.E ? a.E + 3 * bp.off + ((size_t)(d * 3 + c) * S) * S : nullptr;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q, m = e >> 5, n = e & 31;
+        float sr = 0.f, si = 0.f;
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+          sr += lds[ww * 2 * 32 * 33 + m * 33 + n];
+          si += lds[ww * 2 * 32 * 33 + 32 * 33 + m * 33 + n];
         }
+        isum32[q] += sr * sr + si * si;
+        if (Ec && m < S && n < S) Ec[m * S + n] = make_float2(si, -sr);
+      }
+      __syncthreads();
+    }
+  }
+  if (a.I) {
+    float* Ip = a.I + bp.off + (size_t)d * S * S;
+    if (SP == 64) {
+      const int mi = w >> 1, ni = w & 1;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = 32 * mi + 8 * (r >> 2) + 4 * h + (r & 3), n = 32 * ni + l32;
+        if (m < S && n < S) Ip[m * S + n] = isum64[r];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + 256 * q, m = e >> 5, n = e & 31;
+        if (m < S && n < S) Ip[m * S + n] = isum32[q];
       }
     }
   }
+  __syncthreads();   // every wave is done with Dz and the LDS before the next item
 }
 
 constexpr int kBatchLdsBytes = 2 * 128 * 65 * 4;   // U for N <= 128, SP = 64
 
+// Persistent plane kernel.  Workgroup ids are dealt round-robin over the 8 XCDs, so
+// workgroup b serves queue b % 8: the (emitter, plane) items of the emitters assigned to
+// that queue, in order, so that the planes of one emitter run at the same time on one
+// XCD and its folded pupil is read from that XCD's L2.  A workgroup exits when its
+// queue is exhausted; the grid has at least 8 workgroups, one per queue.
 __global__ void __launch_bounds__(256, 2) batch_planes_kernel(BatchArgs a) {
   extern __shared__ float lds[];
-  __shared__ int item;
+  __shared__ long long item;
   const int tid = threadIdx.x;
+  const int x = blockIdx.x & 7;
+  const int lo = a.qoff[x], hi = a.qoff[x + 1];
+  const long long end = a.pre[hi];
+  float2* Dz = a.Dz + (size_t)blockIdx.x * (a.N * a.N / 4);
   for (;;) {
-    if (tid == 0) item = atomicAdd(a.counter, 1);
+    if (tid == 0) item = (long long)atomicAdd(&a.counter[x], 1ull);
     __syncthreads();
-    const int slot = item;
+    const long long it = item;
     __syncthreads();
-    if (slot >= a.n) break;
+    if (it >= end) break;
+    // emitter e of the queue with pre[e] <= it < pre[e + 1]
+    int e0 = lo, e1 = hi - 1;
+    while (e0 < e1) {
+      const int mid = (e0 + e1 + 1) >> 1;
+      if (a.pre[mid] <= it) e0 = mid; else e1 = mid - 1;
+    }
+    const int slot = a.list[e0];
+    const int d = (int)(it - a.pre[e0]);
     const BatchParam bp = a.params[slot];
     if (bp.SP == 32)
-      batch_emitter<32>(a, bp, slot, lds, tid);
+      batch_plane<32>(a, bp, slot, d, lds, tid, Dz);
     else
-      batch_emitter<64>(a, bp, slot, lds, tid);
+      batch_plane<64>(a, bp, slot, d, lds, tid, Dz);
   }
 }
 
@@ -235,12 +369,15 @@ struct rwpsf_batch {
   std::vector<void*> allocations;
   float2* d_Q = nullptr;
   double* d_ksz = nullptr;
-  float2* d_AxT = nullptr;
-  float2* d_AyT = nullptr;
+  float* d_A2T = nullptr;       // [N][96] folded x table (prefactor included)
+  float* d_B1T = nullptr;       // [N][96] folded y table
+  float2* d_pf = nullptr;       // [max][3][N][N] folded pupils
+  float2* d_dz = nullptr;       // per workgroup [N/2][N/2] defocus table
+  long long items = 0;          // (emitter, plane) items of the staged call
   float* d_basis = nullptr;
   float* d_phi = nullptr;
   char* d_upload = nullptr;     // params [max] then coefT [32][max_pad]
-  int* d_counter = nullptr;
+  unsigned long long* d_counter = nullptr;   // [8] queue counters
   char* h_staging = nullptr;    // pinned mirror of d_upload
   size_t upload_bytes = 0;
   int max_pad = 0;
@@ -294,7 +431,17 @@ static int balloc(rwpsf_batch* b, T** p, size_t count) {
   return RWPSF_OK;
 }
 
-// Fill the pinned staging area (cost-sorted params and the coefficient matrix).
+// Upload block: params [max] | coefT [32][max_pad] | list [max] | pre [max + 1] | qoff [9]
+static size_t off_coef(const rwpsf_batch* b) { return sizeof(BatchParam) * b->max_emitters; }
+static size_t off_list(const rwpsf_batch* b) { return off_coef(b) + sizeof(float) * kBasisRows * b->max_pad; }
+static size_t off_pre(const rwpsf_batch* b) {
+  return (off_list(b) + sizeof(int) * b->max_emitters + 7) / 8 * 8;
+}
+static size_t off_qoff(const rwpsf_batch* b) { return off_pre(b) + sizeof(long long) * (b->max_emitters + 1); }
+static size_t upload_size(const rwpsf_batch* b) { return off_qoff(b) + sizeof(int) * 9; }
+
+// Fill the pinned staging area: cost-sorted params, the coefficient matrix, and the
+// eight (emitter, plane) queues (emitters dealt longest first to the least-loaded queue).
 static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
   std::vector<long long> off(n + 1, 0);
   for (int i = 0; i < n; ++i) off[i + 1] = off[i] + (long long)e[i].planes * e[i].crop * e[i].crop;
@@ -304,7 +451,7 @@ static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
   auto cost = [&](int i) { return (double)e[i].planes * sp_of(i) * (b->N + sp_of(i)); };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
   BatchParam* prm = (BatchParam*)b->h_staging;
-  float* coefT = (float*)(b->h_staging + sizeof(BatchParam) * b->max_emitters);
+  float* coefT = (float*)(b->h_staging + off_coef(b));
   for (int slot = 0; slot < n; ++slot) {
     const int i = order[slot];
     prm[slot].zoff = -e[i].z_nm;
@@ -321,15 +468,37 @@ static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
       coefT[(size_t)q * b->max_pad + slot] = (float)v;
     }
   }
+  std::vector<int> queue(n);
+  double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int slot = 0; slot < n; ++slot) {
+    const int x = (int)(std::min_element(load, load + 8) - load);
+    queue[slot] = x;
+    load[x] += cost(order[slot]);
+    count[x] += 1;
+  }
+  int* list = (int*)(b->h_staging + off_list(b));
+  long long* pre = (long long*)(b->h_staging + off_pre(b));
+  int* qoff = (int*)(b->h_staging + off_qoff(b));
+  qoff[0] = 0;
+  for (int x = 0; x < 8; ++x) qoff[x + 1] = qoff[x] + count[x];
+  int fill[8];
+  for (int x = 0; x < 8; ++x) fill[x] = qoff[x];
+  for (int slot = 0; slot < n; ++slot) list[fill[queue[slot]]++] = slot;
+  pre[0] = 0;
+  for (int i = 0; i < n; ++i) pre[i + 1] = pre[i] + prm[list[i]].D;
+  b->items = pre[n];
 }
 
 static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t st) {
   int rc;
   if ((rc = hip_check(hipMemcpyAsync(b->d_upload, b->h_staging, b->upload_bytes, hipMemcpyHostToDevice, st))))
     return rc;
-  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, st, b->d_counter);
+  const long long* d_pre = (const long long*)(b->d_upload + off_pre(b));
+  const int* d_qoff = (const int*)(b->d_upload + off_qoff(b));
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, b->d_counter, d_pre, d_qoff);
   if ((rc = hip_check(hipGetLastError()))) return rc;
-  const float* coefT = (const float*)(b->d_upload + sizeof(BatchParam) * b->max_emitters);
+  const float* coefT = (const float*)(b->d_upload + off_coef(b));
   const int NN = b->N * b->N;
   if ((rc = hip_check(launch_rgemm(coefT, b->max_pad, b->d_basis, NN, b->d_phi, NN, n, NN, kBasisRows, st))))
     return rc;
@@ -338,15 +507,24 @@ static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t
   a.Q = b->d_Q;
   a.ksz = b->d_ksz;
   a.phi = b->d_phi;
-  a.AxT = b->d_AxT;
-  a.AyT = b->d_AyT;
+  a.A2T = b->d_A2T;
+  a.B1T = b->d_B1T;
+  a.Pf = b->d_pf;
+  a.Dz = b->d_dz;
+  a.list = (const int*)(b->d_upload + off_list(b));
+  a.pre = d_pre;
+  a.qoff = d_qoff;
   a.I = I;
   a.E = E;
   a.counter = b->d_counter;
   a.n = n;
   a.N = b->N;
   a.pitch = b->pitch;
-  const int grid = std::max(1, std::min(n, b->num_cus * b->cfg.wg_per_cu));
+  hipLaunchKernelGGL(batch_fold_kernel, dim3(n), dim3(256), 0, st, a);
+  if ((rc = hip_check(hipGetLastError()))) return rc;
+  // at least one workgroup per queue; no more than the configured residency
+  const long long want = std::max<long long>(8, std::min<long long>(b->items, (long long)b->num_cus * b->cfg.wg_per_cu));
+  const int grid = (int)std::min<long long>(want, (long long)b->num_cus * kMaxWgPerCu);
   hipLaunchKernelGGL(batch_planes_kernel, dim3(grid), dim3(256), kBatchLdsBytes, st, a);
   return hip_check(hipGetLastError());
 }
@@ -421,25 +599,30 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
       for (int c = 0; c < 3; ++c) Q[c * NN + cell] = make_float2((float)(w * e[c].real()), (float)(w * e[c].imag()));
       ksz[cell] = b->k * cos_t;
     }
-  std::vector<float2> AxT((size_t)N * kTabRows), AyT((size_t)N * kTabRows);
+  // folded DFT tables: row 2jf + p holds cos (p = 0) or sin (p = 1) of k s[jf] x_r,
+  // x_r = (r - 32) pixel; the x table carries the prefactor f k / 2 pi (E = -i E')
+  std::vector<float> A2T((size_t)N * kTabRows), B1T((size_t)N * kTabRows);
   const double pref = o->focal_length * b->k / kTwoPi;
-  for (int j = 0; j < N; ++j) {
-    const double s = (2.0 * j + 1.0 - N) * b->s_max / N;
+  for (int jf = 0; jf < N / 2; ++jf) {
+    const double s = (2.0 * jf + 1.0 - N) * b->s_max / N;
     for (int r = 0; r < kTabRows; ++r) {
-      const double x = (r - 32) * pixel_nm;
-      const double ph = b->k * s * x;
-      AxT[(size_t)j * kTabRows + r] = make_float2((float)(pref * std::sin(ph)), (float)(-pref * std::cos(ph)));
-      AyT[(size_t)j * kTabRows + r] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+      const double ph = b->k * s * (r - 32) * pixel_nm;
+      A2T[(size_t)(2 * jf) * kTabRows + r] = (float)(pref * std::cos(ph));
+      A2T[(size_t)(2 * jf + 1) * kTabRows + r] = (float)(pref * std::sin(ph));
+      B1T[(size_t)(2 * jf) * kTabRows + r] = (float)std::cos(ph);
+      B1T[(size_t)(2 * jf + 1) * kTabRows + r] = (float)std::sin(ph);
     }
   }
   b->max_pad = (max_emitters + 63) / 64 * 64;
-  b->upload_bytes = sizeof(BatchParam) * max_emitters + sizeof(float) * kBasisRows * b->max_pad;
+  b->upload_bytes = upload_size(b);
   int rc;
   if ((rc = balloc(b, &b->d_Q, 3 * NN)) || (rc = balloc(b, &b->d_ksz, NN)) ||
-      (rc = balloc(b, &b->d_AxT, (size_t)N * kTabRows)) || (rc = balloc(b, &b->d_AyT, (size_t)N * kTabRows)) ||
+      (rc = balloc(b, &b->d_A2T, (size_t)N * kTabRows)) || (rc = balloc(b, &b->d_B1T, (size_t)N * kTabRows)) ||
+      (rc = balloc(b, &b->d_pf, (size_t)max_emitters * 3 * NN)) ||
+      (rc = balloc(b, &b->d_dz, (size_t)b->num_cus * kMaxWgPerCu * (NN / 4))) ||
       (rc = balloc(b, &b->d_basis, (size_t)kBasisRows * NN)) ||
       (rc = balloc(b, &b->d_phi, (size_t)max_emitters * NN)) || (rc = balloc(b, &b->d_upload, b->upload_bytes)) ||
-      (rc = balloc(b, &b->d_counter, 1))) {
+      (rc = balloc(b, &b->d_counter, 8))) {
     delete b;
     return rc;
   }
@@ -452,8 +635,8 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
   if ((rc = hip_check(hipEventCreateWithFlags(&b->upload_done, hipEventDisableTiming))) ||
       (rc = hip_check(hipMemcpy(b->d_Q, Q.data(), Q.size() * sizeof(float2), hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipMemcpy(b->d_ksz, ksz.data(), ksz.size() * sizeof(double), hipMemcpyHostToDevice))) ||
-      (rc = hip_check(hipMemcpy(b->d_AxT, AxT.data(), AxT.size() * sizeof(float2), hipMemcpyHostToDevice))) ||
-      (rc = hip_check(hipMemcpy(b->d_AyT, AyT.data(), AyT.size() * sizeof(float2), hipMemcpyHostToDevice))) ||
+      (rc = hip_check(hipMemcpy(b->d_A2T, A2T.data(), A2T.size() * sizeof(float), hipMemcpyHostToDevice))) ||
+      (rc = hip_check(hipMemcpy(b->d_B1T, B1T.data(), B1T.size() * sizeof(float), hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipMemcpy(b->d_basis, basis.data(), basis.size() * sizeof(float), hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipMemcpy(b->d_upload, b->h_staging, b->upload_bytes, hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipFuncSetAttribute((const void*)batch_planes_kernel,
@@ -483,7 +666,7 @@ int rwpsf_batch_set_graph(rwpsf_batch* b, int enable) {
 }
 
 int rwpsf_batch_set_config(rwpsf_batch* b, const rwpsf_batch_config* c) {
-  if (!b || !c || c->wg_per_cu < 1 || c->wg_per_cu > 4 ||
+  if (!b || !c || c->wg_per_cu < 1 || c->wg_per_cu > rw::kMaxWgPerCu ||
       (c->small_tile_max_crop != 0 && c->small_tile_max_crop != 32))
     return RWPSF_ERR_INVALID_ARG;
   b->cfg = *c;
