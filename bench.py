@@ -17,9 +17,11 @@ the timed steps), the CPU oracle timed on a bounded sample, and the other forms.
 from __future__ import annotations
 
 import argparse
+import glob
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -30,6 +32,35 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+
+
+def sources_digest() -> str:
+    """SHA-256 over the library's kernel sources (csrc/*.hip, csrc/*.h, include/*.h)."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    files = sorted(glob.glob(os.path.join(root, "paper_2502_03170_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(root, "paper_2502_03170_amd", "csrc", "*.h")) +
+                   glob.glob(os.path.join(root, "include", "*.h")))
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
+
+
+def profiled_traffic(summary: str):
+    """HBM bytes per dispatch from a committed rocprofv3 counter summary under profiles/,
+    or None when it is missing or was taken on other kernel sources."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", summary)
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    digest = re.search(r"sources sha256: ([0-9a-f]{64})", text)
+    traffic = re.search(r"HBM bytes per dispatch: ([0-9]+)", text)
+    if not digest or not traffic or digest.group(1) != sources_digest():
+        return None
+    return int(traffic.group(1))
 
 
 def fourier_workload():
@@ -84,7 +115,7 @@ def bench_fourier(rw, torch, steps, warmup):
                  for k, v in kt.items()},
         roofline=dict(kernel="gemm_pupil_kernel", bound="mfma", achieved=round(ach_g1, 3),
                       peak=PEAK_FP32_TFLOPS, unit="TFLOP/s", frac=round(ach_g1 / PEAK_FP32_TFLOPS, 4),
-                      traffic=None, flops_per_launch=per_launch_g1,
+                      traffic=profiled_traffic("gemm_pupil_fourier_plain.txt"), flops_per_launch=per_launch_g1,
                       avg_launch_us=g1_ms / g1_n * 1e3),
         image_gemm=dict(achieved_tflops=round(ach_g2, 3), frac=round(ach_g2 / PEAK_FP32_TFLOPS, 4),
                         flops_per_launch=per_launch_g2, avg_launch_us=g2_ms / g2_n * 1e3),
