@@ -181,19 +181,22 @@ struct FoldDefocusLoader {
       kz[i] = kszf[(size_t)jl * nhp + k0 / 2 + ll];
     }
   }
-  __device__ void store(float* dst, int ldl, int tid) const {
+  // LDS tile [row][k]: rows 4 jl + 2 pj + ri, columns 2 ll + pl
+  __device__ void store(float* dst, int tid) const {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
       const int jl = idx / LF, ll = idx % LF;
       float sn, cs;
       sincosf((float)reduce_2pi(kz[i] * z), &sn, &cs);
-      *reinterpret_cast<float4*>(dst + (2 * ll) * ldl + 4 * jl) =
-          make_float4(v0[i].x * cs - v0[i].y * sn, v0[i].x * sn + v0[i].y * cs, v1[i].x * cs - v1[i].y * sn,
-                      v1[i].x * sn + v1[i].y * cs);
-      *reinterpret_cast<float4*>(dst + (2 * ll + 1) * ldl + 4 * jl) =
-          make_float4(v0[i].z * cs - v0[i].w * sn, v0[i].z * sn + v0[i].w * cs, v1[i].z * cs - v1[i].w * sn,
-                      v1[i].z * sn + v1[i].w * cs);
+      float* d = dst + (4 * jl) * Cfg::LDK + 2 * ll;
+      *reinterpret_cast<float2*>(d) = make_float2(v0[i].x * cs - v0[i].y * sn, v0[i].z * cs - v0[i].w * sn);
+      *reinterpret_cast<float2*>(d + Cfg::LDK) =
+          make_float2(v0[i].x * sn + v0[i].y * cs, v0[i].z * sn + v0[i].w * cs);
+      *reinterpret_cast<float2*>(d + 2 * Cfg::LDK) =
+          make_float2(v1[i].x * cs - v1[i].y * sn, v1[i].z * cs - v1[i].w * sn);
+      *reinterpret_cast<float2*>(d + 3 * Cfg::LDK) =
+          make_float2(v1[i].x * sn + v1[i].y * cs, v1[i].z * sn + v1[i].w * cs);
     }
   }
 };
@@ -232,7 +235,7 @@ struct FoldDefocusLoader {
 #define RW_F2_WN 32
 #endif
 #ifndef RW_F2_OCC
-#define RW_F2_OCC 3
+#define RW_F2_OCC 2
 #endif
 using CfgPupil = RgCfg<RW_F1_BM, RW_F1_BN, RW_F1_BK, RW_F1_WM, RW_F1_WN>;
 using CfgImage = RgCfg<RW_F2_BM, RW_F2_BN, RW_F2_BK, RW_F2_WM, RW_F2_WN>;
@@ -268,9 +271,9 @@ __global__ void __launch_bounds__(CfgPupil::NT, RW_F1_OCC) gemm_pupil_kernel(Gem
   la.z = a.z[a.z0 + zi] + a.zoff[s];
   la.w = w;
   la.nhp = a.nhp;
-  RKMajorLoader<Cfg, Cfg::BN> lb;
-  lb.src = a.B1 + col0;
-  lb.ld = a.nyp;
+  RRowLoader<Cfg, Cfg::BN> lb;
+  lb.src = a.B1 + (size_t)col0 * w;
+  lb.ld = w;
 
   // The pupil is zero outside the disk (2j+1-n)^2 + (2l+1-n)^2 <= n^2: this row block
   // needs the folded columns lf that its row nearest the centre (largest jf) reaches.
@@ -338,10 +341,10 @@ __global__ void __launch_bounds__(CfgImage::NT, RW_F2_OCC) gemm_image_kernel(Gem
 
 #pragma unroll 1
   for (int c = 0; c < 3; ++c) {
-    RKMajorLoader<Cfg, Cfg::BM> la;
-    la.src = a.A2T + row0;
-    la.ld = a.nxp;
-    RKMajorLoader<Cfg, Cfg::BN> lb;
+    RRowLoader<Cfg, Cfg::BM> la;
+    la.src = a.A2 + (size_t)row0 * w;
+    la.ld = w;
+    RColLoader<Cfg, Cfg::BN> lb;
     lb.src = reinterpret_cast<const float*>(a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)w * a.nyp) + col0;
     lb.ld = 2 * a.nyp;
     RgAcc<Cfg> acc;

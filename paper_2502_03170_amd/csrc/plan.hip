@@ -7,8 +7,9 @@
 //   ksz[j,l]  = k s_z                                (FP64, for the defocus phase)
 // and of the folded transforms (jf, lf < nh = ceil(N/2), the mirror-symmetric half):
 //   kszf[jf,lf]   = k s_z                            (FP64)
-//   B1[2lf][n]    = cos(k s_y[lf] y_n),  B1[2lf+1][n] = sin(k s_y[lf] y_n)
-//   A2T[2jf][m]   = pref cos(k s_x[jf] x_m),  A2T[2jf+1][m] = pref sin(...),  pref = f k / 2 pi
+//   B1[n][2lf]    = cos(k s_y[lf] y_n),  B1[n][2lf+1] = sin(k s_y[lf] y_n)
+//   A2[m][2jf]    = pref cos(k s_x[jf] x_m),  A2[m][2jf+1] = pref sin(...),  pref = f k / 2 pi
+// (both with the contraction index contiguous)
 // with x_m = (m - nx/2) dx, y_n = (n - ny/2) dy.
 #include <algorithm>
 #include <cmath>
@@ -62,16 +63,16 @@ static int fourier_plan_init(rwpsf_plan* p) {
     const double sy = (2.0 * lf + 1.0 - N) * s_max / N;
     for (int n = 0; n < ny; ++n) {
       const double ph = k * sy * (double)(n - ny / 2) * p->grid.dy_nm;
-      B1[(size_t)(2 * lf) * nyp + n] = (float)std::cos(ph);
-      B1[(size_t)(2 * lf + 1) * nyp + n] = (float)std::sin(ph);
+      B1[(size_t)n * w + 2 * lf] = (float)std::cos(ph);
+      B1[(size_t)n * w + 2 * lf + 1] = (float)std::sin(ph);
     }
   }
   for (int jf = 0; jf < nh; ++jf) {
     const double sx = (2.0 * jf + 1.0 - N) * s_max / N;
     for (int m = 0; m < nx; ++m) {
       const double ph = k * sx * (double)(m - nx / 2) * p->grid.dx_nm;
-      A2T[(size_t)(2 * jf) * nxp + m] = (float)(pref * std::cos(ph));
-      A2T[(size_t)(2 * jf + 1) * nxp + m] = (float)(pref * std::sin(ph));
+      A2T[(size_t)m * w + 2 * jf] = (float)(pref * std::cos(ph));
+      A2T[(size_t)m * w + 2 * jf + 1] = (float)(pref * std::sin(ph));
     }
   }
   int st;
@@ -181,7 +182,7 @@ static int fourier_gemms(rwpsf_plan* p, int s_local, int ns, const double* zoff,
   if (rc) return rc;
   p->time_end(tr, st);
   Gemm2Args g2{};
-  g2.A2T = p->d_A2T;
+  g2.A2 = p->d_A2T;
   g2.T = p->d_T;
   g2.E = E;
   g2.I = I;

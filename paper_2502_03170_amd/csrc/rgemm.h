@@ -1,13 +1,17 @@
 // Real FP32 GEMM tile engine on the CDNA3/4 matrix cores (v_mfma_f32_32x32x2_f32).
 //
 // A workgroup computes a BM x BN tile of C = A * B with BM/WM x BN/WN waves, each
-// owning a WM x WN tile made of 32 x 32 MFMA blocks.  Both operands are staged in
-// LDS k-major ([k][row] and [k][col], rows padded by 4 words) so that the 32 lanes
-// of a half-wave read 32 consecutive words.  Two LDS stages: the global loads of
-// stage k+1 are issued before the MFMAs of stage k and written to LDS after them.
+// owning a WM x WN tile made of 32 x 32 MFMA blocks.  Both operands are staged in LDS
+// with k contiguous ([row][k] and [col][k], rows padded to BK + 4 words so that a
+// half-wave's 16-byte reads of 32 rows fall in distinct banks).  A lane half reads four
+// consecutive k with one ds_read_b128 and feeds them to four MFMAs: in k-group u,
+// instruction t takes k = 8u + t from lanes 0-31 and k = 8u + 4 + t from lanes 32-63,
+// for A and B alike, so every k of the stage is summed once.  Two LDS stages: the
+// global loads of stage k+1 are issued before the MFMAs of stage k and written to
+// LDS after them.
 //
-// MFMA 32x32x2 f32 lane layout (wave64): A operand lane l holds A[l%32][l/32],
-// B operand lane l holds B[l/32][l%32]; accumulator register r of lane l holds
+// MFMA 32x32x2 f32 lane layout (wave64): A operand lane l holds A[l%32][k(l/32)],
+// B operand lane l holds B[k(l/32)][l%32]; accumulator register r of lane l holds
 // C[(r/4)*8 + (l/32)*4 + r%4][l%32].
 #pragma once
 
@@ -24,24 +28,25 @@ struct RgCfg {
   static constexpr int NWAVES = WAVES_M * WAVES_N;
   static constexpr int NT = NWAVES * 64;
   static constexpr int TM = WM / 32, TN = WN / 32;
-  static constexpr int LDA = BM + 4, LDB = BN + 4;
-  static constexpr int A_FLOATS = BK * LDA;
-  static constexpr int B_FLOATS = BK * LDB;
+  static constexpr int LDK = BK + 4;   // words per staged row
+  static constexpr int A_FLOATS = BM * LDK;
+  static constexpr int B_FLOATS = BN * LDK;
   static constexpr int STAGE_FLOATS = A_FLOATS + B_FLOATS;
   static constexpr int LDS_BYTES = 2 * STAGE_FLOATS * 4;
   static_assert(BM % WM == 0 && BN % WN == 0 && WM % 32 == 0 && WN % 32 == 0, "tile shape");
-  static_assert(BK % 2 == 0, "k-pairs");
+  static_assert(BK % 8 == 0, "k-groups of 8");
 };
 
-// Loader of a k-major real operand: element (k, c) at src[k * ld + c].  Operands are
-// zero-padded to whole tiles (rows to a multiple of BK, columns to a multiple of the
-// tile width, ld a multiple of 4), so every load is an unconditional aligned float4.
-template <class Cfg, int BW>
-struct RKMajorLoader {
-  static constexpr int QUADS_PER_ROW = BW / 4;
-  static constexpr int PER_THREAD = Cfg::BK * QUADS_PER_ROW / Cfg::NT;
-  static_assert(Cfg::BK * QUADS_PER_ROW % Cfg::NT == 0, "loader shape");
-  const float* src;  // already offset to column c0
+// Loader of an operand stored with k contiguous in memory: element (row, k) at
+// src[row * ld + k], staged to LDS as [row][k].  Operands are zero-padded to whole tiles
+// (rows to the tile height, k to a multiple of BK, ld a multiple of 4), so every load is
+// an unconditional aligned float4.
+template <class Cfg, int ROWS>
+struct RRowLoader {
+  static constexpr int QUADS = Cfg::BK / 4;
+  static constexpr int PER_THREAD = ROWS * QUADS / Cfg::NT;
+  static_assert(ROWS * QUADS % Cfg::NT == 0, "loader shape");
+  const float* src;  // already offset to row r0
   int ld;
   float4 v[PER_THREAD];
 
@@ -49,18 +54,54 @@ struct RKMajorLoader {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
-      const int kk = idx / QUADS_PER_ROW;
-      const int cc = 4 * (idx % QUADS_PER_ROW);
-      v[i] = *reinterpret_cast<const float4*>(src + (size_t)(k0 + kk) * ld + cc);
+      const int row = idx / QUADS, kq = 4 * (idx % QUADS);
+      v[i] = *reinterpret_cast<const float4*>(src + (size_t)row * ld + k0 + kq);
     }
   }
-  __device__ void store(float* dst, int ldl, int tid) const {
+  __device__ void store(float* dst, int tid) const {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
-      const int kk = idx / QUADS_PER_ROW;
-      const int cc = 4 * (idx % QUADS_PER_ROW);
-      *reinterpret_cast<float4*>(dst + kk * ldl + cc) = v[i];
+      const int row = idx / QUADS, kq = 4 * (idx % QUADS);
+      *reinterpret_cast<float4*>(dst + row * Cfg::LDK + kq) = v[i];
+    }
+  }
+};
+
+// Loader of an operand stored k-major in memory: element (row, k) at src[k * ld + row],
+// staged to LDS as [row][k].  Each thread moves a 2 (k) x 4 (rows) block: two float4
+// loads along the rows, transposed in registers into four 8-byte LDS writes along k.
+// Consecutive lanes take consecutive k-pairs of the same rows, so a half-wave's writes
+// cover consecutive words of one LDS row (no bank conflicts).
+template <class Cfg, int ROWS>
+struct RColLoader {
+  static constexpr int KPAIRS = Cfg::BK / 2, QUADS = ROWS / 4;
+  static constexpr int PER_THREAD = KPAIRS * QUADS / Cfg::NT;
+  static_assert(KPAIRS * QUADS % Cfg::NT == 0, "loader shape");
+  const float* src;  // already offset to row r0
+  int ld;
+  float4 v0[PER_THREAD], v1[PER_THREAD];
+
+  __device__ void load(int k0, int tid) {
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+      const int idx = tid + i * Cfg::NT;
+      const int kk = 2 * (idx % KPAIRS), rq = 4 * (idx / KPAIRS);
+      const float* p = src + (size_t)(k0 + kk) * ld + rq;
+      v0[i] = *reinterpret_cast<const float4*>(p);
+      v1[i] = *reinterpret_cast<const float4*>(p + ld);
+    }
+  }
+  __device__ void store(float* dst, int tid) const {
+#pragma unroll
+    for (int i = 0; i < PER_THREAD; ++i) {
+      const int idx = tid + i * Cfg::NT;
+      const int kk = 2 * (idx % KPAIRS), rq = 4 * (idx / KPAIRS);
+      float* d = dst + rq * Cfg::LDK + kk;
+      *reinterpret_cast<float2*>(d) = make_float2(v0[i].x, v1[i].x);
+      *reinterpret_cast<float2*>(d + Cfg::LDK) = make_float2(v0[i].y, v1[i].y);
+      *reinterpret_cast<float2*>(d + 2 * Cfg::LDK) = make_float2(v0[i].z, v1[i].z);
+      *reinterpret_cast<float2*>(d + 3 * Cfg::LDK) = make_float2(v0[i].w, v1[i].w);
     }
   }
 };
@@ -83,23 +124,40 @@ __device__ __forceinline__ void rg_stage_mma(RgAcc<Cfg>& acc, const float* a, co
                                              int wcol, int lane) {
   const int h = lane >> 5, l32 = lane & 31;
 #pragma unroll
-  for (int kp = 0; kp < Cfg::BK / 2; ++kp) {
-    const int kk = 2 * kp + h;
-    float av[Cfg::TM], bv[Cfg::TN];
+  for (int u = 0; u < Cfg::BK / 8; ++u) {
+    const int k = 8 * u + 4 * h;
+    float4 av[Cfg::TM], bv[Cfg::TN];
 #pragma unroll
-    for (int i = 0; i < Cfg::TM; ++i) av[i] = a[kk * Cfg::LDA + wrow + 32 * i + l32];
+    for (int i = 0; i < Cfg::TM; ++i)
+      av[i] = *reinterpret_cast<const float4*>(a + (wrow + 32 * i + l32) * Cfg::LDK + k);
 #pragma unroll
-    for (int j = 0; j < Cfg::TN; ++j) bv[j] = b[kk * Cfg::LDB + wcol + 32 * j + l32];
+    for (int j = 0; j < Cfg::TN; ++j)
+      bv[j] = *reinterpret_cast<const float4*>(b + (wcol + 32 * j + l32) * Cfg::LDK + k);
 #pragma unroll
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
       for (int j = 0; j < Cfg::TN; ++j)
-        acc.c[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i], bv[j], acc.c[i][j], 0, 0, 0);
+        acc.c[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].x, bv[j].x, acc.c[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::TN; ++j)
+        acc.c[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].y, bv[j].y, acc.c[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::TN; ++j)
+        acc.c[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].z, bv[j].z, acc.c[i][j], 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+      for (int j = 0; j < Cfg::TN; ++j)
+        acc.c[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(av[i].w, bv[j].w, acc.c[i][j], 0, 0, 0);
   }
 }
 
 // K loop over [k_begin, k_end) (multiples of BK, k_end > k_begin) with double-buffered LDS.
-// The loaders provide load(k0, tid) and store(lds_tile, ld, tid).
+// The loaders provide load(k0, tid) and store(lds_tile, tid).
 template <class Cfg, class ALoader, class BLoader>
 __device__ __forceinline__ void rg_mainloop(RgAcc<Cfg>& acc, ALoader& la, BLoader& lb, int k_begin, int k_end,
                                             float* lds, int tid, int wrow, int wcol, int lane) {
@@ -108,8 +166,8 @@ __device__ __forceinline__ void rg_mainloop(RgAcc<Cfg>& acc, ALoader& la, BLoade
   const int KT = (k_end - k_begin) / Cfg::BK;
   la.load(k_begin, tid);
   lb.load(k_begin, tid);
-  la.store(lds, Cfg::LDA, tid);
-  lb.store(lds + Cfg::A_FLOATS, Cfg::LDB, tid);
+  la.store(lds, tid);
+  lb.store(lds + Cfg::A_FLOATS, tid);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     float* cur = lds + (kt & 1) * Cfg::STAGE_FLOATS;
@@ -121,8 +179,8 @@ __device__ __forceinline__ void rg_mainloop(RgAcc<Cfg>& acc, ALoader& la, BLoade
     }
     rg_stage_mma<Cfg>(acc, cur, cur + Cfg::A_FLOATS, wrow, wcol, lane);
     if (more) {
-      la.store(nxt, Cfg::LDA, tid);
-      lb.store(nxt + Cfg::A_FLOATS, Cfg::LDB, tid);
+      la.store(nxt, tid);
+      lb.store(nxt + Cfg::A_FLOATS, tid);
     }
     __syncthreads();
   }

@@ -155,8 +155,8 @@ struct rwpsf_plan {
   float2* d_Q = nullptr;        // [3][np][np] ds^2 a e_inf,c / s_z (0 outside)
   int nhp = 0;                  // folded pupil cells per axis, padded (2 nhp = np)
   double* d_kszf = nullptr;     // [nhp][nhp] k * s_z on the folded cells
-  float* d_B1 = nullptr;        // [2 nhp][nyp] cos / sin (k s_y[lf] y_n)
-  float* d_A2T = nullptr;       // [2 nhp][nxp] pref cos / sin (k s_x[jf] x_m), pref = f k / 2 pi
+  float* d_B1 = nullptr;        // [nyp][2 nhp] cos / sin (k s_y[lf] y_n)
+  float* d_A2T = nullptr;       // [nxp][2 nhp] pref cos / sin (k s_x[jf] x_m), pref = f k / 2 pi
   float* d_ztab = nullptr;      // [RWPSF_MAX_ZERNIKE][N][N] Noll basis on the pupil cells
   float2* d_P = nullptr;        // workspace [chunk][3][np][np]
   float2* d_Pf = nullptr;       // workspace [chunk][3][2 nhp][2 nhp] folded pupils

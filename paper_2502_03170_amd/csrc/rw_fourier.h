@@ -33,14 +33,14 @@ struct Gemm1Args {
   const float2* Pf;    // [nstk][3][2 nhp][2 nhp]
   const double* kszf;  // [nhp][nhp] k s_z on the folded cells
   const double* z;     // plan planes
-  const float* B1;     // [2 nhp][nyp] cos / sin (k s_y[lf] y_n)
+  const float* B1;     // [nyp][2 nhp] cos / sin (k s_y[lf] y_n), k contiguous
   float2* T;           // [nstk][nzs][3][2 nhp][nyp]
   double zoff[kPupilStacks];
   int n, nhp, nyp, nstk, z0, nzs;   // n: pupil cells per axis
 };
 
 struct Gemm2Args {
-  const float* A2T;    // [2 nhp][nxp] pref cos / sin (k s_x[jf] x_m)
+  const float* A2;     // [nxp][2 nhp] pref cos / sin (k s_x[jf] x_m), k contiguous
   const float2* T;     // [nstk][nzs][3][2 nhp][nyp]
   float2* E;           // [stacks][nz][3][nx][ny] or null
   float* I;            // [stacks][nz][nx][ny] or null
