@@ -121,20 +121,23 @@ struct AdjGArgs {
   const float2* P;     // [chunk][3][np][np]
   const double* ksz;   // [np][np]
   const double* z;     // [nz]
-  float* partial;      // [stacks * 3][np][np]
+  float* partial;      // [stacks * 3 * zgroups][np][np]
   double zoff[kPupilStacks];
   int s0, nstk, nz, nx, nxp, np;
+  int zgroups, zper;   // planes are split into zgroups runs of zper (the last may be shorter)
 };
 
 __global__ void __launch_bounds__(CfgAdj::NT, 2) adj_g_kernel(AdjGArgs a) {
   using Cfg = CfgAdj;
   extern __shared__ float lds[];
   const int tiles = a.np / Cfg::BM;
-  const int nblocks = a.nstk * 3 * tiles * tiles;
+  const int nblocks = a.nstk * 3 * a.zgroups * tiles * tiles;
   int id = xcd_remap(blockIdx.x, nblocks);
   const int tn = id % tiles; id /= tiles;
   const int tm = id % tiles; id /= tiles;
+  const int g = id % a.zgroups; id /= a.zgroups;
   const int c = id % 3, s = id / 3;
+  const int z_begin = g * a.zper, z_end = min(a.nz, z_begin + a.zper);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wrow = (wave / Cfg::WAVES_N) * Cfg::WM, wcol = (wave % Cfg::WAVES_N) * Cfg::WN;
   const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
@@ -149,7 +152,7 @@ __global__ void __launch_bounds__(CfgAdj::NT, 2) adj_g_kernel(AdjGArgs a) {
       for (int r = 0; r < 16; ++r) dphi[i][jj][r] = 0.f;
   const int K = (a.nx + Cfg::BK - 1) / Cfg::BK * Cfg::BK;   // H rows past nx are zero
 #pragma unroll 1
-  for (int z = 0; z < a.nz; ++z) {
+  for (int z = z_begin; z < z_end; ++z) {
     KMajorLoader<Cfg, Cfg::BM> la;
     la.src = a.AxH + row0;
     la.ld = a.np;
@@ -178,7 +181,7 @@ __global__ void __launch_bounds__(CfgAdj::NT, 2) adj_g_kernel(AdjGArgs a) {
         }
       }
   }
-  float* out = a.partial + ((size_t)(a.s0 + s) * 3 + c) * npp;
+  float* out = a.partial + (((size_t)(a.s0 + s) * 3 + c) * a.zgroups + g) * npp;
 #pragma unroll
   for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
@@ -192,15 +195,29 @@ __global__ void __launch_bounds__(CfgAdj::NT, 2) adj_g_kernel(AdjGArgs a) {
     }
 }
 
-// dL/dPhi on the N x N cells: partials summed in group order (FP64).
-__global__ void adj_reduce_kernel(const float* __restrict__ partial, int groups, int n, int np,
-                                  double* __restrict__ dphi, float* __restrict__ dW0) {
+// dL/dPhi on the N x N cells: the partials are summed in group order (FP64) in two
+// levels -- runs of kReduceRun groups (grid.y runs), then the runs in order.
+constexpr int kReduceRun = 32;
+
+__global__ void adj_reduce_runs_kernel(const float* __restrict__ partial, int groups, int n, int np,
+                                       double* __restrict__ runs) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= n * n) return;
   const int j = cell / n, l = cell % n;
   const size_t pc = (size_t)j * np + l, npp = (size_t)np * np;
+  const int g0 = blockIdx.y * kReduceRun, g1 = min(groups, g0 + kReduceRun);
   double s = 0.0;
-  for (int g = 0; g < groups; ++g) s += (double)partial[g * npp + pc];
+#pragma unroll 8
+  for (int g = g0; g < g1; ++g) s += (double)partial[g * npp + pc];
+  runs[(size_t)blockIdx.y * n * n + cell] = s;
+}
+
+__global__ void adj_reduce_kernel(const double* __restrict__ runs, int nruns, int n, double* __restrict__ dphi,
+                                  float* __restrict__ dW0) {
+  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= n * n) return;
+  double s = 0.0;
+  for (int r = 0; r < nruns; ++r) s += runs[(size_t)r * n * n + cell];
   dphi[cell] = s;
   if (dW0) dW0[cell] = (float)s;
 }
@@ -231,6 +248,13 @@ hipError_t adjoint_kernel_attributes() {
 }
 
 // Lazily built adjoint tables and workspace of a Fourier plan.
+// Plane groups of adj_g: enough workgroups to fill the chip (>= 4 per CU of 256).
+static int adjoint_zgroups(const rwpsf_plan* p) {
+  const int tiles = p->np / CfgAdj::BM;
+  const int per_group = kPupilStacks * 3 * tiles * tiles;
+  return std::max(1, std::min(p->grid.nz, (1024 + per_group - 1) / per_group));
+}
+
 static int adjoint_prepare(rwpsf_plan* p, int n_stacks) {
   const int nx = p->grid.nx, ny = p->grid.ny, N = p->num.n_pupil, np = p->np;
   const int nxp = round_up(nx, 64);
@@ -260,11 +284,15 @@ static int adjoint_prepare(rwpsf_plan* p, int n_stacks) {
     if ((st = hip_check(hipMemcpy(p->d_AyH, AyH.data(), AyH.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
     if ((st = hip_check(adjoint_kernel_attributes()))) return st;
   }
-  if (p->partial_groups < 3 * n_stacks) {
+  const int groups = 3 * n_stacks * adjoint_zgroups(p);
+  if (p->partial_groups < groups) {
     float* d = nullptr;
-    if ((st = dev_alloc(p, &d, (size_t)3 * n_stacks * np * np))) return st;
+    if ((st = dev_alloc(p, &d, (size_t)groups * np * np))) return st;
     p->d_partial = d;
-    p->partial_groups = 3 * n_stacks;
+    p->partial_groups = groups;
+    double* r = nullptr;
+    if ((st = dev_alloc(p, &r, (size_t)((groups + kReduceRun - 1) / kReduceRun) * N * N))) return st;
+    p->d_runs = r;
   }
   return RWPSF_OK;
 }
@@ -276,6 +304,7 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
   int rc = adjoint_prepare(p, n);
   if (rc) return rc;
   const int nxp = round_up(nx, 64);
+  const int zg = adjoint_zgroups(p);
   for (int b0 = 0; b0 < n; b0 += kPupilStacks) {
     const int nb = std::min(kPupilStacks, n - b0);
     if ((rc = fourier_build_pupils(p, s + b0, nb, st))) return rc;
@@ -299,15 +328,21 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
     ga.nx = nx;
     ga.nxp = nxp;
     ga.np = np;
+    ga.zgroups = zg;
+    ga.zper = (nz + zg - 1) / zg;
     const int t = np / CfgAdj::BM;
     tr = p->time_begin(RWPSF_KERNEL_ADJ_G, st);
-    hipLaunchKernelGGL(adj_g_kernel, dim3(nb * 3 * t * t), dim3(CfgAdj::NT), CfgAdj::LDS_BYTES, st, ga);
+    hipLaunchKernelGGL(adj_g_kernel, dim3(nb * 3 * zg * t * t), dim3(CfgAdj::NT), CfgAdj::LDS_BYTES, st, ga);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
   }
   int tr = p->time_begin(RWPSF_KERNEL_ADJ_REDUCE, st);
-  hipLaunchKernelGGL(adj_reduce_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, p->d_partial, 3 * n, N,
-                     np, p->d_dphi, dW0);
+  const int groups = 3 * n * zg, nruns = (groups + kReduceRun - 1) / kReduceRun;
+  hipLaunchKernelGGL(adj_reduce_runs_kernel, dim3((N * N + 255) / 256, nruns), dim3(256), 0, st, p->d_partial,
+                     groups, N, np, p->d_runs);
+  if ((rc = hip_check(hipGetLastError()))) return rc;
+  hipLaunchKernelGGL(adj_reduce_kernel, dim3((N * N + 255) / 256), dim3(256), 0, st, p->d_runs, nruns, N,
+                     p->d_dphi, dW0);
   if ((rc = hip_check(hipGetLastError()))) return rc;
   if (n_zernike > 0) {
     hipLaunchKernelGGL(adj_zernike_kernel, dim3(n_zernike), dim3(256), 0, st, p->d_dphi, p->d_ztab, N * N, dc);

@@ -239,15 +239,21 @@ struct FoldDefocusLoader {
 #endif
 using CfgPupil = RgCfg<RW_F1_BM, RW_F1_BN, RW_F1_BK, RW_F1_WM, RW_F1_WN>;
 using CfgImage = RgCfg<RW_F2_BM, RW_F2_BN, RW_F2_BK, RW_F2_WM, RW_F2_WN>;
+// outputs of at most 64 pixels per axis are padded to 64 and use half-height tiles
+using CfgPupilS = RgCfg<128, 64, 16, 64, 32>;
+using CfgImageS = RgCfg<64, 64, 32, 32, 32>;
 static_assert((4 * kFoldPad) % CfgPupil::BM == 0 && (2 * kFoldPad) % CfgPupil::BK == 0, "pupil GEMM padding");
+static_assert((4 * kFoldPad) % CfgPupilS::BM == 0 && kPadSmall % CfgPupilS::BN == 0 && kPadSmall % CfgImageS::BM == 0 &&
+                  (2 * kPadSmall) % CfgImageS::BN == 0 && (2 * kFoldPad) % CfgImageS::BK == 0,
+              "small-output padding");
 static_assert(kPadY % CfgPupil::BN == 0 && kPadX % CfgImage::BM == 0 && (2 * kPadY) % CfgImage::BN == 0 &&
                   (2 * kFoldPad) % CfgImage::BK == 0,
               "image GEMM padding");
 
 // K2: T[s][z][c] = (Pf~ B1) with rows 2q + ri, i.e. the complex [2 nhp] x [nyp] matrix
 // T[q][n] = sum_kk Pf~[q][kk] B1[kk][n], B1[2lf][n] = cos(k s_lf y_n), B1[2lf+1][n] = sin(...)
-__global__ void __launch_bounds__(CfgPupil::NT, RW_F1_OCC) gemm_pupil_kernel(Gemm1Args a) {
-  using Cfg = CfgPupil;
+template <class Cfg, int OCC>
+__global__ void __launch_bounds__(Cfg::NT, OCC) gemm_pupil_kernel(Gemm1Args a) {
   extern __shared__ float lds[];
   const int w = 2 * a.nhp;
   const int tiles_m = 2 * w / Cfg::BM;
@@ -312,8 +318,8 @@ __global__ void __launch_bounds__(CfgPupil::NT, RW_F1_OCC) gemm_pupil_kernel(Gem
 // K3: E'[m][(n, ri)] = sum_kk A2[m][kk] T[kk][(n, ri)] with A2[m][2jf] = pref cos(k s_jf x_m),
 // A2[m][2jf+1] = pref sin(...) for c = x, y, z in one workgroup; E = -i E' and
 // I = sum_c |E_c|^2 are written from registers.
-__global__ void __launch_bounds__(CfgImage::NT, RW_F2_OCC) gemm_image_kernel(Gemm2Args a) {
-  using Cfg = CfgImage;
+template <class Cfg, int OCC>
+__global__ void __launch_bounds__(Cfg::NT, OCC) gemm_image_kernel(Gemm2Args a) {
   extern __shared__ float lds[];
   const int w = 2 * a.nhp;
   const int tiles_m = a.nxp / Cfg::BM;
@@ -412,28 +418,43 @@ hipError_t launch_pupil_fold(const FoldArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
-  using Cfg = CfgPupil;
+template <class Cfg, int OCC>
+static hipError_t gemm_pupil_launch(const Gemm1Args& a, hipStream_t st) {
   const int tiles = (4 * a.nhp / Cfg::BM) * (a.nyp / Cfg::BN);
   const int nblocks = a.nstk * a.nzs * 3 * tiles;
-  hipLaunchKernelGGL(gemm_pupil_kernel, dim3(nblocks), dim3(Cfg::NT), Cfg::LDS_BYTES, st, a);
+  hipLaunchKernelGGL((gemm_pupil_kernel<Cfg, OCC>), dim3(nblocks), dim3(Cfg::NT), Cfg::LDS_BYTES, st, a);
   return hipGetLastError();
+}
+
+template <class Cfg, int OCC>
+static hipError_t gemm_image_launch(const Gemm2Args& a, hipStream_t st) {
+  const int tiles = (a.nxp / Cfg::BM) * (2 * a.nyp / Cfg::BN);
+  const int nblocks = a.nstk * a.nzs * tiles;
+  hipLaunchKernelGGL((gemm_image_kernel<Cfg, OCC>), dim3(nblocks), dim3(Cfg::NT), Cfg::LDS_BYTES, st, a);
+  return hipGetLastError();
+}
+
+// The tile height follows the padding the plan chose (multiples of 128, or of 64 for
+// outputs of at most 64 pixels along that axis).
+hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
+  if (a.nyp % CfgPupil::BN == 0) return gemm_pupil_launch<CfgPupil, RW_F1_OCC>(a, st);
+  return gemm_pupil_launch<CfgPupilS, 4>(a, st);
 }
 
 hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st) {
-  using Cfg = CfgImage;
-  const int tiles = (a.nxp / Cfg::BM) * (2 * a.nyp / Cfg::BN);
-  const int nblocks = a.nstk * a.nzs * tiles;
-  hipLaunchKernelGGL(gemm_image_kernel, dim3(nblocks), dim3(Cfg::NT), Cfg::LDS_BYTES, st, a);
-  return hipGetLastError();
+  if (a.nxp % CfgImage::BM == 0) return gemm_image_launch<CfgImage, RW_F2_OCC>(a, st);
+  return gemm_image_launch<CfgImageS, 4>(a, st);
 }
 
 hipError_t fourier_kernel_attributes() {
-  hipError_t e = hipFuncSetAttribute((const void*)gemm_pupil_kernel,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, CfgPupil::LDS_BYTES);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)gemm_image_kernel,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, CfgImage::LDS_BYTES);
+  const void* k[4] = {(const void*)gemm_pupil_kernel<CfgPupil, RW_F1_OCC>, (const void*)gemm_pupil_kernel<CfgPupilS, 4>,
+                      (const void*)gemm_image_kernel<CfgImage, RW_F2_OCC>, (const void*)gemm_image_kernel<CfgImageS, 4>};
+  const int bytes[4] = {CfgPupil::LDS_BYTES, CfgPupilS::LDS_BYTES, CfgImage::LDS_BYTES, CfgImageS::LDS_BYTES};
+  for (int i = 0; i < 4; ++i) {
+    const hipError_t e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[i]);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace rw

@@ -26,7 +26,7 @@ int bessel_plan_init(rwpsf_plan* p);
 
 static int fourier_plan_init(rwpsf_plan* p) {
   const int N = p->num.n_pupil, nx = p->grid.nx, ny = p->grid.ny;
-  const int np = round_up(N, kPadPupil), nxp = round_up(nx, kPadX), nyp = round_up(ny, kPadY);
+  const int np = round_up(N, kPadPupil), nxp = pad_axis(nx), nyp = pad_axis(ny);
   p->np = np;
   p->nxp = nxp;
   p->nyp = nyp;

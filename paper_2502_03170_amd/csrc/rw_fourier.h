@@ -48,7 +48,9 @@ struct Gemm2Args {
 };
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }
-constexpr int kPadPupil = 64, kPadX = 128, kPadY = 128, kFoldPad = 32;
+constexpr int kPadPupil = 64, kPadX = 128, kPadY = 128, kFoldPad = 32, kPadSmall = 64;
+// padding of an output axis of n pixels: 64 for n <= 64, else a multiple of 128
+inline int pad_axis(int n) { return n <= kPadSmall ? kPadSmall : round_up(n, kPadX); }
 
 hipError_t launch_zernike_table(float* out, int n, int nj, hipStream_t st);
 hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* ztab, float2* P,
