@@ -245,7 +245,7 @@ def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
     plan.close()
     comp = n_stacks * nz * 3
     fwd = comp * 4.0 * (n * n * nx + nx * n * nx)     # folded real GEMMs
-    adj = comp * 8.0 * (nx * nx * n + n * nx * n)     # complex GEMMs of the adjoint
+    adj = comp * 4.0 * (nx * nx * n + n * nx * n)     # folded real GEMMs of the adjoint
     ach = (fwd + adj) / (ms * 1e-3) / 1e12
     vox = n_stacks * nz * nx * nx
     return dict(workload=f"adjoint: {n_stacks} stacks of {nx}x{nx}x{nz} at 100 nm, 256x256 pupil, shared Noll "

@@ -5,13 +5,21 @@
 // For a real loss L(I), I = sum_c |E_c|^2, with g = dL/dI:
 //   dL/dPhi[j,l] = sum_{b,z,c} Im( G[j,l] conj(P~[j,l]) ),  G = Ax'^H (2 g E) conj(Ay)
 //   dL/dW0 = dL/dPhi,  dL/dc_q = 2 pi sum_cells dL/dPhi Z_q.
-// Kernels (complex FP32 GEMMs on the matrix cores, FP32 accumulate):
-//   adj_h_kernel   H[b,z,c] = (2 g E) AyH,  AyH[n][l] = conj(Ay[n][l])   (the scaling
-//                  2 g is applied while E is staged; H is [nx][np])
-//   adj_g_kernel   for each (stack, component) and pupil tile, over the planes z in
-//                  order: G = AxH^T H (AxH[m][j] = conj(Ax'[m][j])), then
-//                  acc += Im(G conj(P~)) -- one partial per (stack, component), no atomics
-//   adj_reduce_kernel  dL/dPhi = sum of the partials in a fixed order (FP64), dL/dW0
+// The pupil grid is mirror-symmetric (s[N-1-j] = -s[j]), so with theta = k s_jf x_m and
+// phi = k s_lf y_n (jf, lf < N/2 the folded indices, j' = N-1-jf, l' = N-1-lf):
+//   H[m][lf], H[m][l'] = Hc -+ i Hs,   Hc, Hs = sum_n (2 g E)[m][n] {cos, sin} phi
+//   G = i pref (CC -+ i CS -+ i SC ...)  with  CC = sum_m cos theta Hc, CS = sum_m cos theta Hs,
+//   SC = sum_m sin theta Hc, SS = sum_m sin theta Hs (pref = f k / 2 pi), i.e.
+//   G[jf,lf] = i pref (CC - iCS - iSC - SS)    G[jf,l'] = i pref (CC + iCS - iSC + SS)
+//   G[j',lf] = i pref (CC - iCS + iSC + SS)    G[j',l'] = i pref (CC + iCS + iSC - SS)
+// Kernels (real-coefficient GEMMs on the FP32 matrix cores, FP32 accumulate):
+//   adj_h_kernel   H'[b,z,c][m][2lf + p] = {Hc, Hs}: rows 2m + re/im of 2 g E (the scaling
+//                  applied while E is staged) times the folded y table
+//   adj_g_kernel   for each (stack, component, plane group) and folded pupil tile, over
+//                  the planes in order: Q = {cos, sin}(theta) H', then the four mirror
+//                  values of G from each lane quad, acc += Im(G conj(P~)) -- one partial
+//                  per (stack, component, plane group), no atomics
+//   adj_reduce_*   dL/dPhi = sum of the partials in a fixed order (FP64), dL/dW0
 //   adj_zernike_kernel dL/dc_q by a fixed-shape tree reduction (FP64)
 // The result does not depend on scheduling: every sum runs in a fixed order.
 #include <algorithm>
@@ -20,21 +28,23 @@
 #include <vector>
 
 #include "cgemm.h"
+#include "rgemm.h"
 #include "rw_common.h"
 #include "rw_fourier.h"
 #include "rw_plan.h"
 
 namespace rw {
 
-using CfgAdj = CgCfg<64, 64, 16, 32, 32>;
+using CfgAdjH = RgCfg<128, 64, 16, 64, 32>;   // rows 2m + re/im, columns 2lf + p, k = n
+using CfgAdjG = RgCfg<64, 128, 16, 32, 64>;   // rows 2jf + p, columns 2(2lf + p) + re/im, k = m
 
-// A operand of adj_h: rows m, contraction n, from E [nx][ny] scaled by 2 dL/dI.
-// Rows past nx read row nx-1 with a zero factor (no branches in the load path).
+// A operand of adj_h: rows 2m + ri of 2 g E ([nx][ny] complex, k = n contiguous); rows
+// past nx read row nx - 1 with a zero factor (no branches in the load path).
 template <class Cfg>
-struct ScaledRowLoader {
-  static constexpr int PAIRS = Cfg::BK / 2;
-  static constexpr int PER_THREAD = Cfg::BM * PAIRS / Cfg::NT;
-  static_assert(Cfg::BM * PAIRS % Cfg::NT == 0, "loader shape");
+struct ScaledFieldLoader {
+  static constexpr int ROWS = Cfg::BM / 2, PAIRS = Cfg::BK / 2;
+  static constexpr int PER_THREAD = ROWS * PAIRS / Cfg::NT;
+  static_assert(ROWS * PAIRS % Cfg::NT == 0, "loader shape");
   const float2* E;
   const float* g;
   int ld, nrows, row0;
@@ -54,15 +64,14 @@ struct ScaledRowLoader {
       f[i] = make_float2(keep * gg.x, keep * gg.y);
     }
   }
-  __device__ void store(float* re, float* im, int ldl, int tid) const {
+  __device__ void store(float* dst, int tid) const {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
       const int row = idx / PAIRS, kk = 2 * (idx % PAIRS);
-      re[kk * ldl + row] = f[i].x * v[i].x;
-      im[kk * ldl + row] = f[i].x * v[i].y;
-      re[(kk + 1) * ldl + row] = f[i].y * v[i].z;
-      im[(kk + 1) * ldl + row] = f[i].y * v[i].w;
+      float* d = dst + (2 * row) * Cfg::LDK + kk;
+      *reinterpret_cast<float2*>(d) = make_float2(f[i].x * v[i].x, f[i].y * v[i].z);
+      *reinterpret_cast<float2*>(d + Cfg::LDK) = make_float2(f[i].x * v[i].y, f[i].y * v[i].w);
     }
   }
 };
@@ -70,15 +79,15 @@ struct ScaledRowLoader {
 struct AdjHArgs {
   const float2* E;     // [stacks][nz][3][nx][ny] (the caller's fields)
   const float* g;      // [stacks][nz][nx][ny]
-  const float2* AyH;   // [ny][np]
-  float2* H;           // [chunk][nz][3][nxp][np]
-  int s0, nstk, nz, nx, ny, nxp, np;
+  const float* CyT;    // [w][nyp] rows 2lf + p: {cos, sin}(k s_lf y_n)
+  float2* H;           // [chunk][nz][3][nxp][w]
+  int s0, nstk, nz, nx, ny, nyp, nxp, w;
 };
 
-__global__ void __launch_bounds__(CfgAdj::NT, 2) adj_h_kernel(AdjHArgs a) {
-  using Cfg = CfgAdj;
+__global__ void __launch_bounds__(CfgAdjH::NT, 2) adj_h_kernel(AdjHArgs a) {
+  using Cfg = CfgAdjH;
   extern __shared__ float lds[];
-  const int tiles_m = a.nxp / Cfg::BM, tiles_n = a.np / Cfg::BN;
+  const int tiles_m = 2 * a.nxp / Cfg::BM, tiles_n = a.w / Cfg::BN;
   const int nblocks = a.nstk * a.nz * 3 * tiles_m * tiles_n;
   int id = xcd_remap(blockIdx.x, nblocks);
   const int tn = id % tiles_n; id /= tiles_n;
@@ -89,95 +98,123 @@ __global__ void __launch_bounds__(CfgAdj::NT, 2) adj_h_kernel(AdjHArgs a) {
   const int wrow = (wave / Cfg::WAVES_N) * Cfg::WM, wcol = (wave % Cfg::WAVES_N) * Cfg::WN;
   const size_t plane = (size_t)a.nx * a.ny;
   const size_t gs = (size_t)(a.s0 + s);
-  ScaledRowLoader<Cfg> la;
+  const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
+  ScaledFieldLoader<Cfg> la;
   la.E = a.E + ((gs * a.nz + z) * 3 + c) * plane;
   la.g = a.g + (gs * a.nz + z) * plane;
   la.ld = a.ny;
   la.nrows = a.nx;
-  la.row0 = tm * Cfg::BM;
-  KMajorLoader<Cfg, Cfg::BN> lb;
-  lb.src = a.AyH + tn * Cfg::BN;
-  lb.ld = a.np;
-  CgAcc<Cfg> acc;
+  la.row0 = row0 / 2;
+  RRowLoader<Cfg, Cfg::BN> lb;
+  lb.src = a.CyT + (size_t)col0 * a.nyp;
+  lb.ld = a.nyp;
+  RgAcc<Cfg> acc;
   acc.zero();
-  cg_mainloop<Cfg>(acc, la, lb, a.ny, lds, tid, wrow, wcol, lane);
-  float2* H = a.H + (size_t)item * a.nxp * a.np;
+  rg_mainloop<Cfg>(acc, la, lb, 0, a.ny, lds, tid, wrow, wcol, lane);
+  // rows 2m + ri: registers r and r + 1 (r even) are the re/im parts of one H'[m][col]
+  float2* H = a.H + (size_t)item * a.nxp * a.w;
 #pragma unroll
   for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
     for (int jj = 0; jj < Cfg::TN; ++jj) {
-      const int col = tn * Cfg::BN + cg_col(wcol, jj, lane);
+      const int col = col0 + rg_col(wcol, jj, lane);
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = tm * Cfg::BM + cg_row(wrow, i, r, lane);
-        H[(size_t)row * a.np + col] = make_float2(acc.re[i][jj][r], acc.im[i][jj][r]);
+      for (int r = 0; r < 16; r += 2) {
+        const int m = (row0 + rg_row(wrow, i, r, lane)) >> 1;
+        H[(size_t)m * a.w + col] = make_float2(acc.c[i][jj][r], acc.c[i][jj][r + 1]);
       }
     }
 }
 
 struct AdjGArgs {
-  const float2* AxH;   // [nxp][np]
-  const float2* H;     // [chunk][nz][3][nxp][np]
-  const float2* P;     // [chunk][3][np][np]
+  const float* CxT;    // [w][nxp] rows 2jf + p: pref {cos, sin}(k s_jf x_m)
+  const float2* H;     // [chunk][nz][3][nxp][w]
+  const float2* P;     // [chunk][3][np][np] base pupils (np = w)
   const double* ksz;   // [np][np]
   const double* z;     // [nz]
   float* partial;      // [stacks * 3 * zgroups][np][np]
   double zoff[kPupilStacks];
-  int s0, nstk, nz, nx, nxp, np;
+  int s0, nstk, nz, nxp, w, n;
   int zgroups, zper;   // planes are split into zgroups runs of zper (the last may be shorter)
 };
 
-__global__ void __launch_bounds__(CfgAdj::NT, 2) adj_g_kernel(AdjGArgs a) {
-  using Cfg = CfgAdj;
+// quad_perm DPP: lane 4t + q reads lane 4t + sel[q]
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+__global__ void __launch_bounds__(CfgAdjG::NT, 2) adj_g_kernel(AdjGArgs a) {
+  using Cfg = CfgAdjG;
   extern __shared__ float lds[];
-  const int tiles = a.np / Cfg::BM;
-  const int nblocks = a.nstk * 3 * a.zgroups * tiles * tiles;
+  const int tiles_m = a.w / Cfg::BM, tiles_n = 2 * a.w / Cfg::BN;
+  const int nblocks = a.nstk * 3 * a.zgroups * tiles_m * tiles_n;
   int id = xcd_remap(blockIdx.x, nblocks);
-  const int tn = id % tiles; id /= tiles;
-  const int tm = id % tiles; id /= tiles;
+  const int tn = id % tiles_n; id /= tiles_n;
+  const int tm = id % tiles_m; id /= tiles_m;
   const int g = id % a.zgroups; id /= a.zgroups;
   const int c = id % 3, s = id / 3;
   const int z_begin = g * a.zper, z_end = min(a.nz, z_begin + a.zper);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wrow = (wave / Cfg::WAVES_N) * Cfg::WM, wcol = (wave % Cfg::WAVES_N) * Cfg::WN;
   const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
-  const size_t npp = (size_t)a.np * a.np;
+  const int n = a.n, nh = (n + 1) / 2;
+  const size_t npp = (size_t)a.w * a.w;
   const float2* P = a.P + ((size_t)s * 3 + c) * npp;
-  float dphi[Cfg::TM][Cfg::TN][16];
+  // lane quad q = lane & 3 of columns 2(2lf + p) + ri: q = 2p + ri.  After the exchange the
+  // lane owns mirror cell q: (jf, lf), (jf, l'), (j', lf), (j', l').
+  const int q = lane & 3;
+  float dphi[Cfg::TM][Cfg::TN][8];
 #pragma unroll
   for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
     for (int jj = 0; jj < Cfg::TN; ++jj)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) dphi[i][jj][r] = 0.f;
-  const int K = (a.nx + Cfg::BK - 1) / Cfg::BK * Cfg::BK;   // H rows past nx are zero
+      for (int r = 0; r < 8; ++r) dphi[i][jj][r] = 0.f;
 #pragma unroll 1
-  for (int z = z_begin; z < z_end; ++z) {
-    KMajorLoader<Cfg, Cfg::BM> la;
-    la.src = a.AxH + row0;
-    la.ld = a.np;
-    KMajorLoader<Cfg, Cfg::BN> lb;
-    lb.src = a.H + ((size_t)(s * a.nz + z) * 3 + c) * a.nxp * a.np + col0;
-    lb.ld = a.np;
-    CgAcc<Cfg> acc;
+  for (int zi = z_begin; zi < z_end; ++zi) {
+    RRowLoader<Cfg, Cfg::BM> la;
+    la.src = a.CxT + (size_t)row0 * a.nxp;
+    la.ld = a.nxp;
+    RColLoader<Cfg, Cfg::BN> lb;
+    lb.src = reinterpret_cast<const float*>(a.H + ((size_t)(s * a.nz + zi) * 3 + c) * a.nxp * a.w) + col0;
+    lb.ld = 2 * a.w;
+    RgAcc<Cfg> acc;
     acc.zero();
-    cg_mainloop<Cfg>(acc, la, lb, K, lds, tid, wrow, wcol, lane);
-    const double zz = a.z[z] + a.zoff[s];
+    rg_mainloop<Cfg>(acc, la, lb, 0, a.nxp, lds, tid, wrow, wcol, lane);
+    const double zz = a.z[zi] + a.zoff[s];
 #pragma unroll
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
       for (int jj = 0; jj < Cfg::TN; ++jj) {
-        const int col = col0 + cg_col(wcol, jj, lane);
+        const int lf = (col0 + rg_col(wcol, jj, lane)) >> 2;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int row = row0 + cg_row(wrow, i, r, lane);
-          const size_t cell = (size_t)row * a.np + col;
-          const float2 p = P[cell];
-          float sn, cs;
-          sincosf((float)reduce_2pi(a.ksz[cell] * zz), &sn, &cs);
-          const float pr = p.x * cs - p.y * sn, pi = p.x * sn + p.y * cs;
-          // Im(G conj(P~)) = Gi Pr - Gr Pi
-          dphi[i][jj][r] += acc.im[i][jj][r] * pr - acc.re[i][jj][r] * pi;
+        for (int r = 0; r < 16; r += 2) {
+          const int jf = (row0 + rg_row(wrow, i, r, lane)) >> 1;
+          // this lane holds row (jf, p = 0) in register r and (jf, 1) in r + 1, column q
+          const float x0 = acc.c[i][jj][r], x1 = acc.c[i][jj][r + 1];
+          // quad values: [q'] of register r -> C* , of register r + 1 -> S*
+          const float c0 = dpp<0x00>(x0), c1 = dpp<0x55>(x0), c2 = dpp<0xAA>(x0), c3 = dpp<0xFF>(x0);
+          const float s0 = dpp<0x00>(x1), s1 = dpp<0x55>(x1), s2 = dpp<0xAA>(x1), s3 = dpp<0xFF>(x1);
+          // CC = c0 + i c1, CS = c2 + i c3, SC = s0 + i s1, SS = s2 + i s3
+          const float sl = (q & 1) ? 1.f : -1.f;   // sign of i CS: - for lf, + for l'
+          const float sj = (q & 2) ? 1.f : -1.f;   // sign of i SC: - for jf, + for j'
+          const float ss = (q == 0 || q == 3) ? -1.f : 1.f;
+          // T = CC + sl i CS + sj i SC + ss SS;  G = i pref T (pref is in the x table)
+          const float tr = c0 - sl * c3 - sj * s1 + ss * s2;
+          const float ti = c1 + sl * c2 + sj * s0 + ss * s3;
+          const float gr = -ti, gi = tr;
+          const int jc = (q & 2) ? n - 1 - jf : jf, lc = (q & 1) ? n - 1 - lf : lf;
+          const bool own = jf < nh && lf < nh && !((q & 2) && jc == jf) && !((q & 1) && lc == lf);
+          if (own) {
+            const size_t cell = (size_t)jc * a.w + lc;
+            const float2 p = P[cell];
+            float sn, cs;
+            sincosf((float)reduce_2pi(a.ksz[cell] * zz), &sn, &cs);
+            const float pr = p.x * cs - p.y * sn, pi = p.x * sn + p.y * cs;
+            // Im(G conj(P~)) = Gi Pr - Gr Pi
+            dphi[i][jj][r >> 1] += gi * pr - gr * pi;
+          }
         }
       }
   }
@@ -186,11 +223,13 @@ __global__ void __launch_bounds__(CfgAdj::NT, 2) adj_g_kernel(AdjGArgs a) {
   for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
     for (int jj = 0; jj < Cfg::TN; ++jj) {
-      const int col = col0 + cg_col(wcol, jj, lane);
+      const int lf = (col0 + rg_col(wcol, jj, lane)) >> 2;
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = row0 + cg_row(wrow, i, r, lane);
-        out[(size_t)row * a.np + col] = dphi[i][jj][r];
+      for (int r = 0; r < 16; r += 2) {
+        const int jf = (row0 + rg_row(wrow, i, r, lane)) >> 1;
+        const int jc = (q & 2) ? n - 1 - jf : jf, lc = (q & 1) ? n - 1 - lf : lf;
+        const bool own = jf < nh && lf < nh && !((q & 2) && jc == jf) && !((q & 1) && lc == lf);
+        if (own) out[(size_t)jc * a.w + lc] = dphi[i][jj][r >> 1];
       }
     }
 }
@@ -241,47 +280,50 @@ __global__ void __launch_bounds__(256) adj_zernike_kernel(const double* __restri
 
 hipError_t adjoint_kernel_attributes() {
   hipError_t e = hipFuncSetAttribute((const void*)adj_h_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     CfgAdj::LDS_BYTES);
+                                     CfgAdjH::LDS_BYTES);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)adj_g_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             CfgAdj::LDS_BYTES);
+                             CfgAdjG::LDS_BYTES);
 }
 
 // Lazily built adjoint tables and workspace of a Fourier plan.
 // Plane groups of adj_g: enough workgroups to fill the chip (>= 4 per CU of 256).
 static int adjoint_zgroups(const rwpsf_plan* p) {
-  const int tiles = p->np / CfgAdj::BM;
-  const int per_group = kPupilStacks * 3 * tiles * tiles;
+  const int tiles = (p->np / CfgAdjG::BM) * (2 * p->np / CfgAdjG::BN);
+  const int per_group = kPupilStacks * 3 * tiles;
   return std::max(1, std::min(p->grid.nz, (1024 + per_group - 1) / per_group));
 }
 
+// Lazily built adjoint tables and workspace of a Fourier plan: the folded DFT tables with
+// the pixel index contiguous, CxT[2jf + p][m] = pref {cos, sin}(k s_jf x_m) and
+// CyT[2lf + p][n] = {cos, sin}(k s_lf y_n) (zero past nx, ny and for jf, lf >= N/2).
 static int adjoint_prepare(rwpsf_plan* p, int n_stacks) {
   const int nx = p->grid.nx, ny = p->grid.ny, N = p->num.n_pupil, np = p->np;
-  const int nxp = round_up(nx, 64);
+  const int nxp = p->nxp, nyp = p->nyp, w = 2 * p->nhp, nh = (N + 1) / 2;
   int st;
-  if (!p->d_AxH) {
+  if (!p->d_CxT) {
     const double s_max = p->s_max, k = p->k;
     const double pref = p->opt.focal_length * k / kTwoPi;
-    std::vector<float2> AxH((size_t)nxp * np, make_float2(0.f, 0.f)), AyH((size_t)ny * np, make_float2(0.f, 0.f));
-    for (int m = 0; m < nx; ++m)
-      for (int j = 0; j < N; ++j) {
-        const double sx = (2.0 * j + 1.0 - N) * s_max / N;
-        const double ph = k * sx * (double)(m - nx / 2) * p->grid.dx_nm;
-        // conj(-i pref e^{i ph}) = i pref e^{-i ph} = pref (sin ph + i cos ph)
-        AxH[(size_t)m * np + j] = make_float2((float)(pref * std::sin(ph)), (float)(pref * std::cos(ph)));
+    std::vector<float> CxT((size_t)w * nxp, 0.f), CyT((size_t)w * nyp, 0.f);
+    for (int f = 0; f < nh; ++f) {
+      const double sv = (2.0 * f + 1.0 - N) * s_max / N;
+      for (int m = 0; m < nx; ++m) {
+        const double ph = k * sv * (double)(m - nx / 2) * p->grid.dx_nm;
+        CxT[(size_t)(2 * f) * nxp + m] = (float)(pref * std::cos(ph));
+        CxT[(size_t)(2 * f + 1) * nxp + m] = (float)(pref * std::sin(ph));
       }
-    for (int n = 0; n < ny; ++n)
-      for (int l = 0; l < N; ++l) {
-        const double sy = (2.0 * l + 1.0 - N) * s_max / N;
-        const double ph = k * sy * (double)(n - ny / 2) * p->grid.dy_nm;
-        AyH[(size_t)n * np + l] = make_float2((float)std::cos(ph), (float)(-std::sin(ph)));
+      for (int n = 0; n < ny; ++n) {
+        const double ph = k * sv * (double)(n - ny / 2) * p->grid.dy_nm;
+        CyT[(size_t)(2 * f) * nyp + n] = (float)std::cos(ph);
+        CyT[(size_t)(2 * f + 1) * nyp + n] = (float)std::sin(ph);
       }
-    if ((st = dev_alloc(p, &p->d_AxH, AxH.size()))) return st;
-    if ((st = dev_alloc(p, &p->d_AyH, AyH.size()))) return st;
+    }
+    if ((st = dev_alloc(p, &p->d_CxT, CxT.size()))) return st;
+    if ((st = dev_alloc(p, &p->d_CyT, CyT.size()))) return st;
     if ((st = dev_alloc(p, &p->d_dphi, (size_t)N * N))) return st;
-    if ((st = dev_alloc(p, &p->d_H, (size_t)kPupilStacks * p->grid.nz * 3 * nxp * np))) return st;
-    if ((st = hip_check(hipMemcpy(p->d_AxH, AxH.data(), AxH.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
-    if ((st = hip_check(hipMemcpy(p->d_AyH, AyH.data(), AyH.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
+    if ((st = dev_alloc(p, &p->d_H, (size_t)kPupilStacks * p->grid.nz * 3 * nxp * w))) return st;
+    if ((st = hip_check(hipMemcpy(p->d_CxT, CxT.data(), CxT.size() * sizeof(float), hipMemcpyHostToDevice)))) return st;
+    if ((st = hip_check(hipMemcpy(p->d_CyT, CyT.data(), CyT.size() * sizeof(float), hipMemcpyHostToDevice)))) return st;
     if ((st = hip_check(adjoint_kernel_attributes()))) return st;
   }
   const int groups = 3 * n_stacks * adjoint_zgroups(p);
@@ -303,19 +345,19 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
   if (nx % 16 || ny % 16) return RWPSF_ERR_UNSUPPORTED;   // whole MFMA k-stages along x and y
   int rc = adjoint_prepare(p, n);
   if (rc) return rc;
-  const int nxp = round_up(nx, 64);
+  const int nxp = p->nxp, w = 2 * p->nhp;
   const int zg = adjoint_zgroups(p);
   for (int b0 = 0; b0 < n; b0 += kPupilStacks) {
     const int nb = std::min(kPupilStacks, n - b0);
     if ((rc = fourier_build_pupils(p, s + b0, nb, st))) return rc;
-    AdjHArgs ha{E, dLdI, p->d_AyH, p->d_H, b0, nb, nz, nx, ny, nxp, np};
-    const int hblocks = nb * nz * 3 * (nxp / CfgAdj::BM) * (np / CfgAdj::BN);
+    AdjHArgs ha{E, dLdI, p->d_CyT, p->d_H, b0, nb, nz, nx, ny, p->nyp, nxp, w};
+    const int hblocks = nb * nz * 3 * (2 * nxp / CfgAdjH::BM) * (w / CfgAdjH::BN);
     int tr = p->time_begin(RWPSF_KERNEL_ADJ_H, st);
-    hipLaunchKernelGGL(adj_h_kernel, dim3(hblocks), dim3(CfgAdj::NT), CfgAdj::LDS_BYTES, st, ha);
+    hipLaunchKernelGGL(adj_h_kernel, dim3(hblocks), dim3(CfgAdjH::NT), CfgAdjH::LDS_BYTES, st, ha);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
     AdjGArgs ga{};
-    ga.AxH = p->d_AxH;
+    ga.CxT = p->d_CxT;
     ga.H = p->d_H;
     ga.P = p->d_P;
     ga.ksz = p->d_ksz;
@@ -325,14 +367,14 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
     ga.s0 = b0;
     ga.nstk = nb;
     ga.nz = nz;
-    ga.nx = nx;
     ga.nxp = nxp;
-    ga.np = np;
+    ga.w = w;
+    ga.n = N;
     ga.zgroups = zg;
     ga.zper = (nz + zg - 1) / zg;
-    const int t = np / CfgAdj::BM;
+    const int gblocks = nb * 3 * zg * (w / CfgAdjG::BM) * (2 * w / CfgAdjG::BN);
     tr = p->time_begin(RWPSF_KERNEL_ADJ_G, st);
-    hipLaunchKernelGGL(adj_g_kernel, dim3(nb * 3 * zg * t * t), dim3(CfgAdj::NT), CfgAdj::LDS_BYTES, st, ga);
+    hipLaunchKernelGGL(adj_g_kernel, dim3(gblocks), dim3(CfgAdjG::NT), CfgAdjG::LDS_BYTES, st, ga);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
   }

@@ -163,9 +163,9 @@ struct rwpsf_plan {
   float2* d_T = nullptr;        // workspace [planes][3][2 nhp][nyp]
   size_t T_planes = 0;          // capacity of d_T in stack-planes
   // adjoint (built on first use)
-  float2* d_AxH = nullptr;      // [nxp][np] conj of the prefactor-scaled x DFT, k-major in x
-  float2* d_AyH = nullptr;      // [ny][np] conj of the y DFT, k-major in y
-  float2* d_H = nullptr;        // [8 stacks][nz][3][nxp][np]
+  float* d_CxT = nullptr;       // [2 nhp][nxp] folded x table (prefactor included), pixels contiguous
+  float* d_CyT = nullptr;       // [2 nhp][nyp] folded y table, pixels contiguous
+  float2* d_H = nullptr;        // [8 stacks][nz][3][nxp][2 nhp] folded H
   float* d_partial = nullptr;   // [stacks * 3][np][np] per-(stack, component) dL/dPhi
   int partial_groups = 0;
   double* d_dphi = nullptr;     // [N][N]
