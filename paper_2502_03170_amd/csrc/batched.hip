@@ -253,14 +253,28 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
     }
     const int mi = (SP == 64) ? (w >> 1) : 0, ni = (SP == 64) ? (w & 1) : 0;
     const int kp1a = (SP == 64) ? 0 : w * (N / 8);               // SP = 32: K split over the waves
-    const int kp1b = (SP == 64) ? N / 2 : (w + 1) * (N / 8);
-#pragma unroll 4
-    for (int kp = kp1a; kp < kp1b; ++kp) {
-      const int kk = 2 * kp + h;
-      const float ar = Ure[kk * LDU + 32 * mi + l32], ai = Uim[kk * LDU + 32 * mi + l32];
-      const float b = a.B1T[kk * kTabRows + r0 + 32 * ni + l32];
-      er = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, b, er, 0, 0, 0);
-      ei = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, b, ei, 0, 0, 0);
+    const int kp1b = (SP == 64) ? N / 2 : (w + 1) * (N / 8);     // (kp1b - kp1a) is a multiple of 4
+    {
+      // the y-table operand comes from global memory: chunks of 4 k-steps are loaded one
+      // chunk ahead of the MFMAs that use them
+      const float* bsrc = a.B1T + h * kTabRows + r0 + 32 * ni + l32;
+      float bc[4], bn[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) bc[t] = bsrc[(2 * (kp1a + t)) * kTabRows];
+      for (int kp = kp1a; kp < kp1b; kp += 4) {
+        const bool more = kp + 4 < kp1b;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bn[t] = more ? bsrc[(2 * (kp + 4 + t)) * kTabRows] : 0.f;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          const int kk = 2 * (kp + t) + h;
+          const float ar = Ure[kk * LDU + 32 * mi + l32], ai = Uim[kk * LDU + 32 * mi + l32];
+          er = __builtin_amdgcn_mfma_f32_32x32x2f32(ar, bc[t], er, 0, 0, 0);
+          ei = __builtin_amdgcn_mfma_f32_32x32x2f32(ai, bc[t], ei, 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bc[t] = bn[t];
+      }
     }
     __syncthreads();   // U is consumed
     // E = -i E' = (Im E', -Re E')
