@@ -11,8 +11,9 @@
 // Dense layers run on the BF16 matrix cores (v_mfma_f32_32x32x16_bf16, FP32
 // accumulate).  In the accurate mode every operand is split x = hi + lo with hi,
 // lo in BF16 and the product is hi*hi + hi*lo + lo*hi (relative error ~1e-5); the
-// fast mode uses hi*hi only.  Transposed convolutions are direct FP32 kernels with
-// the sample and the kernel staged in LDS.  Weight gradients of the convolutions
+// fast mode uses hi*hi only.  Transposed convolutions are direct FP32 kernels: the
+// forward computes all output channels of one pixel per thread with the weights read
+// as wave-uniform scalars; the backward kernels stage a sample in LDS.  Weight gradients of the convolutions
 // and all bias gradients are reduced over the batch in a fixed order through
 // per-chunk partial sums; training updates FP32 master weights with Adam.
 #include <algorithm>
@@ -174,38 +175,122 @@ __global__ void sg_colsum_kernel(const float* __restrict__ g, int rows, int cols
 }
 
 // ---------------------------------------------------------------- transposed convolution
-// One workgroup per sample: the sample's input and the whole kernel in LDS.
-__global__ void __launch_bounds__(256) sg_deconv_fwd_kernel(const float* __restrict__ in,
-                                                             const float* __restrict__ K,
-                                                             const float* __restrict__ bias, int Ci, int Co,
-                                                             int H, int relu, float* __restrict__ out) {
-  extern __shared__ float sh[];
-  float* xin = sh;                 // [Ci][H][H]
-  float* kk = sh + Ci * H * H;     // [Ci][Co][16]
-  const int b = blockIdx.x, HO = 2 * H;
-  const float* src = in + (size_t)b * Ci * H * H;
-  for (int i = threadIdx.x; i < Ci * H * H; i += 256) xin[i] = src[i];
-  for (int i = threadIdx.x; i < Ci * Co * 16; i += 256) kk[i] = K[i];
-  __syncthreads();
-  float* dst = out + (size_t)b * Co * HO * HO;
-  for (int o = threadIdx.x; o < Co * HO * HO; o += 256) {
-    const int co = o / (HO * HO), oy = (o / HO) % HO, ox = o % HO;
-    // taps: ky with oy + 1 - ky even, iy = (oy + 1 - ky) / 2 inside [0, H)
-    float s = bias[co];
-    const int ky0 = (oy + 1) & 1, kx0 = (ox + 1) & 1;
+// Weights re-laid for the forward kernel: Kt[ky][kx][ci][co] = K[ci][co][ky][kx].
+__global__ void sg_deconv_wt_kernel(const float* __restrict__ K, int Ci, int Co, float* __restrict__ Kt) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Ci * Co * 16) return;
+  const int ci = i / (Co * 16), co = (i / 16) % Co, ky = (i / 4) % 4, kx = i % 4;
+  Kt[((ky * 4 + kx) * Ci + ci) * Co + co] = K[i];
+}
+
+// Forward transposed convolution, one output pixel (all Co channels) per thread (used
+// for the 32 -> 16 channel layer, where a 2 x 2 block would need 4 Co accumulators and
+// too many scalar weights per step).  Output (oy, ox) = (2 iy + py, 2 ix + px): the taps
+// of parity p are (iy, ky = 1), (iy - 1, ky = 3) for p = 0 and (iy + 1, ky = 0),
+// (iy, ky = 2) for p = 1.  A workgroup covers 256 pixels of one sample ordered by parity
+// class (4 classes of H x H), so the class -- and every weight address -- is the same
+// across a wave (H * H >= 64) and the weights are read as scalars.
+template <int Ci, int Co, int H>
+__global__ void __launch_bounds__(256) sg_deconv_fwd_pix_kernel(const float* __restrict__ in,
+                                                                const float* __restrict__ Kt,
+                                                                const float* __restrict__ bias, int relu,
+                                                                float* __restrict__ out) {
+  static_assert(H * H >= 64 && (4 * H * H) % 256 == 0, "parity class uniform per wave");
+  constexpr int BPS = 4 * H * H / 256;   // workgroups per sample
+  const int b = blockIdx.x / BPS;
+  const int pix = (blockIdx.x % BPS) * 256 + threadIdx.x;
+  const int cls = __builtin_amdgcn_readfirstlane(pix / (H * H));
+  const int q = pix % (H * H), iy = q / H, ix = q % H;
+  const int py = cls >> 1, px = cls & 1;
+  const float* x = in + (size_t)b * Ci * H * H;
+  float acc[Co];
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      const int ky = ky0 + 2 * a, iy = (oy + 1 - ky) >> 1;
-      if (iy < 0 || iy >= H) continue;
+  for (int co = 0; co < Co; ++co) acc[co] = bias[co];
 #pragma unroll
-      for (int c2 = 0; c2 < 2; ++c2) {
-        const int kx = kx0 + 2 * c2, ix = (ox + 1 - kx) >> 1;
-        if (ix < 0 || ix >= H) continue;
-        for (int ci = 0; ci < Ci; ++ci) s += xin[(ci * H + iy) * H + ix] * kk[(ci * Co + co) * 16 + ky * 4 + kx];
+  for (int a = 0; a < 2; ++a) {
+    const int yy = py ? iy + 1 - a : iy - a, ky = py ? 2 * a : 1 + 2 * a;
+    if (yy < 0 || yy >= H) continue;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int xx = px ? ix + 1 - c : ix - c, kx = px ? 2 * c : 1 + 2 * c;
+      if (xx < 0 || xx >= H) continue;
+      const float* w = Kt + (ky * 4 + kx) * Ci * Co;
+      const float* xp = x + yy * H + xx;
+#pragma unroll 4
+      for (int ci = 0; ci < Ci; ++ci) {
+        const float v = xp[ci * H * H];
+#pragma unroll
+        for (int co = 0; co < Co; ++co) acc[co] = fmaf(v, w[ci * Co + co], acc[co]);
       }
     }
-    dst[o] = relu ? fmaxf(s, 0.f) : s;
   }
+  const int oy = 2 * iy + py, ox = 2 * ix + px, HO = 2 * H;
+  float* o = out + (size_t)b * Co * HO * HO + oy * HO + ox;
+#pragma unroll
+  for (int co = 0; co < Co; ++co) o[co * HO * HO] = relu ? fmaxf(acc[co], 0.f) : acc[co];
+}
+
+// Forward transposed convolution: a thread takes one input position (iy, ix) of one
+// sample and computes the 2 x 2 output block (2 iy + py, 2 ix + px), all Co channels.
+// Output row 2 iy + py gets taps (iy, ky = 1), (iy - 1, ky = 3) when py = 0 and
+// (iy + 1, ky = 0), (iy, ky = 2) when py = 1 (likewise along x), so the block reads the
+// 3 x 3 input neighbourhood; every weight address is the same across the wave (read as
+// scalars), and the block is written as 8-byte pairs.
+template <int Ci, int Co, int H>
+__global__ void __launch_bounds__(256) sg_deconv_fwd2_kernel(const float* __restrict__ in,
+                                                             const float* __restrict__ Kt,
+                                                             const float* __restrict__ bias, int relu,
+                                                             int B, float* __restrict__ out) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= B * H * H) return;   // no barrier below
+  const int b = t / (H * H), q = t % (H * H), iy = q / H, ix = q % H;
+  const float* x = in + (size_t)b * Ci * H * H;
+  float acc[2][2][Co];
+#pragma unroll
+  for (int py = 0; py < 2; ++py)
+#pragma unroll
+    for (int px = 0; px < 2; ++px)
+#pragma unroll
+      for (int co = 0; co < Co; ++co) acc[py][px][co] = bias[co];
+  // rows / columns of the neighbourhood: index 0 = iy - 1, 1 = iy, 2 = iy + 1
+  const bool ry[3] = {iy > 0, true, iy + 1 < H}, rx[3] = {ix > 0, true, ix + 1 < H};
+#pragma unroll 2
+  for (int ci = 0; ci < Ci; ++ci) {
+    float v[3][3];
+#pragma unroll
+    for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+      for (int dx = 0; dx < 3; ++dx)
+        v[dy][dx] = (ry[dy] && rx[dx]) ? x[(ci * H + iy + dy - 1) * H + ix + dx - 1] : 0.f;
+#pragma unroll
+    for (int py = 0; py < 2; ++py)
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int dy = py ? 2 - a : 1 - a, ky = py ? 2 * a : 1 + 2 * a;
+#pragma unroll
+        for (int px = 0; px < 2; ++px)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int dx = px ? 2 - c : 1 - c, kx = px ? 2 * c : 1 + 2 * c;
+            const float* w = Kt + ((ky * 4 + kx) * Ci + ci) * Co;
+#pragma unroll
+            for (int co = 0; co < Co; ++co) acc[py][px][co] = fmaf(v[dy][dx], w[co], acc[py][px][co]);
+          }
+      }
+  }
+  constexpr int HO = 2 * H;
+  float* o = out + (size_t)b * Co * HO * HO + (2 * iy) * HO + 2 * ix;
+#pragma unroll
+  for (int co = 0; co < Co; ++co)
+#pragma unroll
+    for (int py = 0; py < 2; ++py) {
+      float a0 = acc[py][0][co], a1 = acc[py][1][co];
+      if (relu) {
+        a0 = fmaxf(a0, 0.f);
+        a1 = fmaxf(a1, 0.f);
+      }
+      *reinterpret_cast<float2*>(o + co * HO * HO + py * HO) = make_float2(a0, a1);
+    }
 }
 
 // dIn[ci, iy, ix] = sum_{co, ky, kx} dOut[co, 2 iy - 1 + ky, 2 ix - 1 + kx] K[ci, co, ky, kx]
@@ -339,6 +424,7 @@ struct rwpsf_sg {
   float *x = nullptr, *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *d1 = nullptr, *d2 = nullptr, *y = nullptr;
   float *gx = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *gd1 = nullptr, *gd2 = nullptr, *gy = nullptr;
   float* partial = nullptr;   // conv weight partials
+  float* kt = nullptr;        // transposed convolution weights of the forward kernels
   double* loss_partial = nullptr;
   int64_t step = 0;
   ~rwpsf_sg() {
@@ -370,14 +456,22 @@ static int sg_forward_impl(rwpsf_sg* s, int B, const float* coef, const float* z
   if ((rc = hip_check(sg_gemm<false, false>(s->x, 22, s->w + L.W1, 256, s->h1, 256, B, 256, 22, s->w + L.b1, 1, nsplit, st)))) return rc;
   if ((rc = hip_check(sg_gemm<false, false>(s->h1, 256, s->w + L.W2, 1024, s->h2, 1024, B, 1024, 256, s->w + L.b2, 1, nsplit, st)))) return rc;
   if ((rc = hip_check(sg_gemm<false, false>(s->h2, 1024, s->w + L.W3, 2048, s->h3, 2048, B, 2048, 1024, s->w + L.b3, 1, nsplit, st)))) return rc;
-  hipLaunchKernelGGL(sg_deconv_fwd_kernel, dim3(B), dim3(256), (32 * 64 + 32 * 16 * 16) * 4, st, s->h3, s->w + L.K1,
-                     s->w + L.c1, 32, 16, 8, 1, s->d1);
+  float* kt1 = s->kt;
+  float* kt2 = kt1 + 32 * 16 * 16;
+  float* kt3 = kt2 + 16 * 8 * 16;
+  hipLaunchKernelGGL(sg_deconv_wt_kernel, dim3(32), dim3(256), 0, st, s->w + L.K1, 32, 16, kt1);
+  hipLaunchKernelGGL(sg_deconv_wt_kernel, dim3(8), dim3(256), 0, st, s->w + L.K2, 16, 8, kt2);
+  hipLaunchKernelGGL(sg_deconv_wt_kernel, dim3(1), dim3(256), 0, st, s->w + L.K3, 8, 1, kt3);
   if ((rc = hip_check(hipGetLastError()))) return rc;
-  hipLaunchKernelGGL(sg_deconv_fwd_kernel, dim3(B), dim3(256), (16 * 256 + 16 * 8 * 16) * 4, st, s->d1, s->w + L.K2,
-                     s->w + L.c2, 16, 8, 16, 1, s->d2);
+  // one thread per input position (B * H * H threads)
+  hipLaunchKernelGGL((sg_deconv_fwd_pix_kernel<32, 16, 8>), dim3(B), dim3(256), 0, st, s->h3, kt1, s->w + L.c1, 1,
+                     s->d1);
   if ((rc = hip_check(hipGetLastError()))) return rc;
-  hipLaunchKernelGGL(sg_deconv_fwd_kernel, dim3(B), dim3(256), (8 * 1024 + 8 * 16) * 4, st, s->d2, s->w + L.K3,
-                     s->w + L.c3, 8, 1, 32, 0, out);
+  hipLaunchKernelGGL((sg_deconv_fwd2_kernel<16, 8, 16>), dim3(B), dim3(256), 0, st, s->d1, kt2, s->w + L.c2, 1, B,
+                     s->d2);
+  if ((rc = hip_check(hipGetLastError()))) return rc;
+  hipLaunchKernelGGL((sg_deconv_fwd2_kernel<8, 1, 32>), dim3(B * 4), dim3(256), 0, st, s->d2, kt3, s->w + L.c3, 0, B,
+                     out);
   return hip_check(hipGetLastError());
 }
 
@@ -464,7 +558,7 @@ int rwpsf_sg_create(int max_batch, rwpsf_sg** out) {
       (rc = sg_alloc(s, &s->g3, B * 2048)) || (rc = sg_alloc(s, &s->gd1, B * 4096)) ||
       (rc = sg_alloc(s, &s->gd2, B * 8192)) || (rc = sg_alloc(s, &s->gy, B * 4096)) ||
       (rc = sg_alloc(s, &s->partial, (size_t)chunks * (32 * 16 * 16 + 16))) ||
-      (rc = sg_alloc(s, &s->loss_partial, 256))) {
+      (rc = sg_alloc(s, &s->loss_partial, 256)) || (rc = sg_alloc(s, &s->kt, 32 * 16 * 16 + 16 * 8 * 16 + 8 * 16))) {
     delete s;
     return rc;
   }
