@@ -121,6 +121,154 @@ static hipError_t sg_gemm(const float* A, int lda, const float* B, int ldb, floa
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- dense GEMM, aligned fast path
+// C[M][N] = relu(A B + bias) for K % 32 == 0 and N % 128 == 0 (the 256 -> 1024 and
+// 1024 -> 2048 layers).  A is FP32 [M][K], split into BF16 hi / lo while it is staged;
+// B is given pre-split as k-contiguous BF16 planes Bt_hi / Bt_lo [N][K].  Workgroup
+// 128 x 128, 4 waves of 64 x 64 (2 x 2 MFMA blocks of 32 x 32 x 16), k-stage 32, two LDS
+// stages; each lane reads its 8 consecutive k of an operand with one 16-byte LDS read.
+constexpr int FBM = 128, FBN = 128, FBK = 32, FLD = FBK + 8;   // LDS row: 40 bf16 (80 B)
+typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+
+// W [K][N] FP32 -> Bt_hi / Bt_lo [N][K] BF16 (hi = bf16(w), lo = bf16(w - hi))
+__global__ void sg_wsplit_kernel(const float* __restrict__ W, int K, int N, __bf16* __restrict__ hi,
+                                 __bf16* __restrict__ lo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K * N) return;
+  const int k = i / N, n = i % N;
+  const float w = W[i];
+  const __bf16 h = (__bf16)w;
+  hi[(size_t)n * K + k] = h;
+  lo[(size_t)n * K + k] = (__bf16)(w - (float)h);
+}
+
+template <int NSPLIT>
+__global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __restrict__ A,
+                                                              const __bf16* __restrict__ Bhi,
+                                                              const __bf16* __restrict__ Blo,
+                                                              float* __restrict__ C, int M, int N, int K,
+                                                              const float* __restrict__ bias, int relu) {
+  constexpr int PL = FBM * FLD;             // one bf16 plane of a tile
+  constexpr int STAGE = 4 * PL;             // A hi, A lo, B hi, B lo
+  extern __shared__ __bf16 shb[];
+  const int tiles_n = N / FBN;
+  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int row0 = tm * FBM, col0 = tn * FBN;
+  f16v_s acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
+  // A: 128 rows x 32 k = 1024 float4, 4 per thread; B: 128 cols x 32 k bf16 = 512 x 16 B per plane
+  float4 ra[4];
+  uint4 rbh[2], rbl[2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + 256 * i, r = idx >> 3, kq = 4 * (idx & 7);
+      const int gr = min(row0 + r, M - 1);   // rows past M are computed but not stored
+      ra[i] = *reinterpret_cast<const float4*>(A + (size_t)gr * K + k0 + kq);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + 256 * i, c = idx >> 2, k8 = 8 * (idx & 3);
+      rbh[i] = *reinterpret_cast<const uint4*>(Bhi + (size_t)(col0 + c) * K + k0 + k8);
+      if (NSPLIT > 1) rbl[i] = *reinterpret_cast<const uint4*>(Blo + (size_t)(col0 + c) * K + k0 + k8);
+    }
+  };
+  auto store = [&](__bf16* st) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int idx = tid + 256 * i, r = idx >> 3, kq = 4 * (idx & 7);
+      const float v[4] = {ra[i].x, ra[i].y, ra[i].z, ra[i].w};
+      bf4_t h, l;
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        h[t] = (__bf16)v[t];
+        l[t] = (__bf16)(v[t] - (float)h[t]);
+      }
+      *reinterpret_cast<bf4_t*>(st + r * FLD + kq) = h;
+      if (NSPLIT > 1) *reinterpret_cast<bf4_t*>(st + PL + r * FLD + kq) = l;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + 256 * i, c = idx >> 2, k8 = 8 * (idx & 3);
+      *reinterpret_cast<uint4*>(st + 2 * PL + c * FLD + k8) = rbh[i];
+      if (NSPLIT > 1) *reinterpret_cast<uint4*>(st + 3 * PL + c * FLD + k8) = rbl[i];
+    }
+  };
+  const int KT = K / FBK;
+  load(0);
+  store(shb);
+  __syncthreads();
+  for (int kt = 0; kt < KT; ++kt) {
+    __bf16* cur = shb + (kt & 1) * STAGE;
+    __bf16* nxt = shb + ((kt + 1) & 1) * STAGE;
+    const bool more = kt + 1 < KT;
+    if (more) load((kt + 1) * FBK);
+#pragma unroll
+    for (int ks = 0; ks < FBK; ks += 16) {
+      const int kb = ks + 8 * (lane >> 5);
+      bf8_t ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const int r = (wm + 32 * i + (lane & 31)) * FLD + kb;
+        ah[i] = *reinterpret_cast<const bf8_t*>(cur + r);
+        if (NSPLIT > 1) al[i] = *reinterpret_cast<const bf8_t*>(cur + PL + r);
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int c = (wn + 32 * j + (lane & 31)) * FLD + kb;
+        bh[j] = *reinterpret_cast<const bf8_t*>(cur + 2 * PL + c);
+        if (NSPLIT > 1) bl[j] = *reinterpret_cast<const bf8_t*>(cur + 3 * PL + c);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+          if (NSPLIT > 1) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+          }
+        }
+    }
+    if (more) store(nxt);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int n = col0 + wn + 32 * j + (lane & 31);
+    const float bn = bias ? bias[n] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int m = row0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        if (m < M) {
+          float v = acc[i][j][r] + bn;
+          if (relu) v = fmaxf(v, 0.f);
+          C[(size_t)m * N + n] = v;
+        }
+      }
+  }
+}
+
+static hipError_t sg_gemm_fast(const float* A, const __bf16* Bh, const __bf16* Bl, float* C, int M, int N, int K,
+                               const float* bias, int nsplit, hipStream_t st) {
+  const dim3 grid(((M + FBM - 1) / FBM) * (N / FBN));
+  const int lds = 2 * 4 * FBM * FLD * (int)sizeof(__bf16);
+  if (nsplit > 1)
+    hipLaunchKernelGGL(sg_gemm_fast_kernel<3>, grid, dim3(256), lds, st, A, Bh, Bl, C, M, N, K, bias, 1);
+  else
+    hipLaunchKernelGGL(sg_gemm_fast_kernel<1>, grid, dim3(256), lds, st, A, Bh, Bl, C, M, N, K, bias, 1);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- elementwise
 __global__ void sg_features_kernel(const float* __restrict__ coef, const float* __restrict__ z, int B,
                                    float* __restrict__ x) {
@@ -425,6 +573,7 @@ struct rwpsf_sg {
   float *gx = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *gd1 = nullptr, *gd2 = nullptr, *gy = nullptr;
   float* partial = nullptr;   // conv weight partials
   float* kt = nullptr;        // transposed convolution weights of the forward kernels
+  __bf16* wsplit = nullptr;   // BF16 hi / lo planes of W2 and W3, [N][K]
   double* loss_partial = nullptr;
   int64_t step = 0;
   ~rwpsf_sg() {
@@ -454,8 +603,16 @@ static int sg_forward_impl(rwpsf_sg* s, int B, const float* coef, const float* z
   hipLaunchKernelGGL(sg_features_kernel, dim3((B * 22 + 255) / 256), dim3(256), 0, st, coef, z, B, s->x);
   if ((rc = hip_check(hipGetLastError()))) return rc;
   if ((rc = hip_check(sg_gemm<false, false>(s->x, 22, s->w + L.W1, 256, s->h1, 256, B, 256, 22, s->w + L.b1, 1, nsplit, st)))) return rc;
-  if ((rc = hip_check(sg_gemm<false, false>(s->h1, 256, s->w + L.W2, 1024, s->h2, 1024, B, 1024, 256, s->w + L.b2, 1, nsplit, st)))) return rc;
-  if ((rc = hip_check(sg_gemm<false, false>(s->h2, 1024, s->w + L.W3, 2048, s->h3, 2048, B, 2048, 1024, s->w + L.b3, 1, nsplit, st)))) return rc;
+  // the two wide layers on the aligned fast path, with the weights split to BF16 planes
+  __bf16* w2h = s->wsplit;
+  __bf16* w2l = w2h + 256 * 1024;
+  __bf16* w3h = w2l + 256 * 1024;
+  __bf16* w3l = w3h + 1024 * 2048;
+  hipLaunchKernelGGL(sg_wsplit_kernel, dim3(256 * 1024 / 256), dim3(256), 0, st, s->w + L.W2, 256, 1024, w2h, w2l);
+  hipLaunchKernelGGL(sg_wsplit_kernel, dim3(1024 * 2048 / 256), dim3(256), 0, st, s->w + L.W3, 1024, 2048, w3h, w3l);
+  if ((rc = hip_check(hipGetLastError()))) return rc;
+  if ((rc = hip_check(sg_gemm_fast(s->h1, w2h, w2l, s->h2, B, 1024, 256, s->w + L.b2, nsplit, st)))) return rc;
+  if ((rc = hip_check(sg_gemm_fast(s->h2, w3h, w3l, s->h3, B, 2048, 1024, s->w + L.b3, nsplit, st)))) return rc;
   float* kt1 = s->kt;
   float* kt2 = kt1 + 32 * 16 * 16;
   float* kt3 = kt2 + 16 * 8 * 16;
@@ -558,7 +715,16 @@ int rwpsf_sg_create(int max_batch, rwpsf_sg** out) {
       (rc = sg_alloc(s, &s->g3, B * 2048)) || (rc = sg_alloc(s, &s->gd1, B * 4096)) ||
       (rc = sg_alloc(s, &s->gd2, B * 8192)) || (rc = sg_alloc(s, &s->gy, B * 4096)) ||
       (rc = sg_alloc(s, &s->partial, (size_t)chunks * (32 * 16 * 16 + 16))) ||
-      (rc = sg_alloc(s, &s->loss_partial, 256)) || (rc = sg_alloc(s, &s->kt, 32 * 16 * 16 + 16 * 8 * 16 + 8 * 16))) {
+      (rc = sg_alloc(s, &s->loss_partial, 256)) || (rc = sg_alloc(s, &s->kt, 32 * 16 * 16 + 16 * 8 * 16 + 8 * 16)) ||
+      (rc = sg_alloc(s, &s->wsplit, 2 * (256 * 1024 + 1024 * 2048)))) {
+    delete s;
+    return rc;
+  }
+  const int fast_lds = 2 * 4 * FBM * FLD * (int)sizeof(__bf16);
+  if ((rc = hip_check(hipFuncSetAttribute((const void*)sg_gemm_fast_kernel<1>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, fast_lds))) ||
+      (rc = hip_check(hipFuncSetAttribute((const void*)sg_gemm_fast_kernel<3>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, fast_lds)))) {
     delete s;
     return rc;
   }
