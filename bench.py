@@ -123,6 +123,38 @@ def bench_fourier(rw, torch, steps, warmup):
         step_frac=round(step_flops / (ms_step * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4))
 
 
+def bench_chirpz(rw, torch, steps, warmup):
+    """The headline workload through the chirp-z (FFT) evaluation of the same sum, and the
+    matrix DFT vs chirp-z crossover over pupil sizes (8 stacks, 128x128x64)."""
+    w, zp, stacks = fourier_workload()
+    o = w["optics"]
+
+    def run(form, n, st, nsteps):
+        plan = rw.Plan(form=form, na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], nx=128, ny=128, dx=20.0,
+                       dy=20.0, z=zp, e_inc=w["e_inc"], gibson_lanni=w["gl"], n_pupil=n)
+        E = torch.empty((len(st), 64, 3, 128, 128), dtype=torch.complex64, device="cuda")
+        I = torch.empty((len(st), 64, 128, 128), dtype=torch.float32, device="cuda")
+        for _ in range(warmup):
+            plan.compute(st, E=E, I=I)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nsteps):
+            plan.compute(st, E=E, I=I)
+        torch.cuda.synchronize()
+        plan.close()
+        return (time.perf_counter() - t0) * 1e3 / nsteps
+
+    ms = run(rw.FORM_CHIRPZ, 256, stacks, steps)
+    voxels = len(stacks) * 64 * 128 * 128
+    cross = {}
+    for n in (128, 256, 512, 1024):
+        cross[str(n)] = dict(matrix_dft_ms=run(rw.FORM_FOURIER, n, stacks[:8], 3),
+                             chirpz_ms=run(rw.FORM_CHIRPZ, n, stacks[:8], 3))
+    return dict(workload="chirp-z evaluation of the fourier_plain workload (same sum, FFT convolutions of "
+                         "length 512 along y and x)", value=voxels / (ms * 1e-3), unit="voxels/s",
+                ms_per_step=ms, crossover_8_stacks_128x128x64=cross)
+
+
 def bench_bessel(rw, torch, steps, warmup, n_stacks=256):
     import workloads as W
     w = W.bessel_plain(n_stacks=n_stacks)
@@ -344,7 +376,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="bessel,batched,adjoint,surrogate",
+    ap.add_argument("--forms", default="chirpz,bessel,batched,adjoint,surrogate",
                     help="comma list of extra forms, or 'none'")
     ap.add_argument("--train-seconds", type=float, default=20.0)
     ap.add_argument("--copy-reference", action="store_true",
@@ -371,6 +403,9 @@ def main():
     print(f"# fourier: {res['ms_per_step']:.3f} ms/step, {res['value']:.3e} voxels/s", file=sys.stderr,
           flush=True)
     forms = {}
+    if "chirpz" in args.forms.split(","):
+        forms["chirpz"] = bench_chirpz(rw, torch, args.steps, args.warmup)
+        print(f"# chirpz: {forms['chirpz']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if "bessel" in args.forms.split(","):
         forms["bessel"] = bench_bessel(rw, torch, args.steps, args.warmup)
         print(f"# bessel: {forms['bessel']['value']:.3e} voxels/s", file=sys.stderr, flush=True)

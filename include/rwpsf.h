@@ -59,7 +59,13 @@ enum rwpsf_status_code {
   RWPSF_ERR_NO_DEVICE = -6         /* no usable gfx950 device */
 };
 
-enum rwpsf_form { RWPSF_FORM_BESSEL = 0, RWPSF_FORM_FOURIER = 1 };
+/* RWPSF_FORM_CHIRPZ evaluates the same discrete Cartesian sum as RWPSF_FORM_FOURIER
+   with the chirp-z (Bluestein) transform of Sec. 3.3: per z-plane and component, one
+   FFT convolution along y for every pupil row and one along x for every output column
+   (FFT lengths: powers of two >= N + ny - 1 and N + nx - 1, at most 2048; N <= 1024).
+   It needs fewer flops than the matrix DFT for large pupils; the result agrees with
+   RWPSF_FORM_FOURIER to FP32 rounding.  The adjoint is not available for it. */
+enum rwpsf_form { RWPSF_FORM_BESSEL = 0, RWPSF_FORM_FOURIER = 1, RWPSF_FORM_CHIRPZ = 2 };
 
 /* Physical parameters (Sec. 3.1, 3.3, 3.4). */
 typedef struct rwpsf_optics {
@@ -272,6 +278,8 @@ enum rwpsf_kernel_id {
   RWPSF_KERNEL_ADJ_H = 6,             /* adjoint: (2 dL/dI E) conj(Ay) */
   RWPSF_KERNEL_ADJ_G = 7,             /* adjoint: Ax'^H H with Im(G conj(P~)) accumulation */
   RWPSF_KERNEL_ADJ_REDUCE = 8,        /* adjoint: fixed-order reductions to dL/dW0, dL/dc */
+  RWPSF_KERNEL_CZT_ROWS = 9,          /* chirp-z: pupil rows (defocus, FFT convolution along y) */
+  RWPSF_KERNEL_CZT_COLS = 10,         /* chirp-z: output columns (FFT convolution along x), |E|^2 */
   RWPSF_KERNEL_COUNT = 16
 };
 int rwpsf_plan_set_timing(rwpsf_plan* plan, int enable);   /* also resets the totals */

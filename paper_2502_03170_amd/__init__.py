@@ -25,6 +25,7 @@ ERR_HIP = -5
 ERR_NO_DEVICE = -6
 FORM_BESSEL = 0
 FORM_FOURIER = 1
+FORM_CHIRPZ = 2
 KERNEL_PUPIL_BUILD = 0
 KERNEL_GEMM_PUPIL = 1
 KERNEL_GEMM_IMAGE = 2
@@ -34,6 +35,8 @@ KERNEL_BESSEL_EPILOGUE = 5
 KERNEL_ADJ_H = 6
 KERNEL_ADJ_G = 7
 KERNEL_ADJ_REDUCE = 8
+KERNEL_CZT_ROWS = 9
+KERNEL_CZT_COLS = 10
 MAX_ZERNIKE = 36
 CIRCULAR = (1 / math.sqrt(2), 1j / math.sqrt(2))
 

@@ -90,6 +90,9 @@ int validate_plan(const rwpsf_optics* o, const rwpsf_grid* g, const rwpsf_numeri
     if (!std::isfinite(g->z_nm[i])) return RWPSF_ERR_INVALID_ARG;
   if (nm->form == RWPSF_FORM_FOURIER) {
     if (nm->n_pupil < 2 || nm->n_pupil > 1024) return RWPSF_ERR_INVALID_ARG;
+  } else if (nm->form == RWPSF_FORM_CHIRPZ) {
+    if (nm->n_pupil < 2 || nm->n_pupil > 1024) return RWPSF_ERR_INVALID_ARG;
+    if (nm->n_pupil + std::max(g->nx, g->ny) - 1 > 2048) return RWPSF_ERR_UNSUPPORTED;
   } else if (nm->form == RWPSF_FORM_BESSEL) {
     if (nm->n_theta < 2 || nm->n_theta > 4096) return RWPSF_ERR_INVALID_ARG;
     if (nm->n_rho < 8 || nm->n_rho > 65536) return RWPSF_ERR_INVALID_ARG;
@@ -281,6 +284,7 @@ int rwpsf_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, void* E, float* I,
   if (st != RWPSF_OK) return st;
   if (p->num.form == RWPSF_FORM_FOURIER)
     return rw::fourier_compute(p, n, s, (float2*)E, I, (hipStream_t)stream);
+  if (p->num.form == RWPSF_FORM_CHIRPZ) return rw::czt_compute(p, n, s, (float2*)E, I, (hipStream_t)stream);
   return rw::bessel_compute(p, n, s, (float2*)E, I, (hipStream_t)stream);
 }
 

@@ -85,12 +85,13 @@ static int fourier_plan_init(rwpsf_plan* p) {
   if ((st = dev_alloc(p, &p->d_z, (size_t)p->grid.nz))) return st;
   p->P_stacks = kPupilStacks;
   if ((st = dev_alloc(p, &p->d_P, (size_t)p->P_stacks * 3 * npp))) return st;
-  if ((st = dev_alloc(p, &p->d_Pf, (size_t)p->P_stacks * 3 * w * w))) return st;
+  const bool gemm = p->num.form == RWPSF_FORM_FOURIER;   // the chirp-z form needs no GEMM workspaces
+  if (gemm && (st = dev_alloc(p, &p->d_Pf, (size_t)p->P_stacks * 3 * w * w))) return st;
   // plane workspace: whole chunk of stacks x planes, capped at 512 MiB
   const size_t plane_bytes = 3 * (size_t)w * nyp * sizeof(float2);
   const size_t want = (size_t)kPupilStacks * p->grid.nz;
   p->T_planes = std::max<size_t>(1, std::min(want, (size_t)(512u << 20) / plane_bytes));
-  if ((st = dev_alloc(p, &p->d_T, p->T_planes * 3 * (size_t)w * nyp))) return st;
+  if (gemm && (st = dev_alloc(p, &p->d_T, p->T_planes * 3 * (size_t)w * nyp))) return st;
 
   if ((st = hip_check(hipMemcpy(p->d_Q, Q.data(), Q.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
   if ((st = hip_check(hipMemcpy(p->d_ksz, ksz.data(), ksz.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
@@ -126,6 +127,10 @@ int plan_init(rwpsf_plan* p, const rwpsf_optics& o, const rwpsf_grid& g, const r
   p->gl.t_g_d = o.t_g_design_nm;
   p->gl.t_i_d = o.t_i_design_nm;
   if (nm.form == RWPSF_FORM_FOURIER) return fourier_plan_init(p);
+  if (nm.form == RWPSF_FORM_CHIRPZ) {
+    const int st = fourier_plan_init(p);
+    return st ? st : czt_plan_init(p);
+  }
   return bessel_plan_init(p);
 }
 

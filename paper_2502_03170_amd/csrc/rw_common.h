@@ -172,6 +172,14 @@ struct rwpsf_plan {
   double* d_runs = nullptr;     // [partial runs][N][N] first level of the dL/dPhi reduction
   int P_stacks = 0;             // capacity of d_P in stacks
 
+  // chirp-z evaluation of the Fourier form
+  int czt_Ly = 0, czt_Lx = 0, czt_cb = 0;   // FFT lengths, output columns per workgroup
+  float2* d_czt = nullptr;       // tables: pre/post/chat along y, then along x
+  float2 *czt_pre_y = nullptr, *czt_post_y = nullptr, *czt_chat_y = nullptr;
+  float2 *czt_pre_x = nullptr, *czt_post_x = nullptr, *czt_chat_x = nullptr;
+  float2* d_czt_T = nullptr;     // workspace [planes][3][N][ny]
+  size_t czt_planes = 0;
+
   // Bessel form
   int n_theta_total = 0;        // nodes after the critical-angle split
   double* d_theta = nullptr;    // [T] nodes

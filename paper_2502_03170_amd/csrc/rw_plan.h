@@ -15,6 +15,8 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
 int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st);
 int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E, const float* dLdI,
                     int n_zernike, float* dc, float* dW0, hipStream_t st);
+int czt_plan_init(rwpsf_plan* p);
+int czt_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);
 int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);
 
 // Vectorial far field e_inf of Sec. 3.3 eq. "field Gaussian sphere" with q_s = q_p = 1,
