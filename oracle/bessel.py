@@ -38,10 +38,15 @@ def _axisymmetric_phase(sin_t, opt: O.Optics, zernike=None, t_s: float = 0.0,
     return w
 
 
-def theta_rule(opt: O.Optics, n_theta: int, substitute: bool = True):
+def theta_rule(opt: O.Optics, n_theta: int, substitute: bool = True, rule: str = "gauss"):
     """Quadrature nodes/weights on [0, theta_max].
 
-    Without a sample layer: n_theta Gauss-Legendre nodes.  With Gibson-Lanni and a
+    ``rule`` = "simpson": composite Simpson's rule on n_theta (odd) equally spaced
+    nodes including both ends, step h = theta_max / (n_theta - 1) (the rule of
+    Sec. 4.1); "riemann": the left Riemann sum, nodes i h for i < n_theta,
+    h = theta_max / n_theta (the first-order rule of Sec. 5.2.2).  Neither splits
+    the range.  "gauss":
+    without a sample layer: n_theta Gauss-Legendre nodes.  With Gibson-Lanni and a
     critical angle t_c inside the aperture, sqrt(n_s^2 - n_i^2 sin^2 t) has a
     square-root branch point at t_c; the range is split there and, with
     ``substitute``, each side is mapped by t = t_c - t_c (1 - u)^2 resp.
@@ -49,6 +54,19 @@ def theta_rule(opt: O.Optics, n_theta: int, substitute: bool = True):
     integrand smooth in u), with n_theta GL nodes in u on each side.
     """
     tmax = opt.theta_max
+    if rule == "simpson":
+        if n_theta < 3 or n_theta % 2 == 0:
+            raise ValueError("Simpson's rule needs an odd number of nodes >= 3")
+        h = tmax / (n_theta - 1)
+        w = np.full(n_theta, 2.0)
+        w[1::2] = 4.0
+        w[0] = w[-1] = 1.0
+        return h * np.arange(n_theta), w * (h / 3.0)
+    if rule == "riemann":
+        h = tmax / n_theta
+        return h * np.arange(n_theta), np.full(n_theta, h)
+    if rule != "gauss":
+        raise ValueError(rule)
     if opt.gl is None or opt.gl.n_s >= opt.na:
         return O.gauss_legendre(n_theta, 0.0, tmax)
     tc = math.asin(opt.gl.n_s / opt.n_i)
@@ -64,14 +82,20 @@ def theta_rule(opt: O.Optics, n_theta: int, substitute: bool = True):
 
 
 def bessel_integrals(rho, z, opt: O.Optics, n_theta: int = 256, zernike=None, t_s: float = 0.0,
-                     gl_compensated: bool = False, scalar: bool = False, extra_cos: bool = False):
+                     gl_compensated: bool = False, scalar: bool = False, extra_cos: bool = False,
+                     rule: str = "gauss"):
     """I_0, I_1, I_2 (eq. "I0") without the polarisation factor e_inc^a.
 
     Shapes: rho (R,), z (Z,) -> each (Z, R) complex128.  The pupil factor
     p(theta) = a(theta) exp(i W(theta)) multiplies every integrand.  With
     ``scalar`` only I_0 with weight sin t is returned (eq. "polar scalar final").
+
+    With Fresnel media the angular weights follow from integrating eq. "field
+    Gaussian sphere" over phi with q_s, q_p kept: sin t (q_s + q_p cos t) for I_0,
+    q_p sin^2 t for I_1 and sin t (q_p cos t - q_s) for I_2 (q_s = q_p = 1 gives the
+    printed weights).
     """
-    t, w = theta_rule(opt, n_theta)
+    t, w = theta_rule(opt, n_theta, rule=rule)
     sin_t, cos_t = np.sin(t), np.cos(t)
     p = O.amplitude(cos_t, sin_t, opt) * np.exp(1j * _axisymmetric_phase(sin_t, opt, zernike, t_s,
                                                                        gl_compensated))
@@ -85,7 +109,8 @@ def bessel_integrals(rho, z, opt: O.Optics, n_theta: int = 256, zernike=None, t_
     if scalar:
         g = [sin_t]
     else:
-        g = [sin_t * (cos_t + 1.0), sin_t ** 2, sin_t * (cos_t - 1.0)]
+        qs, qp = O.fresnel_q(sin_t, opt)
+        g = [sin_t * (qs + qp * cos_t), qp * sin_t ** 2, sin_t * (qp * cos_t - qs)]
     out = []
     for n, gn in enumerate(g):
         kern = special.jv(n, arg) * (w * gn * p)[None, :]   # (R, T)
@@ -95,14 +120,21 @@ def bessel_integrals(rho, z, opt: O.Optics, n_theta: int = 256, zernike=None, t_
 
 def field_bessel(opt: O.Optics, nx: int, ny: int, dx: float, dy: float, z, x0: float = 0.0,
                  y0: float = 0.0, n_theta: int = 256, zernike=None, t_s: float = 0.0,
-                 gl_compensated: bool = False):
-    """Vectorial field (Z, 3, nx, ny) from eq. "polar vectorial final" at exact pixel radii."""
+                 gl_compensated: bool = False, rule: str = "gauss", scalar: bool = False,
+                 extra_cos: bool = False):
+    """Field at exact pixel radii: vectorial (Z, 3, nx, ny) from eq. "polar vectorial
+    final", or with ``scalar`` (Z, 1, nx, ny) from eq. "polar scalar final"."""
     xs = O.output_axis(nx, dx, x0)
     ys = O.output_axis(ny, dy, y0)
     X, Y = np.meshgrid(xs, ys, indexing="ij")
     rho = np.hypot(X, Y).ravel()
     varphi = np.arctan2(Y, X).ravel()            # 0 on the axis
-    I0, I1, I2 = bessel_integrals(rho, z, opt, n_theta, zernike, t_s, gl_compensated)
+    if scalar:
+        (I0,) = bessel_integrals(rho, z, opt, n_theta, zernike, t_s, gl_compensated, scalar=True,
+                                 extra_cos=extra_cos, rule=rule)
+        return (-1j * opt.f * opt.k * I0).reshape(I0.shape[0], 1, nx, ny)
+    I0, I1, I2 = bessel_integrals(rho, z, opt, n_theta, zernike, t_s, gl_compensated,
+                                  extra_cos=extra_cos, rule=rule)
     ex, ey = opt.e_inc
     c1, s1 = np.cos(varphi), np.sin(varphi)
     c2, s2 = np.cos(2 * varphi), np.sin(2 * varphi)
@@ -146,7 +178,8 @@ def field_polar(opt: O.Optics, points, x0: float = 0.0, y0: float = 0.0, n_theta
         field = amp[None]
     else:
         ex, ey = opt.e_inc
-        field = O.far_field(ex, ey, cos_t, sin_t, cos_p, sin_p) * amp[None]
+        qs, qp = O.fresnel_q(sin_t, opt)
+        field = O.far_field(ex, ey, cos_t, sin_t, cos_p, sin_p, qs, qp) * amp[None]
     field = field.reshape(field.shape[0], -1)
     sx, sy, sz = (sin_t * cos_p).ravel(), (sin_t * sin_p).ravel(), cos_t.ravel()
     pts = np.atleast_2d(np.asarray(points, dtype=np.float64))

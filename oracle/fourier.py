@@ -51,7 +51,9 @@ def pupil_phase(geom, opt: O.Optics, zernike=None, phase_map=None, t_s: float = 
 def base_pupil(geom, opt: O.Optics, phase=None, scalar: bool = False, extra_cos: bool = False):
     """P_c[j, l] = ds^2 * a * exp(iW) * e_inf,c / s_z on the disk, 0 outside.
 
-    ``scalar`` uses e_inf = e_inc as one channel of amplitude 1 (Sec. 3.2);
+    ``scalar`` uses e_inf = e_inc as one channel of amplitude 1 (Sec. 3.2; the scalar
+    model has no Fresnel factors); the vectorial far field carries the Fresnel
+    products q_s, q_p of ``opt.fresnel_media`` (1 when empty);
     ``extra_cos`` multiplies by s_z, which turns the integrand into the
     Fourier transform of the flat disk (the Airy comparison of Sec. 5.2.2).
     """
@@ -69,7 +71,8 @@ def base_pupil(geom, opt: O.Optics, phase=None, scalar: bool = False, extra_cos:
     sin_p = np.where(sin_t > 0, geom["sy"] / np.where(sin_t > 0, sin_t, 1.0), 0.0)
     cos_p = np.where(sin_t > 0, geom["sx"] / np.where(sin_t > 0, sin_t, 1.0), 1.0)
     ex, ey = opt.e_inc
-    e_far = O.far_field(ex, ey, cos_t, sin_t, cos_p, sin_p)
+    qs, qp = O.fresnel_q(sin_t, opt)
+    e_far = O.far_field(ex, ey, cos_t, sin_t, cos_p, sin_p, qs, qp)
     return e_far * common[None]
 
 

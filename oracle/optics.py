@@ -35,6 +35,9 @@ class Optics:
     apodization: bool = True    # sqrt(cos theta), Sec. 3.4.3
     s_env: float = 0.0          # Gaussian envelope width, Sec. 3.4.4 (0 = off)
     gl: GibsonLanni | None = None
+    # Fresnel transmission (Sec. 3.3): indices of the media the light crosses before
+    # the immersion medium, emitter side first, e.g. (n_s, n_g); () = q_s = q_p = 1.
+    fresnel_media: tuple = ()
 
     @property
     def k(self) -> float:
@@ -72,6 +75,29 @@ def far_field(ex, ey, cos_t, sin_t, cos_p, sin_p, qs=1.0, qp=1.0):
         -2.0 * qp * sin_p * sin_t,
     ])
     return vx * (ex / 2.0) + vy * (ey / 2.0)
+
+
+def fresnel_q(sin_t, optics: Optics):
+    """Products q_s, q_p of the Fresnel transmission coefficients (Sec. 3.3, the
+    coefficients that enter eq. "field Gaussian sphere").
+
+    The media are ``optics.fresnel_media`` followed by the immersion n_i.  Every ray
+    keeps n_m sin t_m = n_i sin t, and n_m cos t_m = sqrt(n_m^2 - (n_i sin t)^2) on the
+    principal branch (positive imaginary beyond a critical angle).  Interface m -> m+1
+    transmits q_s^m = 2 n_m cos t_m / (n_m cos t_m + n_{m+1} cos t_{m+1}) and
+    q_p^m = 2 n_m cos t_m / (n_{m+1} cos t_m + n_m cos t_{m+1}).
+    """
+    inv2 = (optics.n_i * np.asarray(sin_t, dtype=np.float64)) ** 2
+    media = [float(n) for n in optics.fresnel_media] + [float(optics.n_i)]
+    qs = np.ones(np.shape(sin_t), dtype=np.complex128)
+    qp = np.ones(np.shape(sin_t), dtype=np.complex128)
+    for n1, n2 in zip(media[:-1], media[1:]):
+        nc1 = np.sqrt((n1 * n1 - inv2).astype(np.complex128))   # n1 cos t1
+        nc2 = np.sqrt((n2 * n2 - inv2).astype(np.complex128))   # n2 cos t2
+        c1, c2 = nc1 / n1, nc2 / n2
+        qs = qs * (2.0 * nc1 / (nc1 + nc2))
+        qp = qp * (2.0 * nc1 / (n2 * c1 + n1 * c2))
+    return qs, qp
 
 
 # ---------------------------------------------------------------------------
