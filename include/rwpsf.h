@@ -26,8 +26,9 @@
  *     division), the emitter at (x0, y0), the defocus of plane p is
  *     z[p] + z_offset (observation plane minus emitter plane);
  *   - outputs follow the paper's (z, channel, x, y) order (Sec. 4.1), y
- *     fastest: E as interleaved complex64 [stack][z][3][nx][ny], I as float
- *     [stack][z][nx][ny];
+ *     fastest: E as interleaved complex64 [stack][z][C][nx][ny] with C = 3
+ *     channels for the vectorial model and C = 1 for the scalar model, I as
+ *     float [stack][z][nx][ny] (the sum of |E_c|^2 over the channels);
  *   - status codes: 0 = RWPSF_OK, negative = error (rwpsf_status_string).
  *     Argument errors are reported before anything is enqueued; kernel
  *     faults surface at the caller's next synchronisation.  No call blocks
@@ -47,7 +48,7 @@
 extern "C" {
 #endif
 
-#define RWPSF_ABI_VERSION 1
+#define RWPSF_ABI_VERSION 2
 
 enum rwpsf_status_code {
   RWPSF_OK = 0,
@@ -67,6 +68,21 @@ enum rwpsf_status_code {
    RWPSF_FORM_FOURIER to FP32 rounding.  The adjoint is not available for it. */
 enum rwpsf_form { RWPSF_FORM_BESSEL = 0, RWPSF_FORM_FOURIER = 1, RWPSF_FORM_CHIRPZ = 2 };
 
+/* Propagation model (Sec. 3.2 and 3.3): the vectorial model rotates the incident
+   polarisation onto the Gaussian sphere (eq. "field Gaussian sphere") and gives three
+   channels; the scalar model takes the far field equal to a unit incident amplitude
+   (eq. "cartesian scalar", eq. "polar scalar final") and gives one channel.  The
+   polarisation fields and the Fresnel factors do not enter the scalar model. */
+enum rwpsf_model { RWPSF_MODEL_VECTORIAL = 0, RWPSF_MODEL_SCALAR = 1 };
+
+/* Theta quadrature of the Bessel form.  GAUSS: n_theta Gauss-Legendre nodes on
+   [0, theta_max], split at the sample's critical angle when Gibson-Lanni puts one
+   inside the aperture.  SIMPSON: composite Simpson's rule on n_theta equally spaced
+   nodes including both ends (n_theta odd, >= 3), the rule of Sec. 4.1.  RIEMANN: left
+   Riemann sum, nodes i h (i < n_theta), h = theta_max / n_theta, the first-order rule
+   of Sec. 5.2.2.  SIMPSON and RIEMANN do not split the range. */
+enum rwpsf_theta_rule { RWPSF_THETA_GAUSS = 0, RWPSF_THETA_SIMPSON = 1, RWPSF_THETA_RIEMANN = 2 };
+
 /* Physical parameters (Sec. 3.1, 3.3, 3.4). */
 typedef struct rwpsf_optics {
   double na;             /* numerical aperture, 0 < na < n_i */
@@ -80,6 +96,15 @@ typedef struct rwpsf_optics {
   int gibson_lanni;      /* 1: add the stratified-layer OPD of Sec. 3.4.1 */
   double n_s, n_g, n_g_design, n_i_design;        /* sample, glass (actual, design), immersion design */
   double t_g_nm, t_g_design_nm, t_i_design_nm;    /* thicknesses; t_i from eq. "gibson lanni t_i" */
+  int fresnel;           /* 1: the far field carries the products q_s, q_p of the Fresnel
+                            transmission coefficients (Sec. 3.3) of the interfaces sample
+                            (n_s) -> coverslip (n_g) -> immersion (n_i); each ray keeps
+                            n_m sin t_m = n_i sin t, and beyond a critical angle n_m cos t_m
+                            is taken on the positive imaginary branch.  Vectorial model only
+                            (RWPSF_ERR_UNSUPPORTED with the scalar model). */
+  int extra_sz;          /* 1: a(s) *= s_z = cos theta, the factor that turns the scalar
+                            integral into the Fourier transform of the flat disk (the Airy
+                            comparison of Sec. 5.2.2); 0 = off */
 } rwpsf_optics;
 
 /* Output sampling.  z_nm (host, nz values) is copied at plan creation. */
@@ -96,6 +121,8 @@ typedef struct rwpsf_numerics {
   int n_pupil;  /* Fourier: pupil cells per axis, 2..1024 */
   int n_theta;  /* Bessel: Gauss-Legendre nodes on [0, theta_max], 2..4096 */
   int n_rho;    /* Bessel: radial samples, 8..65536 */
+  int model;    /* rwpsf_model (0 = vectorial) */
+  int theta_rule; /* Bessel: rwpsf_theta_rule (0 = Gauss-Legendre) */
 } rwpsf_numerics;
 
 /* One stack of a compute call: emitter and aberration (Sec. 3.4.1, 3.4.2). */
@@ -145,7 +172,7 @@ void rwpsf_plan_destroy(rwpsf_plan* plan);
 size_t rwpsf_plan_device_bytes(const rwpsf_plan* plan);
 
 /* Plain forward evaluation of n_stacks stacks (1..RWPSF_MAX_STACKS_PER_CALL).
-   E_out: device complex64 [n_stacks][nz][3][nx][ny] or NULL;
+   E_out: device complex64 [n_stacks][nz][C][nx][ny] (C = 3 vectorial, 1 scalar) or NULL;
    I_out: device float [n_stacks][nz][nx][ny] or NULL (not both NULL).
    Enqueued on `stream`; returns after the enqueue. */
 int rwpsf_compute(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
@@ -161,8 +188,8 @@ int rwpsf_compute(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
               (may be NULL when n_zernike = 0);
      dL_dW0 : device float [n_pupil][n_pupil], dL/dW0 on the pupil cells (radians),
               0 outside the disk; may be NULL.
-   Outputs are overwritten, never accumulated.  Fourier form with nx, ny multiples
-   of 16 (RWPSF_ERR_UNSUPPORTED otherwise).  Every reduction runs in a fixed order,
+   Outputs are overwritten, never accumulated.  Fourier form, vectorial model, with
+   nx, ny multiples of 16 (RWPSF_ERR_UNSUPPORTED otherwise).  Every reduction runs in a fixed order,
    so repeated calls give bitwise-identical results. */
 int rwpsf_adjoint(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, const void* E_in,
                   const float* dL_dI, int n_zernike, float* dL_dc, float* dL_dW0, void* stream);
@@ -171,7 +198,8 @@ int rwpsf_adjoint(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, con
    Thousands of emitters, each with its own sub-pixel position, axial position,
    Zernike vector, crop size and plane count, evaluated by the Fourier form in one
    persistent launch (optionally replayed from a captured hipGraph).  Optics as in
-   rwpsf_optics (the Gibson-Lanni layer is not supported here).  Emitter b gets
+   rwpsf_optics, vectorial model (the Gibson-Lanni layer is not supported here; the
+   Fresnel factors and the extra s_z factor are).  Emitter b gets
    crop x crop pixels at pitch pixel_nm, pixel (i, j) at ((i - crop/2) p, (j - crop/2) p)
    relative to the crop centre, and `planes` planes at z_d = (d - (planes-1)/2) *
    plane_pitch_nm, d = 0..planes-1; its defocus is z_d - z_nm.  Outputs are packed in
@@ -192,7 +220,7 @@ typedef struct rwpsf_emitter {
 typedef struct rwpsf_batch rwpsf_batch;
 
 /* Tables and workspace for up to max_emitters emitters on the current device.
-   n_pupil: 32..256 and a multiple of 32.  Synchronous. */
+   n_pupil: 32, 64, 96 or 128.  Synchronous. */
 int rwpsf_batch_create(const rwpsf_optics* optics, int n_pupil, double pixel_nm,
                        double plane_pitch_nm, int max_emitters, rwpsf_batch** out);
 void rwpsf_batch_destroy(rwpsf_batch* batch);

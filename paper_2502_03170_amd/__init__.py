@@ -26,6 +26,11 @@ ERR_NO_DEVICE = -6
 FORM_BESSEL = 0
 FORM_FOURIER = 1
 FORM_CHIRPZ = 2
+MODEL_VECTORIAL = 0
+MODEL_SCALAR = 1
+THETA_GAUSS = 0
+THETA_SIMPSON = 1
+THETA_RIEMANN = 2
 KERNEL_PUPIL_BUILD = 0
 KERNEL_GEMM_PUPIL = 1
 KERNEL_GEMM_IMAGE = 2
@@ -53,7 +58,8 @@ class Optics(ctypes.Structure):
                 ("ey_re", c_double), ("ey_im", c_double), ("apodization", c_int), ("s_env", c_double),
                 ("gibson_lanni", c_int), ("n_s", c_double), ("n_g", c_double),
                 ("n_g_design", c_double), ("n_i_design", c_double), ("t_g_nm", c_double),
-                ("t_g_design_nm", c_double), ("t_i_design_nm", c_double)]
+                ("t_g_design_nm", c_double), ("t_i_design_nm", c_double), ("fresnel", c_int),
+                ("extra_sz", c_int)]
 
 
 class Grid(ctypes.Structure):
@@ -62,7 +68,8 @@ class Grid(ctypes.Structure):
 
 
 class Numerics(ctypes.Structure):
-    _fields_ = [("form", c_int), ("n_pupil", c_int), ("n_theta", c_int), ("n_rho", c_int)]
+    _fields_ = [("form", c_int), ("n_pupil", c_int), ("n_theta", c_int), ("n_rho", c_int),
+                ("model", c_int), ("theta_rule", c_int)]
 
 
 class Stack(ctypes.Structure):
@@ -159,7 +166,10 @@ def abi_version() -> int:
 
 # ---------------------------------------------------------------- struct builders
 def make_optics(na, wavelength, n_i, e_inc=CIRCULAR, focal_length=1.0, apodization=True, s_env=0.0,
-                gibson_lanni: dict | None = None) -> Optics:
+                gibson_lanni: dict | None = None, fresnel: tuple | None = None,
+                extra_sz: bool = False) -> Optics:
+    """``fresnel`` = (n_s, n_g): Fresnel transmission sample -> coverslip -> immersion
+    (the same indices as the Gibson-Lanni layer when both are given)."""
     ex, ey = complex(e_inc[0]), complex(e_inc[1])
     o = Optics(na=na, wavelength_nm=wavelength, n_i=n_i, focal_length=focal_length, ex_re=ex.real,
                ex_im=ex.imag, ey_re=ey.real, ey_im=ey.imag, apodization=int(bool(apodization)),
@@ -174,6 +184,13 @@ def make_optics(na, wavelength, n_i, e_inc=CIRCULAR, focal_length=1.0, apodizati
         o.t_g_nm = g.get("t_g", 170e3)
         o.t_g_design_nm = g.get("t_g_design", 170e3)
         o.t_i_design_nm = g.get("t_i_design", 150e3)
+    if fresnel is not None:
+        n_s, n_g = float(fresnel[0]), float(fresnel[1])
+        if gibson_lanni and (n_s != o.n_s or n_g != o.n_g):
+            raise ValueError("the Fresnel media must be the Gibson-Lanni layer's n_s, n_g")
+        o.fresnel = 1
+        o.n_s, o.n_g = n_s, n_g
+    o.extra_sz = int(bool(extra_sz))
     return o
 
 
@@ -367,8 +384,10 @@ class Batch:
     """Batched emitters (rwpsf_batch_*): one persistent launch for many small stacks."""
 
     def __init__(self, *, na, wavelength, n_i, pixel, plane_pitch, max_emitters, n_pupil=128,
-                 e_inc=CIRCULAR, focal_length=1.0, apodization=True, s_env=0.0):
-        self.optics = make_optics(na, wavelength, n_i, e_inc, focal_length, apodization, s_env, None)
+                 e_inc=CIRCULAR, focal_length=1.0, apodization=True, s_env=0.0, fresnel=None,
+                 extra_sz=False):
+        self.optics = make_optics(na, wavelength, n_i, e_inc, focal_length, apodization, s_env, None,
+                                  fresnel, extra_sz)
         h = c_void_p()
         _check(load().rwpsf_batch_create(byref(self.optics), n_pupil, pixel, plane_pitch, max_emitters,
                                          byref(h)))
@@ -485,12 +504,16 @@ class Plan:
     def __init__(self, *, form: int, na: float, wavelength: float, n_i: float, nx: int, ny: int,
                  dx: float, dy: float, z, e_inc=CIRCULAR, focal_length: float = 1.0,
                  apodization: bool = True, s_env: float = 0.0, gibson_lanni: dict | None = None,
-                 n_pupil: int = 256, n_theta: int = 200, n_rho: int = 256):
+                 n_pupil: int = 256, n_theta: int = 200, n_rho: int = 256,
+                 model: int = MODEL_VECTORIAL, theta_rule: int = THETA_GAUSS,
+                 fresnel: tuple | None = None, extra_sz: bool = False):
         self.optics = make_optics(na, wavelength, n_i, e_inc, focal_length, apodization, s_env,
-                                  gibson_lanni)
+                                  gibson_lanni, fresnel, extra_sz)
         self.grid = make_grid(nx, ny, dx, dy, list(z))
-        self.num = Numerics(form=form, n_pupil=n_pupil, n_theta=n_theta, n_rho=n_rho)
+        self.num = Numerics(form=form, n_pupil=n_pupil, n_theta=n_theta, n_rho=n_rho, model=model,
+                            theta_rule=theta_rule)
         self.nx, self.ny, self.nz = nx, ny, len(z)
+        self.nc = 1 if model == MODEL_SCALAR else 3   # output channels
         self.handle = plan_create(self.optics, self.grid, self.num)
 
     def set_timing(self, enable: bool) -> None:
@@ -507,9 +530,13 @@ class Plan:
         import torch
         b = len(stacks)
         if fields and E is None:
-            E = torch.empty((b, self.nz, 3, self.nx, self.ny), dtype=torch.complex64, device="cuda")
+            E = torch.empty((b, self.nz, self.nc, self.nx, self.ny), dtype=torch.complex64, device="cuda")
         if intensity and I is None:
             I = torch.empty((b, self.nz, self.nx, self.ny), dtype=torch.float32, device="cuda")
+        if fields and E.numel() < b * self.nz * self.nc * self.nx * self.ny:
+            raise ValueError("E is smaller than [stacks][nz][channels][nx][ny]")
+        if intensity and I.numel() < b * self.nz * self.nx * self.ny:
+            raise ValueError("I is smaller than [stacks][nz][nx][ny]")
         compute(self.handle, stacks, E if fields else None, I if intensity else None, stream)
         return E, I
 

@@ -83,6 +83,12 @@ int validate_plan(const rwpsf_optics* o, const rwpsf_grid* g, const rwpsf_numeri
     for (double v : t)
       if (!std::isfinite(v) || v < 0.0) return RWPSF_ERR_INVALID_ARG;
   }
+  if (o->fresnel != 0 && o->fresnel != 1) return RWPSF_ERR_INVALID_ARG;
+  if (o->extra_sz != 0 && o->extra_sz != 1) return RWPSF_ERR_INVALID_ARG;
+  if (o->fresnel && (!finite_pos(o->n_s) || !finite_pos(o->n_g))) return RWPSF_ERR_INVALID_ARG;
+  if (nm->model != RWPSF_MODEL_VECTORIAL && nm->model != RWPSF_MODEL_SCALAR) return RWPSF_ERR_INVALID_ARG;
+  if (nm->theta_rule < RWPSF_THETA_GAUSS || nm->theta_rule > RWPSF_THETA_RIEMANN) return RWPSF_ERR_INVALID_ARG;
+  if (nm->model == RWPSF_MODEL_SCALAR && o->fresnel) return RWPSF_ERR_UNSUPPORTED;
   if (g->nx < 1 || g->ny < 1 || g->nx > 8192 || g->ny > 8192) return RWPSF_ERR_INVALID_ARG;
   if (!finite_pos(g->dx_nm) || !finite_pos(g->dy_nm)) return RWPSF_ERR_INVALID_ARG;
   if (g->nz < 1 || g->nz > 65536 || !g->z_nm) return RWPSF_ERR_INVALID_ARG;
@@ -95,6 +101,8 @@ int validate_plan(const rwpsf_optics* o, const rwpsf_grid* g, const rwpsf_numeri
     if (nm->n_pupil + std::max(g->nx, g->ny) - 1 > 2048) return RWPSF_ERR_UNSUPPORTED;
   } else if (nm->form == RWPSF_FORM_BESSEL) {
     if (nm->n_theta < 2 || nm->n_theta > 4096) return RWPSF_ERR_INVALID_ARG;
+    if (nm->theta_rule == RWPSF_THETA_SIMPSON && (nm->n_theta < 3 || nm->n_theta % 2 == 0))
+      return RWPSF_ERR_INVALID_ARG;
     if (nm->n_rho < 8 || nm->n_rho > 65536) return RWPSF_ERR_INVALID_ARG;
   } else {
     return RWPSF_ERR_INVALID_ARG;
@@ -292,7 +300,7 @@ int rwpsf_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const void* E, con
                   int n_zernike, float* dc, float* dW0, void* stream) {
   if (!p || !E || !dLdI) return RWPSF_ERR_INVALID_ARG;
   if (n_zernike < 0 || n_zernike > RWPSF_MAX_ZERNIKE || (n_zernike > 0 && !dc)) return RWPSF_ERR_INVALID_ARG;
-  if (p->num.form != RWPSF_FORM_FOURIER) return RWPSF_ERR_UNSUPPORTED;
+  if (p->num.form != RWPSF_FORM_FOURIER || p->num.model != RWPSF_MODEL_VECTORIAL) return RWPSF_ERR_UNSUPPORTED;
   int st = rw::validate_stacks(&p->opt, &p->grid, &p->num, n, s);
   if (st != RWPSF_OK) return st;
   int cur = -1;

@@ -587,7 +587,6 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
   b->s_max = o->na / o->n_i;
   const int N = n_pupil;
   const size_t NN = (size_t)N * N;
-  const std::complex<double> ex(o->ex_re, o->ex_im), ey(o->ey_re, o->ey_im);
   std::vector<float2> Q(3 * NN, make_float2(0.f, 0.f));
   std::vector<double> ksz(NN, 0.0);
   std::vector<float> basis((size_t)kBasisRows * NN, 0.f);
@@ -604,14 +603,10 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
         basis[(size_t)q * NN + cell] =
             (float)(kTwoPi * zernike_noll(q + 1, r, r > 0 ? ru / r : 1.0, r > 0 ? rv / r : 0.0));
       if (u * u + v * v > (long)N * N) continue;
-      const double s2 = sx * sx + sy * sy;
-      const double sin_t = std::sqrt(s2), cos_t = std::sqrt(1.0 - s2);
-      const double cp = sin_t > 0 ? sx / sin_t : 1.0, sp = sin_t > 0 ? sy / sin_t : 0.0;
       std::complex<double> e[3];
-      far_field(ex, ey, cos_t, sin_t, cp, sp, e);
-      const double w = ds * ds * amplitude(*o, cos_t, sin_t) / cos_t;
-      for (int c = 0; c < 3; ++c) Q[c * NN + cell] = make_float2((float)(w * e[c].real()), (float)(w * e[c].imag()));
-      ksz[cell] = b->k * cos_t;
+      base_pupil_cell(*o, 3, ds, sx, sy, e);
+      for (int c = 0; c < 3; ++c) Q[c * NN + cell] = make_float2((float)e[c].real(), (float)e[c].imag());
+      ksz[cell] = b->k * std::sqrt(1.0 - (sx * sx + sy * sy));
     }
   // folded DFT tables: row 2jf + p holds cos (p = 0) or sin (p = 1) of k s[jf] x_r,
   // x_r = (r - 32) pixel; the x table carries the prefactor f k / 2 pi (E = -i E')

@@ -7,16 +7,27 @@
 //   E = -(i f k / 2) [ ex (I0 - I2 cos 2v) - ey I2 sin 2v,
 //                     -ex I2 sin 2v + ey (I0 + I2 cos 2v),
 //                     -2i (ex cos v + ey sin v) I1 ]
-// with v the azimuth of the pixel.  Evaluated as
-//   plan:  Gauss-Legendre nodes t_q, weights w_q on [0, theta_max] (split at the
-//          sample's critical angle when it lies inside), radial samples
-//          rho_r = r drho, and the table B[q][n R + r] = w_q g_n(t_q) J_n(k rho_r sin t_q)
+// with v the azimuth of the pixel.  With the Fresnel products q_s(t), q_p(t) of Sec. 3.3
+// kept in eq. "field Gaussian sphere", the phi integral gives the same combination with
+//   g_0 = sin t (q_s + q_p cos t), g_1 = q_p sin^2 t, g_2 = sin t (q_p cos t - q_s);
+// the scalar model (Sec. 3.2, eq. "polar scalar final") is E = -i f k int p sin t J_0 ... dt.
+// Evaluated as
+//   plan:  theta nodes t_q and weights w_q on [0, theta_max] (Gauss-Legendre, split at
+//          the sample's critical angle when it lies inside; or composite Simpson; or the
+//          left Riemann sum), radial samples rho_r = r drho, and the table
+//          B[q][g R + r] = w_q h_g(t_q) J_{n_g}(k rho_r sin t_q) for the groups g below
 //          (FP64 kernel, stored FP32);
-//   call:  Phi[q][s, z] = p_s(t_q) exp(i k z cos t_q)            (FP64 phase -> FP32)
-//          I_n[s, z, :, r] = sum_q Phi[q][s, z] B[q][n R + r]    (real GEMM on MFMA,
-//                                                                 re/im as two rows)
-//          radial epilogue: 4-point Lagrange in rho (parity ghosts
-//          I_n(-rho) = (-1)^n I_n(rho)), angular combination, |E|^2.
+//   call:  Phi[q][(s, z), v] = p_s(t_q) exp(i k z cos t_q) u_v(t_q)   (FP64 phase -> FP32)
+//          In[(s, z), v, :, g R + r] = sum_q Phi[q][(s, z), v] B[q][g R + r]
+//                                       (real GEMM on MFMA, re/im as two rows)
+//          radial epilogue: the I_n from the (v, g) products, 4-point Lagrange in rho
+//          (parity ghosts I_n(-rho) = (-1)^n I_n(rho)), angular combination, |E|^2.
+// Modes (groups g: order n_g, weight h_g; variants v: factor u_v):
+//   vectorial       g = (J0, sin t (1 + cos t)), (J1, sin^2 t), (J2, sin t (cos t - 1)); u = 1
+//   with Fresnel    g = (J0, sin t), (J0, sin t cos t), (J1, sin^2 t), (J2, sin t cos t),
+//                   (J2, sin t); u = q_s, q_p; I_0 = [s, g0] + [p, g1], I_1 = [p, g2],
+//                   I_2 = [p, g3] - [s, g4]
+//   scalar          g = (J0, sin t); u = 1
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -32,17 +43,36 @@ typedef float f16v_b __attribute__((ext_vector_type(16)));
 // --------------------------------------------------------------------------
 // Plan-time Bessel table (FP64 arithmetic).
 // --------------------------------------------------------------------------
+enum BesselMode { kModeVectorial = 0, kModeFresnel = 1, kModeScalar = 2 };
+inline int bessel_groups(int mode) { return mode == kModeFresnel ? 5 : (mode == kModeScalar ? 1 : 3); }
+inline int bessel_variants(int mode) { return mode == kModeFresnel ? 2 : 1; }
+
 __global__ void bessel_table_kernel(float* __restrict__ out, const double* __restrict__ theta,
-                                    const double* __restrict__ wt, int T, int R, double k, double drho) {
+                                    const double* __restrict__ wt, int T, int R, int mode, double k,
+                                    double drho) {
+  const int G = mode == kModeFresnel ? 5 : (mode == kModeScalar ? 1 : 3);
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 3 * R * T) return;
-  const int q = idx / (3 * R);
-  const int nr = idx % (3 * R);
-  const int n = nr / R, r = nr % R;
+  if (idx >= G * R * T) return;
+  const int q = idx / (G * R);
+  const int gr = idx % (G * R);
+  const int g = gr / R, r = gr % R;
   const double t = theta[q];
   const double st = sin(t), ct = cos(t);
-  const double g = n == 0 ? st * (1.0 + ct) : (n == 1 ? st * st : st * (ct - 1.0));
-  out[(size_t)q * 3 * R + nr] = (float)(wt[q] * g * bessel_j(n, k * (r * drho) * st));
+  int n;
+  double h;
+  if (mode == kModeVectorial) {
+    n = g;
+    h = g == 0 ? st * (1.0 + ct) : (g == 1 ? st * st : st * (ct - 1.0));
+  } else if (mode == kModeFresnel) {
+    const int order[5] = {0, 0, 1, 2, 2};
+    const double w5[5] = {st, st * ct, st * st, st * ct, st};
+    n = order[g];
+    h = w5[g];
+  } else {
+    n = 0;
+    h = st;
+  }
+  out[(size_t)q * G * R + gr] = (float)(wt[q] * h * bessel_j(n, k * (r * drho) * st));
 }
 
 // --------------------------------------------------------------------------
@@ -58,15 +88,16 @@ struct PhiStack {
 };
 constexpr int kPhiStacks = 64;
 struct PhiArgs {
-  int T, nz, nstk, s_base_unused, max_zernike, gibson_lanni, apod;
+  int T, nz, nstk, V, max_zernike, gibson_lanni, apod, extra_sz;   // V: variants per column
   double k, s_max, s_env;
   GLParams gl;
   PhiStack s[kPhiStacks];
 };
 
+// fq: per node (Re q_s, Im q_s, Re q_p, Im q_p) when V = 2.
 __global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
-                                  const double* __restrict__ z, float2* __restrict__ phi,
-                                  int ld_cols, int col0) {
+                                  const double* __restrict__ z, const double* __restrict__ fq,
+                                  float2* __restrict__ phi, int ld_cols) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int per_q = a.nstk * a.nz;
   if (idx >= a.T * per_q) return;
@@ -78,6 +109,7 @@ __global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
   double amp = 1.0;
   if (a.apod) amp *= sqrt(cos_t);
   if (a.s_env > 0.0) amp *= exp(-(sin_t * sin_t) / (a.s_env * a.s_env));
+  if (a.extra_sz) amp *= cos_t;
   double w_re = 0.0, w_im = 0.0;
   if (a.gibson_lanni) gl_opd(a.gl, st.t_s, sin_t, &w_re, &w_im);
   const double r = sin_t / a.s_max;
@@ -87,7 +119,16 @@ __global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
   float sn, cs;
   sincosf((float)reduce_2pi(ph), &sn, &cs);
   const float m = (float)(amp * exp(-w_im));
-  phi[(size_t)q * ld_cols + col0 + rem] = make_float2(m * cs, m * sn);
+  float2* out = phi + (size_t)q * ld_cols + (size_t)rem * a.V;
+  if (a.V == 1) {
+    out[0] = make_float2(m * cs, m * sn);
+  } else {
+    const float qsr = (float)fq[4 * q], qsi = (float)fq[4 * q + 1];
+    const float qpr = (float)fq[4 * q + 2], qpi = (float)fq[4 * q + 3];
+    const float pr = m * cs, pi = m * sn;
+    out[0] = make_float2(pr * qsr - pi * qsi, pr * qsi + pi * qsr);
+    out[1] = make_float2(pr * qpr - pi * qpi, pr * qpi + pi * qpr);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -183,32 +224,68 @@ hipError_t launch_rgemm(const float* A, int lda, const float* B, int ldb, float*
 }
 
 // --------------------------------------------------------------------------
-// Radial epilogue: one workgroup per (stack, plane).  In rows of this plane:
-// re and im planes of [3][R] floats, staged in LDS.
+// Radial epilogue: one workgroup per (stack, plane).  The GEMM rows of this plane,
+// (variant, re/im) x [G][R], are combined into I_n and staged in LDS as
+// [re/im][NI][R] (NI = 3 integrals, or 1 for the scalar model).
 // --------------------------------------------------------------------------
 struct EpiArgs {
-  int nx, ny, nz, R, nstk, s_base;
+  int nx, ny, nz, R, nstk, s_base, mode;
   float dx, dy, inv_drho;
-  float exr, exi, eyr, eyi;   // polarisation times -(i f k / 2)
+  float exr, exi, eyr, eyi;   // polarisation times -(i f k / 2); scalar: exr + i exi = -i f k
   float x0[kPhiStacks], y0[kPhiStacks];
 };
 
 __global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const float* __restrict__ In,
                                                               float2* __restrict__ E,
                                                               float* __restrict__ I) {
-  extern __shared__ float sh[];  // [2][3][R]
+  extern __shared__ float sh[];  // [2][NI][R]
   const int si = blockIdx.x / a.nz, zi = blockIdx.x % a.nz;
   const int R = a.R;
-  const float* src = In + ((size_t)si * a.nz + zi) * 2 * 3 * R;
-  for (int i = threadIdx.x; i < 6 * R; i += blockDim.x) sh[i] = src[i];
+  const int G = a.mode == kModeFresnel ? 5 : (a.mode == kModeScalar ? 1 : 3);
+  const int V = a.mode == kModeFresnel ? 2 : 1;
+  const int NI = a.mode == kModeScalar ? 1 : 3;
+  const float* src = In + ((size_t)si * a.nz + zi) * V * 2 * G * R;
+  for (int i = threadIdx.x; i < 2 * NI * R; i += blockDim.x) {
+    const int ri = i / (NI * R), n = (i / R) % NI, r = i % R;
+    float v;
+    if (a.mode == kModeFresnel) {
+      const float* rs = src + (size_t)ri * G * R;         // variant q_s
+      const float* rp = src + (size_t)(2 + ri) * G * R;   // variant q_p
+      v = n == 0 ? rs[r] + rp[R + r] : (n == 1 ? rp[2 * R + r] : rp[3 * R + r] - rs[4 * R + r]);
+    } else {
+      v = src[(size_t)ri * G * R + n * R + r];
+    }
+    sh[i] = v;
+  }
   __syncthreads();
   const float* re = sh;
-  const float* im = sh + 3 * R;
+  const float* im = sh + NI * R;
   const size_t plane = (size_t)a.nx * a.ny;
   const size_t gs = (size_t)(a.s_base + si);
-  float2* Eb = E ? E + (gs * a.nz + zi) * 3 * plane : nullptr;
+  float2* Eb = E ? E + (gs * a.nz + zi) * NI * plane : nullptr;
   float* Ib = I ? I + (gs * a.nz + zi) * plane : nullptr;
   const float x0 = a.x0[si], y0 = a.y0[si];
+  if (a.mode == kModeScalar) {
+    for (int pix = threadIdx.x; pix < (int)plane; pix += blockDim.x) {
+      const int i = pix / a.ny, j = pix % a.ny;
+      const float x = (float)(i - a.nx / 2) * a.dx - x0;
+      const float y = (float)(j - a.ny / 2) * a.dy - y0;
+      const float t = sqrtf(x * x + y * y) * a.inv_drho;
+      const int r0 = min((int)t, R - 3);
+      const float f = t - (float)r0;
+      const float wm = -f * (f - 1.f) * (f - 2.f) * (1.f / 6.f);
+      const float w0 = (f + 1.f) * (f - 1.f) * (f - 2.f) * 0.5f;
+      const float w1 = -(f + 1.f) * f * (f - 2.f) * 0.5f;
+      const float w2 = (f + 1.f) * f * (f - 1.f) * (1.f / 6.f);
+      const int rm = r0 == 0 ? 1 : r0 - 1;   // I_0 is even in rho
+      const float vr = wm * re[rm] + w0 * re[r0] + w1 * re[r0 + 1] + w2 * re[r0 + 2];
+      const float vi = wm * im[rm] + w0 * im[r0] + w1 * im[r0 + 1] + w2 * im[r0 + 2];
+      const float er = a.exr * vr - a.exi * vi, ei = a.exr * vi + a.exi * vr;
+      if (Eb) Eb[pix] = make_float2(er, ei);
+      if (Ib) Ib[pix] = er * er + ei * ei;
+    }
+    return;
+  }
   for (int pix = threadIdx.x; pix < (int)plane; pix += blockDim.x) {
     const int i = pix / a.ny, j = pix % a.ny;
     const float x = (float)(i - a.nx / 2) * a.dx - x0;
@@ -274,11 +351,13 @@ __global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const f
 int bessel_plan_init(rwpsf_plan* p) {
   const int R = p->num.n_rho;
   if (6 * R * (int)sizeof(float) > 160 * 1024) return RWPSF_ERR_UNSUPPORTED;  // epilogue stages 6R floats
-  // theta rule, split at the critical angle of the sample layer when it lies inside
+  p->bessel_mode = p->num.model == RWPSF_MODEL_SCALAR ? kModeScalar : (p->opt.fresnel ? kModeFresnel : kModeVectorial);
+  const int G = bessel_groups(p->bessel_mode), V = bessel_variants(p->bessel_mode);
   std::vector<double> th, wt;
   const double tmax = p->theta_max;
   double tc = -1.0;
-  if (p->opt.gibson_lanni && p->opt.n_s < p->opt.na) tc = std::asin(p->opt.n_s / p->opt.n_i);
+  if (p->opt.gibson_lanni && p->opt.n_s < p->opt.na && p->num.theta_rule == RWPSF_THETA_GAUSS)
+    tc = std::asin(p->opt.n_s / p->opt.n_i);
   auto add_rule = [&](int n, double a, double b) {
     std::vector<double> x(n), w(n);
     gauss_legendre(n, a, b, x.data(), w.data());
@@ -304,6 +383,22 @@ int bessel_plan_init(rwpsf_plan* p) {
       th.push_back(tc + (tmax - tc) * u[i] * u[i]);
       wt.push_back(wu[i] * 2.0 * (tmax - tc) * u[i]);
     }
+  } else if (p->num.theta_rule == RWPSF_THETA_SIMPSON) {
+    // composite Simpson on n (odd) equally spaced nodes: h/3 (1, 4, 2, 4, ..., 4, 1)
+    const int n = p->num.n_theta;
+    const double h = tmax / (n - 1);
+    for (int i = 0; i < n; ++i) {
+      th.push_back(i * h);
+      wt.push_back(h / 3.0 * ((i == 0 || i == n - 1) ? 1.0 : (i % 2 ? 4.0 : 2.0)));
+    }
+  } else if (p->num.theta_rule == RWPSF_THETA_RIEMANN) {
+    // left Riemann sum: nodes i h, i < n, h = theta_max / n
+    const int n = p->num.n_theta;
+    const double h = tmax / n;
+    for (int i = 0; i < n; ++i) {
+      th.push_back(i * h);
+      wt.push_back(h);
+    }
   } else {
     add_rule(p->num.n_theta, 0.0, tmax);
   }
@@ -316,17 +411,32 @@ int bessel_plan_init(rwpsf_plan* p) {
   int st;
   if ((st = dev_alloc(p, &p->d_theta, T))) return st;
   if ((st = dev_alloc(p, &p->d_wtheta, T))) return st;
-  if ((st = dev_alloc(p, &p->d_btab, (size_t)3 * R * T))) return st;
+  if ((st = dev_alloc(p, &p->d_btab, (size_t)G * R * T))) return st;
   if ((st = dev_alloc(p, &p->d_z, (size_t)p->grid.nz))) return st;
   p->bessel_stacks = kPhiStacks;
-  if ((st = dev_alloc(p, &p->d_phi, (size_t)T * p->bessel_stacks * p->grid.nz))) return st;
-  if ((st = dev_alloc(p, (float**)&p->d_In, (size_t)p->bessel_stacks * p->grid.nz * 2 * 3 * R))) return st;
+  if ((st = dev_alloc(p, &p->d_phi, (size_t)T * p->bessel_stacks * p->grid.nz * V))) return st;
+  if ((st = dev_alloc(p, (float**)&p->d_In, (size_t)p->bessel_stacks * p->grid.nz * V * 2 * G * R))) return st;
+  if (V == 2) {
+    // Fresnel products per node, FP64 (Re q_s, Im q_s, Re q_p, Im q_p)
+    std::vector<double> fq(4 * (size_t)T);
+    for (int q = 0; q < T; ++q) {
+      std::complex<double> qs, qp;
+      fresnel_q(p->opt, std::sin(th[q]), &qs, &qp);
+      fq[4 * q] = qs.real();
+      fq[4 * q + 1] = qs.imag();
+      fq[4 * q + 2] = qp.real();
+      fq[4 * q + 3] = qp.imag();
+    }
+    if ((st = dev_alloc(p, &p->d_fq, fq.size()))) return st;
+    if ((st = hip_check(hipMemcpy(p->d_fq, fq.data(), fq.size() * sizeof(double), hipMemcpyHostToDevice))))
+      return st;
+  }
   if ((st = hip_check(hipMemcpy(p->d_theta, th.data(), T * sizeof(double), hipMemcpyHostToDevice)))) return st;
   if ((st = hip_check(hipMemcpy(p->d_wtheta, wt.data(), T * sizeof(double), hipMemcpyHostToDevice)))) return st;
   if ((st = hip_check(hipMemcpy(p->d_z, p->z.data(), p->z.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
-  const int total = 3 * R * T;
+  const int total = G * R * T;
   hipLaunchKernelGGL(bessel_table_kernel, dim3((total + 255) / 256), dim3(256), 0, 0, p->d_btab,
-                     p->d_theta, p->d_wtheta, T, R, p->k, p->drho);
+                     p->d_theta, p->d_wtheta, T, R, p->bessel_mode, p->k, p->drho);
   if ((st = hip_check(hipGetLastError()))) return st;
   if ((st = hip_check(hipFuncSetAttribute((const void*)bessel_epilogue_kernel,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 6 * R * 4))))
@@ -340,17 +450,24 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
   if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
   if (6 * p->num.n_rho * 4 > 160 * 1024) return RWPSF_ERR_UNSUPPORTED;
   const int T = p->n_theta_total, R = p->num.n_rho, nz = p->grid.nz;
+  const int mode = p->bessel_mode, G = bessel_groups(mode), V = bessel_variants(mode);
   const std::complex<double> pref(0.0, -0.5 * p->opt.focal_length * p->k);
-  const std::complex<double> ex = pref * std::complex<double>(p->opt.ex_re, p->opt.ex_im);
-  const std::complex<double> ey = pref * std::complex<double>(p->opt.ey_re, p->opt.ey_im);
+  std::complex<double> ex = pref * std::complex<double>(p->opt.ex_re, p->opt.ex_im);
+  std::complex<double> ey = pref * std::complex<double>(p->opt.ey_re, p->opt.ey_im);
+  if (mode == kModeScalar) {   // E = -i f k I_0, unit incident amplitude
+    ex = std::complex<double>(0.0, -p->opt.focal_length * p->k);
+    ey = 0.0;
+  }
   for (int b0 = 0; b0 < n; b0 += kPhiStacks) {
     const int nb = std::min(kPhiStacks, n - b0);
     PhiArgs pa{};
     pa.T = T;
     pa.nz = nz;
     pa.nstk = nb;
+    pa.V = V;
     pa.gibson_lanni = p->opt.gibson_lanni;
     pa.apod = p->opt.apodization;
+    pa.extra_sz = p->opt.extra_sz;
     pa.k = p->k;
     pa.s_max = p->s_max;
     pa.s_env = p->opt.s_env;
@@ -369,11 +486,11 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
     const int total = T * cols;
     int tr = p->time_begin(RWPSF_KERNEL_BESSEL_PHI, st);
     hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, p->d_theta,
-                       p->d_z, p->d_phi, cols, 0);
+                       p->d_z, p->d_fq, p->d_phi, cols * V);
     int rc = hip_check(hipGetLastError());
     if (rc) return rc;
     p->time_end(tr, st);
-    const int M = 2 * cols, N = 3 * R;
+    const int M = 2 * cols * V, N = G * R;
     const int blocks = ((M + RBM - 1) / RBM) * ((N + RBN - 1) / RBN);
     tr = p->time_begin(RWPSF_KERNEL_BESSEL_CONTRACT, st);
     hipLaunchKernelGGL(bessel_contract_kernel, dim3(blocks), dim3(256), 0, st, (const float*)p->d_phi,
@@ -387,6 +504,7 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
     ea.R = R;
     ea.nstk = nb;
     ea.s_base = b0;
+    ea.mode = mode;
     ea.dx = (float)p->grid.dx_nm;
     ea.dy = (float)p->grid.dy_nm;
     ea.inv_drho = (float)(1.0 / p->drho);

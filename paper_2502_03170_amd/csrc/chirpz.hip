@@ -154,15 +154,15 @@ __device__ __forceinline__ void fft(float2* buf, int lane) {
 }
 
 struct CztRowArgs {
-  const float2* P;       // [nstk][3][np][np] base pupils
+  const float2* P;       // [nstk][nc][np][np] base pupils
   const double* ksz;     // [np][np]
   const double* z;       // plan planes
   const float2* pre;     // [N]
   const float2* post;    // [ny]
   const float2* chat;    // [L] FFT of the chirp, divided by L
-  float2* T;             // [nstk][nzs][3][N][ny]
+  float2* T;             // [nstk][nzs][nc][N][ny]
   double zoff[kPupilStacks];
-  int n, np, ny, nstk, z0, nzs;
+  int n, np, ny, nstk, z0, nzs, nc;   // nc: channels (3 vectorial, 1 scalar)
 };
 
 template <int L>
@@ -179,7 +179,7 @@ __global__ void __launch_bounds__(256) czt_rows_kernel(CztRowArgs a) {
   float2* buf = cbuf + wave * padded<L>();
   const size_t npp = (size_t)a.np * a.np;
   const double zz = a.z[a.z0 + zi] + a.zoff[s];
-  // defocus factors of this row, shared by the three components (N < L)
+  // defocus factors of this row, shared by the channels (N < L)
   constexpr int MAXT = L / 64;
   float2 dz[MAXT];
 #pragma unroll
@@ -192,8 +192,8 @@ __global__ void __launch_bounds__(256) czt_rows_kernel(CztRowArgs a) {
       dz[t] = cmul(make_float2(cs, sn), a.pre[l]);
     }
   }
-  for (int c = 0; c < 3; ++c) {
-    const float2* Pr = a.P + ((size_t)s * 3 + c) * npp + (size_t)(live ? j : 0) * a.np;
+  for (int c = 0; c < a.nc; ++c) {
+    const float2* Pr = a.P + ((size_t)s * a.nc + c) * npp + (size_t)(live ? j : 0) * a.np;
 #pragma unroll
     for (int t = 0; t < MAXT; ++t) {
       const int l = lane + 64 * t;
@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(256) czt_rows_kernel(CztRowArgs a) {
     wave_lds_order();
     fft<L>(buf, lane);
     if (live) {
-      float2* Tr = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)a.n * a.ny + (size_t)j * a.ny;
+      float2* Tr = a.T + (((size_t)s * a.nzs + zi) * a.nc + c) * (size_t)a.n * a.ny + (size_t)j * a.ny;
       for (int n = lane; n < a.ny; n += 64) {
         const float2 b = buf[pidx(n)];
         Tr[n] = cmul(make_float2(b.x, -b.y), a.post[n]);
@@ -220,13 +220,13 @@ __global__ void __launch_bounds__(256) czt_rows_kernel(CztRowArgs a) {
 }
 
 struct CztColArgs {
-  const float2* T;       // [nstk][nzs][3][N][ny]
+  const float2* T;       // [nstk][nzs][nc][N][ny]
   const float2* pre;     // [N]
   const float2* post;    // [nx], prefactor C included
   const float2* chat;    // [L]
-  float2* E;             // [stacks][nz][3][nx][ny] or null
+  float2* E;             // [stacks][nz][nc][nx][ny] or null
   float* I;              // [stacks][nz][nx][ny] or null
-  int n, nx, ny, nz, cb, nstk, s_base, z0, nzs;
+  int n, nx, ny, nz, cb, nstk, s_base, z0, nzs, nc;
 };
 
 template <int L>
@@ -247,8 +247,8 @@ __global__ void __launch_bounds__(256) czt_cols_kernel(CztColArgs a) {
   const size_t gstk = (size_t)(a.s_base + s), gz = (size_t)(a.z0 + zi);
   const size_t plane = (size_t)a.nx * a.ny;
   for (int idx = tid; idx < a.nx * CB; idx += 256) isum[idx] = 0.f;
-  for (int c = 0; c < 3; ++c) {
-    const float2* Tc = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)a.n * a.ny;
+  for (int c = 0; c < a.nc; ++c) {
+    const float2* Tc = a.T + (((size_t)s * a.nzs + zi) * a.nc + c) * (size_t)a.n * a.ny;
     for (int idx = tid; idx < a.n * CB; idx += 256) {
       const int j = idx / CB, cc = idx % CB;
       stage[cc * a.n + j] = (n0 + cc < a.ny) ? Tc[(size_t)j * a.ny + n0 + cc] : make_float2(0.f, 0.f);
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(256) czt_cols_kernel(CztColArgs a) {
     }
     __syncthreads();   // every wave's columns are in outs
     // rows of E from LDS: CB consecutive columns per row
-    float2* Ec = a.E ? a.E + ((gstk * a.nz + gz) * 3 + c) * plane : nullptr;
+    float2* Ec = a.E ? a.E + ((gstk * a.nz + gz) * a.nc + c) * plane : nullptr;
     for (int idx = tid; idx < a.nx * CB; idx += 256) {   // each thread keeps its own entries
       const int m = idx / CB, cc = idx % CB;
       const float2 v = outs[cc * a.nx + m];
@@ -397,7 +397,7 @@ static int czt_slab(rwpsf_plan* p, int s_local, int ns, const double* zoff, int 
                     float* I, hipStream_t st) {
   const int N = p->num.n_pupil, nx = p->grid.nx, ny = p->grid.ny;
   CztRowArgs ra{};
-  ra.P = p->d_P + (size_t)s_local * 3 * p->np * p->np;
+  ra.P = p->d_P + (size_t)s_local * p->nc * p->np * p->np;
   ra.ksz = p->d_ksz;
   ra.z = p->d_z;
   ra.pre = p->czt_pre_y;
@@ -411,6 +411,7 @@ static int czt_slab(rwpsf_plan* p, int s_local, int ns, const double* zoff, int 
   ra.nstk = ns;
   ra.z0 = z0;
   ra.nzs = nzs;
+  ra.nc = p->nc;
   int tr = p->time_begin(RWPSF_KERNEL_CZT_ROWS, st);
   const int rblocks = ns * nzs * ((N + 3) / 4);
 #define RW_ROWS(LL) launch_rows<LL>(ra, rblocks, st)
@@ -438,6 +439,7 @@ static int czt_slab(rwpsf_plan* p, int s_local, int ns, const double* zoff, int 
   ca.ny = ny;
   ca.nz = p->grid.nz;
   ca.cb = p->czt_cb;
+  ca.nc = p->nc;
   ca.nstk = ns;
   ca.s_base = s_global;
   ca.z0 = z0;

@@ -47,17 +47,17 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
   const int pcell = blockIdx.x * blockDim.x + threadIdx.x;   // padded cell
   if (pcell >= np * np) return;
   const int j = pcell / np, l = pcell % np;
-  float2 q0 = make_float2(0.f, 0.f), q1 = q0, q2 = q0;
-  if (j < n && l < n) {
-    q0 = Q[pcell];
-    q1 = Q[npp + pcell];
-    q2 = Q[2 * npp + pcell];
-  }
-  const bool inside = (q0.x != 0.f || q0.y != 0.f || q1.x != 0.f || q1.y != 0.f || q2.x != 0.f ||
-                       q2.y != 0.f);
+  const int nc = a.nc;
+  float2 q[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+  bool inside = false;
+  if (j < n && l < n)
+    for (int c = 0; c < nc; ++c) {
+      q[c] = Q[c * npp + pcell];
+      inside = inside || q[c].x != 0.f || q[c].y != 0.f;
+    }
   if (!inside) {
     for (int s = 0; s < a.nstk; ++s)
-      for (int c = 0; c < 3; ++c) P[((size_t)s * 3 + c) * npp + pcell] = make_float2(0.f, 0.f);
+      for (int c = 0; c < nc; ++c) P[((size_t)s * nc + c) * npp + pcell] = make_float2(0.f, 0.f);
     return;
   }
   const int cell = j * n + l;   // unpadded index: Zernike table and user phase map
@@ -91,10 +91,9 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
     float sn, cs;
     sincosf(ph, &sn, &cs);
     const float er = amp * cs, ei = amp * sn;
-    float2* out = P + (size_t)s * 3 * npp + pcell;
-    out[0] = make_float2(q0.x * er - q0.y * ei, q0.x * ei + q0.y * er);
-    out[npp] = make_float2(q1.x * er - q1.y * ei, q1.x * ei + q1.y * er);
-    out[2 * npp] = make_float2(q2.x * er - q2.y * ei, q2.x * ei + q2.y * er);
+    float2* out = P + (size_t)s * nc * npp + pcell;
+    for (int c = 0; c < nc; ++c)
+      out[c * npp] = make_float2(q[c].x * er - q[c].y * ei, q[c].x * ei + q[c].y * er);
   }
 }
 
@@ -122,8 +121,8 @@ __global__ void __launch_bounds__(256) pupil_fold_kernel(FoldArgs a) {
   const size_t o00 = (size_t)(2 * jf) * w + 2 * lf;   // (pj, pl) = (0, 0); (0,1) = +1; (1,0) = +w
   const float2 zero = make_float2(0.f, 0.f);
   for (int s = 0; s < a.nstk; ++s)
-    for (int c = 0; c < 3; ++c) {
-      float2* out = a.Pf + ((size_t)s * 3 + c) * fpp + o00;
+    for (int c = 0; c < a.nc; ++c) {
+      float2* out = a.Pf + ((size_t)s * a.nc + c) * fpp + o00;
       if (jf >= nh || lf >= nh) {
         out[0] = zero;
         out[1] = zero;
@@ -131,7 +130,7 @@ __global__ void __launch_bounds__(256) pupil_fold_kernel(FoldArgs a) {
         out[w + 1] = zero;
         continue;
       }
-      const float2* P = a.P + ((size_t)s * 3 + c) * npp;
+      const float2* P = a.P + ((size_t)s * a.nc + c) * npp;
       const int j1 = n - 1 - jf, l1 = n - 1 - lf;
       const bool dj = j1 != jf, dl = l1 != lf;
       const float2 p00 = P[(size_t)jf * a.np + lf];
@@ -258,12 +257,12 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_pupil_kernel(Gemm1Args a) {
   const int w = 2 * a.nhp;
   const int tiles_m = 2 * w / Cfg::BM;
   const int tiles_n = a.nyp / Cfg::BN;
-  const int nblocks = a.nstk * a.nzs * 3 * tiles_m * tiles_n;
+  const int nblocks = a.nstk * a.nzs * a.nc * tiles_m * tiles_n;
   int id = xcd_remap(blockIdx.x, nblocks);
   const int tn = id % tiles_n; id /= tiles_n;
   const int tm = id % tiles_m; id /= tiles_m;
   const int zi = id % a.nzs; id /= a.nzs;
-  const int c = id % 3; id /= 3;
+  const int c = id % a.nc; id /= a.nc;
   const int s = id;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wrow = (wave / Cfg::WAVES_N) * Cfg::WM, wcol = (wave % Cfg::WAVES_N) * Cfg::WN;
@@ -272,7 +271,7 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_pupil_kernel(Gemm1Args a) {
   const int jf0 = row0 / 4;
 
   FoldDefocusLoader<Cfg> la;
-  la.Pf = a.Pf + ((size_t)s * 3 + c) * fpp + (size_t)(2 * jf0) * w;
+  la.Pf = a.Pf + ((size_t)s * a.nc + c) * fpp + (size_t)(2 * jf0) * w;
   la.kszf = a.kszf + (size_t)jf0 * a.nhp;
   la.z = a.z[a.z0 + zi] + a.zoff[s];
   la.w = w;
@@ -301,7 +300,7 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_pupil_kernel(Gemm1Args a) {
   rg_mainloop<Cfg>(acc, la, lb, k_begin, k_end, lds, tid, wrow, wcol, lane);
 
   // rows 2q + ri: registers r and r + 1 (r even) are the re/im parts of one T[q][n]
-  float2* T = a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)w * a.nyp;
+  float2* T = a.T + (((size_t)s * a.nzs + zi) * a.nc + c) * (size_t)w * a.nyp;
 #pragma unroll
   for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
@@ -316,7 +315,7 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_pupil_kernel(Gemm1Args a) {
 }
 
 // K3: E'[m][(n, ri)] = sum_kk A2[m][kk] T[kk][(n, ri)] with A2[m][2jf] = pref cos(k s_jf x_m),
-// A2[m][2jf+1] = pref sin(...) for c = x, y, z in one workgroup; E = -i E' and
+// A2[m][2jf+1] = pref sin(...) for all channels in one workgroup; E = -i E' and
 // I = sum_c |E_c|^2 are written from registers.
 template <class Cfg, int OCC>
 __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_image_kernel(Gemm2Args a) {
@@ -346,12 +345,12 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_image_kernel(Gemm2Args a) {
       for (int r = 0; r < 16; ++r) isum[i][jj][r] = 0.f;
 
 #pragma unroll 1
-  for (int c = 0; c < 3; ++c) {
+  for (int c = 0; c < a.nc; ++c) {
     RRowLoader<Cfg, Cfg::BM> la;
     la.src = a.A2 + (size_t)row0 * w;
     la.ld = w;
     RColLoader<Cfg, Cfg::BN> lb;
-    lb.src = reinterpret_cast<const float*>(a.T + (((size_t)s * a.nzs + zi) * 3 + c) * (size_t)w * a.nyp) + col0;
+    lb.src = reinterpret_cast<const float*>(a.T + (((size_t)s * a.nzs + zi) * a.nc + c) * (size_t)w * a.nyp) + col0;
     lb.ld = 2 * a.nyp;
     RgAcc<Cfg> acc;
     acc.zero();
@@ -359,7 +358,7 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_image_kernel(Gemm2Args a) {
 
     // Lanes 2t and 2t+1 hold Re E' and Im E' of one pixel; a DPP swap within lane pairs
     // gives the even lane both, and it writes E = -i E' = (Im E', -Re E') as one float2.
-    float2* E = a.E ? a.E + ((gstk * a.nz + gz) * 3 + c) * plane : nullptr;
+    float2* E = a.E ? a.E + ((gstk * a.nz + gz) * a.nc + c) * plane : nullptr;
     // the store offsets are the same for every component; keeping them opaque here stops
     // them from being hoisted out of the component loop (32 live offsets would spill)
     int mbase = row0 + rg_row(wrow, 0, 0, lane);
@@ -421,7 +420,7 @@ hipError_t launch_pupil_fold(const FoldArgs& a, hipStream_t st) {
 template <class Cfg, int OCC>
 static hipError_t gemm_pupil_launch(const Gemm1Args& a, hipStream_t st) {
   const int tiles = (4 * a.nhp / Cfg::BM) * (a.nyp / Cfg::BN);
-  const int nblocks = a.nstk * a.nzs * 3 * tiles;
+  const int nblocks = a.nstk * a.nzs * a.nc * tiles;
   hipLaunchKernelGGL((gemm_pupil_kernel<Cfg, OCC>), dim3(nblocks), dim3(Cfg::NT), Cfg::LDS_BYTES, st, a);
   return hipGetLastError();
 }

@@ -3,7 +3,8 @@
 // Sec. 3.4 correction factors) on the cell-centred pupil grid
 //   s_x[j] = (2j + 1 - N) s_max / N,  s_y[l] likewise,  cell area ds^2 = (2 s_max / N)^2,
 // disk mask (2j+1-N)^2 + (2l+1-N)^2 <= N^2 decided in integers:
-//   Q_c[j,l]  = ds^2 a(s) e_inf,c(s) / s_z          (complex64, 0 outside the disk)
+//   Q_c[j,l]  = ds^2 a(s) e_inf,c(s) / s_z          (complex64, 0 outside the disk;
+//               one channel ds^2 a(s) / s_z for the scalar model, Sec. 3.2)
 //   ksz[j,l]  = k s_z                                (FP64, for the defocus phase)
 // and of the folded transforms (jf, lf < nh = ceil(N/2), the mirror-symmetric half):
 //   kszf[jf,lf]   = k s_z                            (FP64)
@@ -31,7 +32,6 @@ static int fourier_plan_init(rwpsf_plan* p) {
   p->nxp = nxp;
   p->nyp = nyp;
   const double s_max = p->s_max, k = p->k;
-  const std::complex<double> ex(p->opt.ex_re, p->opt.ex_im), ey(p->opt.ey_re, p->opt.ey_im);
   const size_t npp = (size_t)np * np;
   std::vector<float2> Q(3 * npp, make_float2(0.f, 0.f));
   std::vector<double> ksz(npp, 0.0);
@@ -42,15 +42,10 @@ static int fourier_plan_init(rwpsf_plan* p) {
       if (u * u + v * v > (long)N * N) continue;
       const size_t cell = (size_t)j * np + l;
       const double sx = u * s_max / N, sy = v * s_max / N;
-      const double s2 = sx * sx + sy * sy;
-      const double sin_t = std::sqrt(s2), cos_t = std::sqrt(1.0 - s2);
-      const double cp = sin_t > 0 ? sx / sin_t : 1.0, sp = sin_t > 0 ? sy / sin_t : 0.0;
       std::complex<double> e[3];
-      far_field(ex, ey, cos_t, sin_t, cp, sp, e);
-      const double w = ds * ds * amplitude(p->opt, cos_t, sin_t) / cos_t;
-      for (int c = 0; c < 3; ++c)
-        Q[c * npp + cell] = make_float2((float)(w * e[c].real()), (float)(w * e[c].imag()));
-      ksz[cell] = k * cos_t;
+      base_pupil_cell(p->opt, p->nc, ds, sx, sy, e);
+      for (int c = 0; c < p->nc; ++c) Q[c * npp + cell] = make_float2((float)e[c].real(), (float)e[c].imag());
+      ksz[cell] = k * std::sqrt(1.0 - (sx * sx + sy * sy));
     }
   const int nh = (N + 1) / 2, nhp = round_up(nh, kFoldPad), w = 2 * nhp;
   p->nhp = nhp;
@@ -114,6 +109,7 @@ int plan_init(rwpsf_plan* p, const rwpsf_optics& o, const rwpsf_grid& g, const r
   p->num = nm;
   p->z.assign(g.z_nm, g.z_nm + g.nz);
   p->grid.z_nm = nullptr;
+  p->nc = nm.model == RWPSF_MODEL_SCALAR ? 1 : 3;
   p->k = kTwoPi * o.n_i / o.wavelength_nm;
   p->s_max = o.na / o.n_i;
   p->theta_max = std::asin(p->s_max);
@@ -141,6 +137,7 @@ int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_
   pa.np = p->np;
   pa.nstk = nb;
   pa.gibson_lanni = p->opt.gibson_lanni;
+  pa.nc = p->nc;
   pa.s_max = p->s_max;
   pa.k = p->k;
   pa.gl = p->gl;
@@ -170,7 +167,7 @@ static int fourier_gemms(rwpsf_plan* p, int s_local, int ns, const double* zoff,
                          float2* E, float* I, hipStream_t st) {
   const int w = 2 * p->nhp;
   Gemm1Args g1{};
-  g1.Pf = p->d_Pf + (size_t)s_local * 3 * w * w;
+  g1.Pf = p->d_Pf + (size_t)s_local * p->nc * w * w;
   g1.kszf = p->d_kszf;
   g1.z = p->d_z;
   g1.B1 = p->d_B1;
@@ -182,6 +179,7 @@ static int fourier_gemms(rwpsf_plan* p, int s_local, int ns, const double* zoff,
   g1.nstk = ns;
   g1.z0 = z0;
   g1.nzs = nzs;
+  g1.nc = p->nc;
   int tr = p->time_begin(RWPSF_KERNEL_GEMM_PUPIL, st);
   int rc = hip_check(launch_gemm_pupil(g1, st));
   if (rc) return rc;
@@ -201,6 +199,7 @@ static int fourier_gemms(rwpsf_plan* p, int s_local, int ns, const double* zoff,
   g2.s_base = s_global;
   g2.z0 = z0;
   g2.nzs = nzs;
+  g2.nc = p->nc;
   tr = p->time_begin(RWPSF_KERNEL_GEMM_IMAGE, st);
   if ((rc = hip_check(launch_gemm_image(g2, st)))) return rc;
   p->time_end(tr, st);
@@ -216,7 +215,7 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
     const int nb = std::min(kPupilStacks, n - b0);
     int rc = fourier_build_pupils(p, s + b0, nb, st);
     if (rc) return rc;
-    FoldArgs fa{p->d_P, p->d_Pf, p->num.n_pupil, p->np, p->nhp, nb};
+    FoldArgs fa{p->d_P, p->d_Pf, p->num.n_pupil, p->np, p->nhp, nb, p->nc};
     int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
     if ((rc = hip_check(launch_pupil_fold(fa, st)))) return rc;
     p->time_end(tr, st);

@@ -144,6 +144,7 @@ struct rwpsf_plan {
   rwpsf_numerics num{};
   std::vector<double> z;
   double k = 0, s_max = 0, theta_max = 0;
+  int nc = 3;                   // output channels: 3 (vectorial model) or 1 (scalar model)
   rw::GLParams gl{};
   size_t device_bytes = 0;
   std::vector<void*> allocations;
@@ -184,9 +185,11 @@ struct rwpsf_plan {
   int n_theta_total = 0;        // nodes after the critical-angle split
   double* d_theta = nullptr;    // [T] nodes
   double* d_wtheta = nullptr;   // [T] weights
-  float* d_btab = nullptr;      // [3][R][T] w_t g_n(t) J_n(k rho_r sin t)
-  float2* d_phi = nullptr;      // workspace [stacks][T][nz] pupil x defocus
-  float2* d_In = nullptr;       // workspace [stacks][3][nz][R]
+  int bessel_mode = 0;          // 0 vectorial, 1 vectorial with Fresnel factors, 2 scalar
+  float* d_btab = nullptr;      // [T][G][R] w_t h_g(t) J_{n_g}(k rho_r sin t)
+  double* d_fq = nullptr;       // [T][4] Fresnel products q_s, q_p per node (Fresnel mode)
+  float2* d_phi = nullptr;      // workspace [T][stacks][nz][V] pupil x defocus (x q_v)
+  float2* d_In = nullptr;       // workspace [stacks][nz][V][re/im][G][R]
   int bessel_stacks = 0;        // capacity of the Bessel workspaces
   double drho = 0;              // radial sample pitch
 

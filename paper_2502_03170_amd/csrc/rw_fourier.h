@@ -13,8 +13,10 @@ struct PupilStack {
   const float* w0;
 };
 
+// Channels: nc = 3 (vectorial model, x, y, z) or 1 (scalar model); every per-channel
+// array below holds nc channels.
 struct PupilArgs {
-  int n, np, nstk, max_zernike, gibson_lanni;   // n: pupil cells per axis, np: padded stride
+  int n, np, nstk, max_zernike, gibson_lanni, nc;   // n: pupil cells per axis, np: padded stride
   double s_max, k;
   GLParams gl;
   PupilStack s[kPupilStacks];
@@ -24,27 +26,27 @@ struct PupilArgs {
 // to 128, nyp = ny rounded up to 128, and the folded pupil axis nh = ceil(n/2) to
 // nhp = nh rounded up to 32 (so 2 nhp = np).
 struct FoldArgs {
-  const float2* P;     // [nstk][3][np][np] base pupils
-  float2* Pf;          // [nstk][3][2 nhp][2 nhp] folded pupils
-  int n, np, nhp, nstk;
+  const float2* P;     // [nstk][nc][np][np] base pupils
+  float2* Pf;          // [nstk][nc][2 nhp][2 nhp] folded pupils
+  int n, np, nhp, nstk, nc;
 };
 
 struct Gemm1Args {
-  const float2* Pf;    // [nstk][3][2 nhp][2 nhp]
+  const float2* Pf;    // [nstk][nc][2 nhp][2 nhp]
   const double* kszf;  // [nhp][nhp] k s_z on the folded cells
   const double* z;     // plan planes
   const float* B1;     // [nyp][2 nhp] cos / sin (k s_y[lf] y_n), k contiguous
-  float2* T;           // [nstk][nzs][3][2 nhp][nyp]
+  float2* T;           // [nstk][nzs][nc][2 nhp][nyp]
   double zoff[kPupilStacks];
-  int n, nhp, nyp, nstk, z0, nzs;   // n: pupil cells per axis
+  int n, nhp, nyp, nstk, z0, nzs, nc;   // n: pupil cells per axis
 };
 
 struct Gemm2Args {
   const float* A2;     // [nxp][2 nhp] pref cos / sin (k s_x[jf] x_m), k contiguous
-  const float2* T;     // [nstk][nzs][3][2 nhp][nyp]
-  float2* E;           // [stacks][nz][3][nx][ny] or null
+  const float2* T;     // [nstk][nzs][nc][2 nhp][nyp]
+  float2* E;           // [stacks][nz][nc][nx][ny] or null
   float* I;            // [stacks][nz][nx][ny] or null
-  int nhp, nxp, nyp, nx, ny, nz, nstk, s_base, z0, nzs;
+  int nhp, nxp, nyp, nx, ny, nz, nstk, s_base, z0, nzs, nc;
 };
 
 inline int round_up(int v, int m) { return (v + m - 1) / m * m; }

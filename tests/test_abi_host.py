@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 12
     for n in names:
         assert hasattr(lib, n), n
-    assert rw.abi_version() == 1
+    assert rw.abi_version() == 2
 
 
 def test_status_strings():
@@ -96,6 +96,29 @@ def test_validation_error_codes():
     assert rw.validate(o, g, rw.Numerics(form=7, n_pupil=256, n_theta=200, n_rho=256)) == rw.ERR_INVALID_ARG
     assert rw.validate(o, g, rw.Numerics(form=0, n_pupil=256, n_theta=1, n_rho=256)) == rw.ERR_INVALID_ARG
     assert rw.validate(o, g, rw.Numerics(form=1, n_pupil=4096, n_theta=200, n_rho=256)) == rw.ERR_INVALID_ARG
+
+
+def test_validation_of_model_rule_and_fresnel_options():
+    o, g, nm = _plan_desc()
+    N = rw.Numerics
+    assert rw.validate(o, g, N(form=0, n_pupil=2, n_theta=201, n_rho=256, model=rw.MODEL_SCALAR,
+                                theta_rule=rw.THETA_SIMPSON)) == rw.OK
+    # Simpson needs an odd node count >= 3; Riemann takes any
+    assert rw.validate(o, g, N(form=0, n_pupil=2, n_theta=200, n_rho=256,
+                                theta_rule=rw.THETA_SIMPSON)) == rw.ERR_INVALID_ARG
+    assert rw.validate(o, g, N(form=0, n_pupil=2, n_theta=200, n_rho=256,
+                                theta_rule=rw.THETA_RIEMANN)) == rw.OK
+    assert rw.validate(o, g, N(form=0, n_pupil=2, n_theta=201, n_rho=256, theta_rule=3)) == rw.ERR_INVALID_ARG
+    assert rw.validate(o, g, N(form=1, n_pupil=64, n_theta=2, n_rho=8, model=2)) == rw.ERR_INVALID_ARG
+    of = rw.make_optics(1.4, 532.0, 1.518, fresnel=(1.33, 1.52))
+    assert rw.validate(of, g, nm) == rw.OK
+    # the scalar model has no Fresnel factors
+    assert rw.validate(of, g, N(form=1, n_pupil=64, n_theta=2, n_rho=8,
+                                 model=rw.MODEL_SCALAR)) == rw.ERR_UNSUPPORTED
+    bad = rw.make_optics(1.4, 532.0, 1.518, fresnel=(0.0, 1.52))
+    assert rw.validate(bad, g, nm) == rw.ERR_INVALID_ARG
+    with pytest.raises(ValueError):
+        rw.make_optics(1.4, 532.0, 1.518, gibson_lanni=dict(n_s=1.33), fresnel=(1.36, 1.5))
 
 
 def test_stack_validation_bessel_needs_axisymmetry():
