@@ -155,6 +155,45 @@ def bench_chirpz(rw, torch, steps, warmup):
                 ms_per_step=ms, crossover_8_stacks_128x128x64=cross)
 
 
+def bench_speed_sweep(rw, torch, reps=10):
+    """The speed benchmark of Sec. 5.2.1 on one GPU: one 201 x 201 image at focus, per
+    propagator (scalar / vectorial x Cartesian / spherical) against the numerical pupil
+    size (Cartesian: cells per axis; spherical: theta nodes), mean of `reps` calls after
+    two warm-up calls, each call synchronised (pupil build and transform included).
+    Optics: NA 1.4, 532 nm, n_i 1.518, circular polarisation, apodization."""
+    sizes = (64, 128, 256, 512, 1024)
+    props = (("cartesian_vectorial", rw.FORM_FOURIER, rw.MODEL_VECTORIAL),
+             ("cartesian_scalar", rw.FORM_FOURIER, rw.MODEL_SCALAR),
+             ("cartesian_chirpz_vectorial", rw.FORM_CHIRPZ, rw.MODEL_VECTORIAL),
+             ("cartesian_chirpz_scalar", rw.FORM_CHIRPZ, rw.MODEL_SCALAR),
+             ("spherical_vectorial", rw.FORM_BESSEL, rw.MODEL_VECTORIAL),
+             ("spherical_scalar", rw.FORM_BESSEL, rw.MODEL_SCALAR))
+    out = {}
+    for name, form, model in props:
+        row = {}
+        for n in sizes:
+            plan = rw.Plan(form=form, na=1.4, wavelength=532.0, n_i=1.518, nx=201, ny=201, dx=20.0, dy=20.0,
+                           z=[0.0], n_pupil=n, n_theta=n, n_rho=256, model=model)
+            nc = 1 if model == rw.MODEL_SCALAR else 3
+            E = torch.empty((1, 1, nc, 201, 201), dtype=torch.complex64, device="cuda")
+            I = torch.empty((1, 1, 201, 201), dtype=torch.float32, device="cuda")
+            st = rw.Stacks([dict()])
+            for _ in range(2):
+                plan.compute(st, E=E, I=I)
+            torch.cuda.synchronize()
+            t = 0.0
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                plan.compute(st, E=E, I=I)
+                torch.cuda.synchronize()
+                t += time.perf_counter() - t0
+            row[str(n)] = t * 1e3 / reps
+            plan.close()
+        out[name] = row
+    return dict(workload="one 201x201 image at focus per call (Sec. 5.2.1 speed benchmark), ms per call vs "
+                         "pupil size", ms_per_call=out)
+
+
 def bench_bessel(rw, torch, steps, warmup, n_stacks=256):
     import workloads as W
     w = W.bessel_plain(n_stacks=n_stacks)
@@ -376,7 +415,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="chirpz,bessel,batched,adjoint,surrogate",
+    ap.add_argument("--forms", default="chirpz,sweep,bessel,batched,adjoint,surrogate",
                     help="comma list of extra forms, or 'none'")
     ap.add_argument("--train-seconds", type=float, default=20.0)
     ap.add_argument("--copy-reference", action="store_true",
@@ -406,6 +445,9 @@ def main():
     if "chirpz" in args.forms.split(","):
         forms["chirpz"] = bench_chirpz(rw, torch, args.steps, args.warmup)
         print(f"# chirpz: {forms['chirpz']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    if "sweep" in args.forms.split(","):
+        forms["speed_sweep"] = bench_speed_sweep(rw, torch)
+        print(f"# speed sweep: {forms['speed_sweep']['ms_per_call']}", file=sys.stderr, flush=True)
     if "bessel" in args.forms.split(","):
         forms["bessel"] = bench_bessel(rw, torch, args.steps, args.warmup)
         print(f"# bessel: {forms['bessel']['value']:.3e} voxels/s", file=sys.stderr, flush=True)
