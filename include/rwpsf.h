@@ -194,6 +194,24 @@ int rwpsf_compute(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
 int rwpsf_adjoint(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, const void* E_in,
                   const float* dL_dI, int n_zernike, float* dL_dc, float* dL_dW0, void* stream);
 
+/* Adjoint of the Bessel form (hand-written; the paper differentiates through PyTorch
+   autograd, Sec. 4.1).  The phase of stack b is W_b(t) = W_GL(t; t_s,b) + 2 pi sum_j c_j
+   Z_j(sin t / s_max) over the axisymmetric Noll terms j = 1, 4, 11, 22, and its planes sit
+   at z + z_offset_b (Sec. 3.4.1, 3.4.2).  Given E_in (device complex64
+   [n_stacks][nz][C][nx][ny], as written by rwpsf_compute for the same plan and stacks) and
+   dL_dI (device float [n_stacks][nz][nx][ny]) of a real loss L(I), writes
+     dL_dc  : device float [4], dL/dc_j for j = 1, 4, 11, 22 (waves) for a change of c_j
+              applied to every stack (the sum over stacks); may be NULL;
+     dL_dts : device float [n_stacks], dL/dt_s per stack (per nm; 0 without the
+              Gibson-Lanni layer, where W does not depend on t_s); may be NULL;
+     dL_dz  : device float [n_stacks], dL/dz_offset per stack (per nm); may be NULL.
+   Outputs are overwritten, never accumulated.  Bessel form, any model and theta rule
+   (RWPSF_ERR_UNSUPPORTED for the other forms).  The gradient is that of the computed
+   discrete model (theta rule, radial interpolation).  Every reduction runs in a fixed
+   order, so repeated calls give bitwise-identical results. */
+int rwpsf_adjoint_bessel(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, const void* E_in,
+                         const float* dL_dI, float* dL_dc, float* dL_dts, float* dL_dz, void* stream);
+
 /* ---- batched emitters ----------------------------------------------------------
    Thousands of emitters, each with its own sub-pixel position, axial position,
    Zernike vector, crop size and plane count, evaluated by the Fourier form in one
@@ -308,6 +326,9 @@ enum rwpsf_kernel_id {
   RWPSF_KERNEL_ADJ_REDUCE = 8,        /* adjoint: fixed-order reductions to dL/dW0, dL/dc */
   RWPSF_KERNEL_CZT_ROWS = 9,          /* chirp-z: pupil rows (defocus, FFT convolution along y) */
   RWPSF_KERNEL_CZT_COLS = 10,         /* chirp-z: output columns (FFT convolution along x), |E|^2 */
+  RWPSF_KERNEL_ADJB_RADIAL = 11,      /* Bessel adjoint: pixels -> radial samples (transposed interpolation) */
+  RWPSF_KERNEL_ADJB_CONTRACT = 12,    /* Bessel adjoint: transposed theta contraction on the matrix cores */
+  RWPSF_KERNEL_ADJB_REDUCE = 13,      /* Bessel adjoint: fixed-order reductions to the parameter gradients */
   RWPSF_KERNEL_COUNT = 16
 };
 int rwpsf_plan_set_timing(rwpsf_plan* plan, int enable);   /* also resets the totals */

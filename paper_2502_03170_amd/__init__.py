@@ -42,6 +42,9 @@ KERNEL_ADJ_G = 7
 KERNEL_ADJ_REDUCE = 8
 KERNEL_CZT_ROWS = 9
 KERNEL_CZT_COLS = 10
+KERNEL_ADJB_RADIAL = 11
+KERNEL_ADJB_CONTRACT = 12
+KERNEL_ADJB_REDUCE = 13
 MAX_ZERNIKE = 36
 CIRCULAR = (1 / math.sqrt(2), 1j / math.sqrt(2))
 
@@ -120,6 +123,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "rwpsf_plan_timing": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(ctypes.c_int64)]),
         "rwpsf_adjoint": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_int, c_void_p,
                                   c_void_p, c_void_p]),
+        "rwpsf_adjoint_bessel": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_void_p,
+                                         c_void_p, c_void_p, c_void_p]),
         "rwpsf_sg_param_count": (c_size_t, []),
         "rwpsf_sg_create": (c_int, [c_int, POINTER(c_void_p)]),
         "rwpsf_sg_destroy": (None, [c_void_p]),
@@ -318,6 +323,26 @@ def adjoint(handle, stacks: list[dict], E, dL_dI, n_zernike: int, dL_dc=None, dL
     _check(load().rwpsf_adjoint(handle, len(stacks), arr, c_void_p(E.data_ptr()), c_void_p(dL_dI.data_ptr()),
                                 n_zernike, c_void_p(dL_dc.data_ptr() if dL_dc is not None else 0),
                                 c_void_p(dL_dW0.data_ptr() if dL_dW0 is not None else 0), c_void_p(stream)))
+
+
+def adjoint_bessel(handle, stacks, E, dL_dI, dL_dc=None, dL_dts=None, dL_dz=None, stream=None):
+    """Enqueue rwpsf_adjoint_bessel (E complex64, dL_dI float32; outputs float32 CUDA
+    tensors: dL_dc [4] for Noll 1, 4, 11, 22, dL_dts and dL_dz [n_stacks]; any may be None)."""
+    import torch
+    arr, _keep = _marshal(stacks)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    for t in (E, dL_dI, dL_dc, dL_dts, dL_dz):
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("adjoint tensors must be contiguous CUDA tensors")
+    if dL_dc is not None and dL_dc.numel() < 4:
+        raise ValueError("dL_dc needs 4 entries (Noll 1, 4, 11, 22)")
+    for t in (dL_dts, dL_dz):
+        if t is not None and t.numel() < len(stacks):
+            raise ValueError("per-stack gradients need n_stacks entries")
+    ptr = lambda t: c_void_p(t.data_ptr() if t is not None else 0)
+    _check(load().rwpsf_adjoint_bessel(handle, len(stacks), arr, ptr(E), ptr(dL_dI), ptr(dL_dc), ptr(dL_dts),
+                                       ptr(dL_dz), c_void_p(stream)))
 
 
 def _psf_function():
@@ -539,6 +564,16 @@ class Plan:
             raise ValueError("I is smaller than [stacks][nz][nx][ny]")
         compute(self.handle, stacks, E if fields else None, I if intensity else None, stream)
         return E, I
+
+    def adjoint_bessel(self, stacks, E, dL_dI, stream=None):
+        """(dL/dc for Noll 1, 4, 11, 22 [4], dL/dt_s [n], dL/dz_offset [n]) of the Bessel form."""
+        import torch
+        n = len(stacks)
+        dc = torch.empty(4, dtype=torch.float32, device="cuda")
+        dts = torch.empty(n, dtype=torch.float32, device="cuda")
+        dz = torch.empty(n, dtype=torch.float32, device="cuda")
+        adjoint_bessel(self.handle, stacks, E, dL_dI, dc, dts, dz, stream)
+        return dc, dts, dz
 
     def adjoint(self, stacks: list[dict], E, dL_dI, n_zernike: int, stream=None):
         """(dL/dc [n_zernike], dL/dW0 [N][N]) for a loss with per-voxel dL/dI."""

@@ -309,4 +309,16 @@ int rwpsf_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const void* E, con
   return rw::fourier_adjoint(p, n, s, (const float2*)E, dLdI, n_zernike, dc, dW0, (hipStream_t)stream);
 }
 
+int rwpsf_adjoint_bessel(rwpsf_plan* p, int n, const rwpsf_stack* s, const void* E, const float* dLdI,
+                         float* dc, float* dts, float* dz, void* stream) {
+  if (!p || !E || !dLdI) return RWPSF_ERR_INVALID_ARG;
+  if (p->num.form != RWPSF_FORM_BESSEL) return RWPSF_ERR_UNSUPPORTED;
+  int st = rw::validate_stacks(&p->opt, &p->grid, &p->num, n, s);
+  if (st != RWPSF_OK) return st;
+  int cur = -1;
+  hipGetDevice(&cur);
+  if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
+  return rw::bessel_adjoint(p, n, s, (const float2*)E, dLdI, dc, dts, dz, (hipStream_t)stream);
+}
+
 }  // extern "C"

@@ -444,6 +444,57 @@ int bessel_plan_init(rwpsf_plan* p) {
   return hip_check(hipDeviceSynchronize());
 }
 
+// Pupil x defocus on the theta nodes for stacks s[0..nb) into the plan's Phi workspace.
+static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st) {
+  const int T = p->n_theta_total, nz = p->grid.nz;
+  PhiArgs pa{};
+  pa.T = T;
+  pa.nz = nz;
+  pa.nstk = nb;
+  pa.V = bessel_variants(p->bessel_mode);
+  pa.gibson_lanni = p->opt.gibson_lanni;
+  pa.apod = p->opt.apodization;
+  pa.extra_sz = p->opt.extra_sz;
+  pa.k = p->k;
+  pa.s_max = p->s_max;
+  pa.s_env = p->opt.s_env;
+  pa.gl = p->gl;
+  int maxz = 0;
+  for (int i = 0; i < nb; ++i) {
+    const rwpsf_stack& x = s[i];
+    pa.s[i].t_s = x.t_s_nm;
+    pa.s[i].zoff = x.z_offset_nm;
+    for (int q = 0; q < kAxiTerms; ++q)
+      pa.s[i].coef[q] = kAxiNoll[q] <= x.n_zernike ? x.zernike_waves[kAxiNoll[q] - 1] : 0.0;
+    maxz = std::max(maxz, x.n_zernike);
+  }
+  pa.max_zernike = maxz;
+  const int cols = nb * nz;   // complex columns of Phi per variant
+  const int total = T * cols;
+  const int tr = p->time_begin(RWPSF_KERNEL_BESSEL_PHI, st);
+  hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, p->d_theta,
+                     p->d_z, p->d_fq, p->d_phi, cols * pa.V);
+  const int rc = hip_check(hipGetLastError());
+  p->time_end(tr, st);
+  return rc;
+}
+
+// Polarisation factors of the angular combination with the prefactor folded in:
+// vectorial -(i f k / 2) (ex, ey); scalar (-i f k, 0).
+static void bessel_pol(const rwpsf_plan* p, float out[4]) {
+  const std::complex<double> pref(0.0, -0.5 * p->opt.focal_length * p->k);
+  std::complex<double> ex = pref * std::complex<double>(p->opt.ex_re, p->opt.ex_im);
+  std::complex<double> ey = pref * std::complex<double>(p->opt.ey_re, p->opt.ey_im);
+  if (p->bessel_mode == kModeScalar) {   // E = -i f k I_0, unit incident amplitude
+    ex = std::complex<double>(0.0, -p->opt.focal_length * p->k);
+    ey = 0.0;
+  }
+  out[0] = (float)ex.real();
+  out[1] = (float)ex.imag();
+  out[2] = (float)ey.real();
+  out[3] = (float)ey.imag();
+}
+
 int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
   int cur = -1;
   hipGetDevice(&cur);
@@ -451,48 +502,16 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
   if (6 * p->num.n_rho * 4 > 160 * 1024) return RWPSF_ERR_UNSUPPORTED;
   const int T = p->n_theta_total, R = p->num.n_rho, nz = p->grid.nz;
   const int mode = p->bessel_mode, G = bessel_groups(mode), V = bessel_variants(mode);
-  const std::complex<double> pref(0.0, -0.5 * p->opt.focal_length * p->k);
-  std::complex<double> ex = pref * std::complex<double>(p->opt.ex_re, p->opt.ex_im);
-  std::complex<double> ey = pref * std::complex<double>(p->opt.ey_re, p->opt.ey_im);
-  if (mode == kModeScalar) {   // E = -i f k I_0, unit incident amplitude
-    ex = std::complex<double>(0.0, -p->opt.focal_length * p->k);
-    ey = 0.0;
-  }
+  float pol[4];
+  bessel_pol(p, pol);
   for (int b0 = 0; b0 < n; b0 += kPhiStacks) {
     const int nb = std::min(kPhiStacks, n - b0);
-    PhiArgs pa{};
-    pa.T = T;
-    pa.nz = nz;
-    pa.nstk = nb;
-    pa.V = V;
-    pa.gibson_lanni = p->opt.gibson_lanni;
-    pa.apod = p->opt.apodization;
-    pa.extra_sz = p->opt.extra_sz;
-    pa.k = p->k;
-    pa.s_max = p->s_max;
-    pa.s_env = p->opt.s_env;
-    pa.gl = p->gl;
-    int maxz = 0;
-    for (int i = 0; i < nb; ++i) {
-      const rwpsf_stack& x = s[b0 + i];
-      pa.s[i].t_s = x.t_s_nm;
-      pa.s[i].zoff = x.z_offset_nm;
-      for (int q = 0; q < kAxiTerms; ++q)
-        pa.s[i].coef[q] = kAxiNoll[q] <= x.n_zernike ? x.zernike_waves[kAxiNoll[q] - 1] : 0.0;
-      maxz = std::max(maxz, x.n_zernike);
-    }
-    pa.max_zernike = maxz;
-    const int cols = nb * nz;   // complex columns of Phi
-    const int total = T * cols;
-    int tr = p->time_begin(RWPSF_KERNEL_BESSEL_PHI, st);
-    hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, p->d_theta,
-                       p->d_z, p->d_fq, p->d_phi, cols * V);
-    int rc = hip_check(hipGetLastError());
+    int rc = bessel_phi(p, s + b0, nb, st);
     if (rc) return rc;
-    p->time_end(tr, st);
+    const int cols = nb * nz;
     const int M = 2 * cols * V, N = G * R;
     const int blocks = ((M + RBM - 1) / RBM) * ((N + RBN - 1) / RBN);
-    tr = p->time_begin(RWPSF_KERNEL_BESSEL_CONTRACT, st);
+    int tr = p->time_begin(RWPSF_KERNEL_BESSEL_CONTRACT, st);
     hipLaunchKernelGGL(bessel_contract_kernel, dim3(blocks), dim3(256), 0, st, (const float*)p->d_phi,
                        M, (const float*)p->d_btab, N, (float*)p->d_In, N, M, N, T);
     if ((rc = hip_check(hipGetLastError()))) return rc;
@@ -508,10 +527,10 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
     ea.dx = (float)p->grid.dx_nm;
     ea.dy = (float)p->grid.dy_nm;
     ea.inv_drho = (float)(1.0 / p->drho);
-    ea.exr = (float)ex.real();
-    ea.exi = (float)ex.imag();
-    ea.eyr = (float)ey.real();
-    ea.eyi = (float)ey.imag();
+    ea.exr = pol[0];
+    ea.exi = pol[1];
+    ea.eyr = pol[2];
+    ea.eyi = pol[3];
     for (int i = 0; i < nb; ++i) {
       ea.x0[i] = (float)s[b0 + i].x0_nm;
       ea.y0[i] = (float)s[b0 + i].y0_nm;
@@ -521,6 +540,307 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
                        (const float*)p->d_In, E, I);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
+  }
+  return RWPSF_OK;
+}
+
+// --------------------------------------------------------------------------
+// Adjoint of the Bessel form.  For a real loss L(I) with g = dL/dI:
+//   G_E = 2 g E;  G_In[n](r) = sum over the pixels whose radial stencil reaches r of
+//   weight(r) conj(C_cn) G_E,c  (the transpose of the Lagrange interpolation and of
+//   the angular combination); G_Phi = G_In B^T (the transpose of the contraction);
+//   X_s[q] = sum_{z,v} conj(G_Phi) Phi;  dL/dtheta = sum_q Re(i dW/dtheta(t_q) X_s[q])
+//   with dW/dc_j = 2 pi Z_j, dW/dt_s = d W_GL / d t_s, dW/dz_offset = k cos t.
+// --------------------------------------------------------------------------
+struct AdjRadArgs {
+  int nx, ny, nz, R, mode, s_base, M;   // M: rows of G_In^T (2 nb nz V)
+  float dx, dy, inv_drho, drho;
+  float exr, exi, eyr, eyi;
+  float x0[kPhiStacks], y0[kPhiStacks];
+};
+
+// One workgroup per (stack, plane); thread r owns radial sample r and gathers, row by
+// row, the pixels whose stencil reaches it (a ring of width four samples), recomputing
+// each pixel's stencil exactly as the forward epilogue does.  Fixed order: bitwise
+// repeatable.  Writes G_In^T[g R + r][2 ((s nz + z) V + v) + re/im].
+__global__ void __launch_bounds__(256) adjb_radial_kernel(AdjRadArgs a, const float2* __restrict__ E,
+                                                          const float* __restrict__ dLdI,
+                                                          float* __restrict__ GInT) {
+  const int si = blockIdx.x / a.nz, zi = blockIdx.x % a.nz;
+  const int R = a.R;
+  const bool scalar = a.mode == kModeScalar;
+  const int NI = scalar ? 1 : 3;
+  const size_t plane = (size_t)a.nx * a.ny;
+  const size_t gsz = (size_t)(a.s_base + si) * a.nz + zi;
+  const float2* Eb = E + gsz * NI * plane;
+  const float* Lb = dLdI + gsz * plane;
+  const float x0 = a.x0[si], y0 = a.y0[si];
+  const double mg = (double)a.drho + 1e-3;     // generous margin of the candidate ring
+  for (int r = threadIdx.x; r < R; r += blockDim.x) {
+    float ar[3] = {0.f, 0.f, 0.f}, ai[3] = {0.f, 0.f, 0.f};
+    const double lo = fmax(0.0, (r - 2) * (double)a.drho - mg);
+    const bool open_hi = r + 2 >= R - 3;           // the last stencil is clamped: all larger radii
+    const double hi = (r + 2) * (double)a.drho + mg;
+    for (int i = 0; i < a.nx; ++i) {
+      const float x = (float)(i - a.nx / 2) * a.dx - x0;
+      const double x2 = (double)x * x;
+      if (!open_hi && hi * hi < x2) continue;
+      const double yhi = open_hi ? 1e30 : sqrt(hi * hi - x2);
+      const double ylo = lo * lo > x2 ? sqrt(lo * lo - x2) : 0.0;
+      // y = (j - ny/2) dy - y0  ->  j = (y + y0) / dy + ny/2.  The ring meets this row in
+      // y in [-yhi, -ylo] and [ylo, yhi]; each becomes a pixel range widened by one pixel,
+      // and ranges that touch are merged so that no pixel is visited twice.
+      auto jrange = [&](double ya, double yb, int* j0, int* j1) {
+        const double ja = fmax(-1.0, fmin((double)a.ny, floor((ya + y0) / a.dy) + a.ny / 2 - 1));
+        const double jb = fmax(-1.0, fmin((double)a.ny, ceil((yb + y0) / a.dy) + a.ny / 2 + 1));
+        *j0 = max(0, (int)ja);
+        *j1 = min(a.ny - 1, (int)jb);
+      };
+      int ra0, ra1, rb0, rb1;
+      jrange(-yhi, -ylo, &ra0, &ra1);
+      jrange(ylo, yhi, &rb0, &rb1);
+      int nrange = 2;
+      if (ra1 >= rb0 - 1) {
+        ra1 = max(ra1, rb1);
+        nrange = 1;
+      }
+      for (int side = 0; side < nrange; ++side) {
+        const int j0 = side == 0 ? ra0 : rb0, j1 = side == 0 ? ra1 : rb1;
+        for (int j = j0; j <= j1; ++j) {
+          const float y = (float)(j - a.ny / 2) * a.dy - y0;
+          const float rho = sqrtf(x * x + y * y);
+          const float t = rho * a.inv_drho;
+          const int r0 = min((int)t, R - 3);
+          const int kk = r - r0 + 1;                 // stencil slot of sample r
+          const bool ghost = r0 == 0 && r == 1;      // node -1 mirrored onto node 1
+          if ((kk < 0 || kk > 3) && !ghost) continue;
+          const float f = t - (float)r0;
+          const float wm = -f * (f - 1.f) * (f - 2.f) * (1.f / 6.f);
+          const float w0 = (f + 1.f) * (f - 1.f) * (f - 2.f) * 0.5f;
+          const float w1 = -(f + 1.f) * f * (f - 2.f) * 0.5f;
+          const float w2 = (f + 1.f) * f * (f - 1.f) * (1.f / 6.f);
+          const float wk = kk == 0 ? wm : (kk == 1 ? w0 : (kk == 2 ? w1 : (kk == 3 ? w2 : 0.f)));
+          const int pix = i * a.ny + j;
+          const float g2 = 2.f * Lb[pix];
+          if (scalar) {
+            const float2 e = Eb[pix];
+            const float gr = g2 * e.x, gi = g2 * e.y;
+            const float w = wk + (ghost ? wm : 0.f);
+            // conj(pref) G
+            ar[0] += w * (a.exr * gr + a.exi * gi);
+            ai[0] += w * (a.exr * gi - a.exi * gr);
+            continue;
+          }
+          const float2 ex = Eb[pix], ey = Eb[plane + pix], ez = Eb[2 * plane + pix];
+          const float gxr = g2 * ex.x, gxi = g2 * ex.y, gyr = g2 * ey.x, gyi = g2 * ey.y;
+          const float gzr = g2 * ez.x, gzi = g2 * ez.y;
+          float c1 = 1.f, s1 = 0.f;
+          if (rho > 0.f) {
+            c1 = x / rho;
+            s1 = y / rho;
+          }
+          const float c2 = c1 * c1 - s1 * s1, s2 = 2.f * s1 * c1;
+          // P0 = conj(ex) Gx + conj(ey) Gy
+          const float p0r = a.exr * gxr + a.exi * gxi + a.eyr * gyr + a.eyi * gyi;
+          const float p0i = a.exr * gxi - a.exi * gxr + a.eyr * gyi - a.eyi * gyr;
+          // P1 = 2i conj(ex c1 + ey s1) Gz
+          const float qr = a.exr * c1 + a.eyr * s1, qi = a.exi * c1 + a.eyi * s1;
+          const float tr_ = qr * gzr + qi * gzi, ti_ = qr * gzi - qi * gzr;   // conj(q) Gz
+          const float p1r = -2.f * ti_, p1i = 2.f * tr_;
+          // P2 = conj(-(ex c2 + ey s2)) Gx + conj(-ex s2 + ey c2) Gy
+          const float ur = -(a.exr * c2 + a.eyr * s2), ui = -(a.exi * c2 + a.eyi * s2);
+          const float vr = -a.exr * s2 + a.eyr * c2, vi = -a.exi * s2 + a.eyi * c2;
+          const float p2r = ur * gxr + ui * gxi + vr * gyr + vi * gyi;
+          const float p2i = ur * gxi - ui * gxr + vr * gyi - vi * gyr;
+          const float wg0 = wk + (ghost ? wm : 0.f), wg1 = wk - (ghost ? wm : 0.f);   // I_1 is odd
+          ar[0] += wg0 * p0r;
+          ai[0] += wg0 * p0i;
+          ar[1] += wg1 * p1r;
+          ai[1] += wg1 * p1i;
+          ar[2] += wg0 * p2r;
+          ai[2] += wg0 * p2i;
+        }
+      }
+    }
+    // scatter G_{I_n} to the (variant, group) rows of the contraction
+    const int V = a.mode == kModeFresnel ? 2 : 1;
+    const int col = (si * a.nz + zi) * V;
+    auto put = [&](int v, int g, float re, float im) {
+      float* d = GInT + (size_t)(g * R + r) * a.M + 2 * (col + v);
+      d[0] = re;
+      d[1] = im;
+    };
+    if (a.mode == kModeFresnel) {
+      put(0, 0, ar[0], ai[0]);
+      put(1, 1, ar[0], ai[0]);
+      put(1, 2, ar[1], ai[1]);
+      put(1, 3, ar[2], ai[2]);
+      put(0, 4, -ar[2], -ai[2]);
+      put(1, 0, 0.f, 0.f);
+      put(0, 1, 0.f, 0.f);
+      put(0, 2, 0.f, 0.f);
+      put(0, 3, 0.f, 0.f);
+      put(1, 4, 0.f, 0.f);
+    } else {
+      for (int n = 0; n < NI; ++n) put(0, n, ar[n], ai[n]);
+    }
+  }
+}
+
+// X_s[q] = sum_{z,v} conj(G_Phi[(s,z,v)][q]) Phi[q][(s,z),v], FP64 accumulation.
+__global__ void adjb_x_kernel(const float* __restrict__ GPhi, const float2* __restrict__ phi,
+                              double2* __restrict__ X, int nb, int nz, int V, int T) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nb * T) return;
+  const int s = idx / T, q = idx % T;
+  const int ld = nb * nz * V;
+  double xr = 0.0, xi = 0.0;
+  for (int z = 0; z < nz; ++z)
+    for (int v = 0; v < V; ++v) {
+      const int col = (s * nz + z) * V + v;
+      const double gr = GPhi[(size_t)(2 * col) * T + q], gi = GPhi[(size_t)(2 * col + 1) * T + q];
+      const float2 ph = phi[(size_t)q * ld + col];
+      xr += gr * ph.x + gi * ph.y;
+      xi += gr * ph.y - gi * ph.x;
+    }
+  X[idx] = make_double2(xr, xi);
+}
+
+// Per stack: dL/dt_s, dL/dz_offset and the stack's share of dL/dc_j (fixed order over q).
+// node[q] = (k cos t, Re dW/dt_s, Im dW/dt_s, 2 pi Z_1, 2 pi Z_4, 2 pi Z_11, 2 pi Z_22).
+__global__ void adjb_stack_kernel(const double2* __restrict__ X, const double* __restrict__ node, int nb,
+                                  int T, int s_base, float* __restrict__ dts, float* __restrict__ dz,
+                                  double* __restrict__ dcp) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nb) return;
+  double a_ts = 0.0, a_z = 0.0, a_c[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int q = 0; q < T; ++q) {
+    const double2 x = X[(size_t)s * T + q];
+    const double* nd = node + 7 * (size_t)q;
+    a_z -= nd[0] * x.y;                       // Re(i w X) = -w Im X for real w
+    a_ts -= nd[1] * x.y + nd[2] * x.x;        // Re(i (a + ib) X)
+    for (int j = 0; j < 4; ++j) a_c[j] -= nd[3 + j] * x.y;
+  }
+  const int gs = s_base + s;
+  if (dts) dts[gs] = (float)a_ts;
+  if (dz) dz[gs] = (float)a_z;
+  for (int j = 0; j < 4; ++j) dcp[4 * (size_t)gs + j] = a_c[j];
+}
+
+__global__ void adjb_coef_kernel(const double* __restrict__ dcp, int n, float* __restrict__ dc) {
+  const int j = threadIdx.x;
+  if (j >= 4) return;
+  double acc = 0.0;
+  for (int s = 0; s < n; ++s) acc += dcp[4 * (size_t)s + j];
+  dc[j] = (float)acc;
+}
+
+__global__ void adjb_transpose_kernel(const float* __restrict__ in, float* __restrict__ out, int rows, int cols) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int r = idx / cols, c = idx % cols;
+  out[(size_t)c * rows + r] = in[idx];
+}
+
+// Tables and workspace of the adjoint, built on first use.
+static int bessel_adjoint_prepare(rwpsf_plan* p) {
+  if (p->d_btabT) return RWPSF_OK;
+  const int T = p->n_theta_total, R = p->num.n_rho, nz = p->grid.nz;
+  const int G = bessel_groups(p->bessel_mode), V = bessel_variants(p->bessel_mode);
+  std::vector<double> th(T);
+  int st;
+  if ((st = hip_check(hipMemcpy(th.data(), p->d_theta, T * sizeof(double), hipMemcpyDeviceToHost)))) return st;
+  std::vector<double> node(7 * (size_t)T);
+  const int noll[4] = {1, 4, 11, 22};
+  for (int q = 0; q < T; ++q) {
+    const double sn = std::sin(th[q]), cs = std::cos(th[q]);
+    node[7 * q] = p->k * cs;
+    double a = 0.0, b = 0.0;
+    if (p->opt.gibson_lanni) {
+      // t_i = t_s + n_i (-t_s / n_s - ...): dW/dt_s = k0 (root(n_s) + (1 - n_i / n_s) root(n_i))
+      const double inv2 = (p->opt.n_i * sn) * (p->opt.n_i * sn);
+      const std::complex<double> rs = std::sqrt(std::complex<double>(p->opt.n_s * p->opt.n_s - inv2, 0.0));
+      const std::complex<double> ri = std::sqrt(std::complex<double>(p->opt.n_i * p->opt.n_i - inv2, 0.0));
+      const std::complex<double> d = (kTwoPi / p->opt.wavelength_nm) * (rs + (1.0 - p->opt.n_i / p->opt.n_s) * ri);
+      a = d.real();
+      b = d.imag();
+    }
+    node[7 * q + 1] = a;
+    node[7 * q + 2] = b;
+    for (int j = 0; j < 4; ++j) node[7 * q + 3 + j] = kTwoPi * zernike_noll(noll[j], sn / p->s_max, 1.0, 0.0);
+  }
+  const size_t M = 2 * (size_t)kPhiStacks * nz * V;
+  if ((st = dev_alloc(p, &p->d_btabT, (size_t)G * R * T))) return st;
+  if ((st = dev_alloc(p, &p->d_GInT, (size_t)G * R * M))) return st;
+  if ((st = dev_alloc(p, &p->d_GPhi, M * T))) return st;
+  if ((st = dev_alloc(p, &p->d_adjX, (size_t)kPhiStacks * T))) return st;
+  if ((st = dev_alloc(p, &p->d_adjnode, node.size()))) return st;
+  if ((st = dev_alloc(p, &p->d_dcp, 4 * (size_t)RWPSF_MAX_STACKS_PER_CALL))) return st;
+  if ((st = hip_check(hipMemcpy(p->d_adjnode, node.data(), node.size() * sizeof(double), hipMemcpyHostToDevice))))
+    return st;
+  const int total = G * R * T;
+  hipLaunchKernelGGL(adjb_transpose_kernel, dim3((total + 255) / 256), dim3(256), 0, 0, p->d_btab, p->d_btabT, T,
+                     G * R);
+  if ((st = hip_check(hipGetLastError()))) return st;
+  return hip_check(hipDeviceSynchronize());
+}
+
+int bessel_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E, const float* dLdI, float* dc,
+                   float* dts, float* dz, hipStream_t st) {
+  int rc = bessel_adjoint_prepare(p);
+  if (rc) return rc;
+  const int T = p->n_theta_total, R = p->num.n_rho, nz = p->grid.nz;
+  const int mode = p->bessel_mode, G = bessel_groups(mode), V = bessel_variants(mode);
+  float pol[4];
+  bessel_pol(p, pol);
+  for (int b0 = 0; b0 < n; b0 += kPhiStacks) {
+    const int nb = std::min(kPhiStacks, n - b0);
+    if ((rc = bessel_phi(p, s + b0, nb, st))) return rc;
+    const int M = 2 * nb * nz * V;
+    AdjRadArgs ra{};
+    ra.nx = p->grid.nx;
+    ra.ny = p->grid.ny;
+    ra.nz = nz;
+    ra.R = R;
+    ra.mode = mode;
+    ra.s_base = b0;
+    ra.M = M;
+    ra.dx = (float)p->grid.dx_nm;
+    ra.dy = (float)p->grid.dy_nm;
+    ra.inv_drho = (float)(1.0 / p->drho);
+    ra.drho = (float)p->drho;
+    ra.exr = pol[0];
+    ra.exi = pol[1];
+    ra.eyr = pol[2];
+    ra.eyi = pol[3];
+    for (int i = 0; i < nb; ++i) {
+      ra.x0[i] = (float)s[b0 + i].x0_nm;
+      ra.y0[i] = (float)s[b0 + i].y0_nm;
+    }
+    int tr = p->time_begin(RWPSF_KERNEL_ADJB_RADIAL, st);
+    hipLaunchKernelGGL(adjb_radial_kernel, dim3(nb * nz), dim3(256), 0, st, ra, E, dLdI, p->d_GInT);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+    p->time_end(tr, st);
+    // G_Phi[m][q] = sum_k G_In^T[k][m] B^T[k][q]
+    const int K = G * R;
+    const int blocks = ((M + RBM - 1) / RBM) * ((T + RBN - 1) / RBN);
+    tr = p->time_begin(RWPSF_KERNEL_ADJB_CONTRACT, st);
+    hipLaunchKernelGGL(bessel_contract_kernel, dim3(blocks), dim3(256), 0, st, (const float*)p->d_GInT, M,
+                       (const float*)p->d_btabT, T, p->d_GPhi, T, M, T, K);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+    p->time_end(tr, st);
+    tr = p->time_begin(RWPSF_KERNEL_ADJB_REDUCE, st);
+    hipLaunchKernelGGL(adjb_x_kernel, dim3((nb * T + 255) / 256), dim3(256), 0, st, (const float*)p->d_GPhi,
+                       (const float2*)p->d_phi, p->d_adjX, nb, nz, V, T);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+    hipLaunchKernelGGL(adjb_stack_kernel, dim3((nb + 63) / 64), dim3(64), 0, st, (const double2*)p->d_adjX,
+                       (const double*)p->d_adjnode, nb, T, b0, dts, dz, p->d_dcp);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+    p->time_end(tr, st);
+  }
+  if (dc) {
+    hipLaunchKernelGGL(adjb_coef_kernel, dim3(1), dim3(64), 0, st, (const double*)p->d_dcp, n, dc);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
   }
   return RWPSF_OK;
 }

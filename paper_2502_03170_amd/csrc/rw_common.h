@@ -192,6 +192,13 @@ struct rwpsf_plan {
   float2* d_In = nullptr;       // workspace [stacks][nz][V][re/im][G][R]
   int bessel_stacks = 0;        // capacity of the Bessel workspaces
   double drho = 0;              // radial sample pitch
+  // Bessel-form adjoint (built on first use)
+  float* d_btabT = nullptr;     // [G][R][T] transposed table
+  float* d_GInT = nullptr;      // workspace [G][R][2 stacks nz V] gradients of the radial samples
+  float* d_GPhi = nullptr;      // workspace [2 stacks nz V][T] gradient of Phi
+  double2* d_adjX = nullptr;    // workspace [stacks][T] sum_z conj(G_Phi) Phi
+  double* d_adjnode = nullptr;  // [T][7] k cos t, dW/dt_s (re, im), 2 pi Z_{1,4,11,22}
+  double* d_dcp = nullptr;      // [max stacks][4] per-stack shares of dL/dc
 
   // per-kernel timing (opt-in)
   struct TimingRec {

@@ -18,6 +18,8 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
 int czt_plan_init(rwpsf_plan* p);
 int czt_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);
 int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);
+int bessel_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E, const float* dLdI, float* dc,
+                   float* dts, float* dz, hipStream_t st);
 
 // Products q_s, q_p of the Fresnel transmission coefficients (Sec. 3.3) of the
 // interfaces sample (n_s) -> coverslip (n_g) -> immersion (n_i) for the ray of immersion

@@ -1,0 +1,156 @@
+"""Bessel-form adjoint on the GPU against the FP64 gradient oracle (which is pinned by
+central differences of the forward oracle), its invariants and its determinism."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import adjoint_bessel as AB
+from oracle import optics as O
+from oracle.adjoint import mse_loss
+from tests.helpers import rel_l2
+
+pytestmark = pytest.mark.gpu
+TOL = 2e-4
+GL = W.GIBSON_LANNI
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _setup(rw, kind, nx=17, dx=40.0, n_stacks=2, seed=21, gl=True):
+    scalar = kind == "scalar"
+    fresnel = kind == "fresnel"
+    z = np.array([-400.0, 0.0, 350.0])
+    glp = dict(GL) if gl else None
+    plan = rw.Plan(form=rw.FORM_BESSEL, na=1.4, wavelength=600.0, n_i=1.518, nx=nx, ny=nx, dx=dx, dy=dx, z=z,
+                   e_inc=W.CIRCULAR, gibson_lanni=glp, n_theta=400, n_rho=256,
+                   model=rw.MODEL_SCALAR if scalar else rw.MODEL_VECTORIAL,
+                   fresnel=(GL["n_s"], GL["n_g"]) if fresnel else None)
+    g = O.GibsonLanni(n_s=GL["n_s"], n_g=GL["n_g"], n_g_design=GL["n_g_design"], n_i_design=GL["n_i_design"],
+                      t_g=GL["t_g"], t_g_design=GL["t_g_design"], t_i_design=GL["t_i_design"]) if gl else None
+    opt = O.Optics(na=1.4, wavelength=600.0, n_i=1.518, e_inc=W.CIRCULAR, gl=g,
+                   fresnel_media=(GL["n_s"], GL["n_g"]) if fresnel else ())
+    rng = np.random.default_rng(seed)
+    coeffs = np.zeros(22)
+    coeffs[3], coeffs[10], coeffs[21] = rng.normal(0, 0.05, 3)
+    ts = rng.uniform(500.0, 3000.0, n_stacks)
+    stacks = [(float(ts[b]), float(rng.uniform(-0.4, 0.4) * dx), float(rng.uniform(-0.4, 0.4) * dx),
+               float(-ts[b] + rng.uniform(-200, 200))) for b in range(n_stacks)]
+    st = [dict(t_s=s[0], x0=s[1], y0=s[2], z_offset=s[3], zernike=coeffs) for s in stacks]
+    return plan, opt, z, coeffs, stacks, st, scalar
+
+
+def _targets(opt, plan, z, coeffs, stacks, scalar, seed=5):
+    # dL/dI of an MSE loss against noisy targets at perturbed coefficients (FP64 oracle)
+    _, I0 = AB.forward(opt, plan.nx, plan.ny, plan.grid.dx_nm, plan.grid.dy_nm, z, coeffs, stacks, 256,
+                       "gauss", scalar)
+    c2 = coeffs.copy()
+    c2[3] += 0.03
+    _, I1 = AB.forward(opt, plan.nx, plan.ny, plan.grid.dx_nm, plan.grid.dy_nm, z, c2, stacks, 256, "gauss",
+                       scalar)
+    s0 = 1.0 / np.max(I0)
+    scale = s0 * (1.0 + 0.1 * np.arange(len(stacks)))
+    rng = np.random.default_rng(seed)
+    Y = scale[:, None, None, None] * I1 * (1 + 0.2 * rng.standard_normal(I1.shape))
+    _, g = mse_loss(I0, Y, scale)
+    return g
+
+
+@pytest.mark.parametrize("kind", ["vectorial", "fresnel", "scalar"])
+def test_bessel_adjoint_matches_oracle(lib, kind):
+    import torch
+    rw = lib
+    plan, opt, z, coeffs, stacks, st, scalar = _setup(rw, kind)
+    g = _targets(opt, plan, z, coeffs, stacks, scalar)
+    E, _ = plan.compute(st, intensity=False)
+    dLdI = torch.tensor(g, dtype=torch.float32, device="cuda").contiguous()
+    dc, dts, dz = plan.adjoint_bessel(st, E, dLdI)
+    torch.cuda.synchronize()
+    rdc, rdts, rdz = AB.gradient(opt, plan.nx, plan.ny, plan.grid.dx_nm, plan.grid.dy_nm, z, coeffs, stacks, g,
+                                 256, "gauss", scalar)
+    assert rel_l2(_np(dc)[1:], rdc[1:]) < TOL
+    assert rel_l2(_np(dts), rdts) < TOL
+    assert rel_l2(_np(dz), rdz) < TOL
+    # a global phase changes no intensity
+    assert abs(_np(dc)[0]) < 1e-4 * np.max(np.abs(rdc[1:]))
+
+
+def test_bessel_adjoint_simpson_without_sample_layer_and_determinism(lib):
+    import torch
+    rw = lib
+    w = W.bessel_plain()
+    z = np.array([-300.0, 100.0])
+    plan = rw.Plan(form=rw.FORM_BESSEL, na=1.4, wavelength=532.0, n_i=1.518, nx=24, ny=24, dx=30.0, dy=30.0,
+                   z=z, e_inc=w["e_inc"], n_theta=129, n_rho=200, theta_rule=rw.THETA_SIMPSON)
+    opt = O.Optics(na=1.4, wavelength=532.0, n_i=1.518, e_inc=w["e_inc"])
+    coeffs = np.zeros(11)
+    coeffs[3], coeffs[10] = 0.05, -0.03
+    stacks = [(0.0, 7.0, -4.0, 120.0), (0.0, -11.0, 9.0, -260.0), (0.0, 0.0, 0.0, 0.0)]
+    st = [dict(x0=s[1], y0=s[2], z_offset=s[3], zernike=coeffs) for s in stacks]
+    rng = np.random.default_rng(8)
+    g = rng.standard_normal((3, 2, 24, 24))
+    E, _ = plan.compute(st, intensity=False)
+    dLdI = torch.tensor(g, dtype=torch.float32, device="cuda")
+    a = plan.adjoint_bessel(st, E, dLdI)
+    b = plan.adjoint_bessel(st, E, dLdI)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert np.array_equal(_np(x), _np(y))
+    rdc, rdts, rdz = AB.gradient(opt, 24, 24, 30.0, 30.0, z, coeffs, stacks, g, 129, "simpson")
+    dc, dts, dz = (_np(x) for x in a)
+    assert rel_l2(dc[1:], rdc[1:]) < TOL
+    assert np.all(dts == 0.0)
+    assert rel_l2(dz, rdz) < TOL
+
+
+def test_bessel_adjoint_workload_size_sampled_and_additive(lib):
+    """65 x 65 x 33 (the Bessel workload's grid), 64 stacks with Gibson-Lanni depths:
+    two stacks against the oracle, and the shared-coefficient gradient additive over calls."""
+    import torch
+    rw = lib
+    w = W.bessel_plain()
+    z = np.asarray(w["z"])
+    glp = dict(GL)
+    plan = rw.Plan(form=rw.FORM_BESSEL, na=1.4, wavelength=532.0, n_i=1.518, nx=65, ny=65, dx=20.0, dy=20.0,
+                   z=z, e_inc=w["e_inc"], gibson_lanni=glp, n_theta=400, n_rho=256)
+    rng = np.random.default_rng(31)
+    coeffs = np.zeros(22)
+    coeffs[3], coeffs[10], coeffs[21] = 0.04, -0.03, 0.02
+    ts = rng.uniform(0.0, 3000.0, 64)
+    st = [dict(t_s=float(ts[b]), z_offset=float(-ts[b]), x0=float(rng.uniform(-8, 8)),
+               y0=float(rng.uniform(-8, 8)), zernike=coeffs) for b in range(64)]
+    E, I = plan.compute(st)
+    g = torch.randn((64, z.size, 65, 65), generator=torch.Generator().manual_seed(3)).to("cuda")
+    dc, dts, dz = plan.adjoint_bessel(st, E, g)
+    parts = [plan.adjoint_bessel(st[i:i + 16], E[i:i + 16], g[i:i + 16].contiguous()) for i in range(0, 64, 16)]
+    torch.cuda.synchronize()
+    tot = sum(_np(p[0]) for p in parts)
+    assert rel_l2(_np(dc)[1:], tot[1:]) < 1e-5
+    assert np.array_equal(_np(dts), np.concatenate([_np(p[1]) for p in parts]))
+    g_np = _np(g).astype(np.float64)
+    gopt = O.GibsonLanni(n_s=GL["n_s"], n_g=GL["n_g"], n_g_design=GL["n_g_design"], n_i_design=GL["n_i_design"],
+                         t_g=GL["t_g"], t_g_design=GL["t_g_design"], t_i_design=GL["t_i_design"])
+    opt = O.Optics(na=1.4, wavelength=532.0, n_i=1.518, e_inc=w["e_inc"], gl=gopt)
+    for b in (0, 37):
+        s = st[b]
+        one = [(s["t_s"], s["x0"], s["y0"], s["z_offset"])]
+        rdc, rdts, rdz = AB.gradient(opt, 65, 65, 20.0, 20.0, z, coeffs, one, g_np[b:b + 1], 256)
+        d1 = plan.adjoint_bessel([s], E[b:b + 1], g[b:b + 1].contiguous())
+        torch.cuda.synchronize()
+        assert rel_l2(_np(d1[0])[1:], rdc[1:]) < TOL
+        assert abs(_np(dts)[b] - rdts[0]) < TOL * abs(rdts[0])
+        assert abs(_np(dz)[b] - rdz[0]) < TOL * abs(rdz[0])
+
+
+def test_bessel_adjoint_rejects_other_forms(lib):
+    import torch
+    rw = lib
+    p = rw.Plan(form=rw.FORM_FOURIER, na=1.4, wavelength=532.0, n_i=1.518, nx=16, ny=16, dx=30.0, dy=30.0,
+                z=[0.0], n_pupil=32)
+    E, I = p.compute([dict()])
+    with pytest.raises(rw.RwpsfError) as ei:
+        p.adjoint_bessel([dict()], E, I)
+    assert ei.value.status == rw.ERR_UNSUPPORTED
