@@ -330,6 +330,57 @@ def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
                               flops_per_step=fwd + adj))
 
 
+def bench_adjoint_bessel(rw, torch, steps, warmup, n_stacks=64):
+    """Gradient step of the Bessel form at the Bessel workload's grid (65x65x33 at 20 nm,
+    200 Gauss-Legendre nodes split at the critical angle, 256 radial samples) with the
+    Gibson-Lanni layer: forward (fields) + adjoint (dL/dc for Noll 1, 4, 11, 22, dL/dt_s,
+    dL/dz_offset per stack) for an MSE loss."""
+    import workloads as W
+    w = W.bessel_plain()
+    z = np.asarray(w["z"])
+    plan = rw.Plan(form=rw.FORM_BESSEL, na=1.4, wavelength=532.0, n_i=1.518, nx=65, ny=65, dx=20.0, dy=20.0,
+                   z=z, e_inc=w["e_inc"], gibson_lanni=dict(W.GIBSON_LANNI), n_theta=200, n_rho=256)
+    rng = np.random.default_rng(405)
+    coeffs = np.zeros(22)
+    coeffs[3], coeffs[10], coeffs[21] = 0.04, -0.03, 0.02
+    st = []
+    for _ in range(n_stacks):
+        ts = rng.uniform(0.0, 5000.0)
+        st.append(dict(t_s=ts, z_offset=-ts, x0=rng.uniform(-10, 10), y0=rng.uniform(-10, 10), zernike=coeffs))
+    st = rw.Stacks(st)
+    nz = z.size
+    E = torch.empty((n_stacks, nz, 3, 65, 65), dtype=torch.complex64, device="cuda")
+    I = torch.empty((n_stacks, nz, 65, 65), dtype=torch.float32, device="cuda")
+    Y = torch.rand_like(I)
+    dc = torch.empty(4, dtype=torch.float32, device="cuda")
+    dts = torch.empty(n_stacks, dtype=torch.float32, device="cuda")
+    dz = torch.empty(n_stacks, dtype=torch.float32, device="cuda")
+
+    def step():
+        plan.compute(st, E=E, I=I)
+        rw.adjoint_bessel(plan.handle, st, E, (2.0 / I.numel()) * (I - Y), dc, dts, dz)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    ms = _cuda_time(torch, step, max(3, steps // 4))
+    kt = {k: plan.timing(v) for k, v in (("bessel_phi", rw.KERNEL_BESSEL_PHI),
+                                          ("bessel_contract", rw.KERNEL_BESSEL_CONTRACT),
+                                          ("bessel_epilogue", rw.KERNEL_BESSEL_EPILOGUE),
+                                          ("adjb_radial", rw.KERNEL_ADJB_RADIAL),
+                                          ("adjb_contract", rw.KERNEL_ADJB_CONTRACT),
+                                          ("adjb_reduce", rw.KERNEL_ADJB_REDUCE))}
+    plan.close()
+    vox = n_stacks * nz * 65 * 65
+    return dict(workload=f"Bessel adjoint: {n_stacks} stacks of 65x65x{nz} at 20 nm, Gibson-Lanni depths "
+                         "U[0, 5] um, m = 0 Zernike; step = forward (fields) + adjoint (dL/dc, dL/dt_s, dL/dz)",
+                value=vox / (ms * 1e-3), unit="voxels/s (forward+adjoint)", ms_per_step=ms,
+                gradient_steps_per_s=1e3 / ms,
+                kernels={k: dict(total_ms=v[0], launches=v[1], avg_us=(v[0] / v[1] * 1e3 if v[1] else None))
+                         for k, v in kt.items()})
+
+
 def bench_surrogate(rw, torch, train_seconds):
     from paper_2502_03170_amd import surrogate_train as ST
     eng = ST.CropEngine(max_emitters=4096)
@@ -415,7 +466,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--forms", default="chirpz,sweep,bessel,batched,adjoint,surrogate",
+    ap.add_argument("--forms", default="chirpz,sweep,bessel,batched,adjoint,adjoint_bessel,surrogate",
                     help="comma list of extra forms, or 'none'")
     ap.add_argument("--train-seconds", type=float, default=20.0)
     ap.add_argument("--copy-reference", action="store_true",
@@ -457,6 +508,10 @@ def main():
     if "adjoint" in args.forms.split(","):
         forms["adjoint"] = bench_adjoint(rw, torch, args.steps, args.warmup)
         print(f"# adjoint: {forms['adjoint']['ms_per_step']:.2f} ms/step", file=sys.stderr, flush=True)
+    if "adjoint_bessel" in args.forms.split(","):
+        forms["adjoint_bessel"] = bench_adjoint_bessel(rw, torch, args.steps, args.warmup)
+        print(f"# adjoint_bessel: {forms['adjoint_bessel']['ms_per_step']:.2f} ms/step", file=sys.stderr,
+              flush=True)
     if "surrogate" in args.forms.split(","):
         forms["surrogate"] = bench_surrogate(rw, torch, args.train_seconds)
         print(f"# surrogate: {forms['surrogate']['speedup_vs_plain']}", file=sys.stderr, flush=True)

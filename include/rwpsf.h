@@ -206,7 +206,8 @@ int rwpsf_adjoint(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, con
               Gibson-Lanni layer, where W does not depend on t_s); may be NULL;
      dL_dz  : device float [n_stacks], dL/dz_offset per stack (per nm); may be NULL.
    Outputs are overwritten, never accumulated.  Bessel form, any model and theta rule
-   (RWPSF_ERR_UNSUPPORTED for the other forms).  The gradient is that of the computed
+   (RWPSF_ERR_UNSUPPORTED for the other forms, or for n_rho > 3200, whose per-sample
+   sums no longer fit one workgroup's LDS).  The gradient is that of the computed
    discrete model (theta rule, radial interpolation).  Every reduction runs in a fixed
    order, so repeated calls give bitwise-identical results. */
 int rwpsf_adjoint_bessel(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, const void* E_in,

@@ -438,8 +438,10 @@ int bessel_plan_init(rwpsf_plan* p) {
   hipLaunchKernelGGL(bessel_table_kernel, dim3((total + 255) / 256), dim3(256), 0, 0, p->d_btab,
                      p->d_theta, p->d_wtheta, T, R, p->bessel_mode, p->k, p->drho);
   if ((st = hip_check(hipGetLastError()))) return st;
+  // the limit belongs to the kernel, not to this plan: allow the whole LDS, so that a later
+  // plan with fewer radial samples cannot lower it below what this plan launches with
   if ((st = hip_check(hipFuncSetAttribute((const void*)bessel_epilogue_kernel,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, 6 * R * 4))))
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))))
     return st;
   return hip_check(hipDeviceSynchronize());
 }
@@ -559,130 +561,133 @@ struct AdjRadArgs {
   float x0[kPhiStacks], y0[kPhiStacks];
 };
 
-// One workgroup per (stack, plane); thread r owns radial sample r and gathers, row by
-// row, the pixels whose stencil reaches it (a ring of width four samples), recomputing
-// each pixel's stencil exactly as the forward epilogue does.  Fixed order: bitwise
-// repeatable.  Writes G_In^T[g R + r][2 ((s nz + z) V + v) + re/im].
+// Projections P_n = sum_c conj(C_cn) G_E,c of one pixel (the transpose of the angular
+// combination), G_E = 2 (dL/dI) E; p[0..5] = (P_0, P_1, P_2) as re, im.
+__device__ __forceinline__ void adjb_project(const AdjRadArgs& a, bool scalar, const float2* Eb, size_t plane,
+                                             float g2, int pix, float x, float y, float rho, float p[6]) {
+  if (scalar) {
+    const float2 e = Eb[pix];
+    const float gr = g2 * e.x, gi = g2 * e.y;
+    p[0] = a.exr * gr + a.exi * gi;    // conj(pref) G
+    p[1] = a.exr * gi - a.exi * gr;
+    p[2] = p[3] = p[4] = p[5] = 0.f;
+    return;
+  }
+  const float2 ex = Eb[pix], ey = Eb[plane + pix], ez = Eb[2 * plane + pix];
+  const float gxr = g2 * ex.x, gxi = g2 * ex.y, gyr = g2 * ey.x, gyi = g2 * ey.y;
+  const float gzr = g2 * ez.x, gzi = g2 * ez.y;
+  float c1 = 1.f, s1 = 0.f;
+  if (rho > 0.f) {
+    c1 = x / rho;
+    s1 = y / rho;
+  }
+  const float c2 = c1 * c1 - s1 * s1, s2 = 2.f * s1 * c1;
+  // P0 = conj(ex) Gx + conj(ey) Gy
+  p[0] = a.exr * gxr + a.exi * gxi + a.eyr * gyr + a.eyi * gyi;
+  p[1] = a.exr * gxi - a.exi * gxr + a.eyr * gyi - a.eyi * gyr;
+  // P1 = 2i conj(ex c1 + ey s1) Gz
+  const float qr = a.exr * c1 + a.eyr * s1, qi = a.exi * c1 + a.eyi * s1;
+  p[2] = -2.f * (qr * gzi - qi * gzr);
+  p[3] = 2.f * (qr * gzr + qi * gzi);
+  // P2 = conj(-(ex c2 + ey s2)) Gx + conj(-ex s2 + ey c2) Gy
+  const float ur = -(a.exr * c2 + a.eyr * s2), ui = -(a.exi * c2 + a.eyi * s2);
+  const float vr = -a.exr * s2 + a.eyr * c2, vi = -a.exi * s2 + a.eyi * c2;
+  p[4] = ur * gxr + ui * gxi + vr * gyr + vi * gyi;
+  p[5] = ur * gxi - ui * gxr + vr * gyi - vi * gyr;
+}
+
+// One workgroup per (stack, plane).  Every pixel adds w_k P_n to the four radial samples
+// of its stencil (node -1 mirrored onto node 1 with the parity (-1)^n), the transpose of
+// the forward interpolation.  The sums are kept in LDS as 64-bit integers in units of
+// 2^-36 of the plane's largest |P|: integer addition is associative, so the atomics give
+// a bitwise repeatable result whatever their order, and the quantisation error (2^-37 of
+// the largest term per term) is far below FP32 rounding.  Writes
+// G_In^T[g R + r][2 ((s nz + z) V + v) + re/im].
 __global__ void __launch_bounds__(256) adjb_radial_kernel(AdjRadArgs a, const float2* __restrict__ E,
                                                           const float* __restrict__ dLdI,
                                                           float* __restrict__ GInT) {
+  extern __shared__ long long accq[];        // [R][6]
+  __shared__ float red[256];
   const int si = blockIdx.x / a.nz, zi = blockIdx.x % a.nz;
-  const int R = a.R;
+  const int R = a.R, tid = threadIdx.x;
   const bool scalar = a.mode == kModeScalar;
   const int NI = scalar ? 1 : 3;
-  const size_t plane = (size_t)a.nx * a.ny;
+  const int P = a.nx * a.ny;
+  const size_t plane = (size_t)P;
   const size_t gsz = (size_t)(a.s_base + si) * a.nz + zi;
   const float2* Eb = E + gsz * NI * plane;
   const float* Lb = dLdI + gsz * plane;
   const float x0 = a.x0[si], y0 = a.y0[si];
-  const double mg = (double)a.drho + 1e-3;     // generous margin of the candidate ring
-  for (int r = threadIdx.x; r < R; r += blockDim.x) {
-    float ar[3] = {0.f, 0.f, 0.f}, ai[3] = {0.f, 0.f, 0.f};
-    const double lo = fmax(0.0, (r - 2) * (double)a.drho - mg);
-    const bool open_hi = r + 2 >= R - 3;           // the last stencil is clamped: all larger radii
-    const double hi = (r + 2) * (double)a.drho + mg;
-    for (int i = 0; i < a.nx; ++i) {
-      const float x = (float)(i - a.nx / 2) * a.dx - x0;
-      const double x2 = (double)x * x;
-      if (!open_hi && hi * hi < x2) continue;
-      const double yhi = open_hi ? 1e30 : sqrt(hi * hi - x2);
-      const double ylo = lo * lo > x2 ? sqrt(lo * lo - x2) : 0.0;
-      // y = (j - ny/2) dy - y0  ->  j = (y + y0) / dy + ny/2.  The ring meets this row in
-      // y in [-yhi, -ylo] and [ylo, yhi]; each becomes a pixel range widened by one pixel,
-      // and ranges that touch are merged so that no pixel is visited twice.
-      auto jrange = [&](double ya, double yb, int* j0, int* j1) {
-        const double ja = fmax(-1.0, fmin((double)a.ny, floor((ya + y0) / a.dy) + a.ny / 2 - 1));
-        const double jb = fmax(-1.0, fmin((double)a.ny, ceil((yb + y0) / a.dy) + a.ny / 2 + 1));
-        *j0 = max(0, (int)ja);
-        *j1 = min(a.ny - 1, (int)jb);
-      };
-      int ra0, ra1, rb0, rb1;
-      jrange(-yhi, -ylo, &ra0, &ra1);
-      jrange(ylo, yhi, &rb0, &rb1);
-      int nrange = 2;
-      if (ra1 >= rb0 - 1) {
-        ra1 = max(ra1, rb1);
-        nrange = 1;
-      }
-      for (int side = 0; side < nrange; ++side) {
-        const int j0 = side == 0 ? ra0 : rb0, j1 = side == 0 ? ra1 : rb1;
-        for (int j = j0; j <= j1; ++j) {
-          const float y = (float)(j - a.ny / 2) * a.dy - y0;
-          const float rho = sqrtf(x * x + y * y);
-          const float t = rho * a.inv_drho;
-          const int r0 = min((int)t, R - 3);
-          const int kk = r - r0 + 1;                 // stencil slot of sample r
-          const bool ghost = r0 == 0 && r == 1;      // node -1 mirrored onto node 1
-          if ((kk < 0 || kk > 3) && !ghost) continue;
-          const float f = t - (float)r0;
-          const float wm = -f * (f - 1.f) * (f - 2.f) * (1.f / 6.f);
-          const float w0 = (f + 1.f) * (f - 1.f) * (f - 2.f) * 0.5f;
-          const float w1 = -(f + 1.f) * f * (f - 2.f) * 0.5f;
-          const float w2 = (f + 1.f) * f * (f - 1.f) * (1.f / 6.f);
-          const float wk = kk == 0 ? wm : (kk == 1 ? w0 : (kk == 2 ? w1 : (kk == 3 ? w2 : 0.f)));
-          const int pix = i * a.ny + j;
-          const float g2 = 2.f * Lb[pix];
-          if (scalar) {
-            const float2 e = Eb[pix];
-            const float gr = g2 * e.x, gi = g2 * e.y;
-            const float w = wk + (ghost ? wm : 0.f);
-            // conj(pref) G
-            ar[0] += w * (a.exr * gr + a.exi * gi);
-            ai[0] += w * (a.exr * gi - a.exi * gr);
-            continue;
-          }
-          const float2 ex = Eb[pix], ey = Eb[plane + pix], ez = Eb[2 * plane + pix];
-          const float gxr = g2 * ex.x, gxi = g2 * ex.y, gyr = g2 * ey.x, gyi = g2 * ey.y;
-          const float gzr = g2 * ez.x, gzi = g2 * ez.y;
-          float c1 = 1.f, s1 = 0.f;
-          if (rho > 0.f) {
-            c1 = x / rho;
-            s1 = y / rho;
-          }
-          const float c2 = c1 * c1 - s1 * s1, s2 = 2.f * s1 * c1;
-          // P0 = conj(ex) Gx + conj(ey) Gy
-          const float p0r = a.exr * gxr + a.exi * gxi + a.eyr * gyr + a.eyi * gyi;
-          const float p0i = a.exr * gxi - a.exi * gxr + a.eyr * gyi - a.eyi * gyr;
-          // P1 = 2i conj(ex c1 + ey s1) Gz
-          const float qr = a.exr * c1 + a.eyr * s1, qi = a.exi * c1 + a.eyi * s1;
-          const float tr_ = qr * gzr + qi * gzi, ti_ = qr * gzi - qi * gzr;   // conj(q) Gz
-          const float p1r = -2.f * ti_, p1i = 2.f * tr_;
-          // P2 = conj(-(ex c2 + ey s2)) Gx + conj(-ex s2 + ey c2) Gy
-          const float ur = -(a.exr * c2 + a.eyr * s2), ui = -(a.exi * c2 + a.eyi * s2);
-          const float vr = -a.exr * s2 + a.eyr * c2, vi = -a.exi * s2 + a.eyi * c2;
-          const float p2r = ur * gxr + ui * gxi + vr * gyr + vi * gyi;
-          const float p2i = ur * gxi - ui * gxr + vr * gyi - vi * gyr;
-          const float wg0 = wk + (ghost ? wm : 0.f), wg1 = wk - (ghost ? wm : 0.f);   // I_1 is odd
-          ar[0] += wg0 * p0r;
-          ai[0] += wg0 * p0i;
-          ar[1] += wg1 * p1r;
-          ai[1] += wg1 * p1i;
-          ar[2] += wg0 * p2r;
-          ai[2] += wg0 * p2i;
+  for (int i = tid; i < 6 * R; i += blockDim.x) accq[i] = 0;
+  // largest |P| of the plane (a max does not depend on the order)
+  float mx = 0.f;
+  for (int pix = tid; pix < P; pix += blockDim.x) {
+    const int i = pix / a.ny, j = pix % a.ny;
+    const float x = (float)(i - a.nx / 2) * a.dx - x0, y = (float)(j - a.ny / 2) * a.dy - y0;
+    float p[6];
+    adjb_project(a, scalar, Eb, plane, 2.f * Lb[pix], pix, x, y, sqrtf(x * x + y * y), p);
+    for (int e = 0; e < 6; ++e) mx = fmaxf(mx, fabsf(p[e]));
+  }
+  red[tid] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) red[tid] = fmaxf(red[tid], red[tid + h]);
+    __syncthreads();
+  }
+  mx = red[0];
+  const double scale = mx > 0.f ? ldexp(1.0, 36 - ilogbf(mx)) : 0.0;
+  if (mx > 0.f) {
+    for (int pix = tid; pix < P; pix += blockDim.x) {
+      const int i = pix / a.ny, j = pix % a.ny;
+      const float x = (float)(i - a.nx / 2) * a.dx - x0, y = (float)(j - a.ny / 2) * a.dy - y0;
+      const float rho = sqrtf(x * x + y * y);
+      const float t = rho * a.inv_drho;
+      const int r0 = min((int)t, R - 3);
+      const float f = t - (float)r0;
+      const float w[4] = {-f * (f - 1.f) * (f - 2.f) * (1.f / 6.f), (f + 1.f) * (f - 1.f) * (f - 2.f) * 0.5f,
+                          -(f + 1.f) * f * (f - 2.f) * 0.5f, (f + 1.f) * f * (f - 1.f) * (1.f / 6.f)};
+      float p[6];
+      adjb_project(a, scalar, Eb, plane, 2.f * Lb[pix], pix, x, y, rho, p);
+      for (int k = 0; k < 4; ++k) {
+        int r = r0 - 1 + k;
+        float sg[6] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
+        if (r < 0) {               // node -1: I_n(-rho) = (-1)^n I_n(rho)
+          r = 1;
+          sg[2] = sg[3] = -1.f;
+        }
+        long long* d = accq + 6 * r;
+        for (int e = 0; e < 6; ++e) {
+          const long long v = llrint((double)(sg[e] * w[k] * p[e]) * scale);
+          if (v) atomicAdd(reinterpret_cast<unsigned long long*>(d + e), (unsigned long long)v);
         }
       }
     }
-    // scatter G_{I_n} to the (variant, group) rows of the contraction
-    const int V = a.mode == kModeFresnel ? 2 : 1;
-    const int col = (si * a.nz + zi) * V;
-    auto put = [&](int v, int g, float re, float im) {
-      float* d = GInT + (size_t)(g * R + r) * a.M + 2 * (col + v);
+  }
+  __syncthreads();
+  const double inv = mx > 0.f ? 1.0 / scale : 0.0;
+  const int V = a.mode == kModeFresnel ? 2 : 1;
+  const int col = (si * a.nz + zi) * V;
+  for (int r = tid; r < R; r += blockDim.x) {
+    float g[6];
+    for (int e = 0; e < 6; ++e) g[e] = (float)((double)accq[6 * r + e] * inv);
+    auto put = [&](int v, int gg, float re, float im) {
+      float* d = GInT + (size_t)(gg * R + r) * a.M + 2 * (col + v);
       d[0] = re;
       d[1] = im;
     };
     if (a.mode == kModeFresnel) {
-      put(0, 0, ar[0], ai[0]);
-      put(1, 1, ar[0], ai[0]);
-      put(1, 2, ar[1], ai[1]);
-      put(1, 3, ar[2], ai[2]);
-      put(0, 4, -ar[2], -ai[2]);
+      put(0, 0, g[0], g[1]);
+      put(1, 1, g[0], g[1]);
+      put(1, 2, g[2], g[3]);
+      put(1, 3, g[4], g[5]);
+      put(0, 4, -g[4], -g[5]);
       put(1, 0, 0.f, 0.f);
       put(0, 1, 0.f, 0.f);
       put(0, 2, 0.f, 0.f);
       put(0, 3, 0.f, 0.f);
       put(1, 4, 0.f, 0.f);
     } else {
-      for (int n = 0; n < NI; ++n) put(0, n, ar[n], ai[n]);
+      for (int n = 0; n < NI; ++n) put(0, n, g[2 * n], g[2 * n + 1]);
     }
   }
 }
@@ -706,25 +711,36 @@ __global__ void adjb_x_kernel(const float* __restrict__ GPhi, const float2* __re
   X[idx] = make_double2(xr, xi);
 }
 
-// Per stack: dL/dt_s, dL/dz_offset and the stack's share of dL/dc_j (fixed order over q).
+// Per stack (one 64-lane workgroup each): dL/dt_s, dL/dz_offset and the stack's share of
+// dL/dc_j.  Lane l sums the nodes q = l, l + 64, ... in order, then a fixed tree joins
+// the lanes: bitwise repeatable.
 // node[q] = (k cos t, Re dW/dt_s, Im dW/dt_s, 2 pi Z_1, 2 pi Z_4, 2 pi Z_11, 2 pi Z_22).
-__global__ void adjb_stack_kernel(const double2* __restrict__ X, const double* __restrict__ node, int nb,
-                                  int T, int s_base, float* __restrict__ dts, float* __restrict__ dz,
-                                  double* __restrict__ dcp) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= nb) return;
-  double a_ts = 0.0, a_z = 0.0, a_c[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int q = 0; q < T; ++q) {
+__global__ void __launch_bounds__(64) adjb_stack_kernel(const double2* __restrict__ X, const double* __restrict__ node,
+                                                        int T, int s_base, float* __restrict__ dts,
+                                                        float* __restrict__ dz, double* __restrict__ dcp) {
+  __shared__ double red[6][64];
+  const int s = blockIdx.x, l = threadIdx.x;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};   // t_s, z, c_1, c_4, c_11, c_22
+  for (int q = l; q < T; q += 64) {
     const double2 x = X[(size_t)s * T + q];
     const double* nd = node + 7 * (size_t)q;
-    a_z -= nd[0] * x.y;                       // Re(i w X) = -w Im X for real w
-    a_ts -= nd[1] * x.y + nd[2] * x.x;        // Re(i (a + ib) X)
-    for (int j = 0; j < 4; ++j) a_c[j] -= nd[3 + j] * x.y;
+    v[1] -= nd[0] * x.y;                   // Re(i w X) = -w Im X for real w
+    v[0] -= nd[1] * x.y + nd[2] * x.x;     // Re(i (a + ib) X)
+    for (int j = 0; j < 4; ++j) v[2 + j] -= nd[3 + j] * x.y;
   }
-  const int gs = s_base + s;
-  if (dts) dts[gs] = (float)a_ts;
-  if (dz) dz[gs] = (float)a_z;
-  for (int j = 0; j < 4; ++j) dcp[4 * (size_t)gs + j] = a_c[j];
+  for (int e = 0; e < 6; ++e) red[e][l] = v[e];
+  __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (l < h)
+      for (int e = 0; e < 6; ++e) red[e][l] += red[e][l + h];
+    __syncthreads();
+  }
+  if (l == 0) {
+    const int gs = s_base + s;
+    if (dts) dts[gs] = (float)red[0][0];
+    if (dz) dz[gs] = (float)red[1][0];
+    for (int j = 0; j < 4; ++j) dcp[4 * (size_t)gs + j] = red[2 + j][0];
+  }
 }
 
 __global__ void adjb_coef_kernel(const double* __restrict__ dcp, int n, float* __restrict__ dc) {
@@ -747,6 +763,8 @@ static int bessel_adjoint_prepare(rwpsf_plan* p) {
   if (p->d_btabT) return RWPSF_OK;
   const int T = p->n_theta_total, R = p->num.n_rho, nz = p->grid.nz;
   const int G = bessel_groups(p->bessel_mode), V = bessel_variants(p->bessel_mode);
+  // per-sample sums [R][6] 64-bit integers in LDS
+  if ((size_t)R * 6 * sizeof(long long) > 150 * 1024) return RWPSF_ERR_UNSUPPORTED;
   std::vector<double> th(T);
   int st;
   if ((st = hip_check(hipMemcpy(th.data(), p->d_theta, T * sizeof(double), hipMemcpyDeviceToHost)))) return st;
@@ -776,7 +794,12 @@ static int bessel_adjoint_prepare(rwpsf_plan* p) {
   if ((st = dev_alloc(p, &p->d_adjX, (size_t)kPhiStacks * T))) return st;
   if ((st = dev_alloc(p, &p->d_adjnode, node.size()))) return st;
   if ((st = dev_alloc(p, &p->d_dcp, 4 * (size_t)RWPSF_MAX_STACKS_PER_CALL))) return st;
+
   if ((st = hip_check(hipMemcpy(p->d_adjnode, node.data(), node.size() * sizeof(double), hipMemcpyHostToDevice))))
+    return st;
+  // the limits are per kernel, not per plan: allow the whole LDS so plans of any size can launch
+  if ((st = hip_check(hipFuncSetAttribute((const void*)adjb_radial_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          150 * 1024))))
     return st;
   const int total = G * R * T;
   hipLaunchKernelGGL(adjb_transpose_kernel, dim3((total + 255) / 256), dim3(256), 0, 0, p->d_btab, p->d_btabT, T,
@@ -818,7 +841,8 @@ int bessel_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E, 
       ra.y0[i] = (float)s[b0 + i].y0_nm;
     }
     int tr = p->time_begin(RWPSF_KERNEL_ADJB_RADIAL, st);
-    hipLaunchKernelGGL(adjb_radial_kernel, dim3(nb * nz), dim3(256), 0, st, ra, E, dLdI, p->d_GInT);
+    hipLaunchKernelGGL(adjb_radial_kernel, dim3(nb * nz), dim3(256), (size_t)R * 6 * sizeof(long long), st, ra, E,
+                       dLdI, p->d_GInT);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
     // G_Phi[m][q] = sum_k G_In^T[k][m] B^T[k][q]
@@ -833,8 +857,8 @@ int bessel_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E, 
     hipLaunchKernelGGL(adjb_x_kernel, dim3((nb * T + 255) / 256), dim3(256), 0, st, (const float*)p->d_GPhi,
                        (const float2*)p->d_phi, p->d_adjX, nb, nz, V, T);
     if ((rc = hip_check(hipGetLastError()))) return rc;
-    hipLaunchKernelGGL(adjb_stack_kernel, dim3((nb + 63) / 64), dim3(64), 0, st, (const double2*)p->d_adjX,
-                       (const double*)p->d_adjnode, nb, T, b0, dts, dz, p->d_dcp);
+    hipLaunchKernelGGL(adjb_stack_kernel, dim3(nb), dim3(64), 0, st, (const double2*)p->d_adjX,
+                       (const double*)p->d_adjnode, T, b0, dts, dz, p->d_dcp);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
   }

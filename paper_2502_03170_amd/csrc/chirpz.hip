@@ -300,9 +300,11 @@ static size_t czt_cols_lds(int cb, int N, int nx, int L) {
   return (size_t)(cb * N + cb * nx + 4 * (L + L / 8)) * sizeof(float2) + (size_t)nx * cb * sizeof(float);
 }
 
+// The limit belongs to the kernel, not to a plan: the column kernel's LDS depends on the
+// plan, so it is allowed the whole LDS (a later plan must not lower it).
 template <int L>
-static void czt_attributes(int cols_lds) {
-  hipFuncSetAttribute((const void*)czt_cols_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize, cols_lds);
+static void czt_attributes() {
+  hipFuncSetAttribute((const void*)czt_cols_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   hipFuncSetAttribute((const void*)czt_rows_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       4 * padded<L>() * (int)sizeof(float2));
 }
@@ -371,15 +373,14 @@ int czt_plan_init(rwpsf_plan* p) {
   const size_t want = (size_t)kPupilStacks * p->grid.nz;
   p->czt_planes = std::max<size_t>(1, std::min(want, (size_t)(512u << 20) / plane_bytes));
   if ((st = dev_alloc(p, &p->d_czt_T, p->czt_planes * 3 * (size_t)N * ny))) return st;
-  const int cl = (int)czt_cols_lds(cb, N, nx, Lx);
   for (int L : {Ly, Lx}) {
     switch (L) {
-      case 64: czt_attributes<64>(cl); break;
-      case 128: czt_attributes<128>(cl); break;
-      case 256: czt_attributes<256>(cl); break;
-      case 512: czt_attributes<512>(cl); break;
-      case 1024: czt_attributes<1024>(cl); break;
-      default: czt_attributes<2048>(cl); break;
+      case 64: czt_attributes<64>(); break;
+      case 128: czt_attributes<128>(); break;
+      case 256: czt_attributes<256>(); break;
+      case 512: czt_attributes<512>(); break;
+      case 1024: czt_attributes<1024>(); break;
+      default: czt_attributes<2048>(); break;
     }
   }
   return hip_check(hipGetLastError());
