@@ -81,11 +81,11 @@ static int fourier_plan_init(rwpsf_plan* p) {
   p->P_stacks = kPupilStacks;
   if ((st = dev_alloc(p, &p->d_P, (size_t)p->P_stacks * 3 * npp))) return st;
   const bool gemm = p->num.form == RWPSF_FORM_FOURIER;   // the chirp-z form needs no GEMM workspaces
-  if (gemm && (st = dev_alloc(p, &p->d_Pf, (size_t)p->P_stacks * 3 * w * w))) return st;
-  // plane workspace: whole chunk of stacks x planes, capped at 512 MiB
+  if (gemm && (st = dev_alloc(p, &p->d_Pf, (size_t)kGemmStacks * 3 * w * w))) return st;
+  // plane workspace: whole group of stacks x planes, capped at 1 GiB
   const size_t plane_bytes = 3 * (size_t)w * nyp * sizeof(float2);
-  const size_t want = (size_t)kPupilStacks * p->grid.nz;
-  p->T_planes = std::max<size_t>(1, std::min(want, (size_t)(512u << 20) / plane_bytes));
+  const size_t want = (size_t)kGemmStacks * p->grid.nz;
+  p->T_planes = std::max<size_t>(1, std::min(want, ((size_t)1 << 30) / plane_bytes));
   if (gemm && (st = dev_alloc(p, &p->d_T, p->T_planes * 3 * (size_t)w * nyp))) return st;
 
   if ((st = hip_check(hipMemcpy(p->d_Q, Q.data(), Q.size() * sizeof(float2), hipMemcpyHostToDevice)))) return st;
@@ -211,15 +211,20 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
   hipGetDevice(&cur);
   if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
   const int nz = p->grid.nz;
-  for (int b0 = 0; b0 < n; b0 += kPupilStacks) {
-    const int nb = std::min(kPupilStacks, n - b0);
-    int rc = fourier_build_pupils(p, s + b0, nb, st);
-    if (rc) return rc;
-    FoldArgs fa{p->d_P, p->d_Pf, p->num.n_pupil, p->np, p->nhp, nb, p->nc};
-    int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
-    if ((rc = hip_check(launch_pupil_fold(fa, st)))) return rc;
-    p->time_end(tr, st);
-    double zoff[kPupilStacks];
+  const size_t fpp = (size_t)4 * p->nhp * p->nhp;
+  for (int b0 = 0; b0 < n; b0 += kGemmStacks) {
+    const int nb = std::min(kGemmStacks, n - b0);
+    int rc;
+    // pupils of the group in launches of up to kPupilStacks, folded side by side
+    for (int c0 = 0; c0 < nb; c0 += kPupilStacks) {
+      const int nc0 = std::min(kPupilStacks, nb - c0);
+      if ((rc = fourier_build_pupils(p, s + b0 + c0, nc0, st))) return rc;
+      FoldArgs fa{p->d_P, p->d_Pf + (size_t)c0 * p->nc * fpp, p->num.n_pupil, p->np, p->nhp, nc0, p->nc};
+      const int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
+      if ((rc = hip_check(launch_pupil_fold(fa, st)))) return rc;
+      p->time_end(tr, st);
+    }
+    double zoff[kGemmStacks];
     for (int i = 0; i < nb; ++i) zoff[i] = s[b0 + i].z_offset_nm;
     // slabs over (stack, plane): a slab is a run of planes of one or more stacks
     const size_t cap = p->T_planes;

@@ -44,8 +44,8 @@ struct RgCfg {
 template <class Cfg, int ROWS>
 struct RRowLoader {
   static constexpr int QUADS = Cfg::BK / 4;
-  static constexpr int PER_THREAD = ROWS * QUADS / Cfg::NT;
-  static_assert(ROWS * QUADS % Cfg::NT == 0, "loader shape");
+  static constexpr int TOTAL = ROWS * QUADS;
+  static constexpr int PER_THREAD = (TOTAL + Cfg::NT - 1) / Cfg::NT;   // the last round may be partial
   const float* src;  // already offset to row r0
   int ld;
   float4 v[PER_THREAD];
@@ -54,6 +54,7 @@ struct RRowLoader {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
+      if (TOTAL % Cfg::NT != 0 && idx >= TOTAL) break;
       const int row = idx / QUADS, kq = 4 * (idx % QUADS);
       v[i] = *reinterpret_cast<const float4*>(src + (size_t)row * ld + k0 + kq);
     }
@@ -62,6 +63,7 @@ struct RRowLoader {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
+      if (TOTAL % Cfg::NT != 0 && idx >= TOTAL) break;
       const int row = idx / QUADS, kq = 4 * (idx % QUADS);
       *reinterpret_cast<float4*>(dst + row * Cfg::LDK + kq) = v[i];
     }
@@ -76,8 +78,8 @@ struct RRowLoader {
 template <class Cfg, int ROWS>
 struct RColLoader {
   static constexpr int KPAIRS = Cfg::BK / 2, QUADS = ROWS / 4;
-  static constexpr int PER_THREAD = KPAIRS * QUADS / Cfg::NT;
-  static_assert(KPAIRS * QUADS % Cfg::NT == 0, "loader shape");
+  static constexpr int TOTAL = KPAIRS * QUADS;
+  static constexpr int PER_THREAD = (TOTAL + Cfg::NT - 1) / Cfg::NT;   // the last round may be partial
   const float* src;  // already offset to row r0
   int ld;
   float4 v0[PER_THREAD], v1[PER_THREAD];
@@ -86,6 +88,7 @@ struct RColLoader {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
+      if (TOTAL % Cfg::NT != 0 && idx >= TOTAL) break;
       const int kk = 2 * (idx % KPAIRS), rq = 4 * (idx / KPAIRS);
       const float* p = src + (size_t)(k0 + kk) * ld + rq;
       v0[i] = *reinterpret_cast<const float4*>(p);
@@ -96,6 +99,7 @@ struct RColLoader {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
+      if (TOTAL % Cfg::NT != 0 && idx >= TOTAL) break;
       const int kk = 2 * (idx % KPAIRS), rq = 4 * (idx / KPAIRS);
       float* d = dst + rq * Cfg::LDK + kk;
       *reinterpret_cast<float2*>(d) = make_float2(v0[i].x, v1[i].x);

@@ -6,6 +6,7 @@
 namespace rw {
 
 constexpr int kPupilStacks = 8;  // stacks per pupil launch (by-value arguments stay < 4 KB)
+constexpr int kGemmStacks = 16;  // stacks per GEMM launch: folded pupils of two pupil launches
 
 struct PupilStack {
   double t_s, x0, y0;
@@ -37,7 +38,7 @@ struct Gemm1Args {
   const double* z;     // plan planes
   const float* B1;     // [nyp][2 nhp] cos / sin (k s_y[lf] y_n), k contiguous
   float2* T;           // [nstk][nzs][nc][2 nhp][nyp]
-  double zoff[kPupilStacks];
+  double zoff[kGemmStacks];
   int n, nhp, nyp, nstk, z0, nzs, nc;   // n: pupil cells per axis
 };
 
