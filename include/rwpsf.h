@@ -190,7 +190,9 @@ int rwpsf_compute(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
               0 outside the disk; may be NULL.
    Outputs are overwritten, never accumulated.  Fourier form, vectorial model, with
    nx, ny multiples of 16 (RWPSF_ERR_UNSUPPORTED otherwise).  Every reduction runs in a fixed order,
-   so repeated calls give bitwise-identical results. */
+   so repeated calls give bitwise-identical results.  The first call allocates the adjoint's
+   tables, and a call with more stacks than any before it grows the partial-sum workspace
+   (device allocations; earlier buffers stay owned by the plan until it is destroyed). */
 int rwpsf_adjoint(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, const void* E_in,
                   const float* dL_dI, int n_zernike, float* dL_dc, float* dL_dW0, void* stream);
 
@@ -209,7 +211,8 @@ int rwpsf_adjoint(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, con
    (RWPSF_ERR_UNSUPPORTED for the other forms, or for n_rho > 3200, whose per-sample
    sums no longer fit one workgroup's LDS).  The gradient is that of the computed
    discrete model (theta rule, radial interpolation).  Every reduction runs in a fixed
-   order, so repeated calls give bitwise-identical results. */
+   order, so repeated calls give bitwise-identical results.  The first call on a plan
+   allocates the adjoint's tables and workspace and synchronises the device. */
 int rwpsf_adjoint_bessel(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks, const void* E_in,
                          const float* dL_dI, float* dL_dc, float* dL_dts, float* dL_dz, void* stream);
 
