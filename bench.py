@@ -275,8 +275,8 @@ def bench_batched(rw, torch, steps, warmup):
     flops = float(np.sum(D * 3 * 4.0 * S * n * (n + S)))     # folded: U = A2_S Pf~, E' = U B1_S per plane
     ach = flops / (ms * 1e-3) / 1e12
     return dict(workload="batched: 4096 emitters, crops U{24..64}, planes U{1..41}, 128x128 pupil, "
-                         "Noll 4-21 N(0,0.04), sub-pixel x0/y0, intensity only, one persistent launch "
-                         "replayed from a hipGraph, autotuned",
+                         "Noll 4-21 N(0,0.04), sub-pixel x0/y0, intensity only, one persistent launch per "
+                         "tile class, replayed from a hipGraph, autotuned",
                 value=off[-1] / (ms * 1e-3), unit="voxels/s", ms_per_launch=ms, voxels=off[-1],
                 autotuned_config=dict(wg_per_cu=cfg[0], small_tile_max_crop=cfg[1]),
                 roofline=dict(kernel="batch_planes_kernel (+ phase GEMM)", bound="mfma",

@@ -1,22 +1,24 @@
 // Batched emitters: the Fourier form (Sec. 3.3 eq. "cartesian vectorial" with the
 // Sec. 3.4 correction factors) for thousands of emitters with individual sub-pixel
 // position, axial position, Zernike vector (Sec. 3.4.2), crop size and plane count,
-// in one persistent launch.
+// in one persistent launch per tile class.
 //
 // Per emitter b the pupil phase is
 //   Phi_b[j,l] = 2 pi sum_q c_bq Z_q(s) - k (s_x x0_b + s_y y0_b)
 // formed for all emitters at once by one real GEMM on the matrix cores,
 //   Phi[b][cell] = sum_k coef[k][b] basis[k][cell],  basis = (2 pi Z_1..Z_21, s_x, s_y).
 // The cell-centred grids are mirror-symmetric, so each emitter's pupil is folded once
-// (four parities per folded cell, written to the workgroup's scratch slot) and each
-// plane d of each field component c is two real-coefficient GEMMs on the matrix cores,
+// (four parities per folded cell, written to the emitter's HBM slot) and each plane d of
+// each field component c is two real-coefficient GEMMs on the matrix cores,
 //   U  = A2_S (Dz o Pf_c)   (S x N; the defocus Dz of the plane is shared by the three
 //                            components and the four mirror cells)
 //   E' = U B1_S             (S x S, U staged in LDS as the A operand),  E = -i E'
 // and I = sum_c |E_c|^2.  A2_S / B1_S are the rows of one 96-row table that cover the
-// crop (pixel i of an S-crop is table row i - S/2 + 32).  A workgroup takes whole
-// emitters from an atomic counter over a cost-sorted (longest first) list until the
-// list is exhausted; every workgroup exits when the counter passes n.
+// crop (pixel i of an S-crop is table row i - S/2 + 32).  Crops are evaluated on 32- or
+// 64-wide tiles (the two tile classes); the (emitter, plane) items of each class are
+// dealt, emitter by emitter and longest first, to eight queues, one per XCD, and the
+// class's persistent kernel takes items from the queues' atomic counters until they are
+// exhausted.
 #include <algorithm>
 #include <cmath>
 #include <complex>
@@ -42,6 +44,7 @@ typedef float f16v_t __attribute__((ext_vector_type(16)));
 constexpr int kTabRows = 96;    // DFT table rows: x_r = (r - 32) * pixel
 constexpr int kBasisRows = 32;  // 21 Zernike + s_x + s_y, zero-padded
 constexpr int kMaxWgPerCu = 4;  // workgroups per CU of the persistent launch (configuration bound)
+constexpr int kQueues = 16;     // 8 XCD queues for each of the two tile classes (32- and 64-wide)
 constexpr int kBK = 16;                       // k-stage of the staged pupil GEMM
 constexpr int kLdaU = 64 + 4, kLdbU = 128 + 4;  // LDS row strides of its A (crop rows) and B (columns)
 constexpr int kStageU = kBK * (kLdaU + 2 * kLdbU);
@@ -63,8 +66,8 @@ struct BatchArgs {
   float2* Dz;                // per workgroup [N/2][N/2] defocus factors of its current plane
   const int* list;           // [n] slots grouped by XCD queue
   const long long* pre;      // [n + 1] plane prefix sums over list
-  const int* qoff;           // [9] queue x owns list[qoff[x] .. qoff[x+1])
-  unsigned long long* counter;   // [8] next item of each queue
+  const int* qoff;           // [17] queue q owns list[qoff[q] .. qoff[q+1]); queues 8 t + x of tile class t
+  unsigned long long* counter;   // [16] next item of each queue
   float* I;
   float2* E;
   int n, N;
@@ -75,7 +78,7 @@ struct BatchArgs {
 // launch sequence can be captured in a graph).
 __global__ void batch_reset_kernel(unsigned long long* counter, const long long* pre, const int* qoff) {
   const int x = threadIdx.x;
-  if (x < 8) counter[x] = (unsigned long long)pre[qoff[x]];
+  if (x < kQueues) counter[x] = (unsigned long long)pre[qoff[x]];
 }
 
 // Folded pupil of every emitter (one workgroup per emitter).  The pupil and pixel grids
@@ -335,16 +338,18 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
 
 constexpr int kBatchLdsBytes = 2 * 128 * 65 * 4;   // U for N <= 128, SP = 64
 
-// Persistent plane kernel.  Workgroup ids are dealt round-robin over the 8 XCDs, so
-// workgroup b serves queue b % 8: the (emitter, plane) items of the emitters assigned to
-// that queue, in order, so that the planes of one emitter run at the same time on one
-// XCD and its folded pupil is read from that XCD's L2.  A workgroup exits when its
-// queue is exhausted; the grid has at least 8 workgroups, one per queue.
+// Persistent plane kernel of one tile class (one launch per class, so that each has the
+// registers of its own tile shape).  Workgroup ids are dealt round-robin over the 8 XCDs,
+// so workgroup b serves queue b % 8 of the class: the (emitter, plane) items of the
+// emitters assigned to that queue, in order, so that the planes of one emitter run at the
+// same time on one XCD and its folded pupil is read from that XCD's L2.  A workgroup exits
+// when its queue is exhausted; the grid has at least 8 workgroups, one per queue.
+template <int SP>
 __global__ void __launch_bounds__(256, 2) batch_planes_kernel(BatchArgs a) {
   extern __shared__ float lds[];
   __shared__ long long item;
   const int tid = threadIdx.x;
-  const int x = blockIdx.x & 7;
+  const int x = 8 * (SP == 64 ? 1 : 0) + (blockIdx.x & 7);
   const int lo = a.qoff[x], hi = a.qoff[x + 1];
   const long long end = a.pre[hi];
   float2* Dz = a.Dz + (size_t)blockIdx.x * (a.N * a.N / 4);
@@ -363,10 +368,7 @@ __global__ void __launch_bounds__(256, 2) batch_planes_kernel(BatchArgs a) {
     const int slot = a.list[e0];
     const int d = (int)(it - a.pre[e0]);
     const BatchParam bp = a.params[slot];
-    if (bp.SP == 32)
-      batch_plane<32>(a, bp, slot, d, lds, tid, Dz);
-    else
-      batch_plane<64>(a, bp, slot, d, lds, tid, Dz);
+    batch_plane<SP>(a, bp, slot, d, lds, tid, Dz);
   }
 }
 
@@ -388,6 +390,7 @@ struct rwpsf_batch {
   float2* d_pf = nullptr;       // [max][3][N][N] folded pupils
   float2* d_dz = nullptr;       // per workgroup [N/2][N/2] defocus table
   long long items = 0;          // (emitter, plane) items of the staged call
+  long long class_items[2] = {0, 0};   // of them, in the 32- and 64-wide tile classes
   float* d_basis = nullptr;
   float* d_phi = nullptr;
   char* d_upload = nullptr;     // params [max] then coefT [32][max_pad]
@@ -445,17 +448,18 @@ static int balloc(rwpsf_batch* b, T** p, size_t count) {
   return RWPSF_OK;
 }
 
-// Upload block: params [max] | coefT [32][max_pad] | list [max] | pre [max + 1] | qoff [9]
+// Upload block: params [max] | coefT [32][max_pad] | list [max] | pre [max + 1] | qoff [17]
 static size_t off_coef(const rwpsf_batch* b) { return sizeof(BatchParam) * b->max_emitters; }
 static size_t off_list(const rwpsf_batch* b) { return off_coef(b) + sizeof(float) * kBasisRows * b->max_pad; }
 static size_t off_pre(const rwpsf_batch* b) {
   return (off_list(b) + sizeof(int) * b->max_emitters + 7) / 8 * 8;
 }
 static size_t off_qoff(const rwpsf_batch* b) { return off_pre(b) + sizeof(long long) * (b->max_emitters + 1); }
-static size_t upload_size(const rwpsf_batch* b) { return off_qoff(b) + sizeof(int) * 9; }
+static size_t upload_size(const rwpsf_batch* b) { return off_qoff(b) + sizeof(int) * (kQueues + 1); }
 
 // Fill the pinned staging area: cost-sorted params, the coefficient matrix, and the
-// eight (emitter, plane) queues (emitters dealt longest first to the least-loaded queue).
+// (emitter, plane) queues: per tile class, eight queues, the class's emitters dealt
+// longest first to its least-loaded queue.
 static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
   std::vector<long long> off(n + 1, 0);
   for (int i = 0; i < n; ++i) off[i + 1] = off[i] + (long long)e[i].planes * e[i].crop * e[i].crop;
@@ -483,21 +487,24 @@ static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
     }
   }
   std::vector<int> queue(n);
-  double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double load[kQueues] = {};
+  int count[kQueues] = {};
+  b->class_items[0] = b->class_items[1] = 0;
   for (int slot = 0; slot < n; ++slot) {
-    const int x = (int)(std::min_element(load, load + 8) - load);
+    const int t = prm[slot].SP == 64 ? 1 : 0;
+    const int x = 8 * t + (int)(std::min_element(load + 8 * t, load + 8 * t + 8) - (load + 8 * t));
     queue[slot] = x;
     load[x] += cost(order[slot]);
     count[x] += 1;
+    b->class_items[t] += prm[slot].D;
   }
   int* list = (int*)(b->h_staging + off_list(b));
   long long* pre = (long long*)(b->h_staging + off_pre(b));
   int* qoff = (int*)(b->h_staging + off_qoff(b));
   qoff[0] = 0;
-  for (int x = 0; x < 8; ++x) qoff[x + 1] = qoff[x] + count[x];
-  int fill[8];
-  for (int x = 0; x < 8; ++x) fill[x] = qoff[x];
+  for (int x = 0; x < kQueues; ++x) qoff[x + 1] = qoff[x] + count[x];
+  int fill[kQueues];
+  for (int x = 0; x < kQueues; ++x) fill[x] = qoff[x];
   for (int slot = 0; slot < n; ++slot) list[fill[queue[slot]]++] = slot;
   pre[0] = 0;
   for (int i = 0; i < n; ++i) pre[i + 1] = pre[i] + prm[list[i]].D;
@@ -536,11 +543,20 @@ static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t
   a.pitch = b->pitch;
   hipLaunchKernelGGL(batch_fold_kernel, dim3(n), dim3(256), 0, st, a);
   if ((rc = hip_check(hipGetLastError()))) return rc;
-  // at least one workgroup per queue; no more than the configured residency
-  const long long want = std::max<long long>(8, std::min<long long>(b->items, (long long)b->num_cus * b->cfg.wg_per_cu));
-  const int grid = (int)std::min<long long>(want, (long long)b->num_cus * kMaxWgPerCu);
-  hipLaunchKernelGGL(batch_planes_kernel, dim3(grid), dim3(256), kBatchLdsBytes, st, a);
-  return hip_check(hipGetLastError());
+  // one launch per tile class, the wide tiles first; at least one workgroup per queue and
+  // no more than the configured residency
+  for (int t = 1; t >= 0; --t) {
+    if (b->class_items[t] == 0) continue;
+    const long long want =
+        std::max<long long>(8, std::min<long long>(b->class_items[t], (long long)b->num_cus * b->cfg.wg_per_cu));
+    const int grid = (int)std::min<long long>(want, (long long)b->num_cus * kMaxWgPerCu);
+    if (t == 1)
+      hipLaunchKernelGGL(batch_planes_kernel<64>, dim3(grid), dim3(256), kBatchLdsBytes, st, a);
+    else
+      hipLaunchKernelGGL(batch_planes_kernel<32>, dim3(grid), dim3(256), kBatchLdsBytes, st, a);
+    if ((rc = hip_check(hipGetLastError()))) return rc;
+  }
+  return RWPSF_OK;
 }
 
 }  // namespace rw
@@ -631,7 +647,7 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
       (rc = balloc(b, &b->d_dz, (size_t)b->num_cus * kMaxWgPerCu * (NN / 4))) ||
       (rc = balloc(b, &b->d_basis, (size_t)kBasisRows * NN)) ||
       (rc = balloc(b, &b->d_phi, (size_t)max_emitters * NN)) || (rc = balloc(b, &b->d_upload, b->upload_bytes)) ||
-      (rc = balloc(b, &b->d_counter, 8))) {
+      (rc = balloc(b, &b->d_counter, kQueues))) {
     delete b;
     return rc;
   }
@@ -648,7 +664,9 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
       (rc = hip_check(hipMemcpy(b->d_B1T, B1T.data(), B1T.size() * sizeof(float), hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipMemcpy(b->d_basis, basis.data(), basis.size() * sizeof(float), hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipMemcpy(b->d_upload, b->h_staging, b->upload_bytes, hipMemcpyHostToDevice))) ||
-      (rc = hip_check(hipFuncSetAttribute((const void*)batch_planes_kernel,
+      (rc = hip_check(hipFuncSetAttribute((const void*)batch_planes_kernel<32>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLdsBytes))) ||
+      (rc = hip_check(hipFuncSetAttribute((const void*)batch_planes_kernel<64>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLdsBytes))) ||
       (rc = hip_check(hipDeviceSynchronize()))) {
     delete b;
