@@ -63,7 +63,10 @@ enum rwpsf_status_code {
 /* RWPSF_FORM_CHIRPZ evaluates the same discrete Cartesian sum as RWPSF_FORM_FOURIER
    with the chirp-z (Bluestein) transform of Sec. 3.3: per z-plane and component, one
    FFT convolution along y for every pupil row and one along x for every output column
-   (FFT lengths: powers of two >= N + ny - 1 and N + nx - 1, at most 2048; N <= 1024).
+   (FFT lengths: powers of two >= N + ny - 1 and N + nx - 1, at least 64 and at most
+   2048; N <= 1024; rwpsf_plan_create returns RWPSF_ERR_UNSUPPORTED when four output
+   columns of the x pass, 4 (N + nx) complex values plus four transform buffers and the
+   intensity sums, exceed the 160 KB of LDS of one workgroup).
    It needs fewer flops than the matrix DFT for large pupils; the result agrees with
    RWPSF_FORM_FOURIER to FP32 rounding.  The adjoint is not available for it. */
 enum rwpsf_form { RWPSF_FORM_BESSEL = 0, RWPSF_FORM_FOURIER = 1, RWPSF_FORM_CHIRPZ = 2 };
