@@ -399,7 +399,7 @@ def bench_surrogate(rw, torch, train_seconds):
     ST.train(sg, train, steps=steps, batch=256, lr=2e-3, lr_end=1e-4, seed=1, log_every=max(1, steps // 4))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    acc = {p: ST.judge(sg, eng, test, precision=p) for p in (rw.SG_BF16X3, rw.SG_BF16)}
+    acc = {p: ST.audit(sg, eng, test, precision=p) for p in (rw.SG_BF16X3, rw.SG_BF16)}
     base = ST.mean_crop_baseline(train, test)
     B = 65536
     coef, z = train["coef"][:B].contiguous(), train["z"][:B].contiguous()
@@ -473,8 +473,8 @@ def main():
                     help="also run a 256 MiB device-to-device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path; run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2502_03170_amd as rw

@@ -3,10 +3,10 @@
 * ``CropEngine``  -- 64 x 64 intensity crops (100 nm pixels, 128 x 128 pupil, NA 1.4,
   600 nm, circular polarisation) from the batched-emitter path, normalised by the
   peak of the unaberrated in-focus PSF; this is both the training-data generator
-  and the judge / fallback of the surrogate.
+  and the audit / fallback of the surrogate.
 * ``train``       -- Adam on mini-batches drawn with a seeded device generator; every
   forward/backward/update is a librwpsf kernel.
-* ``judge``       -- rel-L2 of the surrogate against the plain path, per crop.
+* ``audit``       -- rel-L2 of the surrogate against the plain path, per crop.
 * ``predict``     -- surrogate for in-distribution inputs, plain path for the rest
   (any |c_q| > 4 x 0.05 waves or |z| > 1 um).
 * ``save`` / ``load`` -- checkpoint with parameters, Adam moments and step.
@@ -105,7 +105,7 @@ def rel_l2_per_crop(pred, ref):
     return d / ref.flatten(1).norm(dim=1)
 
 
-def judge(sg: rw.Surrogate, eng: CropEngine, data: dict, precision: int = rw.SG_BF16X3):
+def audit(sg: rw.Surrogate, eng: CropEngine, data: dict, precision: int = rw.SG_BF16X3):
     import torch
     B = data["coef"].shape[0]
     pred = torch.empty_like(data["target"])

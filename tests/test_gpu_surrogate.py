@@ -1,5 +1,5 @@
 """Surrogate kernels against the FP64 network oracle (same weights), and a short training run
-on crops the engine generates, judged by the plain path."""
+on crops the engine generates, audited against the plain path."""
 import numpy as np
 import pytest
 
@@ -129,8 +129,8 @@ def test_surrogate_gradient_is_deterministic(lib):
     np.testing.assert_array_equal(g1, g2)
 
 
-def test_surrogate_training_reduces_error_and_judge(lib):
-    """Train briefly on engine-generated crops; the loss falls and the judge/fallback work."""
+def test_surrogate_training_reduces_error_and_audit(lib):
+    """Train briefly on engine-generated crops; the loss falls and the audit/fallback work."""
     import torch
     from paper_2502_03170_amd import surrogate_train as ST
     rw = lib
@@ -139,10 +139,10 @@ def test_surrogate_training_reduces_error_and_judge(lib):
     test = ST.make_dataset(eng, 512, seed=506)
     sg = rw.Surrogate(max_batch=256)
     sg.set_state(ST.init_params(0))
-    before = ST.judge(sg, eng, test)
+    before = ST.audit(sg, eng, test)
     hist = ST.train(sg, train, steps=1500, batch=256, lr=2e-3, lr_end=1e-4, seed=0)
     assert hist[-1] < 0.5 * hist[0], (hist[0], hist[-1])
-    rep = ST.judge(sg, eng, test)
+    rep = ST.audit(sg, eng, test)
     base = ST.mean_crop_baseline(train, test)
     # a learned approximation: the bar is that the trained network uses its inputs -- it
     # beats the best input-independent prediction (the mean training crop) by a clear
