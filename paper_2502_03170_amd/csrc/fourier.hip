@@ -238,6 +238,9 @@ struct FoldDefocusLoader {
 #endif
 using CfgPupil = RgCfg<RW_F1_BM, RW_F1_BN, RW_F1_BK, RW_F1_WM, RW_F1_WN>;
 using CfgImage = RgCfg<RW_F2_BM, RW_F2_BN, RW_F2_BK, RW_F2_WM, RW_F2_WN>;
+// pupils whose folded row count 4 nhp is a multiple of 256 take 256-row tiles (8 waves;
+// the y-table tile is then shared by twice the rows)
+using CfgPupilL = RgCfg<256, 128, 16, 64, 64>;
 // outputs of at most 64 pixels per axis are padded to 64 and use half-height tiles
 using CfgPupilS = RgCfg<128, 64, 16, 64, 32>;
 using CfgImageS = RgCfg<64, 64, 32, 32, 32>;
@@ -436,6 +439,7 @@ static hipError_t gemm_image_launch(const Gemm2Args& a, hipStream_t st) {
 // The tile height follows the padding the plan chose (multiples of 128, or of 64 for
 // outputs of at most 64 pixels along that axis).
 hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
+  if (a.nyp % CfgPupilL::BN == 0 && (4 * a.nhp) % CfgPupilL::BM == 0) return gemm_pupil_launch<CfgPupilL, 2>(a, st);
   if (a.nyp % CfgPupil::BN == 0) return gemm_pupil_launch<CfgPupil, RW_F1_OCC>(a, st);
   return gemm_pupil_launch<CfgPupilS, 4>(a, st);
 }
@@ -446,10 +450,12 @@ hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st) {
 }
 
 hipError_t fourier_kernel_attributes() {
-  const void* k[4] = {(const void*)gemm_pupil_kernel<CfgPupil, RW_F1_OCC>, (const void*)gemm_pupil_kernel<CfgPupilS, 4>,
-                      (const void*)gemm_image_kernel<CfgImage, RW_F2_OCC>, (const void*)gemm_image_kernel<CfgImageS, 4>};
-  const int bytes[4] = {CfgPupil::LDS_BYTES, CfgPupilS::LDS_BYTES, CfgImage::LDS_BYTES, CfgImageS::LDS_BYTES};
-  for (int i = 0; i < 4; ++i) {
+  const void* k[5] = {(const void*)gemm_pupil_kernel<CfgPupil, RW_F1_OCC>, (const void*)gemm_pupil_kernel<CfgPupilS, 4>,
+                      (const void*)gemm_image_kernel<CfgImage, RW_F2_OCC>, (const void*)gemm_image_kernel<CfgImageS, 4>,
+                      (const void*)gemm_pupil_kernel<CfgPupilL, 2>};
+  const int bytes[5] = {CfgPupil::LDS_BYTES, CfgPupilS::LDS_BYTES, CfgImage::LDS_BYTES, CfgImageS::LDS_BYTES,
+                        CfgPupilL::LDS_BYTES};
+  for (int i = 0; i < 5; ++i) {
     const hipError_t e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[i]);
     if (e != hipSuccess) return e;
   }
