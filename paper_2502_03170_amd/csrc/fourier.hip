@@ -222,7 +222,7 @@ struct FoldDefocusLoader {
 #define RW_F2_BM 128
 #endif
 #ifndef RW_F2_BN
-#define RW_F2_BN 64
+#define RW_F2_BN 128
 #endif
 #ifndef RW_F2_BK
 #define RW_F2_BK 32
