@@ -131,7 +131,7 @@ struct AdjGArgs {
   const float2* H;     // [chunk][nz][3][nxp][w]
   const float2* P;     // [chunk][3][np][np] base pupils (np = w)
   const double* ksz;   // [np][np]
-  const double* z;     // [nz]
+  const float2* D;     // [nz][np][np] exp(i k s_z z) of the plan's planes
   float* partial;      // [stacks * 3 * zgroups][np][np]
   double zoff[kPupilStacks];
   int s0, nstk, nz, nxp, w, n;
@@ -164,6 +164,30 @@ __global__ void __launch_bounds__(CfgAdjG::NT, 2) adj_g_kernel(AdjGArgs a) {
   // lane quad q = lane & 3 of columns 2(2lf + p) + ri: q = 2p + ri.  After the exchange the
   // lane owns mirror cell q: (jf, lf), (jf, l'), (j', lf), (j', l').
   const int q = lane & 3;
+  // The defocus of plane z for stack s is exp(i k s_z z) exp(i k s_z zoff_s): the second
+  // factor is applied to the lane's pupil cells once, the first comes from the plan's table.
+  float2 p0[Cfg::TM][Cfg::TN][8];
+#pragma unroll
+  for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+    for (int jj = 0; jj < Cfg::TN; ++jj) {
+      const int lf = (col0 + rg_col(wcol, jj, lane)) >> 2;
+#pragma unroll
+      for (int r = 0; r < 16; r += 2) {
+        const int jf = (row0 + rg_row(wrow, i, r, lane)) >> 1;
+        const int jc = (q & 2) ? n - 1 - jf : jf, lc = (q & 1) ? n - 1 - lf : lf;
+        const bool own = jf < nh && lf < nh && !((q & 2) && jc == jf) && !((q & 1) && lc == lf);
+        float2 v = make_float2(0.f, 0.f);
+        if (own) {
+          const size_t cell = (size_t)jc * a.w + lc;
+          const float2 pp = P[cell];
+          float sn, cs;
+          sincosf((float)reduce_2pi(a.ksz[cell] * a.zoff[s]), &sn, &cs);
+          v = make_float2(pp.x * cs - pp.y * sn, pp.x * sn + pp.y * cs);
+        }
+        p0[i][jj][r >> 1] = v;
+      }
+    }
   float dphi[Cfg::TM][Cfg::TN][8];
 #pragma unroll
   for (int i = 0; i < Cfg::TM; ++i)
@@ -182,7 +206,7 @@ __global__ void __launch_bounds__(CfgAdjG::NT, 2) adj_g_kernel(AdjGArgs a) {
     RgAcc<Cfg> acc;
     acc.zero();
     rg_mainloop<Cfg>(acc, la, lb, 0, a.nxp, lds, tid, wrow, wcol, lane);
-    const double zz = a.z[zi] + a.zoff[s];
+    const float2* Dz = a.D + (size_t)zi * npp;
 #pragma unroll
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
@@ -207,11 +231,9 @@ __global__ void __launch_bounds__(CfgAdjG::NT, 2) adj_g_kernel(AdjGArgs a) {
           const int jc = (q & 2) ? n - 1 - jf : jf, lc = (q & 1) ? n - 1 - lf : lf;
           const bool own = jf < nh && lf < nh && !((q & 2) && jc == jf) && !((q & 1) && lc == lf);
           if (own) {
-            const size_t cell = (size_t)jc * a.w + lc;
-            const float2 p = P[cell];
-            float sn, cs;
-            sincosf((float)reduce_2pi(a.ksz[cell] * zz), &sn, &cs);
-            const float pr = p.x * cs - p.y * sn, pi = p.x * sn + p.y * cs;
+            const float2 d = Dz[(size_t)jc * a.w + lc];
+            const float2 pv = p0[i][jj][r >> 1];
+            const float pr = pv.x * d.x - pv.y * d.y, pi = pv.x * d.y + pv.y * d.x;
             // Im(G conj(P~)) = Gi Pr - Gr Pi
             dphi[i][jj][r >> 1] += gi * pr - gr * pi;
           }
@@ -297,6 +319,18 @@ static int adjoint_zgroups(const rwpsf_plan* p) {
 // Lazily built adjoint tables and workspace of a Fourier plan: the folded DFT tables with
 // the pixel index contiguous, CxT[2jf + p][m] = pref {cos, sin}(k s_jf x_m) and
 // CyT[2lf + p][n] = {cos, sin}(k s_lf y_n) (zero past nx, ny and for jf, lf >= N/2).
+// exp(i k s_z z) of every plan plane on the padded pupil cells (FP64 phase reduced
+// mod 2 pi before the FP32 sincos); 0 outside the disk where k s_z is 0 -> factor 1.
+__global__ void adj_defocus_kernel(const double* __restrict__ ksz, const double* __restrict__ z, int nz,
+                                   int npp, float2* __restrict__ D) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nz * npp) return;
+  const int zi = (int)(idx / npp), cell = (int)(idx % npp);
+  float sn, cs;
+  sincosf((float)reduce_2pi(ksz[cell] * z[zi]), &sn, &cs);
+  D[idx] = make_float2(cs, sn);
+}
+
 static int adjoint_prepare(rwpsf_plan* p, int n_stacks) {
   const int nx = p->grid.nx, ny = p->grid.ny, N = p->num.n_pupil, np = p->np;
   const int nxp = p->nxp, nyp = p->nyp, w = 2 * p->nhp, nh = (N + 1) / 2;
@@ -322,6 +356,13 @@ static int adjoint_prepare(rwpsf_plan* p, int n_stacks) {
     if ((st = dev_alloc(p, &p->d_CyT, CyT.size()))) return st;
     if ((st = dev_alloc(p, &p->d_dphi, (size_t)N * N))) return st;
     if ((st = dev_alloc(p, &p->d_H, (size_t)kPupilStacks * p->grid.nz * 3 * nxp * w))) return st;
+    const size_t nzpp = (size_t)p->grid.nz * np * np;
+    if ((st = dev_alloc(p, &p->d_adjD, nzpp))) return st;
+    hipLaunchKernelGGL(adj_defocus_kernel, dim3((unsigned)((nzpp + 255) / 256)), dim3(256), 0, 0, p->d_ksz, p->d_z,
+                       p->grid.nz, np * np, p->d_adjD);
+    if ((st = hip_check(hipGetLastError()))) return st;
+    // the table is written on the null stream; the caller's stream may not order after it
+    if ((st = hip_check(hipDeviceSynchronize()))) return st;
     if ((st = hip_check(hipMemcpy(p->d_CxT, CxT.data(), CxT.size() * sizeof(float), hipMemcpyHostToDevice)))) return st;
     if ((st = hip_check(hipMemcpy(p->d_CyT, CyT.data(), CyT.size() * sizeof(float), hipMemcpyHostToDevice)))) return st;
     if ((st = hip_check(adjoint_kernel_attributes()))) return st;
@@ -361,7 +402,7 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
     ga.H = p->d_H;
     ga.P = p->d_P;
     ga.ksz = p->d_ksz;
-    ga.z = p->d_z;
+    ga.D = p->d_adjD;
     ga.partial = p->d_partial;
     for (int i = 0; i < nb; ++i) ga.zoff[i] = s[b0 + i].z_offset_nm;
     ga.s0 = b0;

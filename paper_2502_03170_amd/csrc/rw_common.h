@@ -170,6 +170,7 @@ struct rwpsf_plan {
   float* d_partial = nullptr;   // [stacks * 3][np][np] per-(stack, component) dL/dPhi
   int partial_groups = 0;
   double* d_dphi = nullptr;     // [N][N]
+  float2* d_adjD = nullptr;     // [nz][np][np] exp(i k s_z z) of the plan's planes
   double* d_runs = nullptr;     // [partial runs][N][N] first level of the dL/dPhi reduction
   int P_stacks = 0;             // capacity of d_P in stacks
 
