@@ -242,7 +242,9 @@ using CfgImage = RgCfg<RW_F2_BM, RW_F2_BN, RW_F2_BK, RW_F2_WM, RW_F2_WN>;
 // the y-table tile is then shared by twice the rows)
 using CfgPupilL = RgCfg<256, 128, 16, 64, 64>;
 // outputs of at most 64 pixels per axis are padded to 64 and use half-height tiles
+// (256 rows when the folded row count allows, as above)
 using CfgPupilS = RgCfg<128, 64, 16, 64, 32>;
+using CfgPupilSL = RgCfg<256, 64, 16, 64, 32>;
 using CfgImageS = RgCfg<64, 64, 32, 32, 32>;
 static_assert((4 * kFoldPad) % CfgPupil::BM == 0 && (2 * kFoldPad) % CfgPupil::BK == 0, "pupil GEMM padding");
 static_assert((4 * kFoldPad) % CfgPupilS::BM == 0 && kPadSmall % CfgPupilS::BN == 0 && kPadSmall % CfgImageS::BM == 0 &&
@@ -441,6 +443,7 @@ static hipError_t gemm_image_launch(const Gemm2Args& a, hipStream_t st) {
 hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
   if (a.nyp % CfgPupilL::BN == 0 && (4 * a.nhp) % CfgPupilL::BM == 0) return gemm_pupil_launch<CfgPupilL, 2>(a, st);
   if (a.nyp % CfgPupil::BN == 0) return gemm_pupil_launch<CfgPupil, RW_F1_OCC>(a, st);
+  if ((4 * a.nhp) % CfgPupilSL::BM == 0) return gemm_pupil_launch<CfgPupilSL, 2>(a, st);
   return gemm_pupil_launch<CfgPupilS, 4>(a, st);
 }
 
@@ -450,12 +453,12 @@ hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st) {
 }
 
 hipError_t fourier_kernel_attributes() {
-  const void* k[5] = {(const void*)gemm_pupil_kernel<CfgPupil, RW_F1_OCC>, (const void*)gemm_pupil_kernel<CfgPupilS, 4>,
+  const void* k[6] = {(const void*)gemm_pupil_kernel<CfgPupil, RW_F1_OCC>, (const void*)gemm_pupil_kernel<CfgPupilS, 4>,
                       (const void*)gemm_image_kernel<CfgImage, RW_F2_OCC>, (const void*)gemm_image_kernel<CfgImageS, 4>,
-                      (const void*)gemm_pupil_kernel<CfgPupilL, 2>};
-  const int bytes[5] = {CfgPupil::LDS_BYTES, CfgPupilS::LDS_BYTES, CfgImage::LDS_BYTES, CfgImageS::LDS_BYTES,
-                        CfgPupilL::LDS_BYTES};
-  for (int i = 0; i < 5; ++i) {
+                      (const void*)gemm_pupil_kernel<CfgPupilL, 2>, (const void*)gemm_pupil_kernel<CfgPupilSL, 2>};
+  const int bytes[6] = {CfgPupil::LDS_BYTES, CfgPupilS::LDS_BYTES, CfgImage::LDS_BYTES, CfgImageS::LDS_BYTES,
+                        CfgPupilL::LDS_BYTES, CfgPupilSL::LDS_BYTES};
+  for (int i = 0; i < 6; ++i) {
     const hipError_t e = hipFuncSetAttribute(k[i], hipFuncAttributeMaxDynamicSharedMemorySize, bytes[i]);
     if (e != hipSuccess) return e;
   }
