@@ -283,17 +283,19 @@ __global__ void adj_reduce_kernel(const double* __restrict__ runs, int nruns, in
   if (dW0) dW0[cell] = (float)s;
 }
 
-// dL/dc_q = 2 pi sum_cells dL/dPhi Z_q: one workgroup per q, fixed-shape tree.
-__global__ void __launch_bounds__(256) adj_zernike_kernel(const double* __restrict__ dphi,
-                                                          const float* __restrict__ ztab, int nn,
-                                                          float* __restrict__ dc) {
-  __shared__ double red[256];
+// dL/dc_q = 2 pi sum_cells dL/dPhi Z_q: one workgroup of 1024 threads per q, fixed-shape tree.
+constexpr int kZernThreads = 1024;
+__global__ void __launch_bounds__(kZernThreads) adj_zernike_kernel(const double* __restrict__ dphi,
+                                                                   const float* __restrict__ ztab, int nn,
+                                                                   float* __restrict__ dc) {
+  __shared__ double red[kZernThreads];
   const int q = blockIdx.x;
   double s = 0.0;
-  for (int cell = threadIdx.x; cell < nn; cell += 256) s += dphi[cell] * (double)ztab[(size_t)q * nn + cell];
+  for (int cell = threadIdx.x; cell < nn; cell += kZernThreads)
+    s += dphi[cell] * (double)ztab[(size_t)q * nn + cell];
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kZernThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
@@ -428,7 +430,8 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
                      p->d_dphi, dW0);
   if ((rc = hip_check(hipGetLastError()))) return rc;
   if (n_zernike > 0) {
-    hipLaunchKernelGGL(adj_zernike_kernel, dim3(n_zernike), dim3(256), 0, st, p->d_dphi, p->d_ztab, N * N, dc);
+    hipLaunchKernelGGL(adj_zernike_kernel, dim3(n_zernike), dim3(kZernThreads), 0, st, p->d_dphi, p->d_ztab, N * N,
+                       dc);
     if ((rc = hip_check(hipGetLastError()))) return rc;
   }
   p->time_end(tr, st);
