@@ -39,15 +39,18 @@ __global__ void zernike_table_kernel(float* __restrict__ out, int n, int nj, dou
 // --------------------------------------------------------------------------
 // K1: base pupil of each stack.
 // --------------------------------------------------------------------------
+// One thread per (padded cell, stack): grid.y is the stack.
 __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const float2* __restrict__ Q,
                                                           const float* __restrict__ ztab,
                                                           float2* __restrict__ P) {
   const int n = a.n, np = a.np;
   const size_t npp = (size_t)np * np;
   const int pcell = blockIdx.x * blockDim.x + threadIdx.x;   // padded cell
+  const int s = blockIdx.y;
   if (pcell >= np * np) return;
   const int j = pcell / np, l = pcell % np;
   const int nc = a.nc;
+  float2* out = P + (size_t)s * nc * npp + pcell;
   float2 q[3] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
   bool inside = false;
   if (j < n && l < n)
@@ -56,45 +59,25 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
       inside = inside || q[c].x != 0.f || q[c].y != 0.f;
     }
   if (!inside) {
-    for (int s = 0; s < a.nstk; ++s)
-      for (int c = 0; c < nc; ++c) P[((size_t)s * nc + c) * npp + pcell] = make_float2(0.f, 0.f);
+    for (int c = 0; c < nc; ++c) out[c * npp] = make_float2(0.f, 0.f);
     return;
   }
   const int cell = j * n + l;   // unpadded index: Zernike table and user phase map
   const double sx = (2.0 * j + 1.0 - n) * a.s_max / n;
   const double sy = (2.0 * l + 1.0 - n) * a.s_max / n;
   const double sin_t = sqrt(sx * sx + sy * sy);
-
-  double w_re[kPupilStacks], w_im[kPupilStacks];
-  for (int s = 0; s < kPupilStacks; ++s) {
-    w_re[s] = 0.0;
-    w_im[s] = 0.0;
-  }
-  for (int s = 0; s < a.nstk; ++s) {
-    const PupilStack& st = a.s[s];
-    if (a.gibson_lanni) {
-      double gr, gi;
-      gl_opd(a.gl, st.t_s, sin_t, &gr, &gi);
-      w_re[s] += gr;
-      w_im[s] += gi;
-    }
-    w_re[s] -= a.k * (sx * st.x0 + sy * st.y0);
-    if (st.w0) w_re[s] += (double)st.w0[cell];
-  }
-  for (int q = 0; q < a.max_zernike; ++q) {
-    const double zq = (double)ztab[(size_t)q * n * n + cell];
-    for (int s = 0; s < a.nstk; ++s) w_re[s] += kTwoPi * a.s[s].coef[q] * zq;
-  }
-  for (int s = 0; s < a.nstk; ++s) {
-    const float ph = (float)reduce_2pi(w_re[s]);
-    const float amp = (float)exp(-w_im[s]);
-    float sn, cs;
-    sincosf(ph, &sn, &cs);
-    const float er = amp * cs, ei = amp * sn;
-    float2* out = P + (size_t)s * nc * npp + pcell;
-    for (int c = 0; c < nc; ++c)
-      out[c * npp] = make_float2(q[c].x * er - q[c].y * ei, q[c].x * ei + q[c].y * er);
-  }
+  const PupilStack& st = a.s[s];
+  double w_re = 0.0, w_im = 0.0;
+  if (a.gibson_lanni) gl_opd(a.gl, st.t_s, sin_t, &w_re, &w_im);
+  w_re -= a.k * (sx * st.x0 + sy * st.y0);
+  if (st.w0) w_re += (double)st.w0[cell];
+  for (int k = 0; k < a.max_zernike; ++k) w_re += kTwoPi * st.coef[k] * (double)ztab[(size_t)k * n * n + cell];
+  const float ph = (float)reduce_2pi(w_re);
+  const float amp = (float)exp(-w_im);
+  float sn, cs;
+  sincosf(ph, &sn, &cs);
+  const float er = amp * cs, ei = amp * sn;
+  for (int c = 0; c < nc; ++c) out[c * npp] = make_float2(q[c].x * er - q[c].y * ei, q[c].x * ei + q[c].y * er);
 }
 
 // --------------------------------------------------------------------------
@@ -111,44 +94,45 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
 // depends on s_x^2 + s_y^2 only and is the same for all four mirrors.
 // Layout: Pf[s][c][q = 2 jf + pj][kk = 2 lf + pl], complex, (2 nhp) x (2 nhp).
 // --------------------------------------------------------------------------
+// One thread per (folded cell, stack): grid.y is the stack.
 __global__ void __launch_bounds__(256) pupil_fold_kernel(FoldArgs a) {
   const int nhp = a.nhp, n = a.n, nh = (a.n + 1) / 2;
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+  const int s = blockIdx.y;
   if (cell >= nhp * nhp) return;
   const int jf = cell / nhp, lf = cell % nhp;
   const size_t npp = (size_t)a.np * a.np, fpp = (size_t)4 * nhp * nhp;
   const int w = 2 * nhp;
   const size_t o00 = (size_t)(2 * jf) * w + 2 * lf;   // (pj, pl) = (0, 0); (0,1) = +1; (1,0) = +w
   const float2 zero = make_float2(0.f, 0.f);
-  for (int s = 0; s < a.nstk; ++s)
-    for (int c = 0; c < a.nc; ++c) {
-      float2* out = a.Pf + ((size_t)s * a.nc + c) * fpp + o00;
-      if (jf >= nh || lf >= nh) {
-        out[0] = zero;
-        out[1] = zero;
-        out[w] = zero;
-        out[w + 1] = zero;
-        continue;
-      }
-      const float2* P = a.P + ((size_t)s * a.nc + c) * npp;
-      const int j1 = n - 1 - jf, l1 = n - 1 - lf;
-      const bool dj = j1 != jf, dl = l1 != lf;
-      const float2 p00 = P[(size_t)jf * a.np + lf];
-      const float2 p01 = dl ? P[(size_t)jf * a.np + l1] : zero;
-      const float2 p10 = dj ? P[(size_t)j1 * a.np + lf] : zero;
-      const float2 p11 = (dj && dl) ? P[(size_t)j1 * a.np + l1] : zero;
-      // even/odd in l for each j mirror, then in j
-      const float2 e0 = make_float2(p00.x + p01.x, p00.y + p01.y), o0 = make_float2(p00.x - p01.x, p00.y - p01.y);
-      const float2 e1 = make_float2(p10.x + p11.x, p10.y + p11.y), o1 = make_float2(p10.x - p11.x, p10.y - p11.y);
-      const float2 ee = make_float2(e0.x + e1.x, e0.y + e1.y);
-      const float2 eo = dl ? make_float2(o0.x + o1.x, o0.y + o1.y) : zero;            // odd in l
-      const float2 oe = dj ? make_float2(e0.x - e1.x, e0.y - e1.y) : zero;            // odd in j
-      const float2 oo = (dj && dl) ? make_float2(o0.x - o1.x, o0.y - o1.y) : zero;
-      out[0] = ee;
-      out[1] = make_float2(-eo.y, eo.x);        // i * eo
-      out[w] = make_float2(-oe.y, oe.x);        // i * oe
-      out[w + 1] = make_float2(-oo.x, -oo.y);   // i^2 * oo
+  for (int c = 0; c < a.nc; ++c) {
+    float2* out = a.Pf + ((size_t)s * a.nc + c) * fpp + o00;
+    if (jf >= nh || lf >= nh) {
+      out[0] = zero;
+      out[1] = zero;
+      out[w] = zero;
+      out[w + 1] = zero;
+      continue;
     }
+    const float2* P = a.P + ((size_t)s * a.nc + c) * npp;
+    const int j1 = n - 1 - jf, l1 = n - 1 - lf;
+    const bool dj = j1 != jf, dl = l1 != lf;
+    const float2 p00 = P[(size_t)jf * a.np + lf];
+    const float2 p01 = dl ? P[(size_t)jf * a.np + l1] : zero;
+    const float2 p10 = dj ? P[(size_t)j1 * a.np + lf] : zero;
+    const float2 p11 = (dj && dl) ? P[(size_t)j1 * a.np + l1] : zero;
+    // even/odd in l for each j mirror, then in j
+    const float2 e0 = make_float2(p00.x + p01.x, p00.y + p01.y), o0 = make_float2(p00.x - p01.x, p00.y - p01.y);
+    const float2 e1 = make_float2(p10.x + p11.x, p10.y + p11.y), o1 = make_float2(p10.x - p11.x, p10.y - p11.y);
+    const float2 ee = make_float2(e0.x + e1.x, e0.y + e1.y);
+    const float2 eo = dl ? make_float2(o0.x + o1.x, o0.y + o1.y) : zero;            // odd in l
+    const float2 oe = dj ? make_float2(e0.x - e1.x, e0.y - e1.y) : zero;            // odd in j
+    const float2 oo = (dj && dl) ? make_float2(o0.x - o1.x, o0.y - o1.y) : zero;
+    out[0] = ee;
+    out[1] = make_float2(-eo.y, eo.x);        // i * eo
+    out[w] = make_float2(-oe.y, oe.x);        // i * oe
+    out[w + 1] = make_float2(-oo.x, -oo.y);   // i^2 * oo
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -412,13 +396,13 @@ hipError_t launch_zernike_table(float* out, int n, int nj, hipStream_t st) {
 hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* ztab, float2* P,
                               hipStream_t st) {
   const int cells = a.np * a.np;
-  hipLaunchKernelGGL(pupil_build_kernel, dim3((cells + 255) / 256), dim3(256), 0, st, a, Q, ztab, P);
+  hipLaunchKernelGGL(pupil_build_kernel, dim3((cells + 255) / 256, a.nstk), dim3(256), 0, st, a, Q, ztab, P);
   return hipGetLastError();
 }
 
 hipError_t launch_pupil_fold(const FoldArgs& a, hipStream_t st) {
   const int cells = a.nhp * a.nhp;
-  hipLaunchKernelGGL(pupil_fold_kernel, dim3((cells + 255) / 256), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(pupil_fold_kernel, dim3((cells + 255) / 256, a.nstk), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
