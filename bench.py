@@ -519,7 +519,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)
     out = {
-        "metric": "PSF voxels/sec (vectorial FP32) plain vs batched/surrogate at rel-L2 <=1e-5",
+        "metric": "PSF voxels/sec (vectorial FP32) plain vs batched/surrogate at rel-L2 \u22641e-5",
         "value": res["value"], "unit": "voxels/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": res["ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
