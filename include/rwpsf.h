@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define RWPSF_ABI_VERSION 2
+#define RWPSF_ABI_VERSION 3
 
 enum rwpsf_status_code {
   RWPSF_OK = 0,
@@ -223,8 +223,9 @@ int rwpsf_adjoint_bessel(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stac
    Thousands of emitters, each with its own sub-pixel position, axial position,
    Zernike vector, crop size and plane count, evaluated by the Fourier form in one
    persistent launch (optionally replayed from a captured hipGraph).  Optics as in
-   rwpsf_optics, vectorial model (the Gibson-Lanni layer is not supported here; the
-   Fresnel factors and the extra s_z factor are).  Emitter b gets
+   rwpsf_optics, vectorial model (the Gibson-Lanni layer, the Fresnel factors and the
+   extra s_z factor included; with the layer each emitter carries its own depth t_s).
+   Emitter b gets
    crop x crop pixels at pitch pixel_nm, pixel (i, j) at ((i - crop/2) p, (j - crop/2) p)
    relative to the crop centre, and `planes` planes at z_d = (d - (planes-1)/2) *
    plane_pitch_nm, d = 0..planes-1; its defocus is z_d - z_nm.  Outputs are packed in
@@ -240,6 +241,7 @@ typedef struct rwpsf_emitter {
   int crop;                /* 1..RWPSF_BATCH_MAX_CROP */
   int planes;              /* 1..4096 */
   double zernike_waves[RWPSF_BATCH_MAX_ZERNIKE];   /* Noll 1..21, waves */
+  double t_s_nm;           /* depth below the coverslip, >= 0 (read only with the Gibson-Lanni layer) */
 } rwpsf_emitter;
 
 typedef struct rwpsf_batch rwpsf_batch;

@@ -87,7 +87,7 @@ BATCH_MAX_ZERNIKE = 21
 
 class Emitter(ctypes.Structure):
     _fields_ = [("x0_nm", c_double), ("y0_nm", c_double), ("z_nm", c_double), ("crop", c_int),
-                ("planes", c_int), ("zernike_waves", c_double * BATCH_MAX_ZERNIKE)]
+                ("planes", c_int), ("zernike_waves", c_double * BATCH_MAX_ZERNIKE), ("t_s_nm", c_double)]
 
 
 class BatchConfig(ctypes.Structure):
@@ -386,11 +386,13 @@ def psf_function():
     return _PSF
 
 
-def make_emitters(x0, y0, z, crop, planes, zernike):
+def make_emitters(x0, y0, z, crop, planes, zernike, t_s=None):
+    """``t_s``: per-emitter depth below the coverslip (nm), read with the Gibson-Lanni layer."""
     n = len(x0)
     arr = (Emitter * n)()
     for i in range(n):
         arr[i].x0_nm, arr[i].y0_nm, arr[i].z_nm = float(x0[i]), float(y0[i]), float(z[i])
+        arr[i].t_s_nm = 0.0 if t_s is None else float(t_s[i])
         arr[i].crop, arr[i].planes = int(crop[i]), int(planes[i])
         c = zernike[i]
         for q in range(min(len(c), BATCH_MAX_ZERNIKE)):
@@ -409,9 +411,9 @@ class Batch:
     """Batched emitters (rwpsf_batch_*): one persistent launch for many small stacks."""
 
     def __init__(self, *, na, wavelength, n_i, pixel, plane_pitch, max_emitters, n_pupil=128,
-                 e_inc=CIRCULAR, focal_length=1.0, apodization=True, s_env=0.0, fresnel=None,
-                 extra_sz=False):
-        self.optics = make_optics(na, wavelength, n_i, e_inc, focal_length, apodization, s_env, None,
+                 e_inc=CIRCULAR, focal_length=1.0, apodization=True, s_env=0.0, gibson_lanni=None,
+                 fresnel=None, extra_sz=False):
+        self.optics = make_optics(na, wavelength, n_i, e_inc, focal_length, apodization, s_env, gibson_lanni,
                                   fresnel, extra_sz)
         h = c_void_p()
         _check(load().rwpsf_batch_create(byref(self.optics), n_pupil, pixel, plane_pitch, max_emitters,

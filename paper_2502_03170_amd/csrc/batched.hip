@@ -51,6 +51,7 @@ constexpr int kStageU = kBK * (kLdaU + 2 * kLdbU);
 
 struct BatchParam {
   double zoff;      // -z_e
+  double ts;        // emitter depth below the coverslip (Gibson-Lanni)
   long long off;    // voxel offset of the emitter's output
   int S, D, SP, pad;
 };
@@ -60,6 +61,8 @@ struct BatchArgs {
   const float2* Q;           // [3][N][N]
   const double* ksz;         // [N][N]
   const float* phi;          // [n][N*N], slot order
+  const double4* gl;         // [N*N] Gibson-Lanni phase W = t_s (g1.x + i g1.y) + (g0.x + i g0.y) as
+                             // (g0.x, g0.y, g1.x, g1.y), or null without the layer
   const float* A2T;          // [N][96] rows 2jf + pj: pref cos / sin (k s_x[jf] x_r)
   const float* B1T;          // [N][96] rows 2lf + pl: cos / sin (k s_y[lf] y_r)
   float2* Pf;                // [n][3][N][N] folded pupils, slot order
@@ -91,12 +94,28 @@ __global__ void __launch_bounds__(256) batch_fold_kernel(BatchArgs a) {
   const int N = a.N, NN = N * N, nh = N / 2;
   const float* phi = a.phi + (size_t)slot * NN;
   float2* Pf = a.Pf + (size_t)slot * 3 * NN;
+  const double ts = a.params[slot].ts;
   for (int cell = threadIdx.x; cell < nh * nh; cell += 256) {
     const int jf = cell / nh, lf = cell % nh, j1 = N - 1 - jf, l1 = N - 1 - lf;
     const int idx[4] = {jf * N + lf, jf * N + l1, j1 * N + lf, j1 * N + l1};
     float er[4], ei[4];
+    if (a.gl) {
+      // the layer's phase is formed in FP64 and reduced mod 2 pi before it joins phi;
+      // its imaginary part is the evanescent decay
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sincosf(phi[idx[q]], &ei[q], &er[q]);
+      for (int q = 0; q < 4; ++q) {
+        const double4 g = a.gl[idx[q]];
+        const double wr = ts * g.z + g.x, wi = ts * g.w + g.y;
+        const float amp = (float)exp(-wi);
+        float sn, cs;
+        sincosf((float)reduce_2pi(wr + (double)phi[idx[q]]), &sn, &cs);
+        er[q] = amp * cs;
+        ei[q] = amp * sn;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sincosf(phi[idx[q]], &ei[q], &er[q]);
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       float pr[4], pi[4];
@@ -385,6 +404,7 @@ struct rwpsf_batch {
   std::vector<void*> allocations;
   float2* d_Q = nullptr;
   double* d_ksz = nullptr;
+  double4* d_gl = nullptr;      // [N*N] Gibson-Lanni phase tables, or null
   float* d_A2T = nullptr;       // [N][96] folded x table (prefactor included)
   float* d_B1T = nullptr;       // [N][96] folded y table
   float2* d_pf = nullptr;       // [max][3][N][N] folded pupils
@@ -426,6 +446,7 @@ static int batch_validate(const rwpsf_batch* b, int n, const rwpsf_emitter* e) {
     const rwpsf_emitter& x = e[i];
     if (!std::isfinite(x.x0_nm) || !std::isfinite(x.y0_nm) || !std::isfinite(x.z_nm))
       return RWPSF_ERR_INVALID_ARG;
+    if (b->opt.gibson_lanni && (!std::isfinite(x.t_s_nm) || x.t_s_nm < 0.0)) return RWPSF_ERR_INVALID_ARG;
     if (std::fabs(x.x0_nm) > 4 * b->px || std::fabs(x.y0_nm) > 4 * b->px) return RWPSF_ERR_INVALID_ARG;
     if (x.crop < 1 || x.crop > RWPSF_BATCH_MAX_CROP || x.planes < 1 || x.planes > 4096)
       return RWPSF_ERR_INVALID_ARG;
@@ -473,6 +494,7 @@ static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
   for (int slot = 0; slot < n; ++slot) {
     const int i = order[slot];
     prm[slot].zoff = -e[i].z_nm;
+    prm[slot].ts = b->opt.gibson_lanni ? e[i].t_s_nm : 0.0;
     prm[slot].off = off[i];
     prm[slot].S = e[i].crop;
     prm[slot].D = e[i].planes;
@@ -528,6 +550,7 @@ static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t
   a.Q = b->d_Q;
   a.ksz = b->d_ksz;
   a.phi = b->d_phi;
+  a.gl = b->d_gl;
   a.A2T = b->d_A2T;
   a.B1T = b->d_B1T;
   a.Pf = b->d_pf;
@@ -583,7 +606,6 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
   rwpsf_numerics nm{RWPSF_FORM_FOURIER, n_pupil, 2, 8};
   int st = validate_plan(o, &g, &nm);
   if (st != RWPSF_OK) return st;
-  if (o->gibson_lanni) return RWPSF_ERR_UNSUPPORTED;
   if (n_pupil < 32 || n_pupil > 128 || n_pupil % 32 != 0) return RWPSF_ERR_INVALID_ARG;
   if (!(pixel_nm > 0) || !std::isfinite(pixel_nm) || !(pitch_nm >= 0) || !std::isfinite(pitch_nm))
     return RWPSF_ERR_INVALID_ARG;
@@ -605,6 +627,17 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
   const size_t NN = (size_t)N * N;
   std::vector<float2> Q(3 * NN, make_float2(0.f, 0.f));
   std::vector<double> ksz(NN, 0.0);
+  std::vector<double4> gl(o->gibson_lanni ? NN : 0, make_double4(0.0, 0.0, 0.0, 0.0));
+  GLParams glp{};
+  glp.k0 = kTwoPi / o->wavelength_nm;
+  glp.n_i = o->n_i;
+  glp.n_s = o->n_s;
+  glp.n_g = o->n_g;
+  glp.n_g_d = o->n_g_design;
+  glp.n_i_d = o->n_i_design;
+  glp.t_g = o->t_g_nm;
+  glp.t_g_d = o->t_g_design_nm;
+  glp.t_i_d = o->t_i_design_nm;
   std::vector<float> basis((size_t)kBasisRows * NN, 0.f);
   const double ds = 2.0 * b->s_max / N;
   for (int j = 0; j < N; ++j)
@@ -623,6 +656,15 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
       base_pupil_cell(*o, 3, ds, sx, sy, e);
       for (int c = 0; c < 3; ++c) Q[c * NN + cell] = make_float2((float)e[c].real(), (float)e[c].imag());
       ksz[cell] = b->k * std::sqrt(1.0 - (sx * sx + sy * sy));
+      if (o->gibson_lanni) {
+        // the phase is affine in t_s (t_i is affine in it and each layer's term is linear
+        // in its thickness): store its value at t_s = 0 and its slope
+        const double sin_t = std::sqrt(sx * sx + sy * sy), T = 1.0e4;
+        double r0, i0, r1, i1;
+        gl_opd(glp, 0.0, sin_t, &r0, &i0);
+        gl_opd(glp, T, sin_t, &r1, &i1);
+        gl[cell] = make_double4(r0, i0, (r1 - r0) / T, (i1 - i0) / T);
+      }
     }
   // folded DFT tables: row 2jf + p holds cos (p = 0) or sin (p = 1) of k s[jf] x_r,
   // x_r = (r - 32) pixel; the x table carries the prefactor f k / 2 pi (E = -i E')
@@ -647,7 +689,7 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
       (rc = balloc(b, &b->d_dz, (size_t)b->num_cus * kMaxWgPerCu * (NN / 4))) ||
       (rc = balloc(b, &b->d_basis, (size_t)kBasisRows * NN)) ||
       (rc = balloc(b, &b->d_phi, (size_t)max_emitters * NN)) || (rc = balloc(b, &b->d_upload, b->upload_bytes)) ||
-      (rc = balloc(b, &b->d_counter, kQueues))) {
+      (rc = balloc(b, &b->d_counter, kQueues)) || (o->gibson_lanni && (rc = balloc(b, &b->d_gl, NN)))) {
     delete b;
     return rc;
   }
@@ -662,6 +704,8 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
       (rc = hip_check(hipMemcpy(b->d_ksz, ksz.data(), ksz.size() * sizeof(double), hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipMemcpy(b->d_A2T, A2T.data(), A2T.size() * sizeof(float), hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipMemcpy(b->d_B1T, B1T.data(), B1T.size() * sizeof(float), hipMemcpyHostToDevice))) ||
+      (o->gibson_lanni &&
+       (rc = hip_check(hipMemcpy(b->d_gl, gl.data(), gl.size() * sizeof(double4), hipMemcpyHostToDevice)))) ||
       (rc = hip_check(hipMemcpy(b->d_basis, basis.data(), basis.size() * sizeof(float), hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipMemcpy(b->d_upload, b->h_staging, b->upload_bytes, hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipFuncSetAttribute((const void*)batch_planes_kernel<32>,

@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 12
     for n in names:
         assert hasattr(lib, n), n
-    assert rw.abi_version() == 2
+    assert rw.abi_version() == 3
 
 
 def test_status_strings():

@@ -167,6 +167,47 @@ def test_batched_full_workload_sampled(lib):
         assert rel_l2(In[off[i]:off[i + 1]].reshape(D, S, S), ref) < TOL, (i, S, D)
 
 
+def test_batched_gibson_lanni_per_emitter_depth(lib):
+    # each emitter carries its own depth below the coverslip: against the FP64 oracle
+    # (fields and intensity) and against plain Fourier-form plans with the same layer
+    import torch
+    rw = lib
+    w = W.batched(n_emitters=8, seed=38)
+    w["gl"] = dict(W.GIBSON_LANNI)
+    o = w["optics"]
+    b = rw.Batch(na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], pixel=w["dx"], plane_pitch=w["dz"],
+                 max_emitters=8, n_pupil=w["n_pupil"], e_inc=w["e_inc"], gibson_lanni=w["gl"])
+    crops, planes = np.array([24, 33, 64, 40, 1, 47, 32, 60]), np.array([3, 2, 1, 2, 4, 1, 3, 2])
+    t_s = np.array([0.0, 5000.0, 1234.5, 2500.0, 800.0, 4100.0, 10.0, 3333.0])
+    idx = np.arange(8)
+    em = rw.make_emitters(w["x0"][idx], w["y0"][idx], w["z_e"][idx], crops, planes, w["zernike"][idx], t_s=t_s)
+    off = rw.batch_offsets(em)
+    I = torch.zeros(off[-1], dtype=torch.float32, device="cuda")
+    E = torch.zeros(3 * off[-1], dtype=torch.complex64, device="cuda")
+    b.compute(em, I=I, E=E)
+    torch.cuda.synchronize()
+    In, En = I.cpu().numpy(), E.cpu().numpy()
+    opt = oracle_optics(w)
+    for i in range(8):
+        S, D = int(crops[i]), int(planes[i])
+        z = (np.arange(D) - 0.5 * (D - 1)) * w["dz"] - w["z_e"][i]
+        ref = oracle_fourier_stack(opt, w["n_pupil"], S, S, w["dx"], w["dx"], z, zernike=w["zernike"][i],
+                                   t_s=t_s[i], x0=w["x0"][i], y0=w["y0"][i])
+        got_I = In[off[i]:off[i + 1]].reshape(D, S, S)
+        assert rel_l2(En[3 * off[i]:3 * off[i + 1]].reshape(D, 3, S, S), ref) < TOL, (i, S, D)
+        assert rel_l2(got_I, OF.intensity(ref)) < TOL, (i, S, D)
+        plan = rw.Plan(form=rw.FORM_FOURIER, na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], nx=S,
+                       ny=S, dx=w["dx"], dy=w["dx"], z=z + w["z_e"][i], e_inc=w["e_inc"], n_pupil=w["n_pupil"],
+                       gibson_lanni=w["gl"])
+        _, Ip = plan.compute([dict(x0=w["x0"][i], y0=w["y0"][i], z_offset=-w["z_e"][i], t_s=t_s[i],
+                                   zernike=w["zernike"][i])], fields=False)
+        torch.cuda.synchronize()
+        assert rel_l2(got_I, Ip[0].cpu().numpy()) < 2e-6, i
+    em_bad = rw.make_emitters(w["x0"][:1], w["y0"][:1], w["z_e"][:1], [24], [1], w["zernike"][:1], t_s=[-1.0])
+    with pytest.raises(rw.RwpsfError):
+        b.compute(em_bad, I=I)
+
+
 def test_batched_validation(lib):
     rw = lib
     w = W.batched(n_emitters=3, seed=37)
