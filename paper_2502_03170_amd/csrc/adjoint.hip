@@ -48,10 +48,15 @@ struct ScaledFieldLoader {
   const float2* E;
   const float* g;
   int ld, nrows, row0;
-  float4 v[PER_THREAD];
-  float2 f[PER_THREAD];
+  struct Regs {
+    float4 v[PER_THREAD];
+    float2 f[PER_THREAD];
+  };
 
-  __device__ void load(int k0, int tid) {
+  __device__ Regs load(int k0, int tid) const {
+    Regs r;
+    float4* v = r.v;
+    float2* f = r.f;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
@@ -63,8 +68,11 @@ struct ScaledFieldLoader {
       const float keep = (row0 + row < nrows) ? 2.f : 0.f;
       f[i] = make_float2(keep * gg.x, keep * gg.y);
     }
+    return r;
   }
-  __device__ void store(float* dst, int tid) const {
+  __device__ void store(float* dst, int tid, const Regs& r) const {
+    const float4* v = r.v;
+    const float2* f = r.f;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
@@ -110,7 +118,7 @@ __global__ void __launch_bounds__(CfgAdjH::NT, 2) adj_h_kernel(AdjHArgs a) {
   lb.ld = a.nyp;
   RgAcc<Cfg> acc;
   acc.zero();
-  rg_mainloop<Cfg>(acc, la, lb, 0, a.ny, lds, tid, wrow, wcol, lane);
+  rg_mainloop<Cfg, true>(acc, la, lb, 0, a.ny, lds, tid, wrow, wcol, lane);
   // rows 2m + ri: registers r and r + 1 (r even) are the re/im parts of one H'[m][col]
   float2* H = a.H + (size_t)item * a.nxp * a.w;
 #pragma unroll
@@ -144,7 +152,8 @@ __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
 }
 
-__global__ void __launch_bounds__(CfgAdjG::NT, 2) adj_g_kernel(AdjGArgs a) {
+// at most 168 VGPRs, so that three 4-wave workgroups share a CU
+__global__ void __launch_bounds__(CfgAdjG::NT, 3) adj_g_kernel(AdjGArgs a) {
   using Cfg = CfgAdjG;
   extern __shared__ float lds[];
   const int tiles_m = a.w / Cfg::BM, tiles_n = 2 * a.w / Cfg::BN;
@@ -205,7 +214,7 @@ __global__ void __launch_bounds__(CfgAdjG::NT, 2) adj_g_kernel(AdjGArgs a) {
     lb.ld = 2 * a.w;
     RgAcc<Cfg> acc;
     acc.zero();
-    rg_mainloop<Cfg>(acc, la, lb, 0, a.nxp, lds, tid, wrow, wcol, lane);
+    rg_mainloop<Cfg, false>(acc, la, lb, 0, a.nxp, lds, tid, wrow, wcol, lane);
     const float2* Dz = a.D + (size_t)zi * npp;
 #pragma unroll
     for (int i = 0; i < Cfg::TM; ++i)

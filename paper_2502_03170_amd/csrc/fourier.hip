@@ -150,22 +150,29 @@ struct FoldDefocusLoader {
   const double* kszf;  // [nhp][nhp], from row jf0
   double z;
   int w, nhp;          // w = 2 nhp
-  float4 v0[PER_THREAD], v1[PER_THREAD];
-  double kz[PER_THREAD];
+  struct Regs {
+    float4 v0[PER_THREAD], v1[PER_THREAD];
+    double kz[PER_THREAD];
+  };
 
-  __device__ void load(int k0, int tid) {
+  __device__ Regs load(int k0, int tid) const {
+    Regs r;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
       const int jl = idx / LF, ll = idx % LF;
       const size_t off = (size_t)(2 * jl) * w + k0 + 2 * ll;
-      v0[i] = *reinterpret_cast<const float4*>(Pf + off);       // pj = 0, pl = 0, 1
-      v1[i] = *reinterpret_cast<const float4*>(Pf + off + w);   // pj = 1
-      kz[i] = kszf[(size_t)jl * nhp + k0 / 2 + ll];
+      r.v0[i] = *reinterpret_cast<const float4*>(Pf + off);       // pj = 0, pl = 0, 1
+      r.v1[i] = *reinterpret_cast<const float4*>(Pf + off + w);   // pj = 1
+      r.kz[i] = kszf[(size_t)jl * nhp + k0 / 2 + ll];
     }
+    return r;
   }
   // LDS tile [row][k]: rows 4 jl + 2 pj + ri, columns 2 ll + pl
-  __device__ void store(float* dst, int tid) const {
+  __device__ void store(float* dst, int tid, const Regs& r) const {
+    const float4* v0 = r.v0;
+    const float4* v1 = r.v1;
+    const double* kz = r.kz;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
@@ -286,7 +293,8 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_pupil_kernel(Gemm1Args a) {
   }
   RgAcc<Cfg> acc;
   acc.zero();
-  rg_mainloop<Cfg>(acc, la, lb, k_begin, k_end, lds, tid, wrow, wcol, lane);
+  // unordered: the compiler's interleaving of the defocus arithmetic measured faster here
+  rg_mainloop<Cfg, false>(acc, la, lb, k_begin, k_end, lds, tid, wrow, wcol, lane);
 
   // rows 2q + ri: registers r and r + 1 (r even) are the re/im parts of one T[q][n]
   float2* T = a.T + (((size_t)s * a.nzs + zi) * a.nc + c) * (size_t)w * a.nyp;
@@ -306,67 +314,95 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_pupil_kernel(Gemm1Args a) {
 // K3: E'[m][(n, ri)] = sum_kk A2[m][kk] T[kk][(n, ri)] with A2[m][2jf] = pref cos(k s_jf x_m),
 // A2[m][2jf+1] = pref sin(...) for all channels in one workgroup; E = -i E' and
 // I = sum_c |E_c|^2 are written from registers.
-template <class Cfg, int OCC>
-__global__ void __launch_bounds__(Cfg::NT, OCC) gemm_image_kernel(Gemm2Args a) {
-  extern __shared__ float lds[];
+// One channel of an output tile of K3: the GEMM (its first stage already in ra, rb),
+// then the next channel's first stage is loaded, then this channel's fields are stored
+// and its intensity accumulated.  The loads go first so that the wait before they are
+// staged in LDS does not also wait for the stores.
+template <class Cfg, bool FULL, bool HAS_E, class LA, class LB>
+__device__ __forceinline__ void image_channel(const Gemm2Args& a, float* lds, int c, const LA& la, LB& lb,
+                                              typename LA::Regs& ra, typename LB::Regs& rb, const float* tsrc,
+                                              size_t tch, float* E, int row0, int col0, float (*isum)[Cfg::TN][8]) {
   const int w = 2 * a.nhp;
-  const int tiles_m = a.nxp / Cfg::BM;
-  const int tiles_n = 2 * a.nyp / Cfg::BN;
-  const int nblocks = a.nstk * a.nzs * tiles_m * tiles_n;
-  int id = xcd_remap(blockIdx.x, nblocks);
-  const int tn = id % tiles_n; id /= tiles_n;
-  const int tm = id % tiles_m; id /= tiles_m;
-  const int zi = id % a.nzs; id /= a.nzs;
-  const int s = id;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wrow = (wave / Cfg::WAVES_N) * Cfg::WM, wcol = (wave % Cfg::WAVES_N) * Cfg::WN;
+  const int ri = lane & 1;   // columns alternate re/im with the lane index
+  RgAcc<Cfg> acc;
+  acc.zero();
+  rg_mainloop_pre<Cfg, true>(acc, la, lb, ra, rb, 0, w, lds, tid, wrow, wcol, lane);
+  // first stage of the next channel (the last channel reloads its own, unused)
+  lb.src = tsrc + (size_t)min(c + 1, a.nc - 1) * tch;
+  ra = la.load(0, tid);
+  rb = lb.load(0, tid);
+  __builtin_amdgcn_sched_barrier(0);
+
+  // Lane 2t holds Re E' and lane 2t+1 Im E' of one pixel: E = -i E' = (Im E', -Re E'),
+  // so the odd lane writes E.x = v and the even lane E.y = -v.  A DPP swap within lane
+  // pairs gives each lane its partner's value for the intensity.
+  // The store offsets are the same for every channel; keeping them opaque here stops
+  // them from being hoisted out of the channel loop (32 live offsets would spill).
+  int mbase = row0 + rg_row(wrow, 0, 0, lane);
+  asm volatile("" : "+v"(mbase));
+#pragma unroll
+  for (int i = 0; i < Cfg::TM; ++i)
+#pragma unroll
+    for (int jj = 0; jj < Cfg::TN; ++jj) {
+      const int n = (col0 + rg_col(wcol, jj, lane)) >> 1;
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        float q[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int rr = r + 8 * h;
+          const int m = mbase + 32 * i + (rr >> 2) * 8 + (rr & 3);
+          const float v = acc.c[i][jj][rr];
+          const float u = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+          q[h] = v * v + u * u;
+          if (HAS_E && (FULL || (m < a.nx && n < a.ny))) E[2 * ((size_t)m * a.ny + n) + 1 - ri] = ri ? v : -v;
+        }
+        isum[i][jj][r] += ri ? q[1] : q[0];
+      }
+    }
+}
+
+// One output tile of K3 for every channel.  FULL: the tile lies inside the nx x ny
+// image, so its stores need no per-lane bounds and run as straight-line code.  The
+// first channel is peeled so that every entry into the channel loop follows a batch of
+// stores issued after the loads it waits for.
+template <class Cfg, bool FULL, bool HAS_E>
+__device__ __forceinline__ void image_tile(const Gemm2Args& a, float* lds, int s, int zi, int row0, int col0) {
+  const int w = 2 * a.nhp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wrow = (wave / Cfg::WAVES_N) * Cfg::WM, wcol = (wave % Cfg::WAVES_N) * Cfg::WN;
   const size_t plane = (size_t)a.nx * a.ny;
   const size_t gstk = (size_t)(a.s_base + s), gz = (size_t)(a.z0 + zi);
-  const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
-  const int ri = lane & 1;   // columns alternate re/im with the lane index
+  const int ri = lane & 1;
 
-  float isum[Cfg::TM][Cfg::TN][16];
+  // intensity of the lane pair's 16 pixels per block: the even lane keeps those of
+  // registers 0-7, the odd lane those of registers 8-15
+  float isum[Cfg::TM][Cfg::TN][8];
 #pragma unroll
   for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
     for (int jj = 0; jj < Cfg::TN; ++jj)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) isum[i][jj][r] = 0.f;
+      for (int r = 0; r < 8; ++r) isum[i][jj][r] = 0.f;
 
+  RRowLoader<Cfg, Cfg::BM> la;
+  la.src = a.A2 + (size_t)row0 * w;
+  la.ld = w;
+  RColLoader<Cfg, Cfg::BN> lb;
+  const float* tsrc = reinterpret_cast<const float*>(a.T + ((size_t)s * a.nzs + zi) * a.nc * (size_t)w * a.nyp) + col0;
+  const size_t tch = 2 * (size_t)w * a.nyp;   // floats per channel of T
+  lb.src = tsrc;
+  lb.ld = 2 * a.nyp;
+  auto ra = la.load(0, tid);
+  auto rb = lb.load(0, tid);
+  float* E0 = HAS_E ? reinterpret_cast<float*>(a.E + (gstk * a.nz + gz) * a.nc * plane) : nullptr;
+  image_channel<Cfg, FULL, HAS_E>(a, lds, 0, la, lb, ra, rb, tsrc, tch, E0, row0, col0, isum);
 #pragma unroll 1
-  for (int c = 0; c < a.nc; ++c) {
-    RRowLoader<Cfg, Cfg::BM> la;
-    la.src = a.A2 + (size_t)row0 * w;
-    la.ld = w;
-    RColLoader<Cfg, Cfg::BN> lb;
-    lb.src = reinterpret_cast<const float*>(a.T + (((size_t)s * a.nzs + zi) * a.nc + c) * (size_t)w * a.nyp) + col0;
-    lb.ld = 2 * a.nyp;
-    RgAcc<Cfg> acc;
-    acc.zero();
-    rg_mainloop<Cfg>(acc, la, lb, 0, w, lds, tid, wrow, wcol, lane);
-
-    // Lanes 2t and 2t+1 hold Re E' and Im E' of one pixel; a DPP swap within lane pairs
-    // gives the even lane both, and it writes E = -i E' = (Im E', -Re E') as one float2.
-    float2* E = a.E ? a.E + ((gstk * a.nz + gz) * a.nc + c) * plane : nullptr;
-    // the store offsets are the same for every component; keeping them opaque here stops
-    // them from being hoisted out of the component loop (32 live offsets would spill)
-    int mbase = row0 + rg_row(wrow, 0, 0, lane);
-    asm volatile("" : "+v"(mbase));
-#pragma unroll
-    for (int i = 0; i < Cfg::TM; ++i)
-#pragma unroll
-      for (int jj = 0; jj < Cfg::TN; ++jj) {
-        const int n = (col0 + rg_col(wcol, jj, lane)) >> 1;
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = mbase + 32 * i + (r >> 2) * 8 + (r & 3);
-          const float v = acc.c[i][jj][r];
-          const float u = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
-          isum[i][jj][r] += v * v + u * u;
-          if (E && !ri && m < a.nx && n < a.ny) E[m * a.ny + n] = make_float2(u, -v);
-        }
-      }
-  }
+  for (int c = 1; c < a.nc; ++c)
+    image_channel<Cfg, FULL, HAS_E>(a, lds, c, la, lb, ra, rb, tsrc, tch, HAS_E ? E0 + 2 * c * plane : nullptr,
+                                    row0, col0, isum);
   if (a.I) {
     float* I = a.I + (gstk * a.nz + gz) * plane;
 #pragma unroll
@@ -375,11 +411,37 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_image_kernel(Gemm2Args a) {
       for (int jj = 0; jj < Cfg::TN; ++jj) {
         const int n = (col0 + rg_col(wcol, jj, lane)) >> 1;
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int m = row0 + rg_row(wrow, i, r, lane);
-          if (!ri && m < a.nx && n < a.ny) I[m * a.ny + n] = isum[i][jj][r];
+        for (int r = 0; r < 8; ++r) {
+          const int m = row0 + rg_row(wrow, i, r + 8 * ri, lane);
+          if (FULL || (m < a.nx && n < a.ny)) I[(size_t)m * a.ny + n] = isum[i][jj][r];
         }
       }
+  }
+}
+
+template <class Cfg, int OCC>
+__global__ void __launch_bounds__(Cfg::NT, OCC) gemm_image_kernel(Gemm2Args a) {
+  extern __shared__ float lds[];
+  const int tiles_m = a.nxp / Cfg::BM;
+  const int tiles_n = 2 * a.nyp / Cfg::BN;
+  const int nblocks = a.nstk * a.nzs * tiles_m * tiles_n;
+  int id = xcd_remap(blockIdx.x, nblocks);
+  const int tn = id % tiles_n; id /= tiles_n;
+  const int tm = id % tiles_m; id /= tiles_m;
+  const int zi = id % a.nzs; id /= a.nzs;
+  const int s = id;
+  const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
+  const bool full = row0 + Cfg::BM <= a.nx && col0 + Cfg::BN <= 2 * a.ny;
+  if (a.E) {
+    if (full)
+      image_tile<Cfg, true, true>(a, lds, s, zi, row0, col0);
+    else
+      image_tile<Cfg, false, true>(a, lds, s, zi, row0, col0);
+  } else {
+    if (full)
+      image_tile<Cfg, true, false>(a, lds, s, zi, row0, col0);
+    else
+      image_tile<Cfg, false, false>(a, lds, s, zi, row0, col0);
   }
 }
 

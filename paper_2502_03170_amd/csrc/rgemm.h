@@ -8,7 +8,8 @@
 // instruction t takes k = 8u + t from lanes 0-31 and k = 8u + 4 + t from lanes 32-63,
 // for A and B alike, so every k of the stage is summed once.  Two LDS stages: the
 // global loads of stage k+1 are issued before the MFMAs of stage k and written to
-// LDS after them.
+// LDS after them; the loaders return the staged data by value, so it stays in
+// registers (a loader holding it in a member array ends up in scratch memory).
 //
 // MFMA 32x32x2 f32 lane layout (wave64): A operand lane l holds A[l%32][k(l/32)],
 // B operand lane l holds B[k(l/32)][l%32]; accumulator register r of lane l holds
@@ -48,24 +49,28 @@ struct RRowLoader {
   static constexpr int PER_THREAD = (TOTAL + Cfg::NT - 1) / Cfg::NT;   // the last round may be partial
   const float* src;  // already offset to row r0
   int ld;
-  float4 v[PER_THREAD];
+  struct Regs {
+    float4 v[PER_THREAD];
+  };
 
-  __device__ void load(int k0, int tid) {
+  __device__ Regs load(int k0, int tid) const {
+    Regs r;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
       if (TOTAL % Cfg::NT != 0 && idx >= TOTAL) break;
       const int row = idx / QUADS, kq = 4 * (idx % QUADS);
-      v[i] = *reinterpret_cast<const float4*>(src + (size_t)row * ld + k0 + kq);
+      r.v[i] = *reinterpret_cast<const float4*>(src + (size_t)row * ld + k0 + kq);
     }
+    return r;
   }
-  __device__ void store(float* dst, int tid) const {
+  __device__ void store(float* dst, int tid, const Regs& r) const {
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
       if (TOTAL % Cfg::NT != 0 && idx >= TOTAL) break;
       const int row = idx / QUADS, kq = 4 * (idx % QUADS);
-      *reinterpret_cast<float4*>(dst + row * Cfg::LDK + kq) = v[i];
+      *reinterpret_cast<float4*>(dst + row * Cfg::LDK + kq) = r.v[i];
     }
   }
 };
@@ -82,20 +87,26 @@ struct RColLoader {
   static constexpr int PER_THREAD = (TOTAL + Cfg::NT - 1) / Cfg::NT;   // the last round may be partial
   const float* src;  // already offset to row r0
   int ld;
-  float4 v0[PER_THREAD], v1[PER_THREAD];
+  struct Regs {
+    float4 v0[PER_THREAD], v1[PER_THREAD];
+  };
 
-  __device__ void load(int k0, int tid) {
+  __device__ Regs load(int k0, int tid) const {
+    Regs r;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
       if (TOTAL % Cfg::NT != 0 && idx >= TOTAL) break;
       const int kk = 2 * (idx % KPAIRS), rq = 4 * (idx / KPAIRS);
       const float* p = src + (size_t)(k0 + kk) * ld + rq;
-      v0[i] = *reinterpret_cast<const float4*>(p);
-      v1[i] = *reinterpret_cast<const float4*>(p + ld);
+      r.v0[i] = *reinterpret_cast<const float4*>(p);
+      r.v1[i] = *reinterpret_cast<const float4*>(p + ld);
     }
+    return r;
   }
-  __device__ void store(float* dst, int tid) const {
+  __device__ void store(float* dst, int tid, const Regs& r) const {
+    const float4* v0 = r.v0;
+    const float4* v1 = r.v1;
 #pragma unroll
     for (int i = 0; i < PER_THREAD; ++i) {
       const int idx = tid + i * Cfg::NT;
@@ -160,34 +171,50 @@ __device__ __forceinline__ void rg_stage_mma(RgAcc<Cfg>& acc, const float* a, co
   }
 }
 
-// K loop over [k_begin, k_end) (multiples of BK, k_end > k_begin) with double-buffered LDS.
-// The loaders provide load(k0, tid) and store(lds_tile, tid).
-template <class Cfg, class ALoader, class BLoader>
-__device__ __forceinline__ void rg_mainloop(RgAcc<Cfg>& acc, ALoader& la, BLoader& lb, int k_begin, int k_end,
-                                            float* lds, int tid, int wrow, int wcol, int lane) {
+// K loop whose first stage (k_begin) the caller has already loaded into registers
+// (ra0, rb0), so that a caller can issue those loads before other memory work.
+// The last stage is peeled so that the loop body has no branch around the loads and
+// stores (a conditional there leaves the staged registers in scratch memory).  ORDERED
+// adds scheduling barriers that keep the order loads / MFMAs / stores: without them
+// the compiler may sink the global loads to their LDS stores, or hoist the loader's
+// arithmetic into the MFMA stream, and a wave then waits on global memory once per
+// stage.  Which order is faster depends on the loader (measured per kernel).
+template <class Cfg, bool ORDERED, class ALoader, class BLoader>
+__device__ __forceinline__ void rg_mainloop_pre(RgAcc<Cfg>& acc, const ALoader& la, const BLoader& lb,
+                                                const typename ALoader::Regs& ra0,
+                                                const typename BLoader::Regs& rb0, int k_begin, int k_end,
+                                                float* lds, int tid, int wrow, int wcol, int lane) {
   // stage pointers by arithmetic on the __shared__ base (a pointer picked from a
   // local array loses its address space and turns the LDS reads into flat loads)
   const int KT = (k_end - k_begin) / Cfg::BK;
-  la.load(k_begin, tid);
-  lb.load(k_begin, tid);
-  la.store(lds, tid);
-  lb.store(lds + Cfg::A_FLOATS, tid);
+  la.store(lds, tid, ra0);
+  lb.store(lds + Cfg::A_FLOATS, tid, rb0);
   __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
+  for (int kt = 0; kt < KT - 1; ++kt) {
     float* cur = lds + (kt & 1) * Cfg::STAGE_FLOATS;
     float* nxt = lds + ((kt + 1) & 1) * Cfg::STAGE_FLOATS;
-    const bool more = kt + 1 < KT;
-    if (more) {
-      la.load(k_begin + (kt + 1) * Cfg::BK, tid);
-      lb.load(k_begin + (kt + 1) * Cfg::BK, tid);
-    }
+    const auto ra = la.load(k_begin + (kt + 1) * Cfg::BK, tid);
+    const auto rb = lb.load(k_begin + (kt + 1) * Cfg::BK, tid);
+    if constexpr (ORDERED) __builtin_amdgcn_sched_barrier(0);
     rg_stage_mma<Cfg>(acc, cur, cur + Cfg::A_FLOATS, wrow, wcol, lane);
-    if (more) {
-      la.store(nxt, tid);
-      lb.store(nxt + Cfg::A_FLOATS, tid);
-    }
+    if constexpr (ORDERED) __builtin_amdgcn_sched_barrier(0);
+    la.store(nxt, tid, ra);
+    lb.store(nxt + Cfg::A_FLOATS, tid, rb);
     __syncthreads();
   }
+  float* last = lds + ((KT - 1) & 1) * Cfg::STAGE_FLOATS;
+  rg_stage_mma<Cfg>(acc, last, last + Cfg::A_FLOATS, wrow, wcol, lane);
+  __syncthreads();
+}
+
+// K loop over [k_begin, k_end) (multiples of BK, k_end > k_begin) with double-buffered
+// LDS.  The loaders provide Regs load(k0, tid) and store(lds_tile, tid, regs).
+template <class Cfg, bool ORDERED, class ALoader, class BLoader>
+__device__ __forceinline__ void rg_mainloop(RgAcc<Cfg>& acc, const ALoader& la, const BLoader& lb, int k_begin,
+                                            int k_end, float* lds, int tid, int wrow, int wcol, int lane) {
+  const auto ra = la.load(k_begin, tid);
+  const auto rb = lb.load(k_begin, tid);
+  rg_mainloop_pre<Cfg, ORDERED>(acc, la, lb, ra, rb, k_begin, k_end, lds, tid, wrow, wcol, lane);
 }
 
 // Row/column of accumulator register r in 32 x 32 block (i, j) of this wave.
