@@ -204,26 +204,45 @@ __global__ void __launch_bounds__(CfgAdjG::NT, 3) adj_g_kernel(AdjGArgs a) {
     for (int jj = 0; jj < Cfg::TN; ++jj)
 #pragma unroll
       for (int r = 0; r < 8; ++r) dphi[i][jj][r] = 0.f;
+  RRowLoader<Cfg, Cfg::BM> la;
+  la.src = a.CxT + (size_t)row0 * a.nxp;
+  la.ld = a.nxp;
+  RColLoader<Cfg, Cfg::BN> lb;
+  const float* hsrc = reinterpret_cast<const float*>(a.H) + col0;
+  const size_t hplane = 2 * (size_t)a.nxp * a.w;   // floats per (stack, plane, channel) of H
+  lb.src = hsrc + ((size_t)(s * a.nz + z_begin) * 3 + c) * hplane;
+  lb.ld = 2 * a.w;
+  auto ra = la.load(0, tid);
+  auto rb = lb.load(0, tid);
 #pragma unroll 1
   for (int zi = z_begin; zi < z_end; ++zi) {
-    RRowLoader<Cfg, Cfg::BM> la;
-    la.src = a.CxT + (size_t)row0 * a.nxp;
-    la.ld = a.nxp;
-    RColLoader<Cfg, Cfg::BN> lb;
-    lb.src = reinterpret_cast<const float*>(a.H + ((size_t)(s * a.nz + zi) * 3 + c) * a.nxp * a.w) + col0;
-    lb.ld = 2 * a.w;
     RgAcc<Cfg> acc;
     acc.zero();
-    rg_mainloop<Cfg, false>(acc, la, lb, 0, a.nxp, lds, tid, wrow, wcol, lane);
+    rg_mainloop_pre<Cfg, false>(acc, la, lb, ra, rb, 0, a.nxp, lds, tid, wrow, wcol, lane);
+    // the next plane's first stage (the last plane reloads its own, unused) is loaded
+    // before this plane's epilogue, which hides its latency
+    lb.src = hsrc + ((size_t)(s * a.nz + min(zi + 1, z_end - 1)) * 3 + c) * hplane;
+    ra = la.load(0, tid);
+    rb = lb.load(0, tid);
+    // Per column block: the table cells of its 8 accumulator pairs (the lane's mirror
+    // cell, or cell 0 where the lane owns none: its p0 is zero there, so the product
+    // adds nothing) are all loaded before any is used.
     const float2* Dz = a.D + (size_t)zi * npp;
 #pragma unroll
     for (int i = 0; i < Cfg::TM; ++i)
 #pragma unroll
       for (int jj = 0; jj < Cfg::TN; ++jj) {
         const int lf = (col0 + rg_col(wcol, jj, lane)) >> 2;
+        float2 dz[8];
 #pragma unroll
         for (int r = 0; r < 16; r += 2) {
           const int jf = (row0 + rg_row(wrow, i, r, lane)) >> 1;
+          const int jc = (q & 2) ? n - 1 - jf : jf, lc = (q & 1) ? n - 1 - lf : lf;
+          const bool own = jf < nh && lf < nh && !((q & 2) && jc == jf) && !((q & 1) && lc == lf);
+          dz[r >> 1] = Dz[own ? jc * a.w + lc : 0];
+        }
+#pragma unroll
+        for (int r = 0; r < 16; r += 2) {
           // this lane holds row (jf, p = 0) in register r and (jf, 1) in r + 1, column q
           const float x0 = acc.c[i][jj][r], x1 = acc.c[i][jj][r + 1];
           // quad values: [q'] of register r -> C* , of register r + 1 -> S*
@@ -237,15 +256,11 @@ __global__ void __launch_bounds__(CfgAdjG::NT, 3) adj_g_kernel(AdjGArgs a) {
           const float tr = c0 - sl * c3 - sj * s1 + ss * s2;
           const float ti = c1 + sl * c2 + sj * s0 + ss * s3;
           const float gr = -ti, gi = tr;
-          const int jc = (q & 2) ? n - 1 - jf : jf, lc = (q & 1) ? n - 1 - lf : lf;
-          const bool own = jf < nh && lf < nh && !((q & 2) && jc == jf) && !((q & 1) && lc == lf);
-          if (own) {
-            const float2 d = Dz[(size_t)jc * a.w + lc];
-            const float2 pv = p0[i][jj][r >> 1];
-            const float pr = pv.x * d.x - pv.y * d.y, pi = pv.x * d.y + pv.y * d.x;
-            // Im(G conj(P~)) = Gi Pr - Gr Pi
-            dphi[i][jj][r >> 1] += gi * pr - gr * pi;
-          }
+          const float2 d = dz[r >> 1];
+          const float2 pv = p0[i][jj][r >> 1];
+          const float pr = pv.x * d.x - pv.y * d.y, pi = pv.x * d.y + pv.y * d.x;
+          // Im(G conj(P~)) = Gi Pr - Gr Pi
+          dphi[i][jj][r >> 1] += gi * pr - gr * pi;
         }
       }
   }

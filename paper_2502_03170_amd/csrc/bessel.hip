@@ -565,35 +565,42 @@ struct AdjRadArgs {
 // combination), G_E = 2 (dL/dI) E; p[0..5] = (P_0, P_1, P_2) as re, im.
 __device__ __forceinline__ void adjb_project(const AdjRadArgs& a, bool scalar, const float2* Eb, size_t plane,
                                              float g2, int pix, float x, float y, float rho, float p[6]) {
+  // computed into scalars and stored once, so that p stays in registers
+  float p0, p1, p2 = 0.f, p3 = 0.f, p4 = 0.f, p5 = 0.f;
   if (scalar) {
     const float2 e = Eb[pix];
     const float gr = g2 * e.x, gi = g2 * e.y;
-    p[0] = a.exr * gr + a.exi * gi;    // conj(pref) G
-    p[1] = a.exr * gi - a.exi * gr;
-    p[2] = p[3] = p[4] = p[5] = 0.f;
-    return;
+    p0 = a.exr * gr + a.exi * gi;    // conj(pref) G
+    p1 = a.exr * gi - a.exi * gr;
+  } else {
+    const float2 ex = Eb[pix], ey = Eb[plane + pix], ez = Eb[2 * plane + pix];
+    const float gxr = g2 * ex.x, gxi = g2 * ex.y, gyr = g2 * ey.x, gyi = g2 * ey.y;
+    const float gzr = g2 * ez.x, gzi = g2 * ez.y;
+    float c1 = 1.f, s1 = 0.f;
+    if (rho > 0.f) {
+      c1 = x / rho;
+      s1 = y / rho;
+    }
+    const float c2 = c1 * c1 - s1 * s1, s2 = 2.f * s1 * c1;
+    // P0 = conj(ex) Gx + conj(ey) Gy
+    p0 = a.exr * gxr + a.exi * gxi + a.eyr * gyr + a.eyi * gyi;
+    p1 = a.exr * gxi - a.exi * gxr + a.eyr * gyi - a.eyi * gyr;
+    // P1 = 2i conj(ex c1 + ey s1) Gz
+    const float qr = a.exr * c1 + a.eyr * s1, qi = a.exi * c1 + a.eyi * s1;
+    p2 = -2.f * (qr * gzi - qi * gzr);
+    p3 = 2.f * (qr * gzr + qi * gzi);
+    // P2 = conj(-(ex c2 + ey s2)) Gx + conj(-ex s2 + ey c2) Gy
+    const float ur = -(a.exr * c2 + a.eyr * s2), ui = -(a.exi * c2 + a.eyi * s2);
+    const float vr = -a.exr * s2 + a.eyr * c2, vi = -a.exi * s2 + a.eyi * c2;
+    p4 = ur * gxr + ui * gxi + vr * gyr + vi * gyi;
+    p5 = ur * gxi - ui * gxr + vr * gyi - vi * gyr;
   }
-  const float2 ex = Eb[pix], ey = Eb[plane + pix], ez = Eb[2 * plane + pix];
-  const float gxr = g2 * ex.x, gxi = g2 * ex.y, gyr = g2 * ey.x, gyi = g2 * ey.y;
-  const float gzr = g2 * ez.x, gzi = g2 * ez.y;
-  float c1 = 1.f, s1 = 0.f;
-  if (rho > 0.f) {
-    c1 = x / rho;
-    s1 = y / rho;
-  }
-  const float c2 = c1 * c1 - s1 * s1, s2 = 2.f * s1 * c1;
-  // P0 = conj(ex) Gx + conj(ey) Gy
-  p[0] = a.exr * gxr + a.exi * gxi + a.eyr * gyr + a.eyi * gyi;
-  p[1] = a.exr * gxi - a.exi * gxr + a.eyr * gyi - a.eyi * gyr;
-  // P1 = 2i conj(ex c1 + ey s1) Gz
-  const float qr = a.exr * c1 + a.eyr * s1, qi = a.exi * c1 + a.eyi * s1;
-  p[2] = -2.f * (qr * gzi - qi * gzr);
-  p[3] = 2.f * (qr * gzr + qi * gzi);
-  // P2 = conj(-(ex c2 + ey s2)) Gx + conj(-ex s2 + ey c2) Gy
-  const float ur = -(a.exr * c2 + a.eyr * s2), ui = -(a.exi * c2 + a.eyi * s2);
-  const float vr = -a.exr * s2 + a.eyr * c2, vi = -a.exi * s2 + a.eyi * c2;
-  p[4] = ur * gxr + ui * gxi + vr * gyr + vi * gyi;
-  p[5] = ur * gxi - ui * gxr + vr * gyi - vi * gyr;
+  p[0] = p0;
+  p[1] = p1;
+  p[2] = p2;
+  p[3] = p3;
+  p[4] = p4;
+  p[5] = p5;
 }
 
 // One workgroup per (stack, plane).  Every pixel adds w_k P_n to the four radial samples
@@ -626,6 +633,7 @@ __global__ void __launch_bounds__(256) adjb_radial_kernel(AdjRadArgs a, const fl
     const float x = (float)(i - a.nx / 2) * a.dx - x0, y = (float)(j - a.ny / 2) * a.dy - y0;
     float p[6];
     adjb_project(a, scalar, Eb, plane, 2.f * Lb[pix], pix, x, y, sqrtf(x * x + y * y), p);
+#pragma unroll
     for (int e = 0; e < 6; ++e) mx = fmaxf(mx, fabsf(p[e]));
   }
   red[tid] = mx;
@@ -648,16 +656,15 @@ __global__ void __launch_bounds__(256) adjb_radial_kernel(AdjRadArgs a, const fl
                           -(f + 1.f) * f * (f - 2.f) * 0.5f, (f + 1.f) * f * (f - 1.f) * (1.f / 6.f)};
       float p[6];
       adjb_project(a, scalar, Eb, plane, 2.f * Lb[pix], pix, x, y, rho, p);
+      // fully unrolled, so that w, p and the signs stay in registers
+#pragma unroll
       for (int k = 0; k < 4; ++k) {
-        int r = r0 - 1 + k;
-        float sg[6] = {1.f, 1.f, 1.f, 1.f, 1.f, 1.f};
-        if (r < 0) {               // node -1: I_n(-rho) = (-1)^n I_n(rho)
-          r = 1;
-          sg[2] = sg[3] = -1.f;
-        }
-        long long* d = accq + 6 * r;
+        const bool ghost = r0 - 1 + k < 0;   // node -1: I_n(-rho) = (-1)^n I_n(rho)
+        long long* d = accq + 6 * (ghost ? 1 : r0 - 1 + k);
+#pragma unroll
         for (int e = 0; e < 6; ++e) {
-          const long long v = llrint((double)(sg[e] * w[k] * p[e]) * scale);
+          const float sg = (ghost && (e == 2 || e == 3)) ? -1.f : 1.f;
+          const long long v = llrint((double)(sg * w[k] * p[e]) * scale);
           if (v) atomicAdd(reinterpret_cast<unsigned long long*>(d + e), (unsigned long long)v);
         }
       }
@@ -669,6 +676,7 @@ __global__ void __launch_bounds__(256) adjb_radial_kernel(AdjRadArgs a, const fl
   const int col = (si * a.nz + zi) * V;
   for (int r = tid; r < R; r += blockDim.x) {
     float g[6];
+#pragma unroll
     for (int e = 0; e < 6; ++e) g[e] = (float)((double)accq[6 * r + e] * inv);
     auto put = [&](int v, int gg, float re, float im) {
       float* d = GInT + (size_t)(gg * R + r) * a.M + 2 * (col + v);
@@ -687,7 +695,9 @@ __global__ void __launch_bounds__(256) adjb_radial_kernel(AdjRadArgs a, const fl
       put(0, 3, 0.f, 0.f);
       put(1, 4, 0.f, 0.f);
     } else {
-      for (int n = 0; n < NI; ++n) put(0, n, g[2 * n], g[2 * n + 1]);
+#pragma unroll
+      for (int n = 0; n < 3; ++n)
+        if (n < NI) put(0, n, g[2 * n], g[2 * n + 1]);
     }
   }
 }

@@ -216,7 +216,7 @@ struct FoldDefocusLoader {
 #define RW_F2_BN 128
 #endif
 #ifndef RW_F2_BK
-#define RW_F2_BK 32
+#define RW_F2_BK 16
 #endif
 #ifndef RW_F2_WM
 #define RW_F2_WM 64
@@ -224,8 +224,9 @@ struct FoldDefocusLoader {
 #ifndef RW_F2_WN
 #define RW_F2_WN 32
 #endif
+// at most 128 VGPRs: two 8-wave workgroups per CU (one 16-byte value spills, once per tile)
 #ifndef RW_F2_OCC
-#define RW_F2_OCC 2
+#define RW_F2_OCC 4
 #endif
 using CfgPupil = RgCfg<RW_F1_BM, RW_F1_BN, RW_F1_BK, RW_F1_WM, RW_F1_WN>;
 using CfgImage = RgCfg<RW_F2_BM, RW_F2_BN, RW_F2_BK, RW_F2_WM, RW_F2_WN>;

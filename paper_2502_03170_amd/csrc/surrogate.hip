@@ -164,9 +164,16 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][j][r] = 0.f;
   // A: 128 rows x 32 k = 1024 float4, 4 per thread; B: 128 cols x 32 k bf16 = 512 x 16 B per plane
-  float4 ra[4];
-  uint4 rbh[2], rbl[2];
+  struct Staged {
+    float4 ra[4];
+    uint4 rbh[2], rbl[2];
+  };
+  // the staged tile is returned by value, so that it stays in registers
   auto load = [&](int k0) {
+    Staged g;
+    float4* ra = g.ra;
+    uint4* rbh = g.rbh;
+    uint4* rbl = g.rbl;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + 256 * i, r = idx >> 3, kq = 4 * (idx & 7);
@@ -179,8 +186,12 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
       rbh[i] = *reinterpret_cast<const uint4*>(Bhi + (size_t)(col0 + c) * K + k0 + k8);
       if (NSPLIT > 1) rbl[i] = *reinterpret_cast<const uint4*>(Blo + (size_t)(col0 + c) * K + k0 + k8);
     }
+    return g;
   };
-  auto store = [&](__bf16* st) {
+  auto store = [&](__bf16* st, const Staged& g) {
+    const float4* ra = g.ra;
+    const uint4* rbh = g.rbh;
+    const uint4* rbl = g.rbl;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + 256 * i, r = idx >> 3, kq = 4 * (idx & 7);
@@ -202,14 +213,7 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
     }
   };
   const int KT = K / FBK;
-  load(0);
-  store(shb);
-  __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
-    __bf16* cur = shb + (kt & 1) * STAGE;
-    __bf16* nxt = shb + ((kt + 1) & 1) * STAGE;
-    const bool more = kt + 1 < KT;
-    if (more) load((kt + 1) * FBK);
+  auto mma = [&](const __bf16* cur) {
 #pragma unroll
     for (int ks = 0; ks < FBK; ks += 16) {
       const int kb = ks + 8 * (lane >> 5);
@@ -237,9 +241,17 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
           }
         }
     }
-    if (more) store(nxt);
+  };
+  store(shb, load(0));
+  __syncthreads();
+  // the last stage is peeled, so that no branch surrounds the loads and stores
+  for (int kt = 0; kt < KT - 1; ++kt) {
+    const Staged g = load((kt + 1) * FBK);
+    mma(shb + (kt & 1) * STAGE);
+    store(shb + ((kt + 1) & 1) * STAGE, g);
     __syncthreads();
   }
+  mma(shb + ((KT - 1) & 1) * STAGE);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int n = col0 + wn + 32 * j + (lane & 31);
