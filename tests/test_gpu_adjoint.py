@@ -56,7 +56,7 @@ def _targets(w, shifts):
     return Y, scale
 
 
-@pytest.mark.parametrize("n_pupil,nx,nz,n_stacks", [(32, 16, 3, 2), (64, 32, 4, 3), (96, 48, 2, 9)])
+@pytest.mark.parametrize("n_pupil,nx,nz,n_stacks", [(32, 16, 3, 2), (64, 32, 4, 3), (96, 48, 2, 9), (45, 32, 3, 2)])
 def test_adjoint_matches_oracle_gradient(lib, n_pupil, nx, nz, n_stacks):
     import torch
     rw = lib
