@@ -485,17 +485,37 @@ static hipError_t gemm_image_launch(const Gemm2Args& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// Compute units of the current device (queried once per device).
+static int device_cus() {
+  static int cus[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cus[dev] == 0) {
+    int n = 0;
+    hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    cus[dev] = n > 0 ? n : 256;
+  }
+  return cus[dev];
+}
+
 // The tile height follows the padding the plan chose (multiples of 128, or of 64 for
-// outputs of at most 64 pixels along that axis).
+// outputs of at most 64 pixels along that axis).  A launch whose large tiles would give
+// fewer than two workgroups per CU (a few planes, e.g. one image) takes the small tiles
+// instead: its time is then set by how many CUs work on it, not by the tile efficiency.
 hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
-  if (a.nyp % CfgPupilL::BN == 0 && (4 * a.nhp) % CfgPupilL::BM == 0) return gemm_pupil_launch<CfgPupilL, 2>(a, st);
-  if (a.nyp % CfgPupil::BN == 0) return gemm_pupil_launch<CfgPupil, RW_F1_OCC>(a, st);
-  if ((4 * a.nhp) % CfgPupilSL::BM == 0) return gemm_pupil_launch<CfgPupilSL, 2>(a, st);
+  const long long work = (long long)a.nstk * a.nzs * a.nc;
+  const bool few = work * ((4 * a.nhp + 127) / 128) * ((a.nyp + 127) / 128) < 2LL * device_cus();
+  if (!few && a.nyp % CfgPupilL::BN == 0 && (4 * a.nhp) % CfgPupilL::BM == 0)
+    return gemm_pupil_launch<CfgPupilL, 2>(a, st);
+  if (!few && a.nyp % CfgPupil::BN == 0) return gemm_pupil_launch<CfgPupil, RW_F1_OCC>(a, st);
+  if (!few && (4 * a.nhp) % CfgPupilSL::BM == 0) return gemm_pupil_launch<CfgPupilSL, 2>(a, st);
   return gemm_pupil_launch<CfgPupilS, 4>(a, st);
 }
 
 hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st) {
-  if (a.nxp % CfgImage::BM == 0) return gemm_image_launch<CfgImage, RW_F2_OCC>(a, st);
+  const long long work = (long long)a.nstk * a.nzs;
+  const bool few = work * ((a.nxp + 127) / 128) * ((2 * a.nyp + 127) / 128) < 2LL * device_cus();
+  if (!few && a.nxp % CfgImage::BM == 0) return gemm_image_launch<CfgImage, RW_F2_OCC>(a, st);
   return gemm_image_launch<CfgImageS, 4>(a, st);
 }
 
