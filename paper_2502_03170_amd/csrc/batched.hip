@@ -152,12 +152,12 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
   const float2* Pf = a.Pf + (size_t)slot * 3 * NN;
   float* Ure = lds;
   float* Uim = lds + N * LDU;
-  const double z = (d - 0.5 * (bp.D - 1)) * a.pitch + bp.zoff;
-  // ---- defocus of this plane on the folded cells (FP64 phase, reduced mod 2 pi)
+  const double zrev = ((d - 0.5 * (bp.D - 1)) * a.pitch + bp.zoff) * (1.0 / kTwoPi);
+  // ---- defocus of this plane on the folded cells (FP64 phase in revolutions, reduced)
   for (int cell = tid; cell < nh * nh; cell += 256) {
     const int jf = cell / nh, lf = cell % nh;
     float sn, cs;
-    sincosf((float)reduce_2pi(a.ksz[jf * N + lf] * z), &sn, &cs);
+    sincos_rev(a.ksz[jf * N + lf] * zrev, &sn, &cs);
     Dz[cell] = make_float2(cs, sn);
   }
   // the defocus table was written by other waves of this workgroup

@@ -178,7 +178,7 @@ __global__ void __launch_bounds__(256) czt_rows_kernel(CztRowArgs a) {
   const bool live = j < a.n;   // a wave past the last row still takes part in the barriers
   float2* buf = cbuf + wave * padded<L>();
   const size_t npp = (size_t)a.np * a.np;
-  const double zz = a.z[a.z0 + zi] + a.zoff[s];
+  const double zrev = (a.z[a.z0 + zi] + a.zoff[s]) * (1.0 / kTwoPi);
   // defocus factors of this row, shared by the channels (N < L)
   constexpr int MAXT = L / 64;
   float2 dz[MAXT];
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(256) czt_rows_kernel(CztRowArgs a) {
     dz[t] = make_float2(0.f, 0.f);
     if (live && l < a.n) {
       float sn, cs;
-      sincosf((float)reduce_2pi(a.ksz[(size_t)j * a.np + l] * zz), &sn, &cs);
+      sincos_rev(a.ksz[(size_t)j * a.np + l] * zrev, &sn, &cs);
       dz[t] = cmul(make_float2(cs, sn), a.pre[l]);
     }
   }

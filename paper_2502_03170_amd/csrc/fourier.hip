@@ -139,7 +139,8 @@ __global__ void __launch_bounds__(256) pupil_fold_kernel(FoldArgs a) {
 // A operand of K2: rows 2q + ri (q = 2 jf + pj, ri = re/im) and contraction index
 // kk = 2 lf + pl of the folded pupil, with the defocus factor exp(i k s_z z) applied
 // on the way into LDS.  One thread takes one folded cell (jf, lf): its four values
-// share one defocus factor, formed in FP64 and reduced mod 2 pi before the FP32 sincos.
+// share one defocus factor, whose phase is formed and reduced in FP64 (in revolutions)
+// before the FP32 hardware sine and cosine.
 // --------------------------------------------------------------------------
 template <class Cfg>
 struct FoldDefocusLoader {
@@ -148,7 +149,7 @@ struct FoldDefocusLoader {
   static_assert(JF * LF % Cfg::NT == 0, "loader shape");
   const float2* Pf;    // [2 nhp][2 nhp] of this stack and component, from folded row jf0
   const double* kszf;  // [nhp][nhp], from row jf0
-  double z;
+  double zrev;         // z / 2 pi, so that k s_z zrev is the phase in revolutions
   int w, nhp;          // w = 2 nhp
   struct Regs {
     float4 v0[PER_THREAD], v1[PER_THREAD];
@@ -178,7 +179,7 @@ struct FoldDefocusLoader {
       const int idx = tid + i * Cfg::NT;
       const int jl = idx / LF, ll = idx % LF;
       float sn, cs;
-      sincosf((float)reduce_2pi(kz[i] * z), &sn, &cs);
+      sincos_rev(kz[i] * zrev, &sn, &cs);
       float* d = dst + (4 * jl) * Cfg::LDK + 2 * ll;
       *reinterpret_cast<float2*>(d) = make_float2(v0[i].x * cs - v0[i].y * sn, v0[i].z * cs - v0[i].w * sn);
       *reinterpret_cast<float2*>(d + Cfg::LDK) =
@@ -270,7 +271,7 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_pupil_kernel(Gemm1Args a) {
   FoldDefocusLoader<Cfg> la;
   la.Pf = a.Pf + ((size_t)s * a.nc + c) * fpp + (size_t)(2 * jf0) * w;
   la.kszf = a.kszf + (size_t)jf0 * a.nhp;
-  la.z = a.z[a.z0 + zi] + a.zoff[s];
+  la.zrev = (a.z[a.z0 + zi] + a.zoff[s]) * (1.0 / kTwoPi);
   la.w = w;
   la.nhp = a.nhp;
   RRowLoader<Cfg, Cfg::BN> lb;
@@ -492,8 +493,8 @@ static int device_cus() {
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
   if (cus[dev] == 0) {
     int n = 0;
-    hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
-    cus[dev] = n > 0 ? n : 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cus[dev] = n;
   }
   return cus[dev];
 }
