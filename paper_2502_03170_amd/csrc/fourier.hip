@@ -214,7 +214,7 @@ struct FoldDefocusLoader {
 #define RW_F2_BM 128
 #endif
 #ifndef RW_F2_BN
-#define RW_F2_BN 128
+#define RW_F2_BN 256
 #endif
 #ifndef RW_F2_BK
 #define RW_F2_BK 16
@@ -223,11 +223,10 @@ struct FoldDefocusLoader {
 #define RW_F2_WM 64
 #endif
 #ifndef RW_F2_WN
-#define RW_F2_WN 32
+#define RW_F2_WN 64
 #endif
-// at most 128 VGPRs: two 8-wave workgroups per CU (one 16-byte value spills, once per tile)
 #ifndef RW_F2_OCC
-#define RW_F2_OCC 4
+#define RW_F2_OCC 2
 #endif
 using CfgPupil = RgCfg<RW_F1_BM, RW_F1_BN, RW_F1_BK, RW_F1_WM, RW_F1_WN>;
 using CfgImage = RgCfg<RW_F2_BM, RW_F2_BN, RW_F2_BK, RW_F2_WM, RW_F2_WN>;
@@ -516,7 +515,8 @@ hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st) {
 hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st) {
   const long long work = (long long)a.nstk * a.nzs;
   const bool few = work * ((a.nxp + 127) / 128) * ((2 * a.nyp + 127) / 128) < 2LL * device_cus();
-  if (!few && a.nxp % CfgImage::BM == 0) return gemm_image_launch<CfgImage, RW_F2_OCC>(a, st);
+  if (!few && a.nxp % CfgImage::BM == 0 && (2 * a.nyp) % CfgImage::BN == 0)
+    return gemm_image_launch<CfgImage, RW_F2_OCC>(a, st);
   return gemm_image_launch<CfgImageS, 4>(a, st);
 }
 

@@ -26,7 +26,7 @@ def _fourier_plan(rw, w, n_pupil, nx, ny, dx, z, gl=True):
                    n_pupil=n_pupil)
 
 
-@pytest.mark.parametrize("n_pupil,nx,ny", [(40, 33, 29), (37, 20, 70), (130, 65, 131), (48, 200, 150)])
+@pytest.mark.parametrize("n_pupil,nx,ny", [(40, 33, 29), (37, 20, 70), (130, 65, 131), (48, 200, 150), (40, 90, 40)])
 def test_fourier_small_all_corrections(lib, n_pupil, nx, ny):
     import torch
     rw = lib
