@@ -155,14 +155,18 @@ static hipEvent_t pool_get(std::vector<hipEvent_t>& pool) {
 int rwpsf_plan::time_begin(int kernel, hipStream_t st) {
   if (!timing) return -1;
   TimingRec r{kernel, pool_get(event_pool), pool_get(event_pool)};
-  if (!r.a || !r.b) return -1;
-  hipEventRecord(r.a, st);
+  if (!r.a || !r.b || hipEventRecord(r.a, st) != hipSuccess) {   // this launch is then not timed
+    if (r.a) event_pool.push_back(r.a);
+    if (r.b) event_pool.push_back(r.b);
+    return -1;
+  }
   timing_recs.push_back(r);
   return (int)timing_recs.size() - 1;
 }
 
 void rwpsf_plan::time_end(int rec, hipStream_t st) {
-  if (rec >= 0) hipEventRecord(timing_recs[rec].b, st);
+  // a failed record leaves the end event unrecorded; timing_flush then skips this launch
+  if (rec >= 0) (void)hipEventRecord(timing_recs[rec].b, st);
 }
 
 void rwpsf_plan::timing_flush() {
@@ -178,13 +182,13 @@ void rwpsf_plan::timing_flush() {
   timing_recs.clear();
 }
 
-rwpsf_plan::~rwpsf_plan() {
+rwpsf_plan::~rwpsf_plan() {   // teardown: failures cannot be reported and are ignored
   for (TimingRec& r : timing_recs) {
-    hipEventDestroy(r.a);
-    hipEventDestroy(r.b);
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
   }
-  for (hipEvent_t e : event_pool) hipEventDestroy(e);
-  for (void* p : allocations) hipFree(p);
+  for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+  for (void* p : allocations) (void)hipFree(p);
 }
 
 extern "C" {
@@ -253,14 +257,14 @@ int rwpsf_plan_create(const rwpsf_optics* o, const rwpsf_grid* g, const rwpsf_nu
   return RWPSF_OK;
 }
 
-void rwpsf_plan_destroy(rwpsf_plan* p) {
+void rwpsf_plan_destroy(rwpsf_plan* p) {   // teardown: HIP failures are ignored
   if (!p) return;
   int cur = 0;
-  hipGetDevice(&cur);
-  hipSetDevice(p->device);
-  hipDeviceSynchronize();
+  const bool had = hipGetDevice(&cur) == hipSuccess;
+  (void)hipSetDevice(p->device);
+  (void)hipDeviceSynchronize();
   delete p;
-  hipSetDevice(cur);
+  if (had) (void)hipSetDevice(cur);
 }
 
 size_t rwpsf_plan_device_bytes(const rwpsf_plan* p) { return p ? p->device_bytes : 0; }
@@ -304,8 +308,7 @@ int rwpsf_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const void* E, con
   int st = rw::validate_stacks(&p->opt, &p->grid, &p->num, n, s);
   if (st != RWPSF_OK) return st;
   int cur = -1;
-  hipGetDevice(&cur);
-  if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
+  if (hipGetDevice(&cur) != hipSuccess || cur != p->device) return RWPSF_ERR_INVALID_ARG;
   return rw::fourier_adjoint(p, n, s, (const float2*)E, dLdI, n_zernike, dc, dW0, (hipStream_t)stream);
 }
 
@@ -316,8 +319,7 @@ int rwpsf_adjoint_bessel(rwpsf_plan* p, int n, const rwpsf_stack* s, const void*
   int st = rw::validate_stacks(&p->opt, &p->grid, &p->num, n, s);
   if (st != RWPSF_OK) return st;
   int cur = -1;
-  hipGetDevice(&cur);
-  if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
+  if (hipGetDevice(&cur) != hipSuccess || cur != p->device) return RWPSF_ERR_INVALID_ARG;
   return rw::bessel_adjoint(p, n, s, (const float2*)E, dLdI, dc, dts, dz, (hipStream_t)stream);
 }
 

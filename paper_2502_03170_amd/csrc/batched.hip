@@ -430,11 +430,11 @@ struct rwpsf_batch {
     int wg = 0, small = 0;
     hipStream_t st = nullptr;
   } gkey;
-  ~rwpsf_batch() {
-    if (gexec) hipGraphExecDestroy(gexec);
-    if (upload_done) hipEventDestroy(upload_done);
-    if (h_staging) hipHostFree(h_staging);
-    for (void* p : allocations) hipFree(p);
+  ~rwpsf_batch() {   // teardown: failures cannot be reported and are ignored
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (upload_done) (void)hipEventDestroy(upload_done);
+    if (h_staging) (void)hipHostFree(h_staging);
+    for (void* p : allocations) (void)hipFree(p);
   }
 };
 
@@ -614,8 +614,12 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
   if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) return RWPSF_ERR_NO_DEVICE;
   rwpsf_batch* b = new (std::nothrow) rwpsf_batch();
   if (!b) return RWPSF_ERR_OOM;
-  hipGetDevice(&b->device);
-  hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, b->device);
+  if (hipGetDevice(&b->device) != hipSuccess ||
+      hipDeviceGetAttribute(&b->num_cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess ||
+      b->num_cus < 1) {
+    delete b;
+    return RWPSF_ERR_NO_DEVICE;
+  }
   b->opt = *o;
   b->N = n_pupil;
   b->px = pixel_nm;
@@ -720,14 +724,14 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
   return RWPSF_OK;
 }
 
-void rwpsf_batch_destroy(rwpsf_batch* b) {
+void rwpsf_batch_destroy(rwpsf_batch* b) {   // teardown: HIP failures are ignored
   if (!b) return;
   int cur = 0;
-  hipGetDevice(&cur);
-  hipSetDevice(b->device);
-  hipDeviceSynchronize();
+  const bool had = hipGetDevice(&cur) == hipSuccess;
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
   delete b;
-  hipSetDevice(cur);
+  if (had) (void)hipSetDevice(cur);
 }
 
 int rwpsf_batch_set_graph(rwpsf_batch* b, int enable) {
@@ -756,8 +760,7 @@ int rwpsf_batch_compute(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I,
   if (rc) return rc;
   if (!I && !E) return RWPSF_ERR_INVALID_ARG;
   int cur = -1;
-  hipGetDevice(&cur);
-  if (cur != b->device) return RWPSF_ERR_INVALID_ARG;
+  if (hipGetDevice(&cur) != hipSuccess || cur != b->device) return RWPSF_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
   if (b->use_graph && !st) return RWPSF_ERR_INVALID_ARG;   // the legacy default stream cannot be captured
   // the previous upload must have left the pinned staging area before it is rewritten
@@ -771,7 +774,7 @@ int rwpsf_batch_compute(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I,
                       b->gkey.st == st;
     if (!same) {
       if (b->gexec) {
-        hipGraphExecDestroy(b->gexec);
+        (void)hipGraphExecDestroy(b->gexec);
         b->gexec = nullptr;
       }
       hipGraph_t g = nullptr;
@@ -779,12 +782,12 @@ int rwpsf_batch_compute(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I,
       const int erc = batch_enqueue(b, n, I, (float2*)E, st);
       hipError_t ce = hipStreamEndCapture(st, &g);
       if (erc) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);
         return erc;
       }
       if ((rc = hip_check(ce))) return rc;
       ce = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
-      hipGraphDestroy(g);
+      (void)hipGraphDestroy(g);
       if ((rc = hip_check(ce))) return rc;
       b->gkey = {n, I, E, b->cfg.wg_per_cu, b->cfg.small_tile_max_crop, st};
     }
@@ -891,9 +894,12 @@ int rwpsf_batch_autotune(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I
   const rwpsf_batch_config saved = b->cfg;
   const bool saved_graph = b->use_graph;
   b->use_graph = false;
-  hipEvent_t t0, t1;
-  hipEventCreate(&t0);
-  hipEventCreate(&t1);
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if ((rc = hip_check(hipEventCreate(&t0))) || (rc = hip_check(hipEventCreate(&t1)))) {
+    if (t0) (void)hipEventDestroy(t0);
+    b->use_graph = saved_graph;
+    return rc;
+  }
   rwpsf_batch_config best = saved;
   float best_t = 1e30f;
   const int wgs[3] = {1, 2, 3};
@@ -902,21 +908,19 @@ int rwpsf_batch_autotune(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I
     for (int si = 0; si < 2; ++si) {
       b->cfg = {wgs[wi], smalls[si]};
       if ((rc = rwpsf_batch_compute(b, n, e, I, nullptr, st))) break;   // warm-up
-      hipEventRecord(t0, st);
+      if ((rc = hip_check(hipEventRecord(t0, st)))) break;
       for (int r = 0; r < 2 && !rc; ++r) rc = rwpsf_batch_compute(b, n, e, I, nullptr, st);
-      hipEventRecord(t1, st);
-      if (rc) break;
-      hipEventSynchronize(t1);
+      if (rc || (rc = hip_check(hipEventRecord(t1, st)))) break;
       float ms = 0.f;
-      hipEventElapsedTime(&ms, t0, t1);
+      if ((rc = hip_check(hipEventSynchronize(t1))) || (rc = hip_check(hipEventElapsedTime(&ms, t0, t1)))) break;
       ms *= 0.5f;
       if (ms < best_t) {
         best_t = ms;
         best = b->cfg;
       }
     }
-  hipEventDestroy(t0);
-  hipEventDestroy(t1);
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
   b->use_graph = saved_graph;
   b->cfg = rc ? saved : best;
   if (rc) return rc;

@@ -499,8 +499,7 @@ static void bessel_pol(const rwpsf_plan* p, float out[4]) {
 
 int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
   int cur = -1;
-  hipGetDevice(&cur);
-  if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
+  if (hipGetDevice(&cur) != hipSuccess || cur != p->device) return RWPSF_ERR_INVALID_ARG;
   if (6 * p->num.n_rho * 4 > 160 * 1024) return RWPSF_ERR_UNSUPPORTED;
   const int T = p->n_theta_total, R = p->num.n_rho, nz = p->grid.nz;
   const int mode = p->bessel_mode, G = bessel_groups(mode), V = bessel_variants(mode);

@@ -303,10 +303,12 @@ static size_t czt_cols_lds(int cb, int N, int nx, int L) {
 // The limit belongs to the kernel, not to a plan: the column kernel's LDS depends on the
 // plan, so it is allowed the whole LDS (a later plan must not lower it).
 template <int L>
-static void czt_attributes() {
-  hipFuncSetAttribute((const void*)czt_cols_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)czt_rows_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      4 * padded<L>() * (int)sizeof(float2));
+static hipError_t czt_attributes() {
+  const hipError_t e =
+      hipFuncSetAttribute((const void*)czt_cols_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)czt_rows_kernel<L>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             4 * padded<L>() * (int)sizeof(float2));
 }
 
 static int pow2_at_least(int v) {
@@ -374,14 +376,16 @@ int czt_plan_init(rwpsf_plan* p) {
   p->czt_planes = std::max<size_t>(1, std::min(want, (size_t)(512u << 20) / plane_bytes));
   if ((st = dev_alloc(p, &p->d_czt_T, p->czt_planes * 3 * (size_t)N * ny))) return st;
   for (int L : {Ly, Lx}) {
+    hipError_t e;
     switch (L) {
-      case 64: czt_attributes<64>(); break;
-      case 128: czt_attributes<128>(); break;
-      case 256: czt_attributes<256>(); break;
-      case 512: czt_attributes<512>(); break;
-      case 1024: czt_attributes<1024>(); break;
-      default: czt_attributes<2048>(); break;
+      case 64: e = czt_attributes<64>(); break;
+      case 128: e = czt_attributes<128>(); break;
+      case 256: e = czt_attributes<256>(); break;
+      case 512: e = czt_attributes<512>(); break;
+      case 1024: e = czt_attributes<1024>(); break;
+      default: e = czt_attributes<2048>(); break;
     }
+    if ((st = hip_check(e))) return st;
   }
   return hip_check(hipGetLastError());
 }
@@ -465,8 +469,7 @@ static int czt_slab(rwpsf_plan* p, int s_local, int ns, const double* zoff, int 
 
 int czt_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
   int cur = -1;
-  hipGetDevice(&cur);
-  if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
+  if (hipGetDevice(&cur) != hipSuccess || cur != p->device) return RWPSF_ERR_INVALID_ARG;
   const int nz = p->grid.nz;
   for (int b0 = 0; b0 < n; b0 += kPupilStacks) {
     const int nb = std::min(kPupilStacks, n - b0);

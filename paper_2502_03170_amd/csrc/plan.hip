@@ -208,8 +208,7 @@ static int fourier_gemms(rwpsf_plan* p, int s_local, int ns, const double* zoff,
 
 int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
   int cur = -1;
-  hipGetDevice(&cur);
-  if (cur != p->device) return RWPSF_ERR_INVALID_ARG;
+  if (hipGetDevice(&cur) != hipSuccess || cur != p->device) return RWPSF_ERR_INVALID_ARG;
   const int nz = p->grid.nz;
   const size_t fpp = (size_t)4 * p->nhp * p->nhp;
   for (int b0 = 0; b0 < n; b0 += kGemmStacks) {

@@ -588,8 +588,8 @@ struct rwpsf_sg {
   __bf16* wsplit = nullptr;   // BF16 hi / lo planes of W2 and W3, [N][K]
   double* loss_partial = nullptr;
   int64_t step = 0;
-  ~rwpsf_sg() {
-    for (void* p : allocations) hipFree(p);
+  ~rwpsf_sg() {   // teardown: failures cannot be reported and are ignored
+    for (void* p : allocations) (void)hipFree(p);
   }
 };
 
@@ -712,7 +712,10 @@ int rwpsf_sg_create(int max_batch, rwpsf_sg** out) {
   if (hipGetDeviceCount(&dev_count) != hipSuccess || dev_count < 1) return RWPSF_ERR_NO_DEVICE;
   rwpsf_sg* s = new (std::nothrow) rwpsf_sg();
   if (!s) return RWPSF_ERR_OOM;
-  hipGetDevice(&s->device);
+  if (hipGetDevice(&s->device) != hipSuccess) {
+    delete s;
+    return RWPSF_ERR_NO_DEVICE;
+  }
   s->max_batch = max_batch;
   s->L = layout();
   const size_t P = s->L.total, B = (size_t)max_batch;
@@ -740,10 +743,8 @@ int rwpsf_sg_create(int max_batch, rwpsf_sg** out) {
     delete s;
     return rc;
   }
-  hipMemset(s->m, 0, P * sizeof(float));
-  hipMemset(s->v, 0, P * sizeof(float));
-  hipMemset(s->w, 0, P * sizeof(float));
-  if ((rc = hip_check(hipDeviceSynchronize()))) {
+  if ((rc = hip_check(hipMemset(s->m, 0, P * sizeof(float)))) || (rc = hip_check(hipMemset(s->v, 0, P * sizeof(float)))) ||
+      (rc = hip_check(hipMemset(s->w, 0, P * sizeof(float)))) || (rc = hip_check(hipDeviceSynchronize()))) {
     delete s;
     return rc;
   }
@@ -751,9 +752,9 @@ int rwpsf_sg_create(int max_batch, rwpsf_sg** out) {
   return RWPSF_OK;
 }
 
-void rwpsf_sg_destroy(rwpsf_sg* s) {
+void rwpsf_sg_destroy(rwpsf_sg* s) {   // teardown: HIP failures are ignored
   if (!s) return;
-  hipDeviceSynchronize();
+  (void)hipDeviceSynchronize();
   delete s;
 }
 
