@@ -160,8 +160,9 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
     sincos_rev(a.ksz[jf * N + lf] * zrev, &sn, &cs);
     Dz[cell] = make_float2(cs, sn);
   }
-  // the defocus table was written by other waves of this workgroup
-  __threadfence();
+  // the defocus table was written by other waves of this workgroup and is read only by
+  // it: the barrier's workgroup-scope release/acquire orders those accesses (a
+  // device-scope fence here would write the whole L2 back to memory on every plane)
   __syncthreads();
   float isum64[16];   // SP = 64: this wave's 32x32 block of E, MFMA C layout
   float isum32[4];    // SP = 32: elements tid + 256 q of the 32x32 image
