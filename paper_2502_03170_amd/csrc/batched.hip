@@ -10,8 +10,8 @@
 // The cell-centred grids are mirror-symmetric, so each emitter's pupil is folded once
 // (four parities per folded cell, written to the emitter's HBM slot) and each plane d of
 // each field component c is two real-coefficient GEMMs on the matrix cores,
-//   U  = A2_S (Dz o Pf_c)   (S x N; the defocus Dz of the plane is shared by the three
-//                            components and the four mirror cells)
+//   U  = A2_S (D o Pf_c)    (S x N; D = exp(i k s_z z) of each folded cell, formed as the
+//                            operand is staged: FP64 phase in revolutions, hardware sin/cos)
 //   E' = U B1_S             (S x S, U staged in LDS as the A operand),  E = -i E'
 // and I = sum_c |E_c|^2.  A2_S / B1_S are the rows of one 96-row table that cover the
 // crop (pixel i of an S-crop is table row i - S/2 + 32).  Crops are evaluated on 32- or
@@ -66,7 +66,6 @@ struct BatchArgs {
   const float* A2T;          // [N][96] rows 2jf + pj: pref cos / sin (k s_x[jf] x_r)
   const float* B1T;          // [N][96] rows 2lf + pl: cos / sin (k s_y[lf] y_r)
   float2* Pf;                // [n][3][N][N] folded pupils, slot order
-  float2* Dz;                // per workgroup [N/2][N/2] defocus factors of its current plane
   const int* list;           // [n] slots grouped by XCD queue
   const long long* pre;      // [n + 1] plane prefix sums over list
   const int* qoff;           // [17] queue q owns list[qoff[q] .. qoff[q+1]); queues 8 t + x of tile class t
@@ -138,32 +137,21 @@ __global__ void __launch_bounds__(256) batch_fold_kernel(BatchArgs a) {
 // MFMA 32x32x2 f32: A lane l -> A[l%32][l/32], B lane l -> B[l/32][l%32],
 // C register r of lane l -> C[8(r/4) + 4(l/32) + r%4][l%32].
 //
-// Plane d of emitter `slot`:  U = A2 (Dz o Pf_c)  (real x complex),  E' = U B1
-// (complex x real),  E = -i E',  I = sum_c |E_c|^2, with the defocus Dz[jf][lf] =
-// exp(i k s_z z) shared by the three components and the four mirror cells.
+// Plane d of emitter `slot`:  U = A2 (D o Pf_c)  (real x complex),  E' = U B1
+// (complex x real),  E = -i E',  I = sum_c |E_c|^2, with the defocus D[jf][lf] =
+// exp(i k s_z z) of the folded cell, the same for its four mirror cells.
 template <int SP>
 __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam& bp, int slot, int d,
-                                            float* lds, int tid, float2* __restrict__ Dz) {
+                                            float* lds, int tid) {
   constexpr int TI = SP / 32;
   constexpr int LDU = SP + 1;
   const int lane = tid & 63, w = tid >> 6, h = lane >> 5, l32 = lane & 31;
-  const int N = a.N, NN = N * N, nh = N / 2, S = bp.S;
+  const int N = a.N, NN = N * N, S = bp.S;
   const int r0 = 32 - S / 2;
   const float2* Pf = a.Pf + (size_t)slot * 3 * NN;
   float* Ure = lds;
   float* Uim = lds + N * LDU;
   const double zrev = ((d - 0.5 * (bp.D - 1)) * a.pitch + bp.zoff) * (1.0 / kTwoPi);
-  // ---- defocus of this plane on the folded cells (FP64 phase in revolutions, reduced)
-  for (int cell = tid; cell < nh * nh; cell += 256) {
-    const int jf = cell / nh, lf = cell % nh;
-    float sn, cs;
-    sincos_rev(a.ksz[jf * N + lf] * zrev, &sn, &cs);
-    Dz[cell] = make_float2(cs, sn);
-  }
-  // the defocus table was written by other waves of this workgroup and is read only by
-  // it: the barrier's workgroup-scope release/acquire orders those accesses (a
-  // device-scope fence here would write the whole L2 back to memory on every plane)
-  __syncthreads();
   float isum64[16];   // SP = 64: this wave's 32x32 block of E, MFMA C layout
   float isum32[4];    // SP = 32: elements tid + 256 q of the 32x32 image
 #pragma unroll
@@ -172,13 +160,13 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
   for (int q = 0; q < 4; ++q) isum32[q] = 0.f;
   for (int c = 0; c < 3; ++c) {
     const float2* Pc = Pf + (size_t)c * NN;
-    // ---- U[m][col] = sum_k A2[r0 + m][k] (Dz o Pf)[k][col]: k-stages of A2 rows and of the
+    // ---- U[m][col] = sum_k A2[r0 + m][k] (D o Pf)[k][col]: k-stages of A2 rows and of the
     // defocused folded pupil (re / im planes) staged in LDS, double-buffered; wave w owns
     // columns 32 w .. 32 w + 31
     {
       float ra[4];      // A prefetch: BK x SP floats, up to 4 per thread
       float4 rp[4];     // B prefetch: BK x N/2 float4, up to 4 per thread
-      float2 rd[4];
+      double rd[4];     // k s_z of the staged folded cell
       const int na = kBK * SP / 256, nb = kBK * (N / 2) / 256;
       auto load = [&](int k0) {
 #pragma unroll
@@ -192,7 +180,7 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
           if (i < nb) {
             const int idx = tid + 256 * i, kk = idx / (N / 2), c2 = idx % (N / 2);
             rp[i] = *reinterpret_cast<const float4*>(Pc + (size_t)(k0 + kk) * N + 2 * c2);
-            rd[i] = Dz[((k0 + kk) >> 1) * nh + c2];
+            rd[i] = a.ksz[((k0 + kk) >> 1) * N + c2];
           }
       };
       auto store = [&](float* st) {
@@ -209,7 +197,8 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
         for (int i = 0; i < 4; ++i)
           if (i < nb) {
             const int idx = tid + 256 * i, kk = idx / (N / 2), c2 = idx % (N / 2);
-            const float2 dz = rd[i];
+            float2 dz;   // exp(i k s_z z): FP64 phase in revolutions, hardware sine and cosine
+            sincos_rev(rd[i] * zrev, &dz.y, &dz.x);
             *reinterpret_cast<float2*>(sr + kk * kLdbU + 2 * c2) =
                 make_float2(rp[i].x * dz.x - rp[i].y * dz.y, rp[i].z * dz.x - rp[i].w * dz.y);
             *reinterpret_cast<float2*>(si + kk * kLdbU + 2 * c2) =
@@ -353,7 +342,7 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
       }
     }
   }
-  __syncthreads();   // every wave is done with Dz and the LDS before the next item
+  __syncthreads();   // every wave is done with the LDS before the next item
 }
 
 constexpr int kBatchLdsBytes = 2 * 128 * 65 * 4;   // U for N <= 128, SP = 64
@@ -372,7 +361,6 @@ __global__ void __launch_bounds__(256, 2) batch_planes_kernel(BatchArgs a) {
   const int x = 8 * (SP == 64 ? 1 : 0) + (blockIdx.x & 7);
   const int lo = a.qoff[x], hi = a.qoff[x + 1];
   const long long end = a.pre[hi];
-  float2* Dz = a.Dz + (size_t)blockIdx.x * (a.N * a.N / 4);
   for (;;) {
     if (tid == 0) item = (long long)atomicAdd(&a.counter[x], 1ull);
     __syncthreads();
@@ -388,7 +376,7 @@ __global__ void __launch_bounds__(256, 2) batch_planes_kernel(BatchArgs a) {
     const int slot = a.list[e0];
     const int d = (int)(it - a.pre[e0]);
     const BatchParam bp = a.params[slot];
-    batch_plane<SP>(a, bp, slot, d, lds, tid, Dz);
+    batch_plane<SP>(a, bp, slot, d, lds, tid);
   }
 }
 
@@ -409,7 +397,6 @@ struct rwpsf_batch {
   float* d_A2T = nullptr;       // [N][96] folded x table (prefactor included)
   float* d_B1T = nullptr;       // [N][96] folded y table
   float2* d_pf = nullptr;       // [max][3][N][N] folded pupils
-  float2* d_dz = nullptr;       // per workgroup [N/2][N/2] defocus table
   long long items = 0;          // (emitter, plane) items of the staged call
   long long class_items[2] = {0, 0};   // of them, in the 32- and 64-wide tile classes
   float* d_basis = nullptr;
@@ -555,7 +542,6 @@ static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t
   a.A2T = b->d_A2T;
   a.B1T = b->d_B1T;
   a.Pf = b->d_pf;
-  a.Dz = b->d_dz;
   a.list = (const int*)(b->d_upload + off_list(b));
   a.pre = d_pre;
   a.qoff = d_qoff;
@@ -691,7 +677,6 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
   if ((rc = balloc(b, &b->d_Q, 3 * NN)) || (rc = balloc(b, &b->d_ksz, NN)) ||
       (rc = balloc(b, &b->d_A2T, (size_t)N * kTabRows)) || (rc = balloc(b, &b->d_B1T, (size_t)N * kTabRows)) ||
       (rc = balloc(b, &b->d_pf, (size_t)max_emitters * 3 * NN)) ||
-      (rc = balloc(b, &b->d_dz, (size_t)b->num_cus * kMaxWgPerCu * (NN / 4))) ||
       (rc = balloc(b, &b->d_basis, (size_t)kBasisRows * NN)) ||
       (rc = balloc(b, &b->d_phi, (size_t)max_emitters * NN)) || (rc = balloc(b, &b->d_upload, b->upload_bytes)) ||
       (rc = balloc(b, &b->d_counter, kQueues)) || (o->gibson_lanni && (rc = balloc(b, &b->d_gl, NN)))) {
