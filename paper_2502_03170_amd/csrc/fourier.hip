@@ -237,7 +237,7 @@ using CfgPupilL = RgCfg<256, 128, 16, 64, 64>;
 // outputs of at most 64 pixels per axis are padded to 64 and use half-height tiles
 // (256 rows when the folded row count allows, as above)
 using CfgPupilS = RgCfg<128, 64, 16, 64, 32>;
-using CfgPupilSL = RgCfg<256, 64, 16, 64, 32>;
+using CfgPupilSL = RgCfg<256, 64, 16, 64, 64>;
 using CfgImageS = RgCfg<64, 64, 32, 32, 32>;
 static_assert((4 * kFoldPad) % CfgPupil::BM == 0 && (2 * kFoldPad) % CfgPupil::BK == 0, "pupil GEMM padding");
 static_assert((4 * kFoldPad) % CfgPupilS::BM == 0 && kPadSmall % CfgPupilS::BN == 0 && kPadSmall % CfgImageS::BM == 0 &&
