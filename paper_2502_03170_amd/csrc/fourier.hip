@@ -230,6 +230,9 @@ struct FoldDefocusLoader {
 #define RW_F2_OCC 2
 #endif
 using CfgPupil = RgCfg<RW_F1_BM, RW_F1_BN, RW_F1_BK, RW_F1_WM, RW_F1_WN>;
+// image GEMM: 128 x 256 tiles (a whole padded row of re/im columns at 128-pixel width) on
+// eight 64 x 64 waves; launches whose padded width 2 nyp is not a multiple of 256, or
+// that would underfill the GPU, take CfgImageS
 using CfgImage = RgCfg<RW_F2_BM, RW_F2_BN, RW_F2_BK, RW_F2_WM, RW_F2_WN>;
 // pupils whose folded row count 4 nhp is a multiple of 256 take 256-row tiles (8 waves;
 // the y-table tile is then shared by twice the rows)
