@@ -181,3 +181,22 @@ def test_bessel_matches_fourier_on_gpu_as_pupil_grows(lib):
         errs.append(rel_l2(_np(If[0]), _np(Ib[0])))
     assert errs[0] > errs[1] > errs[2]
     assert errs[2] < 2e-3
+
+
+def test_fourier_small_tile_launch_matches_large_tile_launch(lib):
+    """A launch that would underfill the GPU with large tiles (one plane of one stack) takes
+    the small-tile kernels: the same planes computed inside the 16-stack, 64-plane launch
+    (large tiles) must agree with it to FP32 rounding of a different summation tiling."""
+    import torch
+    rw = lib
+    w = W.fourier_plain()
+    zp = np.linspace(-1000.0, 1000.0, 64)
+    stacks = [dict(t_s=w["t_s"][b], z_offset=-w["t_s"][b], zernike=w["zernike"][b]) for b in range(16)]
+    E, I = _fourier_plan(rw, w, 256, 128, 128, 20.0, zp).compute(stacks)
+    torch.cuda.synchronize()
+    for b, zi in ((0, 0), (5, 31), (15, 63)):
+        one = _fourier_plan(rw, w, 256, 128, 128, 20.0, [zp[zi]])
+        E1, I1 = one.compute([stacks[b]])
+        torch.cuda.synchronize()
+        assert rel_l2(_np(E1[0, 0]), _np(E[b, zi])) < 2e-6, (b, zi)
+        assert rel_l2(_np(I1[0, 0]), _np(I[b, zi])) < 2e-6, (b, zi)
