@@ -56,9 +56,14 @@ def profiled_traffic(summary: str):
         text = open(path).read()
     except OSError:
         return None
+    return traffic_from_summary(text, sources_digest())
+
+
+def traffic_from_summary(text: str, digest_now: str):
+    """The summary's bytes per dispatch if it records the digest `digest_now`, else None."""
     digest = re.search(r"sources sha256: ([0-9a-f]{64})", text)
     traffic = re.search(r"HBM bytes per dispatch: ([0-9]+)", text)
-    if not digest or not traffic or digest.group(1) != sources_digest():
+    if not digest or not traffic or digest.group(1) != digest_now:
         return None
     return int(traffic.group(1))
 
