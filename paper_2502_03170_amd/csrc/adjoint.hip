@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(kZernThreads) adj_zernike_kernel(const double*
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = kZernThreads / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) dc[q] = (float)(kTwoPi * red[0]);

@@ -590,7 +590,7 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
   *out = nullptr;
   double zero = 0.0;
   rwpsf_grid g{1, 1, 1.0, 1.0, 1, &zero};
-  rwpsf_numerics nm{RWPSF_FORM_FOURIER, n_pupil, 2, 8};
+  rwpsf_numerics nm{RWPSF_FORM_FOURIER, n_pupil, 2, 8, RWPSF_MODEL_VECTORIAL, RWPSF_THETA_GAUSS};
   int st = validate_plan(o, &g, &nm);
   if (st != RWPSF_OK) return st;
   if (n_pupil < 32 || n_pupil > 128 || n_pupil % 32 != 0) return RWPSF_ERR_INVALID_ARG;

@@ -25,7 +25,7 @@ namespace rw {
 // --------------------------------------------------------------------------
 // Plan-time table: orthonormal Noll Zernike basis on the cell-centred pupil grid.
 // --------------------------------------------------------------------------
-__global__ void zernike_table_kernel(float* __restrict__ out, int n, int nj, double s_max_unused) {
+__global__ void zernike_table_kernel(float* __restrict__ out, int n, int nj) {
   const int cell = blockIdx.x * blockDim.x + threadIdx.x;
   if (cell >= n * n) return;
   const int j = cell / n, l = cell % n;
@@ -455,8 +455,7 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_image_kernel(Gemm2Args a) {
 // --------------------------------------------------------------------------
 hipError_t launch_zernike_table(float* out, int n, int nj, hipStream_t st) {
   const int cells = n * n;
-  hipLaunchKernelGGL(zernike_table_kernel, dim3((cells + 255) / 256), dim3(256), 0, st, out, n, nj,
-                     0.0);
+  hipLaunchKernelGGL(zernike_table_kernel, dim3((cells + 255) / 256), dim3(256), 0, st, out, n, nj);
   return hipGetLastError();
 }
 

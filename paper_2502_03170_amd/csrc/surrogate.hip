@@ -311,7 +311,7 @@ __global__ void __launch_bounds__(256) sg_mse_kernel(const float* __restrict__ y
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
