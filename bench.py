@@ -308,7 +308,7 @@ def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
 
     def step():
         plan.compute(st, E=E, I=I)
-        rw.adjoint(plan.handle, st, E, (2.0 / I.numel()) * (I - Y), 21, dc, dw)
+        rw.adjoint(plan, st, E, (2.0 / I.numel()) * (I - Y), 21, dc, dw)
 
     for _ in range(warmup):
         step()
@@ -363,7 +363,7 @@ def bench_adjoint_bessel(rw, torch, steps, warmup, n_stacks=64):
 
     def step():
         plan.compute(st, E=E, I=I)
-        rw.adjoint_bessel(plan.handle, st, E, (2.0 / I.numel()) * (I - Y), dc, dts, dz)
+        rw.adjoint_bessel(plan, st, E, (2.0 / I.numel()) * (I - Y), dc, dts, dz)
 
     for _ in range(warmup):
         step()

@@ -169,6 +169,33 @@ def abi_version() -> int:
     return load().rwpsf_abi_version()
 
 
+def check_tensor(t, name: str, dtype, numel: int, required: bool = True) -> c_void_p:
+    """The device pointer of tensor ``t`` after checking what the library will assume of
+    it: ``dtype``, contiguous, at least ``numel`` elements, on the current CUDA device.
+    None gives a NULL pointer when the argument is optional.  Raises ValueError before
+    anything reaches the library (an undersized or mistyped buffer would otherwise be
+    read or written out of bounds on the device)."""
+    import torch
+    if t is None:
+        if required:
+            raise ValueError(f"{name} is required")
+        return c_void_p(0)
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < numel:
+        raise ValueError(f"{name} has {t.numel()} elements, needs at least {numel}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.device.index != torch.cuda.current_device():
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the current device is "
+                         f"cuda:{torch.cuda.current_device()}")
+    return c_void_p(t.data_ptr())
+
+
 # ---------------------------------------------------------------- struct builders
 def make_optics(na, wavelength, n_i, e_inc=CIRCULAR, focal_length=1.0, apodization=True, s_env=0.0,
                 gibson_lanni: dict | None = None, fresnel: tuple | None = None,
@@ -206,7 +233,10 @@ def make_grid(nx, ny, dx, dy, z):
     return g
 
 
-def make_stacks(stacks: list[dict]):
+def make_stacks(stacks: list[dict], n_pupil: int | None = None):
+    """rwpsf_stack array; a phase map must be a float32 CUDA tensor of n_pupil^2 cells
+    (checked against n_pupil when it is given, else when the stacks reach a plan)."""
+    import torch
     arr = (Stack * len(stacks))()
     keep = []
     for i, s in enumerate(stacks):
@@ -223,7 +253,8 @@ def make_stacks(stacks: list[dict]):
         pm = s.get("phase_map")
         if pm is not None:
             keep.append(pm)
-            arr[i].phase_map = c_void_p(pm.data_ptr())
+            arr[i].phase_map = check_tensor(pm, f"stacks[{i}].phase_map", torch.float32,
+                                            0 if n_pupil is None else n_pupil * n_pupil)
     return arr, keep
 
 
@@ -231,18 +262,23 @@ class Stacks:
     """A list of stack dicts marshalled once into an rwpsf_stack array, for calls that
     repeat with the same stacks (the marshalling of many stacks costs host time)."""
 
-    def __init__(self, stacks: list[dict]):
-        self.arr, self.keep = make_stacks(stacks)
+    def __init__(self, stacks: list[dict], n_pupil: int | None = None):
+        self.arr, self.keep = make_stacks(stacks, n_pupil)
+        self.maps = [s["phase_map"] for s in stacks if s.get("phase_map") is not None]
         self.n = len(stacks)
 
     def __len__(self):
         return self.n
 
 
-def _marshal(stacks):
+def _marshal(stacks, n_pupil: int | None = None):
     if isinstance(stacks, Stacks):
+        if n_pupil is not None:
+            for pm in stacks.maps:
+                if pm.numel() < n_pupil * n_pupil:
+                    raise ValueError(f"a phase map has {pm.numel()} cells, the plan's pupil {n_pupil ** 2}")
         return stacks.arr, stacks.keep
-    return make_stacks(stacks)
+    return make_stacks(stacks, n_pupil)
 
 
 # ---------------------------------------------------------------- ABI mirrors
@@ -296,53 +332,51 @@ def plan_timing(handle, kernel: int):
     return ms.value, n.value
 
 
-def compute(handle, stacks: list[dict], E=None, I=None, stream=None) -> None:
-    """Enqueue rwpsf_compute; E (complex64) and I (float32) are CUDA tensors or None.
+def _stream(stream):
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream if stream is None else stream)
+
+
+def compute(plan, stacks, E=None, I=None, stream=None) -> None:
+    """Enqueue rwpsf_compute for a ``Plan``: E complex64 [stacks][nz][channels][nx][ny] and
+    I float32 [stacks][nz][nx][ny] CUDA tensors (either may be None, not both).
     ``stacks`` is a list of dicts or a ``Stacks``."""
     import torch
-    arr, _keep = _marshal(stacks)
-    if stream is None:
-        stream = torch.cuda.current_stream().cuda_stream
-    for t, dt in ((E, torch.complex64), (I, torch.float32)):
-        if t is not None and (not t.is_cuda or t.dtype != dt or not t.is_contiguous()):
-            raise ValueError("outputs must be contiguous CUDA tensors of complex64 (E) / float32 (I)")
-    _check(load().rwpsf_compute(handle, len(stacks), arr, c_void_p(E.data_ptr() if E is not None else 0),
-                                c_void_p(I.data_ptr() if I is not None else 0), c_void_p(stream)))
+    arr, _keep = _marshal(stacks, plan.num.n_pupil if plan.num.form != FORM_BESSEL else None)
+    vox = len(stacks) * plan.nz * plan.nx * plan.ny
+    e = check_tensor(E, "E", torch.complex64, vox * plan.nc, required=False)
+    i = check_tensor(I, "I", torch.float32, vox, required=False)
+    _check(load().rwpsf_compute(plan.handle, len(stacks), arr, e, i, _stream(stream)))
 
 
-def adjoint(handle, stacks: list[dict], E, dL_dI, n_zernike: int, dL_dc=None, dL_dW0=None, stream=None):
-    """Enqueue rwpsf_adjoint (E complex64, dL_dI float32, outputs float32; CUDA tensors).
-    ``stacks`` is a list of dicts or a ``Stacks``."""
+def adjoint(plan, stacks, E, dL_dI, n_zernike: int, dL_dc=None, dL_dW0=None, stream=None):
+    """Enqueue rwpsf_adjoint for a Fourier ``Plan``: E complex64 and dL_dI float32 as
+    written by ``compute``; outputs float32 dL_dc [n_zernike] and dL_dW0 [N][N] (either may
+    be None).  ``stacks`` is a list of dicts or a ``Stacks``."""
+    import torch
+    arr, _keep = _marshal(stacks, plan.num.n_pupil)
+    vox = len(stacks) * plan.nz * plan.nx * plan.ny
+    if n_zernike < 0 or n_zernike > MAX_ZERNIKE:
+        raise ValueError(f"n_zernike must be in 0..{MAX_ZERNIKE}")
+    args = (check_tensor(E, "E", torch.complex64, vox * plan.nc), check_tensor(dL_dI, "dL_dI", torch.float32, vox),
+            n_zernike, check_tensor(dL_dc, "dL_dc", torch.float32, n_zernike, required=False),
+            check_tensor(dL_dW0, "dL_dW0", torch.float32, plan.num.n_pupil ** 2, required=False))
+    _check(load().rwpsf_adjoint(plan.handle, len(stacks), arr, *args, _stream(stream)))
+
+
+def adjoint_bessel(plan, stacks, E, dL_dI, dL_dc=None, dL_dts=None, dL_dz=None, stream=None):
+    """Enqueue rwpsf_adjoint_bessel for a Bessel ``Plan`` (E complex64, dL_dI float32; outputs
+    float32 CUDA tensors: dL_dc [4] for Noll 1, 4, 11, 22, dL_dts and dL_dz [n_stacks]; any
+    may be None)."""
     import torch
     arr, _keep = _marshal(stacks)
-    if stream is None:
-        stream = torch.cuda.current_stream().cuda_stream
-    for t in (E, dL_dI, dL_dc, dL_dW0):
-        if t is not None and (not t.is_cuda or not t.is_contiguous()):
-            raise ValueError("adjoint tensors must be contiguous CUDA tensors")
-    _check(load().rwpsf_adjoint(handle, len(stacks), arr, c_void_p(E.data_ptr()), c_void_p(dL_dI.data_ptr()),
-                                n_zernike, c_void_p(dL_dc.data_ptr() if dL_dc is not None else 0),
-                                c_void_p(dL_dW0.data_ptr() if dL_dW0 is not None else 0), c_void_p(stream)))
-
-
-def adjoint_bessel(handle, stacks, E, dL_dI, dL_dc=None, dL_dts=None, dL_dz=None, stream=None):
-    """Enqueue rwpsf_adjoint_bessel (E complex64, dL_dI float32; outputs float32 CUDA
-    tensors: dL_dc [4] for Noll 1, 4, 11, 22, dL_dts and dL_dz [n_stacks]; any may be None)."""
-    import torch
-    arr, _keep = _marshal(stacks)
-    if stream is None:
-        stream = torch.cuda.current_stream().cuda_stream
-    for t in (E, dL_dI, dL_dc, dL_dts, dL_dz):
-        if t is not None and (not t.is_cuda or not t.is_contiguous()):
-            raise ValueError("adjoint tensors must be contiguous CUDA tensors")
-    if dL_dc is not None and dL_dc.numel() < 4:
-        raise ValueError("dL_dc needs 4 entries (Noll 1, 4, 11, 22)")
-    for t in (dL_dts, dL_dz):
-        if t is not None and t.numel() < len(stacks):
-            raise ValueError("per-stack gradients need n_stacks entries")
-    ptr = lambda t: c_void_p(t.data_ptr() if t is not None else 0)
-    _check(load().rwpsf_adjoint_bessel(handle, len(stacks), arr, ptr(E), ptr(dL_dI), ptr(dL_dc), ptr(dL_dts),
-                                       ptr(dL_dz), c_void_p(stream)))
+    n = len(stacks)
+    vox = n * plan.nz * plan.nx * plan.ny
+    args = (check_tensor(E, "E", torch.complex64, vox * plan.nc), check_tensor(dL_dI, "dL_dI", torch.float32, vox),
+            check_tensor(dL_dc, "dL_dc", torch.float32, 4, required=False),
+            check_tensor(dL_dts, "dL_dts", torch.float32, n, required=False),
+            check_tensor(dL_dz, "dL_dz", torch.float32, n, required=False))
+    _check(load().rwpsf_adjoint_bessel(plan.handle, n, arr, *args, _stream(stream)))
 
 
 def _psf_function():
@@ -369,7 +403,7 @@ def _psf_function():
             n = ctx.nz
             dc = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
             dw = torch.empty_like(ctx.stacks[0]["phase_map"])
-            adjoint(ctx.plan.handle, ctx.stacks, E, grad_I.contiguous().float(), n, dc, dw)
+            adjoint(ctx.plan, ctx.stacks, E, grad_I.contiguous().float(), n, dc, dw)
             return dc[:n].to(ctx.c_device, ctx.c_dtype), dw, None, None
 
     return PSFFunction
@@ -433,20 +467,19 @@ class Batch:
         return cfg.wg_per_cu, cfg.small_tile_max_crop
 
     def compute(self, emitters, I=None, E=None, stream=None):
+        """I float32 [total voxels] and E complex64 [3 total voxels] (CUDA; either may be None)."""
         import torch
-        if stream is None:
-            stream = torch.cuda.current_stream().cuda_stream
-        _check(load().rwpsf_batch_compute(self.handle, len(emitters), emitters,
-                                          c_void_p(I.data_ptr() if I is not None else 0),
-                                          c_void_p(E.data_ptr() if E is not None else 0), c_void_p(stream)))
+        vox = batch_offsets(emitters)[-1]
+        i = check_tensor(I, "I", torch.float32, vox, required=False)
+        e = check_tensor(E, "E", torch.complex64, 3 * vox, required=False)
+        _check(load().rwpsf_batch_compute(self.handle, len(emitters), emitters, i, e, _stream(stream)))
 
     def autotune(self, emitters, I, stream=None):
         import torch
-        if stream is None:
-            stream = torch.cuda.current_stream().cuda_stream
+        i = check_tensor(I, "I", torch.float32, batch_offsets(emitters)[-1])
         cfg, ms = BatchConfig(), c_double()
-        _check(load().rwpsf_batch_autotune(self.handle, len(emitters), emitters, c_void_p(I.data_ptr()),
-                                           c_void_p(stream), byref(cfg), byref(ms)))
+        _check(load().rwpsf_batch_autotune(self.handle, len(emitters), emitters, i, _stream(stream),
+                                           byref(cfg), byref(ms)))
         return (cfg.wg_per_cu, cfg.small_tile_max_crop), ms.value
 
     def close(self):
@@ -489,29 +522,34 @@ class Surrogate:
                                          c_void_p(v.ctypes.data), c_void_p(g.ctypes.data), byref(step)))
         return dict(params=w, adam_m=m, adam_v=v, grads=g, step=step.value)
 
-    def forward(self, coef, z, out=None, precision=SG_BF16X3, stream=None):
+    def _inputs(self, coef, z):
         import torch
+        if coef.dim() != 2 or coef.shape[1] != 21:
+            raise ValueError("coef must be [B][21]")
+        B = coef.shape[0]
+        if not 1 <= B <= self.max_batch:
+            raise ValueError(f"batch {B} outside 1..{self.max_batch}")
+        return B, check_tensor(coef, "coef", torch.float32, 21 * B), check_tensor(z, "z", torch.float32, B)
+
+    def forward(self, coef, z, out=None, precision=SG_BF16X3, stream=None):
+        """out = net(coef [B][21], z [B]) as float32 [B][64][64] (CUDA tensors)."""
+        import torch
+        B, c, zz = self._inputs(coef, z)
         if out is None:
-            out = torch.empty((coef.shape[0], 64, 64), dtype=torch.float32, device="cuda")
-        if stream is None:
-            stream = torch.cuda.current_stream().cuda_stream
-        _check(load().rwpsf_sg_forward(self.handle, coef.shape[0], c_void_p(coef.data_ptr()), c_void_p(z.data_ptr()),
-                                       c_void_p(out.data_ptr()), precision, c_void_p(stream)))
+            out = torch.empty((B, 64, 64), dtype=torch.float32, device="cuda")
+        o = check_tensor(out, "out", torch.float32, B * 64 * 64)
+        _check(load().rwpsf_sg_forward(self.handle, B, c, zz, o, precision, _stream(stream)))
         return out
 
     def gradient(self, coef, z, target, loss=None, stream=None):
         import torch
-        if stream is None:
-            stream = torch.cuda.current_stream().cuda_stream
-        _check(load().rwpsf_sg_gradient(self.handle, coef.shape[0], c_void_p(coef.data_ptr()),
-                                        c_void_p(z.data_ptr()), c_void_p(target.data_ptr()),
-                                        c_void_p(loss.data_ptr() if loss is not None else 0), c_void_p(stream)))
+        B, c, zz = self._inputs(coef, z)
+        t = check_tensor(target, "target", torch.float32, B * 64 * 64)
+        lo = check_tensor(loss, "loss", torch.float32, 1, required=False)
+        _check(load().rwpsf_sg_gradient(self.handle, B, c, zz, t, lo, _stream(stream)))
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
-        import torch
-        if stream is None:
-            stream = torch.cuda.current_stream().cuda_stream
-        _check(load().rwpsf_sg_adam(self.handle, lr, beta1, beta2, eps, c_void_p(stream)))
+        _check(load().rwpsf_sg_adam(self.handle, lr, beta1, beta2, eps, _stream(stream)))
 
     def close(self):
         if self.handle:
@@ -560,29 +598,29 @@ class Plan:
             E = torch.empty((b, self.nz, self.nc, self.nx, self.ny), dtype=torch.complex64, device="cuda")
         if intensity and I is None:
             I = torch.empty((b, self.nz, self.nx, self.ny), dtype=torch.float32, device="cuda")
-        if fields and E.numel() < b * self.nz * self.nc * self.nx * self.ny:
-            raise ValueError("E is smaller than [stacks][nz][channels][nx][ny]")
-        if intensity and I.numel() < b * self.nz * self.nx * self.ny:
-            raise ValueError("I is smaller than [stacks][nz][nx][ny]")
-        compute(self.handle, stacks, E if fields else None, I if intensity else None, stream)
+        compute(self, stacks, E if fields else None, I if intensity else None, stream)
         return E, I
 
-    def adjoint_bessel(self, stacks, E, dL_dI, stream=None):
-        """(dL/dc for Noll 1, 4, 11, 22 [4], dL/dt_s [n], dL/dz_offset [n]) of the Bessel form."""
+    def adjoint_bessel(self, stacks, E, dL_dI, dc=None, dts=None, dz=None, stream=None):
+        """(dL/dc for Noll 1, 4, 11, 22 [4], dL/dt_s [n], dL/dz_offset [n]) of the Bessel form,
+        into the given float32 tensors or new ones."""
         import torch
         n = len(stacks)
-        dc = torch.empty(4, dtype=torch.float32, device="cuda")
-        dts = torch.empty(n, dtype=torch.float32, device="cuda")
-        dz = torch.empty(n, dtype=torch.float32, device="cuda")
-        adjoint_bessel(self.handle, stacks, E, dL_dI, dc, dts, dz, stream)
+        dc = torch.empty(4, dtype=torch.float32, device="cuda") if dc is None else dc
+        dts = torch.empty(n, dtype=torch.float32, device="cuda") if dts is None else dts
+        dz = torch.empty(n, dtype=torch.float32, device="cuda") if dz is None else dz
+        adjoint_bessel(self, stacks, E, dL_dI, dc, dts, dz, stream)
         return dc, dts, dz
 
-    def adjoint(self, stacks: list[dict], E, dL_dI, n_zernike: int, stream=None):
-        """(dL/dc [n_zernike], dL/dW0 [N][N]) for a loss with per-voxel dL/dI."""
+    def adjoint(self, stacks, E, dL_dI, n_zernike: int, dc=None, dw=None, stream=None):
+        """(dL/dc [n_zernike], dL/dW0 [N][N]) for a loss with per-voxel dL/dI, into the given
+        float32 tensors or new ones."""
         import torch
-        dc = torch.empty(max(n_zernike, 1), dtype=torch.float32, device="cuda")
-        dw = torch.empty((self.num.n_pupil, self.num.n_pupil), dtype=torch.float32, device="cuda")
-        adjoint(self.handle, stacks, E, dL_dI, n_zernike, dc, dw, stream)
+        if dc is None:
+            dc = torch.empty(max(n_zernike, 1), dtype=torch.float32, device="cuda")
+        if dw is None:
+            dw = torch.empty((self.num.n_pupil, self.num.n_pupil), dtype=torch.float32, device="cuda")
+        adjoint(self, stacks, E, dL_dI, n_zernike, dc, dw, stream)
         return dc[:n_zernike], dw
 
     def close(self):

@@ -399,6 +399,7 @@ struct rwpsf_batch {
   float2* d_pf = nullptr;       // [max][3][N][N] folded pupils
   long long items = 0;          // (emitter, plane) items of the staged call
   long long class_items[2] = {0, 0};   // of them, in the 32- and 64-wide tile classes
+  int class_grid[2] = {0, 0};          // persistent grid of each class (0 = class not launched)
   float* d_basis = nullptr;
   float* d_phi = nullptr;
   char* d_upload = nullptr;     // params [max] then coefT [32][max_pad]
@@ -416,6 +417,7 @@ struct rwpsf_batch {
     void* I = nullptr;
     void* E = nullptr;
     int wg = 0, small = 0;
+    int grid[2] = {0, 0};   // the captured launches: a replay must launch the same classes
     hipStream_t st = nullptr;
   } gkey;
   ~rwpsf_batch() {   // teardown: failures cannot be reported and are ignored
@@ -519,6 +521,14 @@ static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
   pre[0] = 0;
   for (int i = 0; i < n; ++i) pre[i + 1] = pre[i] + prm[list[i]].D;
   b->items = pre[n];
+  // persistent grid of each class: at least one workgroup per queue, no more than the
+  // configured residency, none for an empty class
+  for (int t = 0; t < 2; ++t) {
+    const long long want =
+        std::max<long long>(8, std::min<long long>(b->class_items[t], (long long)b->num_cus * b->cfg.wg_per_cu));
+    b->class_grid[t] =
+        b->class_items[t] == 0 ? 0 : (int)std::min<long long>(want, (long long)b->num_cus * kMaxWgPerCu);
+  }
 }
 
 static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t st) {
@@ -556,10 +566,8 @@ static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t
   // one launch per tile class, the wide tiles first; at least one workgroup per queue and
   // no more than the configured residency
   for (int t = 1; t >= 0; --t) {
-    if (b->class_items[t] == 0) continue;
-    const long long want =
-        std::max<long long>(8, std::min<long long>(b->class_items[t], (long long)b->num_cus * b->cfg.wg_per_cu));
-    const int grid = (int)std::min<long long>(want, (long long)b->num_cus * kMaxWgPerCu);
+    const int grid = b->class_grid[t];
+    if (grid == 0) continue;
     if (t == 1)
       hipLaunchKernelGGL(batch_planes_kernel<64>, dim3(grid), dim3(256), kBatchLdsBytes, st, a);
     else
@@ -757,6 +765,7 @@ int rwpsf_batch_compute(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I,
   } else {
     const bool same = b->gexec && b->gkey.n == n && b->gkey.I == I && b->gkey.E == E &&
                       b->gkey.wg == b->cfg.wg_per_cu && b->gkey.small == b->cfg.small_tile_max_crop &&
+                      b->gkey.grid[0] == b->class_grid[0] && b->gkey.grid[1] == b->class_grid[1] &&
                       b->gkey.st == st;
     if (!same) {
       if (b->gexec) {
@@ -775,7 +784,7 @@ int rwpsf_batch_compute(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I,
       ce = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if ((rc = hip_check(ce))) return rc;
-      b->gkey = {n, I, E, b->cfg.wg_per_cu, b->cfg.small_tile_max_crop, st};
+      b->gkey = {n, I, E, b->cfg.wg_per_cu, b->cfg.small_tile_max_crop, {b->class_grid[0], b->class_grid[1]}, st};
     }
     rc = hip_check(hipGraphLaunch(b->gexec, st));
   }

@@ -239,3 +239,37 @@ def test_batched_autotune_cache(lib, tmp_path, monkeypatch):
     b2 = _batch(rw, w, 64)
     cfg2, ms2 = b2.autotune(em, I)                    # served from the cache, no timing
     assert cfg2 == cfg1 and abs(ms2 - ms1) < 1e-3
+
+
+def test_batched_graph_recaptures_when_tile_classes_change(lib):
+    """A captured graph launches only the tile classes (and grid sizes) of its capture:
+    a call with the same emitter count and outputs but a crop mix that fills another
+    class must not replay it."""
+    import torch
+    rw = lib
+    n = 40
+    w = W.batched(n_emitters=n, seed=37)
+    b = _batch(rw, w, n)
+    b.set_config(2, 32)
+    s = torch.cuda.Stream()
+    # capture: every crop above 32 (64-wide class only); then: half the crops at most 32
+    crops_a = np.full(n, 48)
+    crops_b = np.where(np.arange(n) % 2 == 0, 24, 40)
+    planes = np.full(n, 3)
+    em_a = _emitters(rw, w, np.arange(n), crops_a, planes)
+    em_b = _emitters(rw, w, np.arange(n), crops_b, planes)
+    size = max(rw.batch_offsets(em_a)[-1], rw.batch_offsets(em_b)[-1])
+    I = torch.zeros(size, dtype=torch.float32, device="cuda")
+    b.set_graph(True)
+    for em in (em_a, em_b):
+        with torch.cuda.stream(s):
+            I.fill_(-1.0)
+            b.compute(em, I=I, stream=s.cuda_stream)
+        s.synchronize()
+        b.set_graph(False)
+        ref = torch.full_like(I, -1.0)
+        b.compute(em, I=ref)
+        torch.cuda.synchronize()
+        b.set_graph(True)
+        np.testing.assert_array_equal(I.cpu().numpy(), ref.cpu().numpy())
+    b.set_graph(False)
