@@ -213,9 +213,10 @@ def test_batched_validation(lib):
     w = W.batched(n_emitters=3, seed=37)
     b = _batch(rw, w, 2)
     import torch
-    I = torch.zeros(100000, dtype=torch.float32, device="cuda")
+    em3 = _emitters(rw, w, np.arange(3))
+    I = torch.zeros(rw.batch_offsets(em3)[-1], dtype=torch.float32, device="cuda")   # output large enough
     with pytest.raises(rw.RwpsfError):
-        b.compute(_emitters(rw, w, np.arange(3)), I=I)            # more than max_emitters
+        b.compute(em3, I=I)                                       # more than max_emitters
     with pytest.raises(rw.RwpsfError):
         b.compute(_emitters(rw, w, np.arange(1), crop=[65]), I=I)  # crop too large
     with pytest.raises(rw.RwpsfError):
