@@ -57,7 +57,8 @@ enum rwpsf_status_code {
   RWPSF_ERR_UNSUPPORTED = -3,      /* option not implemented for this form */
   RWPSF_ERR_OOM = -4,              /* device or host allocation failed */
   RWPSF_ERR_HIP = -5,              /* a HIP runtime call failed; rwpsf_last_hip_error() has the code */
-  RWPSF_ERR_NO_DEVICE = -6         /* no usable gfx950 device */
+  RWPSF_ERR_NO_DEVICE = -6,        /* no usable gfx950 device */
+  RWPSF_ERR_SCRATCH_LIMIT = -7     /* rwpsf_compute_noalloc: one stack needs more than its fixed scratch */
 };
 
 /* RWPSF_FORM_CHIRPZ evaluates the same discrete Cartesian sum as RWPSF_FORM_FOURIER
@@ -180,6 +181,23 @@ size_t rwpsf_plan_device_bytes(const rwpsf_plan* plan);
    Enqueued on `stream`; returns after the enqueue. */
 int rwpsf_compute(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
                   void* E_out, float* I_out, void* stream);
+
+/* Allocation-free variant of rwpsf_compute, for callers that cannot allocate device
+   memory during the call (code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc).  Same arguments, outputs and results as rwpsf_compute; Bessel
+   form only (RWPSF_ERR_UNSUPPORTED otherwise).  The per-call workspace (the pupil x
+   defocus matrix on the theta nodes and the radial integrals I_n) lives in one fixed
+   device array of RWPSF_NOALLOC_SCRATCH_BYTES inside the library, which every device the
+   library runs on holds until the process ends; the call allocates and frees nothing.
+   Stacks go through the array in chunks; a plan whose single stack needs more than the
+   array (per stack: 8 T nz V + 8 nz V G n_rho bytes, T theta nodes, V = 2 with the
+   Fresnel factors else 1, G = 5 with them, 1 scalar, else 3) gets RWPSF_ERR_SCRATCH_LIMIT
+   before anything is enqueued.  All calls on one device share the array and a call
+   leaves its contents behind: calls that may overlap on one device (different streams,
+   or host threads) race and must be serialised by the caller. */
+#define RWPSF_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int rwpsf_compute_noalloc(rwpsf_plan* plan, int n_stacks, const rwpsf_stack* stacks,
+                          void* E_out, float* I_out, void* stream);
 
 /* Adjoint of the Fourier form (the paper differentiates through PyTorch autograd,
    Sec. 4.1; this is the hand-written transposed chain).  Given the fields E_in

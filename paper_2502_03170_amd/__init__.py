@@ -45,6 +45,8 @@ KERNEL_CZT_COLS = 10
 KERNEL_ADJB_RADIAL = 11
 KERNEL_ADJB_CONTRACT = 12
 KERNEL_ADJB_REDUCE = 13
+ERR_SCRATCH_LIMIT = -7
+NOALLOC_SCRATCH_BYTES = 16 << 20
 MAX_ZERNIKE = 36
 CIRCULAR = (1 / math.sqrt(2), 1j / math.sqrt(2))
 
@@ -119,6 +121,7 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "rwpsf_plan_destroy": (None, [c_void_p]),
         "rwpsf_plan_device_bytes": (c_size_t, [c_void_p]),
         "rwpsf_compute": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_void_p]),
+        "rwpsf_compute_noalloc": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_void_p]),
         "rwpsf_plan_set_timing": (c_int, [c_void_p, c_int]),
         "rwpsf_plan_timing": (c_int, [c_void_p, c_int, POINTER(c_double), POINTER(ctypes.c_int64)]),
         "rwpsf_adjoint": (c_int, [c_void_p, c_int, POINTER(Stack), c_void_p, c_void_p, c_int, c_void_p,
@@ -337,16 +340,18 @@ def _stream(stream):
     return c_void_p(torch.cuda.current_stream().cuda_stream if stream is None else stream)
 
 
-def compute(plan, stacks, E=None, I=None, stream=None) -> None:
+def compute(plan, stacks, E=None, I=None, stream=None, noalloc: bool = False) -> None:
     """Enqueue rwpsf_compute for a ``Plan``: E complex64 [stacks][nz][channels][nx][ny] and
     I float32 [stacks][nz][nx][ny] CUDA tensors (either may be None, not both).
-    ``stacks`` is a list of dicts or a ``Stacks``."""
+    ``stacks`` is a list of dicts or a ``Stacks``.  ``noalloc`` calls the allocation-free
+    variant rwpsf_compute_noalloc instead (Bessel form)."""
     import torch
     arr, _keep = _marshal(stacks, plan.num.n_pupil if plan.num.form != FORM_BESSEL else None)
     vox = len(stacks) * plan.nz * plan.nx * plan.ny
     e = check_tensor(E, "E", torch.complex64, vox * plan.nc, required=False)
     i = check_tensor(I, "I", torch.float32, vox, required=False)
-    _check(load().rwpsf_compute(plan.handle, len(stacks), arr, e, i, _stream(stream)))
+    fn = load().rwpsf_compute_noalloc if noalloc else load().rwpsf_compute
+    _check(fn(plan.handle, len(stacks), arr, e, i, _stream(stream)))
 
 
 def adjoint(plan, stacks, E, dL_dI, n_zernike: int, dL_dc=None, dL_dW0=None, stream=None):
@@ -591,14 +596,14 @@ class Plan:
         return load().rwpsf_plan_device_bytes(self.handle)
 
     def compute(self, stacks: list[dict], fields: bool = True, intensity: bool = True, E=None, I=None,
-                stream=None):
+                stream=None, noalloc: bool = False):
         import torch
         b = len(stacks)
         if fields and E is None:
             E = torch.empty((b, self.nz, self.nc, self.nx, self.ny), dtype=torch.complex64, device="cuda")
         if intensity and I is None:
             I = torch.empty((b, self.nz, self.nx, self.ny), dtype=torch.float32, device="cuda")
-        compute(self, stacks, E if fields else None, I if intensity else None, stream)
+        compute(self, stacks, E if fields else None, I if intensity else None, stream, noalloc)
         return E, I
 
     def adjoint_bessel(self, stacks, E, dL_dI, dc=None, dts=None, dz=None, stream=None):

@@ -204,6 +204,8 @@ const char* rwpsf_status_string(int s) {
     case RWPSF_ERR_OOM: return "out of memory";
     case RWPSF_ERR_HIP: return "HIP runtime error";
     case RWPSF_ERR_NO_DEVICE: return "no usable gfx950 device";
+    case RWPSF_ERR_SCRATCH_LIMIT:
+      return "one stack needs more than the fixed scratch of the allocation-free entry point";
     default: return "unknown status";
   }
 }
@@ -298,6 +300,15 @@ int rwpsf_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, void* E, float* I,
     return rw::fourier_compute(p, n, s, (float2*)E, I, (hipStream_t)stream);
   if (p->num.form == RWPSF_FORM_CHIRPZ) return rw::czt_compute(p, n, s, (float2*)E, I, (hipStream_t)stream);
   return rw::bessel_compute(p, n, s, (float2*)E, I, (hipStream_t)stream);
+}
+
+int rwpsf_compute_noalloc(rwpsf_plan* p, int n, const rwpsf_stack* s, void* E, float* I, void* stream) {
+  if (!p) return RWPSF_ERR_INVALID_ARG;
+  if (!E && !I) return RWPSF_ERR_INVALID_ARG;
+  if (p->num.form != RWPSF_FORM_BESSEL) return RWPSF_ERR_UNSUPPORTED;
+  int st = rw::validate_stacks(&p->opt, &p->grid, &p->num, n, s);
+  if (st != RWPSF_OK) return st;
+  return rw::bessel_compute_noalloc(p, n, s, (float2*)E, I, (hipStream_t)stream);
 }
 
 int rwpsf_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const void* E, const float* dLdI,

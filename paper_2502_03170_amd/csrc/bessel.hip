@@ -31,6 +31,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <mutex>
 #include <vector>
 
 #include "rw_common.h"
@@ -348,6 +349,8 @@ __global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const f
 // --------------------------------------------------------------------------
 // Plan and dispatch
 // --------------------------------------------------------------------------
+int bessel_scratch_init(int dev, float** out);
+
 int bessel_plan_init(rwpsf_plan* p) {
   const int R = p->num.n_rho;
   if (6 * R * (int)sizeof(float) > 160 * 1024) return RWPSF_ERR_UNSUPPORTED;  // epilogue stages 6R floats
@@ -414,6 +417,7 @@ int bessel_plan_init(rwpsf_plan* p) {
   if ((st = dev_alloc(p, &p->d_btab, (size_t)G * R * T))) return st;
   if ((st = dev_alloc(p, &p->d_z, (size_t)p->grid.nz))) return st;
   p->bessel_stacks = kPhiStacks;
+  if ((st = bessel_scratch_init(p->device, &p->scratch))) return st;
   if ((st = dev_alloc(p, &p->d_phi, (size_t)T * p->bessel_stacks * p->grid.nz * V))) return st;
   if ((st = dev_alloc(p, (float**)&p->d_In, (size_t)p->bessel_stacks * p->grid.nz * V * 2 * G * R))) return st;
   if (V == 2) {
@@ -447,7 +451,7 @@ int bessel_plan_init(rwpsf_plan* p) {
 }
 
 // Pupil x defocus on the theta nodes for stacks s[0..nb) into the plan's Phi workspace.
-static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st) {
+static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* phi, hipStream_t st) {
   const int T = p->n_theta_total, nz = p->grid.nz;
   PhiArgs pa{};
   pa.T = T;
@@ -475,7 +479,7 @@ static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t s
   const int total = T * cols;
   const int tr = p->time_begin(RWPSF_KERNEL_BESSEL_PHI, st);
   hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, p->d_theta,
-                     p->d_z, p->d_fq, p->d_phi, cols * pa.V);
+                     p->d_z, p->d_fq, phi, cols * pa.V);
   const int rc = hip_check(hipGetLastError());
   p->time_end(tr, st);
   return rc;
@@ -497,7 +501,10 @@ static void bessel_pol(const rwpsf_plan* p, float out[4]) {
   out[3] = (float)ey.imag();
 }
 
-int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
+// Stacks s[0..n) in chunks of up to `chunk` stacks, with Phi and I_n of a chunk in the
+// workspaces phi ([T][chunk nz V] complex) and In ([chunk nz V][2][G][R] float).
+static int bessel_compute_ws(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, float2* phi,
+                             float* In, int chunk, hipStream_t st) {
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != p->device) return RWPSF_ERR_INVALID_ARG;
   if (6 * p->num.n_rho * 4 > 160 * 1024) return RWPSF_ERR_UNSUPPORTED;
@@ -505,16 +512,16 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
   const int mode = p->bessel_mode, G = bessel_groups(mode), V = bessel_variants(mode);
   float pol[4];
   bessel_pol(p, pol);
-  for (int b0 = 0; b0 < n; b0 += kPhiStacks) {
-    const int nb = std::min(kPhiStacks, n - b0);
-    int rc = bessel_phi(p, s + b0, nb, st);
+  for (int b0 = 0; b0 < n; b0 += chunk) {
+    const int nb = std::min(chunk, n - b0);
+    int rc = bessel_phi(p, s + b0, nb, phi, st);
     if (rc) return rc;
     const int cols = nb * nz;
     const int M = 2 * cols * V, N = G * R;
     const int blocks = ((M + RBM - 1) / RBM) * ((N + RBN - 1) / RBN);
     int tr = p->time_begin(RWPSF_KERNEL_BESSEL_CONTRACT, st);
-    hipLaunchKernelGGL(bessel_contract_kernel, dim3(blocks), dim3(256), 0, st, (const float*)p->d_phi,
-                       M, (const float*)p->d_btab, N, (float*)p->d_In, N, M, N, T);
+    hipLaunchKernelGGL(bessel_contract_kernel, dim3(blocks), dim3(256), 0, st, (const float*)phi, M,
+                       (const float*)p->d_btab, N, In, N, M, N, T);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
     EpiArgs ea{};
@@ -538,11 +545,65 @@ int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float*
     }
     tr = p->time_begin(RWPSF_KERNEL_BESSEL_EPILOGUE, st);
     hipLaunchKernelGGL(bessel_epilogue_kernel, dim3(nb * nz), dim3(256), 6 * R * sizeof(float), st, ea,
-                       (const float*)p->d_In, E, I);
+                       (const float*)In, E, I);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
   }
   return RWPSF_OK;
+}
+
+int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
+  return bessel_compute_ws(p, n, s, E, I, p->d_phi, (float*)p->d_In, kPhiStacks, st);
+}
+
+// --------------------------------------------------------------------------
+// Allocation-free evaluation.  Phi and I_n of each chunk of stacks live in `scratch`, a
+// fixed array in the library's device image (each device that loads the library holds
+// its own copy until the process ends), so the call allocates nothing.  The host takes
+// the array's device address once per device with hipGetSymbolAddress, with that device
+// current (at the first Bessel plan created on it) and passes only that address on.
+// Every call on one device shares the array: calls that overlap on a device race.
+// --------------------------------------------------------------------------
+constexpr size_t kScratchFloats = RWPSF_NOALLOC_SCRATCH_BYTES / sizeof(float);
+constexpr size_t kScratchAlign = 64;   // floats (256 bytes) between Phi and I_n
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) float scratch[kScratchFloats];
+
+static std::mutex g_scratch_mutex;
+static float* g_scratch_ptr[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device `dev` (looked up once per device).
+int bessel_scratch_init(int dev, float** out) {
+  *out = nullptr;
+  if (dev < 0 || dev >= kScratchDevices) return RWPSF_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_check(e);
+    if (!ptr) return RWPSF_ERR_HIP;
+    g_scratch_ptr[dev] = (float*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RWPSF_OK;
+}
+
+// Scratch floats one stack of this plan needs (Phi, then I_n), without the alignment gap.
+static size_t bessel_scratch_per_stack(const rwpsf_plan* p) {
+  const size_t V = bessel_variants(p->bessel_mode), G = bessel_groups(p->bessel_mode);
+  const size_t nz = p->grid.nz, T = p->n_theta_total, R = p->num.n_rho;
+  return 2 * T * nz * V + nz * V * 2 * G * R;
+}
+
+int bessel_compute_noalloc(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
+  if (!p->scratch) return RWPSF_ERR_HIP;   // the plan could not resolve the array's address
+  const size_t per = bessel_scratch_per_stack(p);
+  if (per + kScratchAlign > kScratchFloats) return RWPSF_ERR_SCRATCH_LIMIT;
+  const int chunk = (int)std::min<size_t>(kPhiStacks, (kScratchFloats - kScratchAlign) / per);
+  const size_t V = bessel_variants(p->bessel_mode);
+  const size_t phi_floats = 2 * (size_t)p->n_theta_total * chunk * p->grid.nz * V;
+  const size_t in_off = (phi_floats + kScratchAlign - 1) / kScratchAlign * kScratchAlign;
+  return bessel_compute_ws(p, n, s, E, I, (float2*)p->scratch, p->scratch + in_off, chunk, st);
 }
 
 // --------------------------------------------------------------------------
@@ -827,7 +888,7 @@ int bessel_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E, 
   bessel_pol(p, pol);
   for (int b0 = 0; b0 < n; b0 += kPhiStacks) {
     const int nb = std::min(kPhiStacks, n - b0);
-    if ((rc = bessel_phi(p, s + b0, nb, st))) return rc;
+    if ((rc = bessel_phi(p, s + b0, nb, p->d_phi, st))) return rc;
     const int M = 2 * nb * nz * V;
     AdjRadArgs ra{};
     ra.nx = p->grid.nx;

@@ -201,6 +201,7 @@ struct rwpsf_plan {
   float2* d_phi = nullptr;      // workspace [T][stacks][nz][V] pupil x defocus (x q_v)
   float2* d_In = nullptr;       // workspace [stacks][nz][V][re/im][G][R]
   int bessel_stacks = 0;        // capacity of the Bessel workspaces
+  float* scratch = nullptr;     // device address of the allocation-free entry point's fixed array
   double drho = 0;              // radial sample pitch
   // Bessel-form adjoint (built on first use)
   float* d_btabT = nullptr;     // [G][R][T] transposed table

@@ -18,6 +18,7 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
 int czt_plan_init(rwpsf_plan* p);
 int czt_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);
 int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);
+int bessel_compute_noalloc(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);
 int bessel_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E, const float* dLdI, float* dc,
                    float* dts, float* dz, hipStream_t st);
 
