@@ -32,6 +32,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_TFLOPS = 157.3   # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0      # MI355X HBM3E
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 
 
 def sources_digest() -> str:
@@ -48,24 +49,44 @@ def sources_digest() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic(summary: str):
-    """HBM bytes per dispatch from a committed rocprofv3 counter summary under profiles/,
-    or None when it is missing or was taken on other kernel sources."""
+def _summary_text(summary: str):
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", summary)
     try:
-        text = open(path).read()
+        with open(path) as f:
+            return f.read()
     except OSError:
         return None
-    return traffic_from_summary(text, sources_digest())
 
 
-def traffic_from_summary(text: str, digest_now: str):
-    """The summary's bytes per dispatch if it records the digest `digest_now`, else None."""
+def summary_field(text: str, field: str, kernel: str, digest_now: str):
+    """The number recorded as '<field> (<kernel>): <number>' in a profile summary that
+    records the sources digest `digest_now`, else None."""
     digest = re.search(r"sources sha256: ([0-9a-f]{64})", text)
-    traffic = re.search(r"HBM bytes per dispatch: ([0-9]+)", text)
-    if not digest or not traffic or digest.group(1) != digest_now:
+    if not digest or digest.group(1) != digest_now:
         return None
-    return int(traffic.group(1))
+    m = re.search(re.escape(f"{field} ({kernel}):") + r" ([0-9]+(?:\.[0-9]*)?)", text)
+    return float(m.group(1)) if m else None
+
+
+def traffic_from_summary(text: str, kernel: str, digest_now: str):
+    """HBM bytes per dispatch of `kernel` from a summary taken at `digest_now`, else None."""
+    v = summary_field(text, "HBM bytes per dispatch", kernel, digest_now)
+    return None if v is None else int(v)
+
+
+def profiled_traffic(summary: str, kernel: str):
+    """HBM bytes per dispatch of `kernel` from a committed rocprofv3 counter summary under
+    profiles/ (FETCH_SIZE and WRITE_SIZE, scaled by a device copy of known size), or None
+    when it is missing or was taken on other kernel sources."""
+    text = _summary_text(summary)
+    return None if text is None else traffic_from_summary(text, kernel, sources_digest())
+
+
+def profiled_average(summary: str, kernel: str):
+    """Average dispatch duration (us) of `kernel` in the committed rocprofv3 kernel trace of
+    the same bench command, or None when missing or taken on other kernel sources."""
+    text = _summary_text(summary)
+    return None if text is None else summary_field(text, "trace average us", kernel, sources_digest())
 
 
 def fourier_workload():
@@ -120,8 +141,9 @@ def bench_fourier(rw, torch, steps, warmup):
                  for k, v in kt.items()},
         roofline=dict(kernel="gemm_pupil_kernel", bound="mfma", achieved=round(ach_g1, 3),
                       peak=PEAK_FP32_TFLOPS, unit="TFLOP/s", frac=round(ach_g1 / PEAK_FP32_TFLOPS, 4),
-                      traffic=profiled_traffic("gemm_pupil_fourier_plain.txt"), flops_per_launch=per_launch_g1,
-                      avg_launch_us=g1_ms / g1_n * 1e3),
+                      traffic=profiled_traffic("gemm_pupil_fourier_plain.txt", "gemm_pupil_kernel"),
+                      flops_per_launch=per_launch_g1, avg_launch_us=g1_ms / g1_n * 1e3,
+                      profiled_avg_us=profiled_average("gemm_pupil_fourier_plain.txt", "gemm_pupil_kernel")),
         image_gemm=dict(achieved_tflops=round(ach_g2, 3), frac=round(ach_g2 / PEAK_FP32_TFLOPS, 4),
                         flops_per_launch=per_launch_g2, avg_launch_us=g2_ms / g2_n * 1e3),
         step_tflops=round(step_flops / (ms_step * 1e-3) / 1e12, 3),
@@ -134,7 +156,7 @@ def bench_chirpz(rw, torch, steps, warmup):
     w, zp, stacks = fourier_workload()
     o = w["optics"]
 
-    def run(form, n, st, nsteps):
+    def run(form, n, st, nsteps, timing=False):
         plan = rw.Plan(form=form, na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], nx=128, ny=128, dx=20.0,
                        dy=20.0, z=zp, e_inc=w["e_inc"], gibson_lanni=w["gl"], n_pupil=n)
         E = torch.empty((len(st), 64, 3, 128, 128), dtype=torch.complex64, device="cuda")
@@ -142,22 +164,47 @@ def bench_chirpz(rw, torch, steps, warmup):
         for _ in range(warmup):
             plan.compute(st, E=E, I=I)
         torch.cuda.synchronize()
+        if timing:
+            plan.set_timing(True)
         t0 = time.perf_counter()
         for _ in range(nsteps):
             plan.compute(st, E=E, I=I)
         torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / nsteps
+        kt = {k: plan.timing(v) for k, v in (("czt_rows", rw.KERNEL_CZT_ROWS), ("czt_cols", rw.KERNEL_CZT_COLS))}
         plan.close()
-        return (time.perf_counter() - t0) * 1e3 / nsteps
+        return (ms, kt) if timing else ms
 
-    ms = run(rw.FORM_CHIRPZ, 256, stacks, steps)
+    ms, kt = run(rw.FORM_CHIRPZ, 256, stacks, steps, timing=True)
     voxels = len(stacks) * 64 * 128 * 128
+    # algorithmic work: one forward and one inverse FFT of length L per transformed line,
+    # 5 L log2 L flop each (split-radix-free count); the y pass transforms the N pupil rows,
+    # the x pass the nx output columns, of every (stack, plane, component)
+    L, n, nx = 512, 256, 128
+    lines = len(stacks) * 64 * 3
+    rows_flops = lines * n * 2 * 5.0 * L * math.log2(L)
+    cols_flops = lines * nx * 2 * 5.0 * L * math.log2(L)
+    r_ms, r_n = kt["czt_rows"]
+    c_ms, c_n = kt["czt_cols"]
+    per_launch = rows_flops * steps / r_n
+    ach = per_launch / (r_ms / r_n * 1e-3) / 1e12
+    ach_c = cols_flops * steps / c_n / (c_ms / c_n * 1e-3) / 1e12
     cross = {}
     for n in (128, 256, 512, 1024):
         cross[str(n)] = dict(matrix_dft_ms=run(rw.FORM_FOURIER, n, stacks[:8], 3),
                              chirpz_ms=run(rw.FORM_CHIRPZ, n, stacks[:8], 3))
     return dict(workload="chirp-z evaluation of the fourier_plain workload (same sum, FFT convolutions of "
                          "length 512 along y and x)", value=voxels / (ms * 1e-3), unit="voxels/s",
-                ms_per_step=ms, crossover_8_stacks_128x128x64=cross)
+                ms_per_step=ms, crossover_8_stacks_128x128x64=cross,
+                kernels={k: dict(total_ms=v[0], launches=v[1], avg_us=(v[0] / v[1] * 1e3 if v[1] else None))
+                         for k, v in kt.items()},
+                roofline=dict(kernel="czt_rows_kernel<512>", bound="alu", achieved=round(ach, 3),
+                              peak=PEAK_FP32_TFLOPS, unit="TFLOP/s", frac=round(ach / PEAK_FP32_TFLOPS, 4),
+                              traffic=profiled_traffic("czt_chirpz_fourier_plain.txt", "czt_rows_kernel"),
+                              flops_per_launch=per_launch, avg_launch_us=r_ms / r_n * 1e3,
+                              profiled_avg_us=profiled_average("czt_chirpz_fourier_plain.txt", "czt_rows_kernel")),
+                cols_kernel=dict(kernel="czt_cols_kernel<512>", achieved_tflops=round(ach_c, 3),
+                                 frac=round(ach_c / PEAK_FP32_TFLOPS, 4)))
 
 
 def bench_speed_sweep(rw, torch, reps=10):
@@ -242,7 +289,9 @@ def bench_bessel(rw, torch, steps, warmup, n_stacks=256):
                          for k, v in kt.items()},
                 roofline=dict(kernel="bessel_epilogue_kernel", bound="hbm", achieved=round(ach, 1),
                               peak=PEAK_HBM_GBS, unit="GB/s", frac=round(ach / PEAK_HBM_GBS, 4),
-                              traffic=None, bytes_per_launch=bytes_per_launch))
+                              traffic=profiled_traffic("bessel_bessel_plain.txt", "bessel_epilogue_kernel"),
+                              bytes_per_launch=bytes_per_launch, avg_launch_us=e_ms / e_n * 1e3,
+                              profiled_avg_us=profiled_average("bessel_bessel_plain.txt", "bessel_epilogue_kernel")))
 
 
 def _cuda_time(torch, fn, reps):
@@ -286,7 +335,9 @@ def bench_batched(rw, torch, steps, warmup):
                 autotuned_config=dict(wg_per_cu=cfg[0], small_tile_max_crop=cfg[1]),
                 roofline=dict(kernel="batch_planes_kernel (+ phase GEMM)", bound="mfma",
                               achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
-                              frac=round(ach / PEAK_FP32_TFLOPS, 4), traffic=None, flops_per_launch=flops))
+                              frac=round(ach / PEAK_FP32_TFLOPS, 4),
+                              traffic=profiled_traffic("batch_planes_batched.txt", "batched call"),
+                              flops_per_launch=flops, avg_launch_us=ms * 1e3))
 
 
 def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
@@ -331,7 +382,8 @@ def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
                 kernels={k: dict(total_ms=v[0], launches=v[1], avg_us=(v[0] / v[1] * 1e3 if v[1] else None))
                          for k, v in kt.items()},
                 roofline=dict(kernel="whole step", bound="mfma", achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS,
-                              unit="TFLOP/s", frac=round(ach / PEAK_FP32_TFLOPS, 4), traffic=None,
+                              unit="TFLOP/s", frac=round(ach / PEAK_FP32_TFLOPS, 4),
+                              traffic=profiled_traffic("adjoint_adjoint.txt", "adjoint step"),
                               flops_per_step=fwd + adj))
 
 
@@ -378,93 +430,217 @@ def bench_adjoint_bessel(rw, torch, steps, warmup, n_stacks=64):
                                           ("adjb_reduce", rw.KERNEL_ADJB_REDUCE))}
     plan.close()
     vox = n_stacks * nz * 65 * 65
+    nsteps = max(3, steps // 4)         # the timed repetitions
+    r_ms, r_n = kt["adjb_radial"]
+    # algorithmic bytes of the transposed interpolation: E (24 B) and dL/dI (4 B) read per voxel
+    bytes_per_launch = 28.0 * vox * nsteps / r_n if r_n else None
+    ach = bytes_per_launch / (r_ms / r_n * 1e-3) / 1e9 if r_n else None
     return dict(workload=f"Bessel adjoint: {n_stacks} stacks of 65x65x{nz} at 20 nm, Gibson-Lanni depths "
                          "U[0, 5] um, m = 0 Zernike; step = forward (fields) + adjoint (dL/dc, dL/dt_s, dL/dz)",
                 value=vox / (ms * 1e-3), unit="voxels/s (forward+adjoint)", ms_per_step=ms,
                 gradient_steps_per_s=1e3 / ms,
                 kernels={k: dict(total_ms=v[0], launches=v[1], avg_us=(v[0] / v[1] * 1e3 if v[1] else None))
-                         for k, v in kt.items()})
+                         for k, v in kt.items()},
+                roofline=dict(kernel="adjb_radial_kernel", bound="hbm", achieved=ach and round(ach, 1),
+                              peak=PEAK_HBM_GBS, unit="GB/s", frac=ach and round(ach / PEAK_HBM_GBS, 4),
+                              traffic=profiled_traffic("adjb_bessel_adjoint.txt", "adjb_radial_kernel"),
+                              bytes_per_launch=bytes_per_launch, avg_launch_us=r_n and r_ms / r_n * 1e3,
+                              note="bound in practice by its LDS atomics, not by HBM"))
 
 
-def bench_surrogate(rw, torch, train_seconds):
+def surrogate_flops_per_crop() -> float:
+    """Algorithmic flops of one surrogate crop: the dense layers (22->1024->1024->1024, the
+    basis branch 1024->256->4096) and the three transposed convolutions (each output takes
+    Ci x 4 taps: 16x16x16 outputs x 64, 8x32x32 x 64, 64x64 x 32)."""
+    dense = 22 * 1024 + 1024 * 1024 * 2 + 1024 * 256 + 256 * 4096
+    conv = 16 * 16 * 16 * 64 + 8 * 32 * 32 * 64 + 64 * 64 * 32
+    return 2.0 * (dense + conv)
+
+
+def bench_surrogate(rw, torch, train_seconds, bar=0.1):
+    """Train the surrogate for about `train_seconds` on 200000 engine crops, fit its
+    error-gated fallback at the stated bar (p95 rel-L2 of the crops the network serves)
+    on 4096 calibration crops, judge it on 2048 held-out crops, and time inference and
+    gated serving against the plain path on 65536 inputs."""
     from paper_2502_03170_amd import surrogate_train as ST
     eng = ST.CropEngine(max_emitters=4096)
     train = ST.make_dataset(eng, 200_000, seed=505)
+    calib = ST.make_dataset(eng, 4096, seed=507)
     test = ST.make_dataset(eng, 2048, seed=506)
+    basis = ST.crop_basis(train, 4096)
     sg = rw.Surrogate(max_batch=65536)
-    sg.set_state(ST.init_params(0))
+    sg.set_state(ST.init_params(0, basis=basis))
     # time a short run (after a few untimed steps that absorb first-call costs) to size
     # the schedule to the budget, then one cosine schedule from fresh parameters
-    ST.train(sg, train, steps=20, batch=256, lr=2e-3, seed=0, log_every=20)
+    ST.train(sg, train, steps=20, batch=ST.BATCH, lr=1e-5, seed=0, log_every=20)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ST.train(sg, train, steps=50, batch=256, lr=2e-3, seed=0, log_every=50)
+    ST.train(sg, train, steps=30, batch=ST.BATCH, lr=1e-5, seed=0, log_every=30)
     torch.cuda.synchronize()
-    per_step = (time.perf_counter() - t0) / 50
+    per_step = (time.perf_counter() - t0) / 30
     steps = max(100, int(train_seconds / per_step))
-    sg.set_state(ST.init_params(0))
+    sg.set_state(ST.init_params(0, basis=basis))
     t0 = time.perf_counter()
-    ST.train(sg, train, steps=steps, batch=256, lr=2e-3, lr_end=1e-4, seed=1, log_every=max(1, steps // 4))
+    ST.train(sg, train, steps=steps, batch=ST.BATCH, lr=ST.LR, lr_end=1e-5, seed=1, log_every=max(1, steps // 4))
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    acc = {p: ST.audit(sg, eng, test, precision=p) for p in (rw.SG_BF16X3, rw.SG_BF16)}
-    base = ST.mean_crop_baseline(train, test)
+    print(f"# surrogate: {steps} training steps in {train_s:.0f} s", file=sys.stderr, flush=True)
+    acc = {name: ST.audit(sg, eng, test, precision=p) for name, p in (("bf16x3", rw.SG_BF16X3), ("bf16", rw.SG_BF16))}
+    gate = ST.fit_gate(sg, calib, bar)
+    judged = ST.judge(sg, eng, test, gate)
     B = 65536
-    coef, z = train["coef"][:B].contiguous(), train["z"][:B].contiguous()
+    serve = ST.make_dataset(eng, B, seed=508)
+    coef, z = serve["coef"], serve["z"]
     out = torch.empty((B, 64, 64), dtype=torch.float32, device="cuda")
     res = {}
+    flops = surrogate_flops_per_crop() * B
     for name, p in (("bf16x3", rw.SG_BF16X3), ("bf16", rw.SG_BF16)):
         sg.forward(coef, z, out=out, precision=p)
-        ms = _cuda_time(torch, lambda: sg.forward(coef, z, out=out, precision=p), 3)
-        res[name] = dict(ms_per_batch=ms, crops_per_s=B / (ms * 1e-3), px_per_s=B * 4096 / (ms * 1e-3))
-    em = rw.make_emitters(np.zeros(4096), np.zeros(4096), -z[:4096].double().cpu().numpy(), [64] * 4096,
-                          [1] * 4096, coef[:4096].double().cpu().numpy())
-    I = torch.empty(4096 * 4096, dtype=torch.float32, device="cuda")
-    eng.batch.compute(em, I=I)
-    ms_plain = _cuda_time(torch, lambda: eng.batch.compute(em, I=I), 3) * (B / 4096)
+        ms = _cuda_time(torch, lambda: sg.forward(coef, z, out=out, precision=p), 5)
+        res[name] = dict(ms_per_batch=ms, crops_per_s=B / (ms * 1e-3), px_per_s=B * 4096 / (ms * 1e-3),
+                         tflops=flops / (ms * 1e-3) / 1e12)
+
+    def wall(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    plain_ms = wall(lambda: eng.crops(coef, z))
+    gated_ms = wall(lambda: ST.predict(sg, eng, coef, z, gate))
+    _, fb = ST.predict(sg, eng, coef, z, gate)
+    fallback_serve = float(fb.float().mean().item())
+    # context: the plain path on a 32 x 32 pupil (its aliasing period, 6.9 um, still exceeds
+    # the 6.4 um crop) against the 128 x 128 reference crops
+    coarse = ST.CropEngine(max_emitters=4096, n_pupil=32)
+    cc = coarse.crops(test["coef"], test["z"]) * (coarse.norm / eng.norm)
+    ec = ST.rel_l2_per_crop(cc, test["target"]).cpu().numpy()
+    coarse_ms = wall(lambda: coarse.crops(coef, z))
     sg.close()
-    return dict(workload="surrogate: (Noll 1-21, z) -> 64x64 crop, 2.38M parameters, trained on 200000 engine "
-                         "crops (Noll 4-21 N(0,0.05), z U(+-1 um), 128x128 pupil, 100 nm pixels) for "
-                         f"{steps} Adam steps of 256 ({train_s:.0f} s); inference batch 65536",
-                value=res["bf16"]["px_per_s"], unit="px/s (inference, bf16)", inference=res,
-                plain_path=dict(ms_per_batch=ms_plain, crops_per_s=B / (ms_plain * 1e-3),
-                                px_per_s=B * 4096 / (ms_plain * 1e-3)),
-                speedup_vs_plain=dict(bf16=ms_plain / res["bf16"]["ms_per_batch"],
-                                      bf16x3=ms_plain / res["bf16x3"]["ms_per_batch"]),
-                accuracy_vs_plain=dict(bf16x3=acc[rw.SG_BF16X3], bf16=acc[rw.SG_BF16]),
-                mean_crop_predictor=base, train_ms_per_step=train_s * 1e3 / steps,
-                train_steps=steps)
+    ach = res["bf16x3"]["tflops"]
+    return dict(workload="surrogate: (Noll 1-21, z) -> 64x64 crop, 3.44M parameters (3 dense layers of 1024, a "
+                         "256-crop basis branch and a transposed-convolution branch), trained on 200000 engine crops "
+                         "(Noll 4-21 N(0,0.05), z U(+-1 um), 128x128 pupil, 100 nm pixels) for "
+                         f"{steps} Adam steps of {ST.BATCH} ({train_s:.0f} s); inference batch 65536",
+                value=res["bf16x3"]["px_per_s"], unit="px/s (inference, bf16x3: FP32-level products)",
+                inference=res,
+                roofline=dict(kernel="whole inference (dense GEMMs + fused decoder)", bound="mfma",
+                              achieved=round(ach, 2), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
+                              frac=round(ach / PEAK_BF16_TFLOPS, 4), traffic=None,
+                              flops_per_batch=flops,
+                              note="bf16x3 executes three BF16 products per algorithmic one"),
+                accuracy_network_vs_plain=acc,
+                gate=dict(bar=f"p95 rel-L2 <= {bar} over the crops the network serves", bar_value=bar,
+                          calibration_crops=4096, accepted_on_calibration=gate["accepted_calibration"],
+                          error_model_corr=gate["fit_corr"]),
+                judged_held_out=judged,
+                serving_65536=dict(plain_ms=plain_ms, gated_ms=gated_ms, fallback_fraction=fallback_serve,
+                                   gain_vs_plain=plain_ms / gated_ms,
+                                   plain_crops_per_s=B / (plain_ms * 1e-3), gated_crops_per_s=B / (gated_ms * 1e-3)),
+                plain_pupil_32=dict(median_rel_l2=float(np.median(ec)), p95_rel_l2=float(np.percentile(ec, 95)),
+                                    ms_per_65536=coarse_ms, crops_per_s=B / (coarse_ms * 1e-3)),
+                train_ms_per_step=train_s * 1e3 / steps, train_steps=steps, train_batch=ST.BATCH)
+
+
+def cpu_model() -> str | None:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_separable_rate(seconds: float, threads: int | None):
+    """Voxels/s of the separable FP64 oracle (pupil build included) over the headline
+    workload's stacks in order, with BLAS limited to `threads` (None: as configured)."""
+    from contextlib import nullcontext
+
+    from oracle import fourier as OF
+    from tests.helpers import oracle_optics
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(threads) if threads else nullcontext()
+    except ImportError:
+        ctx = nullcontext()
+    w, _, _ = fourier_workload()
+    opt = oracle_optics(w)
+    g = OF.pupil_geometry(256, opt)
+    planes = 0
+    with ctx:
+        t0 = time.perf_counter()
+        b = 0
+        while time.perf_counter() - t0 < seconds:
+            s = b % 16
+            P = OF.base_pupil(g, opt, OF.pupil_phase(g, opt, zernike=w["zernike"][s], t_s=w["t_s"][s]))
+            for z in w["z"][s]:
+                OF.field_separable(P, g, opt, 128, 128, 20.0, 20.0, [z])
+                planes += 1
+                if time.perf_counter() - t0 > seconds:
+                    break
+            b += 1
+        dt = time.perf_counter() - t0
+    return planes * 128 * 128 / dt, planes, dt
+
+
+def _oracle_direct_rate(seconds: float):
+    """Voxels/s of the brute-force double sum over the pupil (one complex exponential of
+    the whole phase per cell and voxel) on seeded voxels of the first headline stack."""
+    from oracle import fourier as OF
+    from oracle import optics as O
+    from tests.helpers import oracle_optics
+    w, _, _ = fourier_workload()
+    opt = oracle_optics(w)
+    g = OF.pupil_geometry(256, opt)
+    P = OF.base_pupil(g, opt, OF.pupil_phase(g, opt, zernike=w["zernike"][0], t_s=w["t_s"][0]))
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(2024)
+    xs, ys = O.output_axis(128, 20.0), O.output_axis(128, 20.0)
+    n = 0
+    try:
+        from threadpoolctl import threadpool_limits
+        ctx = threadpool_limits(1)
+    except ImportError:
+        from contextlib import nullcontext
+        ctx = nullcontext()
+    with ctx:
+        while time.perf_counter() - t0 < seconds:
+            pts = np.stack([xs[rng.integers(0, 128, 64)], ys[rng.integers(0, 128, 64)],
+                            w["z"][0][rng.integers(0, 64, 64)]], axis=1)
+            OF.field_direct(P, g, opt, pts)
+            n += 64
+    dt = time.perf_counter() - t0
+    return n / dt, n, dt
 
 
 def cpu_baseline(seconds: float):
-    """The FP64 oracle (pupil build + separable evaluation) on whole stacks for about `seconds`."""
-    from oracle import fourier as OF
-    from tests.helpers import oracle_optics
+    """The FP64 oracle on the host cores: the separable evaluation (whole planes, pupil
+    build included) with every core BLAS uses and with one thread, and the brute-force
+    double sum on seeded voxels; `seconds` is split 2 : 1 : 1 between the three."""
     try:
         from threadpoolctl import threadpool_info
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         threads = 1
-    w, zp, _ = fourier_workload()
-    opt = oracle_optics(w)
-    g = OF.pupil_geometry(256, opt)
-    t0 = time.perf_counter()
-    planes = 0
-    b = 0
-    while time.perf_counter() - t0 < seconds:
-        s = b % 16
-        P = OF.base_pupil(g, opt, OF.pupil_phase(g, opt, zernike=w["zernike"][s], t_s=w["t_s"][s]))
-        for z in w["z"][s]:
-            OF.field_separable(P, g, opt, 128, 128, 20.0, 20.0, [z])
-            planes += 1
-            if time.perf_counter() - t0 > seconds:
-                break
-        b += 1
-    dt = time.perf_counter() - t0
-    return dict(value=planes * 128 * 128 / dt, unit="voxels/s", cores=threads, kind="oracle",
-                sample=f"separable FP64 oracle (pupil build included) over the headline workload's "
-                       f"stacks in order: {planes} planes of 128x128 (3 field components), {dt:.1f} s, "
-                       f"NumPy/BLAS threads = {threads}")
+    affinity = len(os.sched_getaffinity(0))
+    v_all, planes_all, dt_all = _oracle_separable_rate(seconds * 0.5, None)
+    v_one, planes_one, dt_one = _oracle_separable_rate(seconds * 0.25, 1)
+    v_dir, n_dir, dt_dir = _oracle_direct_rate(seconds * 0.25)
+    return dict(value=v_all, unit="voxels/s", cores=threads, kind="oracle",
+                sample=f"separable FP64 oracle (pupil build included) over the headline workload's stacks in "
+                       f"order: {planes_all} planes of 128x128 (3 field components) in {dt_all:.1f} s with "
+                       f"{threads} BLAS threads; the same with 1 thread: {planes_one} planes in {dt_one:.1f} s; "
+                       f"brute-force double sum over the 51,468-cell disk: {n_dir} seeded voxels of stack 0 in "
+                       f"{dt_dir:.1f} s (1 thread)",
+                cpu_model=cpu_model(), affinity_cores=affinity, blas_threads=threads,
+                single_thread=dict(value=v_one, unit="voxels/s", planes=planes_one, seconds=dt_one),
+                direct_double_sum=dict(value=v_dir, unit="voxels/s", voxels=n_dir, seconds=dt_dir,
+                                       threads=1))
 
 
 def main():
@@ -472,11 +648,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="chirpz,sweep,bessel,batched,adjoint,adjoint_bessel,surrogate",
                     help="comma list of extra forms, or 'none'")
-    ap.add_argument("--train-seconds", type=float, default=20.0)
+    ap.add_argument("--train-seconds", type=float, default=90.0)
     ap.add_argument("--copy-reference", action="store_true",
                     help="also run a 256 MiB device-to-device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()
@@ -522,7 +698,7 @@ def main():
               flush=True)
     if "surrogate" in args.forms.split(","):
         forms["surrogate"] = bench_surrogate(rw, torch, args.train_seconds)
-        print(f"# surrogate: {forms['surrogate']['speedup_vs_plain']}", file=sys.stderr, flush=True)
+        print(f"# surrogate: {forms['surrogate']['serving_65536']}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.cpu_seconds)

@@ -302,19 +302,25 @@ int rwpsf_batch_autotune(rwpsf_batch* batch, int n, const rwpsf_emitter* emitter
                          void* stream, rwpsf_batch_config* best, double* best_ms);
 
 /* ---- learned surrogate ----------------------------------------------------------
-   A network (~2.4M parameters) from 21 Noll coefficients (waves) and a defocus z (nm)
+   A network (3.44M parameters) from 21 Noll coefficients (waves) and a defocus z (nm)
    to a 64 x 64 intensity crop, trained on crops this engine generates (the paper
    motivates PSF models as generators of training data for networks, Sec. 6):
-     x = (c / 0.05, z / 1000); three dense layers 22 -> 256 -> 1024 -> 2048 with relu;
-     2048 read as 32 x 8 x 8; three stride-2 transposed convolutions (4 x 4 kernel,
-     padding 1) 32 -> 16 -> 8 -> 1 channels, relu after the first two.
-   Parameters are one flat FP32 array in the order W1 [22][256], b1, W2 [256][1024], b2,
-   W3 [1024][2048], b3, K1 [32][16][4][4], c1, K2 [16][8][4][4], c2, K3 [8][1][4][4], c3
-   (rwpsf_sg_param_count values).  Dense layers run on the BF16 matrix cores; with
-   RWPSF_SG_BF16X3 each operand is split into two BF16 parts (FP32-level accuracy),
-   with RWPSF_SG_BF16 only the leading parts are multiplied.  All device arrays are
-   caller-owned except the parameters, gradients and Adam moments, which the handle
-   owns.  Gradient reductions run in a fixed order. */
+     x = (c / 0.05, z / 1000); dense layers 22 -> 1024 -> 1024 -> 1024 (h3), relu;
+     convolution branch: h3 read as 16 x 8 x 8, three stride-2 transposed convolutions
+       (4 x 4 kernel, padding 1) 16 -> 16 -> 8 -> 1 channels, relu after the first two;
+     basis branch: a = h3 Wa + ba (256 coefficients, linear), a Wb + bb (a learned basis
+       of 256 crops plus a mean crop);
+     output = convolution branch + basis branch.
+   Parameters are one flat FP32 array in the order W1 [22][1024], b1, W2 [1024][1024], b2,
+   W3 [1024][1024], b3, K1 [16][16][4][4], c1, K2 [16][8][4][4], c2, K3 [8][1][4][4], c3,
+   Wa [1024][256], ba, Wb [256][4096], bb (rwpsf_sg_param_count values).  Dense layers
+   and the first two transposed convolutions run on the BF16 matrix cores (the
+   convolutions as implicit GEMMs per output parity class); the last convolution runs in
+   FP32.  With RWPSF_SG_BF16X3 each matrix-core operand is split into two BF16 parts and
+   three products are summed (FP32-level accuracy, about 1e-6 relative); with
+   RWPSF_SG_BF16 only the leading parts are multiplied (about 1e-2 relative).  All device
+   arrays are caller-owned except the parameters, gradients and Adam moments, which the
+   handle owns.  Gradient reductions run in a fixed order. */
 enum rwpsf_sg_precision { RWPSF_SG_BF16X3 = 0, RWPSF_SG_BF16 = 1 };
 typedef struct rwpsf_sg rwpsf_sg;
 size_t rwpsf_sg_param_count(void);
@@ -335,6 +341,16 @@ int rwpsf_sg_gradient(rwpsf_sg* sg, int B, const float* coef, const float* z, co
                       float* loss, void* stream);
 /* One Adam step (Kingma & Ba, bias-corrected) on the FP32 parameters with the stored gradient. */
 int rwpsf_sg_adam(rwpsf_sg* sg, float lr, float beta1, float beta2, float eps, void* stream);
+/* Error model of the surrogate's fallback gate: the predicted log rel-L2 of a crop against
+   the plain path is w . phi(c, z), phi = (1, (c_1/0.05)^2 .. (c_21/0.05)^2, (z/1000)^2,
+   |z|/1000) (RWPSF_SG_GATE_FEATURES values; c in waves, z in nm).  The weights are fitted
+   by the caller on crops judged by the plain path.  rwpsf_sg_error_features writes phi
+   (device float [B][24]); rwpsf_sg_error_predict writes w . phi (device float [B]) for
+   device weights w [24].  coef device float [B][21], z device float [B]. */
+#define RWPSF_SG_GATE_FEATURES 24
+int rwpsf_sg_error_features(int B, const float* coef, const float* z, float* phi, void* stream);
+int rwpsf_sg_error_predict(int B, const float* coef, const float* z, const float* weights, float* log_err,
+                           void* stream);
 
 /* ---- per-kernel timing, for benchmarking -------------------------------------
    When enabled, every kernel the plan launches is bracketed by HIP events on

@@ -31,6 +31,7 @@ MODEL_SCALAR = 1
 THETA_GAUSS = 0
 THETA_SIMPSON = 1
 THETA_RIEMANN = 2
+SG_GATE_FEATURES = 24
 KERNEL_PUPIL_BUILD = 0
 KERNEL_GEMM_PUPIL = 1
 KERNEL_GEMM_IMAGE = 2
@@ -138,6 +139,8 @@ def load(path: str | None = None) -> ctypes.CDLL:
         "rwpsf_sg_gradient": (c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
         "rwpsf_sg_adam": (c_int, [c_void_p, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   c_void_p]),
+        "rwpsf_sg_error_features": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+        "rwpsf_sg_error_predict": (c_int, [c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
         "rwpsf_batch_create": (c_int, [POINTER(Optics), c_int, c_double, c_double, c_int, POINTER(c_void_p)]),
         "rwpsf_batch_destroy": (None, [c_void_p]),
         "rwpsf_batch_offsets": (c_int, [c_int, POINTER(Emitter), POINTER(ctypes.c_int64)]),
@@ -426,16 +429,27 @@ def psf_function():
 
 
 def make_emitters(x0, y0, z, crop, planes, zernike, t_s=None):
-    """``t_s``: per-emitter depth below the coverslip (nm), read with the Gibson-Lanni layer."""
+    """An rwpsf_emitter array from per-emitter sequences (filled through a NumPy view of the
+    ctypes array, field by field).  ``t_s``: per-emitter depth below the coverslip (nm),
+    read with the Gibson-Lanni layer."""
+    import numpy as np
     n = len(x0)
     arr = (Emitter * n)()
-    for i in range(n):
-        arr[i].x0_nm, arr[i].y0_nm, arr[i].z_nm = float(x0[i]), float(y0[i]), float(z[i])
-        arr[i].t_s_nm = 0.0 if t_s is None else float(t_s[i])
-        arr[i].crop, arr[i].planes = int(crop[i]), int(planes[i])
-        c = zernike[i]
-        for q in range(min(len(c), BATCH_MAX_ZERNIKE)):
-            arr[i].zernike_waves[q] = float(c[q])
+    if n == 0:
+        return arr
+    dt = np.dtype({"names": [f[0] for f in Emitter._fields_],
+                   "formats": ["f8", "f8", "f8", "i4", "i4", ("f8", (BATCH_MAX_ZERNIKE,)), "f8"],
+                   "offsets": [getattr(Emitter, f[0]).offset for f in Emitter._fields_],
+                   "itemsize": ctypes.sizeof(Emitter)})
+    v = np.frombuffer(arr, dtype=dt)
+    v["x0_nm"], v["y0_nm"], v["z_nm"] = (np.asarray(a, dtype=np.float64).reshape(n) for a in (x0, y0, z))
+    v["t_s_nm"] = 0.0 if t_s is None else np.asarray(t_s, dtype=np.float64).reshape(n)
+    v["crop"], v["planes"] = (np.asarray(a).reshape(n).astype(np.int32) for a in (crop, planes))
+    c = np.zeros((n, BATCH_MAX_ZERNIKE))
+    zz = np.asarray(zernike, dtype=np.float64).reshape(n, -1)
+    q = min(zz.shape[1], BATCH_MAX_ZERNIKE)
+    c[:, :q] = zz[:, :q]
+    v["zernike_waves"] = c
     return arr
 
 
@@ -555,6 +569,27 @@ class Surrogate:
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
         _check(load().rwpsf_sg_adam(self.handle, lr, beta1, beta2, eps, _stream(stream)))
+
+    def error_features(self, coef, z, out=None, stream=None):
+        """Features phi(c, z) [B][24] of the gate's error model (rwpsf_sg_error_features)."""
+        import torch
+        B, c, zz = self._inputs(coef, z)
+        if out is None:
+            out = torch.empty((B, SG_GATE_FEATURES), dtype=torch.float32, device="cuda")
+        o = check_tensor(out, "out", torch.float32, B * SG_GATE_FEATURES)
+        _check(load().rwpsf_sg_error_features(B, c, zz, o, _stream(stream)))
+        return out
+
+    def error_predict(self, coef, z, weights, out=None, stream=None):
+        """Predicted log rel-L2 w . phi(c, z) [B] for the gate weights w [24]."""
+        import torch
+        B, c, zz = self._inputs(coef, z)
+        w = check_tensor(weights, "weights", torch.float32, SG_GATE_FEATURES)
+        if out is None:
+            out = torch.empty(B, dtype=torch.float32, device="cuda")
+        o = check_tensor(out, "out", torch.float32, B)
+        _check(load().rwpsf_sg_error_predict(B, c, zz, w, o, _stream(stream)))
+        return out
 
     def close(self):
         if self.handle:

@@ -1,19 +1,23 @@
 // Learned surrogate of the PSF engine: (21 Noll coefficients, z) -> 64 x 64 intensity.
 //
 //   x  = (c / 0.05, z / 1000 nm)                                   22 features
-//   h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), h3 = relu(h2 W3 + b3)   256, 1024, 2048
-//   d1 = relu(T(h3 as 32x8x8; K1) + c1)    16 x 16 x 16
-//   d2 = relu(T(d1; K2) + c2)              8 x 32 x 32
-//   y  = T(d2; K3) + c3                    64 x 64
+//   h1 = relu(x W1 + b1), h2 = relu(h1 W2 + b2), h3 = relu(h2 W3 + b3)   1024 each
+//   convolution branch:
+//     d1 = relu(T(h3 as 16x8x8; K1) + c1)  16 x 16 x 16
+//     d2 = relu(T(d1; K2) + c2)            8 x 32 x 32
+//     yd = T(d2; K3) + c3                  64 x 64
+//   basis branch: a = h3 Wa + ba (256), yb = a Wb + bb (64 x 64)
+//   y = yd + yb
 // T: stride-2 transposed convolution, 4 x 4 kernel, 1 pixel padding,
 //   out[co, oy, ox] = sum_{ci,ky,kx} in[ci, iy, ix] K[ci, co, ky, kx], oy = 2 iy - 1 + ky.
 //
 // Dense layers run on the BF16 matrix cores (v_mfma_f32_32x32x16_bf16, FP32
 // accumulate).  In the accurate mode every operand is split x = hi + lo with hi,
 // lo in BF16 and the product is hi*hi + hi*lo + lo*hi (relative error ~1e-5); the
-// fast mode uses hi*hi only.  Transposed convolutions are direct FP32 kernels: the
-// forward computes all output channels of one pixel per thread with the weights read
-// as wave-uniform scalars; the backward kernels stage a sample in LDS.  Weight gradients of the convolutions
+// fast mode uses hi*hi only.  The forward transposed convolutions run in one fused
+// kernel per sample: the first two as implicit GEMMs on v_mfma_f32_16x16x32_bf16 (same
+// splitting), the last (one output channel) in FP32, activations in LDS.  The backward
+// kernels stage a sample in LDS (FP32).  Weight gradients of the convolutions
 // and all bias gradients are reduced over the batch in a fixed order through
 // per-chunk partial sums; training updates FP32 master weights with Adam.
 #include <algorithm>
@@ -40,7 +44,7 @@ template <bool TA, bool TB, int NSPLIT>
 __global__ void __launch_bounds__(256) sg_gemm_kernel(const float* __restrict__ A, int lda,
                                                       const float* __restrict__ B, int ldb,
                                                       float* __restrict__ C, int ldc, int M, int N, int K,
-                                                      const float* __restrict__ bias, int relu) {
+                                                      const float* __restrict__ bias, int relu, int accumulate) {
   __shared__ float As[SBM * SLD];
   __shared__ float Bs[SBN * SLD];
   const int tiles_n = (N + SBN - 1) / SBN;
@@ -101,7 +105,7 @@ __global__ void __launch_bounds__(256) sg_gemm_kernel(const float* __restrict__ 
   for (int r = 0; r < 16; ++r) {
     const int m = row0 + wm + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
     if (m < M && n < N) {
-      float v = acc[r] + (bias ? bias[n] : 0.f);
+      float v = acc[r] + (bias ? bias[n] : 0.f) + (accumulate ? C[(size_t)m * ldc + n] : 0.f);
       if (relu) v = fmaxf(v, 0.f);
       C[(size_t)m * ldc + n] = v;
     }
@@ -110,20 +114,20 @@ __global__ void __launch_bounds__(256) sg_gemm_kernel(const float* __restrict__ 
 
 template <bool TA, bool TB>
 static hipError_t sg_gemm(const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
-                          int K, const float* bias, int relu, int nsplit, hipStream_t st) {
+                          int K, const float* bias, int relu, int nsplit, hipStream_t st, int accumulate = 0) {
   const dim3 grid(((M + SBM - 1) / SBM) * ((N + SBN - 1) / SBN));
   if (nsplit > 1)
     hipLaunchKernelGGL((sg_gemm_kernel<TA, TB, 3>), grid, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K,
-                       bias, relu);
+                       bias, relu, accumulate);
   else
     hipLaunchKernelGGL((sg_gemm_kernel<TA, TB, 1>), grid, dim3(256), 0, st, A, lda, B, ldb, C, ldc, M, N, K,
-                       bias, relu);
+                       bias, relu, accumulate);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- dense GEMM, aligned fast path
-// C[M][N] = relu(A B + bias) for K % 32 == 0 and N % 128 == 0 (the 256 -> 1024 and
-// 1024 -> 2048 layers).  A is FP32 [M][K], split into BF16 hi / lo while it is staged;
+// C[M][N] = (relu)(A B + bias) for K % 32 == 0 and N % 128 == 0 (the 1024-wide layers
+// and the basis branch).  A is FP32 [M][K], split into BF16 hi / lo while it is staged;
 // B is given pre-split as k-contiguous BF16 planes Bt_hi / Bt_lo [N][K].  Workgroup
 // 128 x 128, 4 waves of 64 x 64 (2 x 2 MFMA blocks of 32 x 32 x 16), k-stage 32, two LDS
 // stages; each lane reads its 8 consecutive k of an operand with one 16-byte LDS read.
@@ -147,7 +151,8 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
                                                               const __bf16* __restrict__ Bhi,
                                                               const __bf16* __restrict__ Blo,
                                                               float* __restrict__ C, int M, int N, int K,
-                                                              const float* __restrict__ bias, int relu) {
+                                                              const float* __restrict__ bias, int relu,
+                                                              int Kc, int accumulate) {
   constexpr int PL = FBM * FLD;             // one bf16 plane of a tile
   constexpr int STAGE = 4 * PL;             // A hi, A lo, B hi, B lo
   extern __shared__ __bf16 shb[];
@@ -156,6 +161,10 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int row0 = tm * FBM, col0 = tn * FBN;
+  // split K: slice blockIdx.y covers k in [kbase, kbase + Kc) and, when there are several
+  // slices, writes its raw partial product to slice blockIdx.y of C (reduced afterwards)
+  const int kbase = blockIdx.y * Kc;
+  if (gridDim.y > 1) C += (size_t)blockIdx.y * M * N;
   f16v_s acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -178,13 +187,13 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
     for (int i = 0; i < 4; ++i) {
       const int idx = tid + 256 * i, r = idx >> 3, kq = 4 * (idx & 7);
       const int gr = min(row0 + r, M - 1);   // rows past M are computed but not stored
-      ra[i] = *reinterpret_cast<const float4*>(A + (size_t)gr * K + k0 + kq);
+      ra[i] = *reinterpret_cast<const float4*>(A + (size_t)gr * K + kbase + k0 + kq);
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       const int idx = tid + 256 * i, c = idx >> 2, k8 = 8 * (idx & 3);
-      rbh[i] = *reinterpret_cast<const uint4*>(Bhi + (size_t)(col0 + c) * K + k0 + k8);
-      if (NSPLIT > 1) rbl[i] = *reinterpret_cast<const uint4*>(Blo + (size_t)(col0 + c) * K + k0 + k8);
+      rbh[i] = *reinterpret_cast<const uint4*>(Bhi + (size_t)(col0 + c) * K + kbase + k0 + k8);
+      if (NSPLIT > 1) rbl[i] = *reinterpret_cast<const uint4*>(Blo + (size_t)(col0 + c) * K + kbase + k0 + k8);
     }
     return g;
   };
@@ -212,7 +221,7 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
       if (NSPLIT > 1) *reinterpret_cast<uint4*>(st + 3 * PL + c * FLD + k8) = rbl[i];
     }
   };
-  const int KT = K / FBK;
+  const int KT = Kc / FBK;
   auto mma = [&](const __bf16* cur) {
 #pragma unroll
     for (int ks = 0; ks < FBK; ks += 16) {
@@ -252,32 +261,78 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
     __syncthreads();
   }
   mma(shb + ((KT - 1) & 1) * STAGE);
+  const bool raw = gridDim.y > 1;
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
     const int n = col0 + wn + 32 * j + (lane & 31);
-    const float bn = bias ? bias[n] : 0.f;
+    const float bn = (bias && !raw) ? bias[n] : 0.f;
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int m = row0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         if (m < M) {
-          float v = acc[i][j][r] + bn;
-          if (relu) v = fmaxf(v, 0.f);
+          float v = acc[i][j][r];
+          if (!raw) {
+            v += bn + (accumulate ? C[(size_t)m * N + n] : 0.f);
+            if (relu) v = fmaxf(v, 0.f);
+          }
           C[(size_t)m * N + n] = v;
         }
       }
   }
 }
 
+// C = (relu)(sum over slices of ws[s] (in slice order) + bias (+ C)) after a split-K product
+__global__ void sg_splitk_reduce_kernel(const float* __restrict__ ws, int slices, size_t MN, int N,
+                                        const float* __restrict__ bias, int relu, int accumulate,
+                                        float* __restrict__ C) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= MN) return;
+  float v = 0.f;
+  for (int s = 0; s < slices; ++s) v += ws[(size_t)s * MN + i];
+  if (bias) v += bias[i % N];
+  if (accumulate) v += C[i];
+  C[i] = relu ? fmaxf(v, 0.f) : v;
+}
+
+// W [n] FP32 -> hi / lo BF16 in the same order (the transposed operand of C = A W^T)
+__global__ void sg_split_kernel(const float* __restrict__ W, size_t n, __bf16* __restrict__ hi,
+                                __bf16* __restrict__ lo) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float w = W[i];
+  const __bf16 h = (__bf16)w;
+  hi[i] = h;
+  lo[i] = (__bf16)(w - (float)h);
+}
+
+// C = (relu)(A B + bias (+ C)) with B given as BF16 planes Bt [N][K].  A product with few
+// row tiles is split over K (up to 16 slices, each at least 128 deep) into the workspace
+// ws (ws_floats floats) and reduced in slice order, so the result does not depend on the
+// launch.
 static hipError_t sg_gemm_fast(const float* A, const __bf16* Bh, const __bf16* Bl, float* C, int M, int N, int K,
-                               const float* bias, int nsplit, hipStream_t st) {
-  const dim3 grid(((M + FBM - 1) / FBM) * (N / FBN));
+                               const float* bias, int relu, int nsplit, hipStream_t st, int accumulate = 0,
+                               float* ws = nullptr, size_t ws_floats = 0, int target_wg = 0) {
+  const int tiles = ((M + FBM - 1) / FBM) * (N / FBN);
+  int slices = 1;
+  while (ws && slices < 16 && tiles * slices * 2 <= target_wg && K % (2 * slices * FBK) == 0 &&
+         K / (2 * slices) >= 128 && (size_t)2 * slices * M * N <= ws_floats)
+    slices *= 2;
+  const dim3 grid(tiles, slices);
   const int lds = 2 * 4 * FBM * FLD * (int)sizeof(__bf16);
+  float* out = slices > 1 ? ws : C;
   if (nsplit > 1)
-    hipLaunchKernelGGL(sg_gemm_fast_kernel<3>, grid, dim3(256), lds, st, A, Bh, Bl, C, M, N, K, bias, 1);
+    hipLaunchKernelGGL(sg_gemm_fast_kernel<3>, grid, dim3(256), lds, st, A, Bh, Bl, out, M, N, K, bias, relu,
+                       K / slices, accumulate);
   else
-    hipLaunchKernelGGL(sg_gemm_fast_kernel<1>, grid, dim3(256), lds, st, A, Bh, Bl, C, M, N, K, bias, 1);
+    hipLaunchKernelGGL(sg_gemm_fast_kernel<1>, grid, dim3(256), lds, st, A, Bh, Bl, out, M, N, K, bias, relu,
+                       K / slices, accumulate);
+  if (slices > 1) {
+    const size_t MN = (size_t)M * N;
+    hipLaunchKernelGGL(sg_splitk_reduce_kernel, dim3((unsigned)((MN + 255) / 256)), dim3(256), 0, st, ws, slices, MN,
+                       N, bias, relu, accumulate, C);
+  }
   return hipGetLastError();
 }
 
@@ -288,6 +343,37 @@ __global__ void sg_features_kernel(const float* __restrict__ coef, const float* 
   if (i >= B * 22) return;
   const int b = i / 22, f = i % 22;
   x[i] = f < 21 ? coef[b * 21 + f] * (1.f / 0.05f) : z[b] * (1.f / 1000.f);
+}
+
+// Error model of the surrogate: log rel-L2 ~ w . phi(c, z) with the features
+// phi = (1, (c_1 / 0.05)^2 .. (c_21 / 0.05)^2, (z / 1000 nm)^2, |z| / 1000 nm).
+constexpr int kGateFeatures = 24;
+__device__ __forceinline__ float sg_gate_feature(const float* __restrict__ c, float z, int f) {
+  if (f == 0) return 1.f;
+  if (f <= 21) {
+    const float u = c[f - 1] * (1.f / 0.05f);
+    return u * u;
+  }
+  const float t = z * (1.f / 1000.f);
+  return f == 22 ? t * t : fabsf(t);
+}
+
+__global__ void sg_gate_features_kernel(const float* __restrict__ coef, const float* __restrict__ z, int B,
+                                        float* __restrict__ phi) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= B * kGateFeatures) return;
+  const int b = i / kGateFeatures, f = i % kGateFeatures;
+  phi[i] = sg_gate_feature(coef + (size_t)b * 21, z[b], f);
+}
+
+__global__ void sg_gate_predict_kernel(const float* __restrict__ coef, const float* __restrict__ z, int B,
+                                       const float* __restrict__ w, float* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  float s = 0.f;
+#pragma unroll
+  for (int f = 0; f < kGateFeatures; ++f) s = fmaf(w[f], sg_gate_feature(coef + (size_t)b * 21, z[b], f), s);
+  out[b] = s;
 }
 
 // g *= (h > 0): derivative of relu through its output
@@ -325,132 +411,295 @@ __global__ void sg_sum_kernel(const double* __restrict__ partial, int n, double 
   }
 }
 
-// column sums of g [rows][cols] in row order, per column (bias gradients of dense layers)
-__global__ void sg_colsum_kernel(const float* __restrict__ g, int rows, int cols, float* __restrict__ out) {
+// column sums of g [rows][cols] (bias gradients), two levels in a fixed order: chunk
+// blockIdx.y sums its rows in order into part[chunk][col]; sg_colsum_final_kernel sums the
+// chunks in order
+__global__ void sg_colsum_kernel(const float* __restrict__ g, int rows, int cols, int rows_per_chunk,
+                                 double* __restrict__ part) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  const int r0 = blockIdx.y * rows_per_chunk, r1 = min(rows, r0 + rows_per_chunk);
+  double s = 0.0;
+  for (int r = r0; r < r1; ++r) s += g[(size_t)r * cols + c];
+  part[(size_t)blockIdx.y * cols + c] = s;
+}
+
+__global__ void sg_colsum_final_kernel(const double* __restrict__ part, int chunks, int cols,
+                                       float* __restrict__ out) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   double s = 0.0;
-  for (int r = 0; r < rows; ++r) s += g[(size_t)r * cols + c];
+  for (int k = 0; k < chunks; ++k) s += part[(size_t)k * cols + c];
   out[c] = (float)s;
 }
 
+constexpr int kColChunks = 64;   // row chunks of the column sums (partials: kColChunks x 4096 doubles)
+
+static hipError_t sg_colsum(const float* g, int rows, int cols, float* out, double* part, hipStream_t st) {
+  const int chunks = std::min(kColChunks, std::max(1, rows / 16));
+  const int per = (rows + chunks - 1) / chunks;
+  const int used = (rows + per - 1) / per;
+  hipLaunchKernelGGL(sg_colsum_kernel, dim3((cols + 255) / 256, used), dim3(256), 0, st, g, rows, cols, per, part);
+  hipLaunchKernelGGL(sg_colsum_final_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, part, used, cols, out);
+  return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- transposed convolution
-// Weights re-laid for the forward kernel: Kt[ky][kx][ci][co] = K[ci][co][ky][kx].
-__global__ void sg_deconv_wt_kernel(const float* __restrict__ K, int Ci, int Co, float* __restrict__ Kt) {
+// ---------------------------------------------------------------- fused decoder on the matrix cores
+// The three transposed convolutions of one sample in one workgroup, activations kept in
+// LDS.  Output pixel (2Y + py, 2X + px) of a stride-2, 4 x 4, pad-1 transposed convolution
+// takes input rows Y + dy and kernel rows ky with (dy, ky) = (0, 1), (-1, 3) for py = 0 and
+// (+1, 0), (0, 2) for py = 1 (the same along x), so each output parity class is a plain
+// GEMM over the input pixels: M = pixels, K = (tap, input channel), N = output channels.
+//   layer 1 (C0 -> C1 = 16, 8x8 -> 16x16): one GEMM per class (py, px), K = 4 C0, N = 16;
+//   layer 2 (C1 -> C2 = 8, 16x16 -> 32x32): one GEMM per row class py with both column
+//     classes side by side in N = 2 C2 = 16 (K = 6 C1 over the input columns X-1, X, X+1;
+//     the tap a column class does not use has a zero weight);
+//   layer 3 (C2 -> 1, 32x32 -> 64x64): N = 1 is a matrix-vector product, done in FP32 on
+//     the vector units (a thread owns 2 x 2 input pixels and their 4 x 4 outputs).
+// Layers 1 and 2 run v_mfma_f32_16x16x32_bf16: A lane l holds row l % 16 and eight
+// consecutive k of group l / 16, B lane l holds column l % 16 and the same eight k, C
+// register r of lane l holds row 4 (l / 16) + r, column l % 16.  Activations sit in LDS
+// channel-last with a zero border, so the eight k of a lane are eight consecutive
+// channels of one source pixel (two 16-byte reads), with no bounds tests.  Weights are
+// pre-arranged as B fragments ([class][k-step][lane][8] BF16 hi / lo) and held in
+// registers for all samples of the workgroup.
+constexpr int DC0 = 16, DC1 = 16, DC2 = 8;          // decoder channels (layer inputs)
+constexpr int DX0 = DC0 + 4, DX1 = DC1 + 4, DX2 = DC2;   // LDS floats per pixel (padded)
+constexpr int DL0 = 10 * 10 * DX0, DL1 = 18 * 18 * DX1, DL2 = 34 * 34 * DX2;
+constexpr int DK1 = 4 * DC0 / 32, DK2 = 6 * DC1 / 32;    // k-steps of the layer-1 / layer-2 GEMMs
+constexpr int kDecLdsBytes = (DL0 + DL1 + DL2) * 4;
+static_assert(DC1 == 16 && 2 * DC2 == 16 && DC0 % 8 == 0 && DC1 % 8 == 0, "decoder tile shapes");
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+
+// B fragments: layer 1 [4 classes][DK1][64][8], layer 2 [2 row classes][DK2][64][8], hi and lo
+__global__ void sg_dec_wprep_kernel(const float* __restrict__ K1, const float* __restrict__ K2,
+                                    __bf16* __restrict__ f1h, __bf16* __restrict__ f1l,
+                                    __bf16* __restrict__ f2h, __bf16* __restrict__ f2l) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= Ci * Co * 16) return;
-  const int ci = i / (Co * 16), co = (i / 16) % Co, ky = (i / 4) % 4, kx = i % 4;
-  Kt[((ky * 4 + kx) * Ci + ci) * Co + co] = K[i];
+  const int n1 = 4 * DK1 * 64 * 8, n2 = 2 * DK2 * 64 * 8;
+  if (i < n1) {
+    const int q = i % 8, l = (i / 8) % 64, s = (i / 512) % DK1, p = i / (512 * DK1);
+    const int py = p >> 1, px = p & 1, co = l % 16, k = 32 * s + 8 * (l / 16) + q;
+    const int tap = k / DC0, ci = k % DC0, a = tap >> 1, c = tap & 1;
+    const int ky = py ? 2 * a : 1 + 2 * a, kx = px ? 2 * c : 1 + 2 * c;
+    const float w = K1[((ci * DC1 + co) * 4 + ky) * 4 + kx];
+    const __bf16 h = (__bf16)w;
+    f1h[i] = h;
+    f1l[i] = (__bf16)(w - (float)h);
+  } else if (i < n1 + n2) {
+    const int j = i - n1;
+    const int q = j % 8, l = (j / 8) % 64, s = (j / 512) % DK2, py = j / (512 * DK2);
+    const int n = l % 16, px = n / DC2, co = n % DC2, k = 32 * s + 8 * (l / 16) + q;
+    const int t6 = k / DC1, ci = k % DC1, a = t6 / 3, c3 = t6 % 3;
+    const int ky = py ? 2 * a : 1 + 2 * a;
+    // column tap c3 reads input column X + c3 - 1: px = 0 uses kx = 3, 1 (c3 = 0, 1),
+    // px = 1 uses kx = 2, 0 (c3 = 1, 2)
+    const int kx = px == 0 ? (c3 == 0 ? 3 : c3 == 1 ? 1 : -1) : (c3 == 0 ? -1 : c3 == 1 ? 2 : 0);
+    const float w = kx < 0 ? 0.f : K2[((ci * DC2 + co) * 4 + ky) * 4 + kx];
+    const __bf16 h = (__bf16)w;
+    f2h[j] = h;
+    f2l[j] = (__bf16)(w - (float)h);
+  }
 }
 
-// Forward transposed convolution, one output pixel (all Co channels) per thread (used
-// for the 32 -> 16 channel layer, where a 2 x 2 block would need 4 Co accumulators and
-// too many scalar weights per step).  Output (oy, ox) = (2 iy + py, 2 ix + px): the taps
-// of parity p are (iy, ky = 1), (iy - 1, ky = 3) for p = 0 and (iy + 1, ky = 0),
-// (iy, ky = 2) for p = 1.  A workgroup covers 256 pixels of one sample ordered by parity
-// class (4 classes of H x H), so the class -- and every weight address -- is the same
-// across a wave (H * H >= 64) and the weights are read as scalars.
-template <int Ci, int Co, int H>
-__global__ void __launch_bounds__(256) sg_deconv_fwd_pix_kernel(const float* __restrict__ in,
-                                                                const float* __restrict__ Kt,
-                                                                const float* __restrict__ bias, int relu,
-                                                                float* __restrict__ out) {
-  static_assert(H * H >= 64 && (4 * H * H) % 256 == 0, "parity class uniform per wave");
-  constexpr int BPS = 4 * H * H / 256;   // workgroups per sample
-  const int b = blockIdx.x / BPS;
-  const int pix = (blockIdx.x % BPS) * 256 + threadIdx.x;
-  const int cls = __builtin_amdgcn_readfirstlane(pix / (H * H));
-  const int q = pix % (H * H), iy = q / H, ix = q % H;
-  const int py = cls >> 1, px = cls & 1;
-  const float* x = in + (size_t)b * Ci * H * H;
-  float acc[Co];
+// eight FP32 values -> BF16 hi (and lo = bf16(x - hi))
+__device__ __forceinline__ void split8(const float4 u, const float4 v, bf8_t& hi, bf8_t& lo) {
+  const float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
 #pragma unroll
-  for (int co = 0; co < Co; ++co) acc[co] = bias[co];
+  for (int q = 0; q < 8; ++q) {
+    hi[q] = (__bf16)x[q];
+    lo[q] = (__bf16)(x[q] - (float)hi[q]);
+  }
+}
+
+template <int NSPLIT>
+__device__ __forceinline__ f4v_t mma16(const bf8_t& ah, const bf8_t& al, const bf8_t& bh, const bf8_t& bl,
+                                       f4v_t acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+  if (NSPLIT > 1) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+// h3 [B][DC0][8][8] (relu applied) -> y [B][64][64] += T(T(T(h3))); d1 [B][DC1][16][16] and d2
+// [B][DC2][32][32] (post-relu) are also written when the pointers are not null (training).
+// Persistent: workgroup g serves samples g, g + gridDim.x, ...
+template <int NSPLIT>
+__global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restrict__ h3, int B,
+                                                            const bf8_t* __restrict__ f1h,
+                                                            const bf8_t* __restrict__ f1l,
+                                                            const bf8_t* __restrict__ f2h,
+                                                            const bf8_t* __restrict__ f2l,
+                                                            const float* __restrict__ c1,
+                                                            const float* __restrict__ c2,
+                                                            const float* __restrict__ K3,
+                                                            const float* __restrict__ c3,
+                                                            float* __restrict__ y, float* __restrict__ d1g,
+                                                            float* __restrict__ d2g) {
+  extern __shared__ float dls[];
+  float* X0 = dls;            // [10][10][DX0]
+  float* X1 = X0 + DL0;       // [18][18][DX1]
+  float* X2 = X1 + DL1;       // [34][34][DX2]
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, r16 = lane & 15;
+  for (int i = tid; i < DL0 + DL1 + DL2; i += 256) dls[i] = 0.f;   // zero borders (interiors are rewritten)
+  // B fragments of this wave: layer-1 class p = w, layer-2 row class py2 = w / 2
+  bf8_t w1h[DK1], w1l[DK1], w2h[DK2], w2l[DK2];
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int yy = py ? iy + 1 - a : iy - a, ky = py ? 2 * a : 1 + 2 * a;
-    if (yy < 0 || yy >= H) continue;
+  for (int s = 0; s < DK1; ++s) {
+    w1h[s] = f1h[(w * DK1 + s) * 64 + lane];
+    if (NSPLIT > 1) w1l[s] = f1l[(w * DK1 + s) * 64 + lane];
+  }
+  const int py2 = w >> 1;
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int xx = px ? ix + 1 - c : ix - c, kx = px ? 2 * c : 1 + 2 * c;
-      if (xx < 0 || xx >= H) continue;
-      const float* w = Kt + (ky * 4 + kx) * Ci * Co;
-      const float* xp = x + yy * H + xx;
-#pragma unroll 4
-      for (int ci = 0; ci < Ci; ++ci) {
-        const float v = xp[ci * H * H];
+  for (int s = 0; s < DK2; ++s) {
+    w2h[s] = f2h[(py2 * DK2 + s) * 64 + lane];
+    if (NSPLIT > 1) w2l[s] = f2l[(py2 * DK2 + s) * 64 + lane];
+  }
+  const float bias1 = c1[r16];
+  const float bias2 = c2[r16 % DC2];
+  const float bias3 = c3[0];
+  // staged h3 of the next sample: DC0 * 64 floats, 8 per thread as two float4
+  constexpr int NV = DC0 * 64 / 4 / 256;
+  float4 hv[NV];
+  auto fetch = [&](int b) {
 #pragma unroll
-        for (int co = 0; co < Co; ++co) acc[co] = fmaf(v, w[ci * Co + co], acc[co]);
+    for (int v = 0; v < NV; ++v)
+      hv[v] = b < B ? *reinterpret_cast<const float4*>(h3 + (size_t)b * DC0 * 64 + 4 * (tid + 256 * v))
+                    : make_float4(0.f, 0.f, 0.f, 0.f);
+  };
+  fetch(blockIdx.x);
+  __syncthreads();   // borders zeroed before any interior write
+  for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    // ---- stage h3 [ci][Y][X] -> X0 [Y+1][X+1][ci]
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int e = 4 * (tid + 256 * v), ci = e / 64, pix = e % 64;
+      const float xs[4] = {hv[v].x, hv[v].y, hv[v].z, hv[v].w};
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int Y = (pix + t) / 8, X = (pix + t) % 8;
+        X0[((Y + 1) * 10 + X + 1) * DX0 + ci] = xs[t];
       }
     }
-  }
-  const int oy = 2 * iy + py, ox = 2 * ix + px, HO = 2 * H;
-  float* o = out + (size_t)b * Co * HO * HO + oy * HO + ox;
+    fetch(b + gridDim.x);
+    __syncthreads();
+    // ---- layer 1: wave w = class (py, px); M-tiles of 16 pixels (Y, X) of the 8 x 8 input
+    {
+      const int py = w >> 1, px = w & 1;
 #pragma unroll
-  for (int co = 0; co < Co; ++co) o[co * HO * HO] = relu ? fmaxf(acc[co], 0.f) : acc[co];
-}
-
-// Forward transposed convolution: a thread takes one input position (iy, ix) of one
-// sample and computes the 2 x 2 output block (2 iy + py, 2 ix + px), all Co channels.
-// Output row 2 iy + py gets taps (iy, ky = 1), (iy - 1, ky = 3) when py = 0 and
-// (iy + 1, ky = 0), (iy, ky = 2) when py = 1 (likewise along x), so the block reads the
-// 3 x 3 input neighbourhood; every weight address is the same across the wave (read as
-// scalars), and the block is written as 8-byte pairs.
-template <int Ci, int Co, int H>
-__global__ void __launch_bounds__(256) sg_deconv_fwd2_kernel(const float* __restrict__ in,
-                                                             const float* __restrict__ Kt,
-                                                             const float* __restrict__ bias, int relu,
-                                                             int B, float* __restrict__ out) {
-  const int t = blockIdx.x * 256 + threadIdx.x;
-  if (t >= B * H * H) return;   // no barrier below
-  const int b = t / (H * H), q = t % (H * H), iy = q / H, ix = q % H;
-  const float* x = in + (size_t)b * Ci * H * H;
-  float acc[2][2][Co];
+      for (int mt = 0; mt < 4; ++mt) {
+        const int m = 16 * mt + r16, Y = m >> 3, X = m & 7;
+        f4v_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int py = 0; py < 2; ++py)
+        for (int s = 0; s < DK1; ++s) {
+          const int k0 = 32 * s + 8 * g, tap = k0 / DC0, ci = k0 % DC0, a = tap >> 1, c = tap & 1;
+          const int dy = py ? 1 - a : -a, dx = px ? 1 - c : -c;
+          const float* src = X0 + ((Y + dy + 1) * 10 + X + dx + 1) * DX0 + ci;
+          bf8_t ah, al;
+          split8(*reinterpret_cast<const float4*>(src), *reinterpret_cast<const float4*>(src + 4), ah, al);
+          acc = mma16<NSPLIT>(ah, al, w1h[s], w1l[s], acc);
+        }
+        // C: rows 4 g + i (pixels), column r16 (output channel)
 #pragma unroll
-    for (int px = 0; px < 2; ++px)
-#pragma unroll
-      for (int co = 0; co < Co; ++co) acc[py][px][co] = bias[co];
-  // rows / columns of the neighbourhood: index 0 = iy - 1, 1 = iy, 2 = iy + 1
-  const bool ry[3] = {iy > 0, true, iy + 1 < H}, rx[3] = {ix > 0, true, ix + 1 < H};
+        for (int i = 0; i < 4; ++i) {
+          const int mm = 16 * mt + 4 * g + i, YY = mm >> 3, XX = mm & 7;
+          X1[((2 * YY + py + 1) * 18 + 2 * XX + px + 1) * DX1 + r16] = fmaxf(acc[i] + bias1, 0.f);
+        }
+      }
+    }
+    __syncthreads();
+    if (d1g) {   // training: d1 [co][16][16]
+      float* o = d1g + (size_t)b * DC1 * 256;
+      for (int e = tid; e < DC1 * 256; e += 256) {
+        const int co = e / 256, pix = e % 256;
+        o[e] = X1[((pix / 16 + 1) * 18 + pix % 16 + 1) * DX1 + co];
+      }
+    }
+    // ---- layer 2: wave w = row class py2, M-tiles 8 (w & 1) .. + 7 of the 16 x 16 input
+    {
 #pragma unroll 2
-  for (int ci = 0; ci < Ci; ++ci) {
-    float v[3][3];
+      for (int t = 0; t < 8; ++t) {
+        const int mt = 8 * (w & 1) + t;
+        const int m = 16 * mt + r16, Y = m >> 4, X = m & 15;
+        f4v_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int dy = 0; dy < 3; ++dy)
+        for (int s = 0; s < DK2; ++s) {
+          const int k0 = 32 * s + 8 * g, t6 = k0 / DC1, ci = k0 % DC1, a = t6 / 3, c3 = t6 % 3;
+          const int dy = py2 ? 1 - a : -a, dx = c3 - 1;
+          const float* src = X1 + ((Y + dy + 1) * 18 + X + dx + 1) * DX1 + ci;
+          bf8_t ah, al;
+          split8(*reinterpret_cast<const float4*>(src), *reinterpret_cast<const float4*>(src + 4), ah, al);
+          acc = mma16<NSPLIT>(ah, al, w2h[s], w2l[s], acc);
+        }
+        const int px = r16 / DC2, co = r16 % DC2;
 #pragma unroll
-      for (int dx = 0; dx < 3; ++dx)
-        v[dy][dx] = (ry[dy] && rx[dx]) ? x[(ci * H + iy + dy - 1) * H + ix + dx - 1] : 0.f;
-#pragma unroll
-    for (int py = 0; py < 2; ++py)
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int dy = py ? 2 - a : 1 - a, ky = py ? 2 * a : 1 + 2 * a;
-#pragma unroll
-        for (int px = 0; px < 2; ++px)
-#pragma unroll
-          for (int c = 0; c < 2; ++c) {
-            const int dx = px ? 2 - c : 1 - c, kx = px ? 2 * c : 1 + 2 * c;
-            const float* w = Kt + ((ky * 4 + kx) * Ci + ci) * Co;
-#pragma unroll
-            for (int co = 0; co < Co; ++co) acc[py][px][co] = fmaf(v[dy][dx], w[co], acc[py][px][co]);
-          }
+        for (int i = 0; i < 4; ++i) {
+          const int mm = 16 * mt + 4 * g + i, YY = mm >> 4, XX = mm & 15;
+          X2[((2 * YY + py2 + 1) * 34 + 2 * XX + px + 1) * DX2 + co] = fmaxf(acc[i] + bias2, 0.f);
+        }
       }
-  }
-  constexpr int HO = 2 * H;
-  float* o = out + (size_t)b * Co * HO * HO + (2 * iy) * HO + 2 * ix;
-#pragma unroll
-  for (int co = 0; co < Co; ++co)
-#pragma unroll
-    for (int py = 0; py < 2; ++py) {
-      float a0 = acc[py][0][co], a1 = acc[py][1][co];
-      if (relu) {
-        a0 = fmaxf(a0, 0.f);
-        a1 = fmaxf(a1, 0.f);
-      }
-      *reinterpret_cast<float2*>(o + co * HO * HO + py * HO) = make_float2(a0, a1);
     }
+    __syncthreads();
+    if (d2g) {   // training: d2 [co][32][32]
+      float* o = d2g + (size_t)b * DC2 * 1024;
+      for (int e = tid; e < DC2 * 1024; e += 256) {
+        const int co = e / 1024, pix = e % 1024;
+        o[e] = X2[((pix / 32 + 1) * 34 + pix % 32 + 1) * DX2 + co];
+      }
+    }
+    // ---- layer 3 (FP32): thread owns input pixels (2 Yb + u, 2 Xb + v), u, v in {0, 1},
+    // reads the 4 x 4 neighbourhood rows 2 Yb - 1 .. 2 Yb + 2 and writes the 4 x 4 outputs
+    {
+      const int Yb = tid >> 4, Xb = tid & 15;
+      float out[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[i][j] = bias3;
+#pragma unroll
+      for (int hc = 0; hc < DC2; hc += 4) {
+        float4 nb[4][4];   // channels hc .. hc + 3 at padded rows 2 Yb .. 2 Yb + 3, cols 2 Xb .. 2 Xb + 3
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            nb[i][j] = *reinterpret_cast<const float4*>(X2 + ((2 * Yb + i) * 34 + 2 * Xb + j) * DX2 + hc);
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+          const int ci = hc + cc;
+#pragma unroll
+          for (int oy = 0; oy < 4; ++oy)      // output row 4 Yb + oy = 2 (2 Yb + u) + py
+#pragma unroll
+            for (int ox = 0; ox < 4; ++ox) {
+              const int u = oy >> 1, py = oy & 1, v = ox >> 1, px = ox & 1;
+#pragma unroll
+              for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                  const int dy = py ? 1 - a : -a, dx = px ? 1 - c : -c;
+                  const int ky = py ? 2 * a : 1 + 2 * a, kx = px ? 2 * c : 1 + 2 * c;
+                  // input pixel (2 Yb + u + dy, 2 Xb + v + dx) sits at nb[u + dy + 1][v + dx + 1]
+                  const float4 q = nb[u + dy + 1][v + dx + 1];
+                  const float xv = cc == 0 ? q.x : cc == 1 ? q.y : cc == 2 ? q.z : q.w;
+                  out[oy][ox] = fmaf(xv, K3[ci * 16 + ky * 4 + kx], out[oy][ox]);
+                }
+            }
+        }
+      }
+      // y holds the basis branch already: add the convolution branch to it
+      float* o = y + (size_t)b * 4096 + (4 * Yb) * 64 + 4 * Xb;
+#pragma unroll
+      for (int oy = 0; oy < 4; ++oy) {
+        const float4 prev = *reinterpret_cast<const float4*>(o + oy * 64);
+        *reinterpret_cast<float4*>(o + oy * 64) =
+            make_float4(prev.x + out[oy][0], prev.y + out[oy][1], prev.z + out[oy][2], prev.w + out[oy][3]);
+      }
+    }
+    // the next iteration's staging writes X0 only; X1 / X2 are rewritten after its barriers
+  }
 }
 
 // dIn[ci, iy, ix] = sum_{co, ky, kx} dOut[co, 2 iy - 1 + ky, 2 ix - 1 + kx] K[ci, co, ky, kx]
@@ -557,23 +806,27 @@ __global__ void sg_adam_kernel(float* __restrict__ w, const float* __restrict__ 
 
 // ---------------------------------------------------------------- host side
 namespace {
+constexpr int kBasis = 256;   // rank of the linear crop basis
 struct Layout {
-  size_t W1, b1, W2, b2, W3, b3, K1, c1, K2, c2, K3, c3, total;
+  size_t W1, b1, W2, b2, W3, b3, K1, c1, K2, c2, K3, c3, Wa, ba, Wb, bb, total;
 };
 Layout layout() {
   Layout L{};
   size_t o = 0;
   auto take = [&](size_t n) { size_t r = o; o += n; return r; };
-  L.W1 = take(22 * 256); L.b1 = take(256);
-  L.W2 = take(256 * 1024); L.b2 = take(1024);
-  L.W3 = take(1024 * 2048); L.b3 = take(2048);
-  L.K1 = take(32 * 16 * 16); L.c1 = take(16);
+  L.W1 = take(22 * 1024); L.b1 = take(1024);
+  L.W2 = take(1024 * 1024); L.b2 = take(1024);
+  L.W3 = take(1024 * 1024); L.b3 = take(1024);
+  L.K1 = take(16 * 16 * 16); L.c1 = take(16);
   L.K2 = take(16 * 8 * 16); L.c2 = take(8);
   L.K3 = take(8 * 1 * 16); L.c3 = take(1);
+  L.Wa = take(1024 * kBasis); L.ba = take(kBasis);
+  L.Wb = take(kBasis * 4096); L.bb = take(4096);
   L.total = o;
   return L;
 }
 constexpr int kMaxChunks = 256;   // partial sums of the convolution weight gradients per step
+constexpr size_t kSplitKFloats = (size_t)16 << 20;   // split-K workspace of the training products
 }  // namespace
 
 struct rwpsf_sg {
@@ -583,9 +836,14 @@ struct rwpsf_sg {
   float *w = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;   // [L.total]
   float *x = nullptr, *h1 = nullptr, *h2 = nullptr, *h3 = nullptr, *d1 = nullptr, *d2 = nullptr, *y = nullptr;
   float *gx = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr, *gd1 = nullptr, *gd2 = nullptr, *gy = nullptr;
+  float *a = nullptr, *ga = nullptr;   // basis coefficients [B][kBasis] and their gradient
   float* partial = nullptr;   // conv weight partials
-  float* kt = nullptr;        // transposed convolution weights of the forward kernels
-  __bf16* wsplit = nullptr;   // BF16 hi / lo planes of W2 and W3, [N][K]
+  __bf16* decw = nullptr;     // B fragments of the decoder's matrix-core layers (hi / lo)
+  int num_cus = 0;
+  __bf16* wsplit = nullptr;   // BF16 hi / lo planes of W2, W3, Wa, Wb, [N][K]
+  __bf16* wsplit_t = nullptr; // the same weights split in their own order (operands of g W^T)
+  float* ws = nullptr;        // split-K partial products
+  double* colpart = nullptr;  // column-sum partials
   double* loss_partial = nullptr;
   int64_t step = 0;
   ~rwpsf_sg() {   // teardown: failures cannot be reported and are ignored
@@ -608,39 +866,59 @@ static int sg_alloc(rwpsf_sg* s, T** p, size_t count) {
   return RWPSF_OK;
 }
 
+// keep: also write d1 and d2 (the backward pass needs them)
 static int sg_forward_impl(rwpsf_sg* s, int B, const float* coef, const float* z, float* out, int nsplit,
-                           hipStream_t st) {
+                           bool keep, hipStream_t st) {
   const Layout& L = s->L;
   int rc;
   hipLaunchKernelGGL(sg_features_kernel, dim3((B * 22 + 255) / 256), dim3(256), 0, st, coef, z, B, s->x);
   if ((rc = hip_check(hipGetLastError()))) return rc;
-  if ((rc = hip_check(sg_gemm<false, false>(s->x, 22, s->w + L.W1, 256, s->h1, 256, B, 256, 22, s->w + L.b1, 1, nsplit, st)))) return rc;
   // the two wide layers on the aligned fast path, with the weights split to BF16 planes
+  if ((rc = hip_check(sg_gemm<false, false>(s->x, 22, s->w + L.W1, 1024, s->h1, 1024, B, 1024, 22, s->w + L.b1, 1,
+                                            nsplit, st)))) return rc;
+  // the wide layers on the aligned fast path, with the weights split to BF16 planes
   __bf16* w2h = s->wsplit;
-  __bf16* w2l = w2h + 256 * 1024;
-  __bf16* w3h = w2l + 256 * 1024;
-  __bf16* w3l = w3h + 1024 * 2048;
-  hipLaunchKernelGGL(sg_wsplit_kernel, dim3(256 * 1024 / 256), dim3(256), 0, st, s->w + L.W2, 256, 1024, w2h, w2l);
-  hipLaunchKernelGGL(sg_wsplit_kernel, dim3(1024 * 2048 / 256), dim3(256), 0, st, s->w + L.W3, 1024, 2048, w3h, w3l);
+  __bf16* w2l = w2h + 1024 * 1024;
+  __bf16* w3h = w2l + 1024 * 1024;
+  __bf16* w3l = w3h + 1024 * 1024;
+  __bf16* wah = w3l + 1024 * 1024;
+  __bf16* wal = wah + 1024 * kBasis;
+  __bf16* wbh = wal + 1024 * kBasis;
+  __bf16* wbl = wbh + kBasis * 4096;
+  hipLaunchKernelGGL(sg_wsplit_kernel, dim3(1024 * 1024 / 256), dim3(256), 0, st, s->w + L.W2, 1024, 1024, w2h, w2l);
+  hipLaunchKernelGGL(sg_wsplit_kernel, dim3(1024 * 1024 / 256), dim3(256), 0, st, s->w + L.W3, 1024, 1024, w3h, w3l);
+  hipLaunchKernelGGL(sg_wsplit_kernel, dim3(1024 * kBasis / 256), dim3(256), 0, st, s->w + L.Wa, 1024, kBasis, wah,
+                     wal);
+  hipLaunchKernelGGL(sg_wsplit_kernel, dim3(kBasis * 4096 / 256), dim3(256), 0, st, s->w + L.Wb, kBasis, 4096, wbh,
+                     wbl);
   if ((rc = hip_check(hipGetLastError()))) return rc;
-  if ((rc = hip_check(sg_gemm_fast(s->h1, w2h, w2l, s->h2, B, 1024, 256, s->w + L.b2, nsplit, st)))) return rc;
-  if ((rc = hip_check(sg_gemm_fast(s->h2, w3h, w3l, s->h3, B, 2048, 1024, s->w + L.b3, nsplit, st)))) return rc;
-  float* kt1 = s->kt;
-  float* kt2 = kt1 + 32 * 16 * 16;
-  float* kt3 = kt2 + 16 * 8 * 16;
-  hipLaunchKernelGGL(sg_deconv_wt_kernel, dim3(32), dim3(256), 0, st, s->w + L.K1, 32, 16, kt1);
-  hipLaunchKernelGGL(sg_deconv_wt_kernel, dim3(8), dim3(256), 0, st, s->w + L.K2, 16, 8, kt2);
-  hipLaunchKernelGGL(sg_deconv_wt_kernel, dim3(1), dim3(256), 0, st, s->w + L.K3, 8, 1, kt3);
+  if ((rc = hip_check(sg_gemm_fast(s->h1, w2h, w2l, s->h2, B, 1024, 1024, s->w + L.b2, 1, nsplit, st)))) return rc;
+  if ((rc = hip_check(sg_gemm_fast(s->h2, w3h, w3l, s->h3, B, 1024, 1024, s->w + L.b3, 1, nsplit, st)))) return rc;
+  // basis branch (linear): a = h3 Wa + ba, out = a Wb + bb; the decoder then adds its output
+  if ((rc = hip_check(sg_gemm_fast(s->h3, wah, wal, s->a, B, kBasis, 1024, s->w + L.ba, 0, nsplit, st)))) return rc;
+  if ((rc = hip_check(sg_gemm_fast(s->a, wbh, wbl, out, B, 4096, kBasis, s->w + L.bb, 0, nsplit, st)))) return rc;
+  // decoder: B fragments of the two matrix-core layers, then one persistent launch
+  __bf16* f1h = s->decw;
+  __bf16* f1l = f1h + 4 * DK1 * 64 * 8;
+  __bf16* f2h = f1l + 4 * DK1 * 64 * 8;
+  __bf16* f2l = f2h + 2 * DK2 * 64 * 8;
+  const int nprep = (4 * DK1 + 2 * DK2) * 64 * 8;
+  hipLaunchKernelGGL(sg_dec_wprep_kernel, dim3((nprep + 255) / 256), dim3(256), 0, st, s->w + L.K1, s->w + L.K2,
+                     f1h, f1l, f2h, f2l);
   if ((rc = hip_check(hipGetLastError()))) return rc;
-  // one thread per input position (B * H * H threads)
-  hipLaunchKernelGGL((sg_deconv_fwd_pix_kernel<32, 16, 8>), dim3(B), dim3(256), 0, st, s->h3, kt1, s->w + L.c1, 1,
-                     s->d1);
-  if ((rc = hip_check(hipGetLastError()))) return rc;
-  hipLaunchKernelGGL((sg_deconv_fwd2_kernel<16, 8, 16>), dim3(B), dim3(256), 0, st, s->d1, kt2, s->w + L.c2, 1, B,
-                     s->d2);
-  if ((rc = hip_check(hipGetLastError()))) return rc;
-  hipLaunchKernelGGL((sg_deconv_fwd2_kernel<8, 1, 32>), dim3(B * 4), dim3(256), 0, st, s->d2, kt3, s->w + L.c3, 0, B,
-                     out);
+  const int grid = std::min(B, 2 * s->num_cus);
+  const bf8_t* F1h = reinterpret_cast<const bf8_t*>(f1h);
+  const bf8_t* F1l = reinterpret_cast<const bf8_t*>(f1l);
+  const bf8_t* F2h = reinterpret_cast<const bf8_t*>(f2h);
+  const bf8_t* F2l = reinterpret_cast<const bf8_t*>(f2l);
+  float* d1 = keep ? s->d1 : nullptr;
+  float* d2 = keep ? s->d2 : nullptr;
+  if (nsplit > 1)
+    hipLaunchKernelGGL(sg_decoder_kernel<3>, dim3(grid), dim3(256), kDecLdsBytes, st, s->h3, B, F1h, F1l, F2h, F2l,
+                       s->w + L.c1, s->w + L.c2, s->w + L.K3, s->w + L.c3, out, d1, d2);
+  else
+    hipLaunchKernelGGL(sg_decoder_kernel<1>, dim3(grid), dim3(256), kDecLdsBytes, st, s->h3, B, F1h, F1l, F2h, F2l,
+                       s->w + L.c1, s->w + L.c2, s->w + L.K3, s->w + L.c3, out, d1, d2);
   return hip_check(hipGetLastError());
 }
 
@@ -660,7 +938,35 @@ static int sg_backward_impl(rwpsf_sg* s, int B, const float* target, float* loss
   struct Conv { float *in, *gin, *gout; int Ci, Co, H; size_t K, c; bool relu_in; };
   const Conv convs[3] = {{s->d2, s->gd2, s->gy, 8, 1, 32, L.K3, L.c3, true},
                          {s->d1, s->gd1, s->gd2, 16, 8, 16, L.K2, L.c2, true},
-                         {s->h3, s->g3, s->gd1, 32, 16, 8, L.K1, L.c1, true}};
+                         {s->h3, s->g3, s->gd1, 16, 16, 8, L.K1, L.c1, true}};
+  // weights split to BF16 in their own order: B operands of the products g W^T
+  __bf16* w3h = s->wsplit_t;
+  __bf16* w3l = w3h + 1024 * 1024;
+  __bf16* w2h = w3l + 1024 * 1024;
+  __bf16* w2l = w2h + 1024 * 1024;
+  __bf16* wah = w2l + 1024 * 1024;
+  __bf16* wal = wah + 1024 * kBasis;
+  __bf16* wbh = wal + 1024 * kBasis;
+  __bf16* wbl = wbh + kBasis * 4096;
+  const struct { size_t off, n; __bf16 *h, *l; } splits[4] = {{L.W3, 1024 * 1024, w3h, w3l},
+                                                              {L.W2, 1024 * 1024, w2h, w2l},
+                                                              {L.Wa, 1024 * (size_t)kBasis, wah, wal},
+                                                              {L.Wb, (size_t)kBasis * 4096, wbh, wbl}};
+  for (const auto& sp : splits)
+    hipLaunchKernelGGL(sg_split_kernel, dim3((unsigned)((sp.n + 255) / 256)), dim3(256), 0, st, s->w + sp.off, sp.n,
+                       sp.h, sp.l);
+  if ((rc = hip_check(hipGetLastError()))) return rc;
+  const int twg = 2 * s->num_cus;
+  // basis branch first: dWb = a^T gy, dbb, ga = gy Wb^T, dWa = h3^T ga, dba; its gradient of
+  // h3 joins the convolution branch's before the relu mask
+  if ((rc = hip_check(sg_gemm<true, false>(s->a, kBasis, s->gy, 4096, s->g + L.Wb, 4096, kBasis, 4096, B, nullptr, 0,
+                                           3, st)))) return rc;
+  if ((rc = hip_check(sg_colsum(s->gy, B, 4096, s->g + L.bb, s->colpart, st)))) return rc;
+  if ((rc = hip_check(sg_gemm_fast(s->gy, wbh, wbl, s->ga, B, kBasis, 4096, nullptr, 0, 3, st, 0, s->ws,
+                                   kSplitKFloats, twg)))) return rc;
+  if ((rc = hip_check(sg_gemm<true, false>(s->h3, 1024, s->ga, kBasis, s->g + L.Wa, kBasis, 1024, kBasis, B, nullptr,
+                                           0, 3, st)))) return rc;
+  if ((rc = hip_check(sg_colsum(s->ga, B, kBasis, s->g + L.ba, s->colpart, st)))) return rc;
   for (const Conv& c : convs) {
     const int np = c.Ci * c.Co * 16;
     const int lds = (c.Ci * c.H * c.H + c.Co * 4 * c.H * c.H + np + c.Co) * 4;
@@ -674,22 +980,26 @@ static int sg_backward_impl(rwpsf_sg* s, int B, const float* target, float* loss
     hipLaunchKernelGGL(sg_deconv_bwd_data_kernel, dim3(B), dim3(256), (c.Co * HO * HO + c.Ci * c.Co * 16) * 4, st,
                        c.gout, s->w + c.K, c.Ci, c.Co, c.H, c.gin);
     if ((rc = hip_check(hipGetLastError()))) return rc;
+    // h3 also feeds the basis branch: g3 += ga Wa^T before the relu mask
+    if (c.gin == s->g3 &&
+        (rc = hip_check(sg_gemm_fast(s->ga, wah, wal, s->g3, B, 1024, kBasis, nullptr, 0, 3, st, 1, s->ws,
+                                     kSplitKFloats, twg)))) return rc;
     const size_t n = (size_t)B * c.Ci * c.H * c.H;
     hipLaunchKernelGGL(sg_relu_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c.gin, c.in, n);
     if ((rc = hip_check(hipGetLastError()))) return rc;
   }
   // dense layers: g3 = dL/d(pre3) already masked
-  struct Dense { float *hin, *gin, *gout; int in, out; size_t W, b; const float* hmask; };
-  const Dense dense[3] = {{s->h2, s->g2, s->g3, 1024, 2048, L.W3, L.b3, s->h2},
-                          {s->h1, s->g1, s->g2, 256, 1024, L.W2, L.b2, s->h1},
-                          {s->x, s->gx, s->g1, 22, 256, L.W1, L.b1, nullptr}};
+  struct Dense { float *hin, *gin, *gout; int in, out; size_t W, b; const float* hmask; const __bf16 *th, *tl; };
+  const Dense dense[3] = {{s->h2, s->g2, s->g3, 1024, 1024, L.W3, L.b3, s->h2, w3h, w3l},
+                          {s->h1, s->g1, s->g2, 1024, 1024, L.W2, L.b2, s->h1, w2h, w2l},
+                          {s->x, s->gx, s->g1, 22, 1024, L.W1, L.b1, nullptr, nullptr, nullptr}};
   for (const Dense& d : dense) {
     // dW = hin^T gout  (in x out, K = B), db = column sums, gin = gout W^T
     if ((rc = hip_check(sg_gemm<true, false>(d.hin, d.in, d.gout, d.out, s->g + d.W, d.out, d.in, d.out, B, nullptr, 0, 3, st)))) return rc;
-    hipLaunchKernelGGL(sg_colsum_kernel, dim3((d.out + 255) / 256), dim3(256), 0, st, d.gout, B, d.out, s->g + d.b);
-    if ((rc = hip_check(hipGetLastError()))) return rc;
+    if ((rc = hip_check(sg_colsum(d.gout, B, d.out, s->g + d.b, s->colpart, st)))) return rc;
     if (d.hmask) {
-      if ((rc = hip_check(sg_gemm<false, true>(d.gout, d.out, s->w + d.W, d.out, d.gin, d.in, B, d.in, d.out, nullptr, 0, 3, st)))) return rc;
+      if ((rc = hip_check(sg_gemm_fast(d.gout, d.th, d.tl, d.gin, B, d.in, d.out, nullptr, 0, 3, st, 0, s->ws,
+                                       kSplitKFloats, twg)))) return rc;
       const size_t n = (size_t)B * d.in;
       hipLaunchKernelGGL(sg_relu_mask_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, d.gin, d.hmask, n);
       if ((rc = hip_check(hipGetLastError()))) return rc;
@@ -722,24 +1032,36 @@ int rwpsf_sg_create(int max_batch, rwpsf_sg** out) {
   const int chunks = std::min(max_batch, kMaxChunks);
   int rc;
   if ((rc = sg_alloc(s, &s->w, P)) || (rc = sg_alloc(s, &s->g, P)) || (rc = sg_alloc(s, &s->m, P)) ||
-      (rc = sg_alloc(s, &s->v, P)) || (rc = sg_alloc(s, &s->x, B * 22)) || (rc = sg_alloc(s, &s->h1, B * 256)) ||
-      (rc = sg_alloc(s, &s->h2, B * 1024)) || (rc = sg_alloc(s, &s->h3, B * 2048)) ||
+      (rc = sg_alloc(s, &s->v, P)) || (rc = sg_alloc(s, &s->x, B * 22)) || (rc = sg_alloc(s, &s->h1, B * 1024)) ||
+      (rc = sg_alloc(s, &s->h2, B * 1024)) || (rc = sg_alloc(s, &s->h3, B * 1024)) ||
       (rc = sg_alloc(s, &s->d1, B * 4096)) || (rc = sg_alloc(s, &s->d2, B * 8192)) ||
       (rc = sg_alloc(s, &s->y, B * 4096)) || (rc = sg_alloc(s, &s->gx, B * 22)) ||
-      (rc = sg_alloc(s, &s->g1, B * 256)) || (rc = sg_alloc(s, &s->g2, B * 1024)) ||
-      (rc = sg_alloc(s, &s->g3, B * 2048)) || (rc = sg_alloc(s, &s->gd1, B * 4096)) ||
+      (rc = sg_alloc(s, &s->g1, B * 1024)) || (rc = sg_alloc(s, &s->g2, B * 1024)) ||
+      (rc = sg_alloc(s, &s->g3, B * 1024)) || (rc = sg_alloc(s, &s->gd1, B * 4096)) ||
       (rc = sg_alloc(s, &s->gd2, B * 8192)) || (rc = sg_alloc(s, &s->gy, B * 4096)) ||
-      (rc = sg_alloc(s, &s->partial, (size_t)chunks * (32 * 16 * 16 + 16))) ||
-      (rc = sg_alloc(s, &s->loss_partial, 256)) || (rc = sg_alloc(s, &s->kt, 32 * 16 * 16 + 16 * 8 * 16 + 8 * 16)) ||
-      (rc = sg_alloc(s, &s->wsplit, 2 * (256 * 1024 + 1024 * 2048)))) {
+      (rc = sg_alloc(s, &s->partial, (size_t)chunks * (16 * 16 * 16 + 16))) ||
+      (rc = sg_alloc(s, &s->loss_partial, 256)) || (rc = sg_alloc(s, &s->decw, 2 * (4 * DK1 + 2 * DK2) * 64 * 8)) ||
+      (rc = sg_alloc(s, &s->a, B * kBasis)) || (rc = sg_alloc(s, &s->ga, B * kBasis)) ||
+      (rc = sg_alloc(s, &s->wsplit, 2 * (1024 * 1024 + 1024 * 1024 + 1024 * kBasis + kBasis * 4096))) ||
+      (rc = sg_alloc(s, &s->wsplit_t, 2 * (1024 * 1024 + 1024 * 1024 + 1024 * kBasis + kBasis * 4096))) ||
+      (rc = sg_alloc(s, &s->ws, kSplitKFloats)) || (rc = sg_alloc(s, &s->colpart, kColChunks * 4096))) {
     delete s;
     return rc;
+  }
+  if (hipDeviceGetAttribute(&s->num_cus, hipDeviceAttributeMultiprocessorCount, s->device) != hipSuccess ||
+      s->num_cus < 1) {
+    delete s;
+    return RWPSF_ERR_NO_DEVICE;
   }
   const int fast_lds = 2 * 4 * FBM * FLD * (int)sizeof(__bf16);
   if ((rc = hip_check(hipFuncSetAttribute((const void*)sg_gemm_fast_kernel<1>,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, fast_lds))) ||
       (rc = hip_check(hipFuncSetAttribute((const void*)sg_gemm_fast_kernel<3>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, fast_lds)))) {
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, fast_lds))) ||
+      (rc = hip_check(hipFuncSetAttribute((const void*)sg_decoder_kernel<1>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, kDecLdsBytes))) ||
+      (rc = hip_check(hipFuncSetAttribute((const void*)sg_decoder_kernel<3>,
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, kDecLdsBytes)))) {
     delete s;
     return rc;
   }
@@ -786,16 +1108,32 @@ int rwpsf_sg_forward(rwpsf_sg* s, int B, const float* coef, const float* z, floa
                      void* stream) {
   if (!s || B < 1 || B > s->max_batch || !coef || !z || !out) return RWPSF_ERR_INVALID_ARG;
   if (precision != RWPSF_SG_BF16X3 && precision != RWPSF_SG_BF16) return RWPSF_ERR_INVALID_ARG;
-  return rw::sg_forward_impl(s, B, coef, z, out, precision == RWPSF_SG_BF16X3 ? 3 : 1, (hipStream_t)stream);
+  return rw::sg_forward_impl(s, B, coef, z, out, precision == RWPSF_SG_BF16X3 ? 3 : 1, false, (hipStream_t)stream);
 }
 
 int rwpsf_sg_gradient(rwpsf_sg* s, int B, const float* coef, const float* z, const float* target, float* loss,
                       void* stream) {
   if (!s || B < 1 || B > s->max_batch || !coef || !z || !target) return RWPSF_ERR_INVALID_ARG;
   hipStream_t st = (hipStream_t)stream;
-  int rc = rw::sg_forward_impl(s, B, coef, z, s->y, 3, st);
+  int rc = rw::sg_forward_impl(s, B, coef, z, s->y, 3, true, st);
   if (rc) return rc;
   return rw::sg_backward_impl(s, B, target, loss, st);
+}
+
+int rwpsf_sg_error_features(int B, const float* coef, const float* z, float* phi, void* stream) {
+  if (B < 1 || !coef || !z || !phi) return RWPSF_ERR_INVALID_ARG;
+  const long long n = (long long)B * rw::kGateFeatures;
+  hipLaunchKernelGGL(rw::sg_gate_features_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     (hipStream_t)stream, coef, z, B, phi);
+  return rw::hip_check(hipGetLastError());
+}
+
+int rwpsf_sg_error_predict(int B, const float* coef, const float* z, const float* weights, float* log_err,
+                           void* stream) {
+  if (B < 1 || !coef || !z || !weights || !log_err) return RWPSF_ERR_INVALID_ARG;
+  hipLaunchKernelGGL(rw::sg_gate_predict_kernel, dim3((B + 255) / 256), dim3(256), 0, (hipStream_t)stream, coef, z, B,
+                     weights, log_err);
+  return rw::hip_check(hipGetLastError());
 }
 
 int rwpsf_sg_adam(rwpsf_sg* s, float lr, float beta1, float beta2, float eps, void* stream) {

@@ -2,13 +2,19 @@
 
 * ``CropEngine``  -- 64 x 64 intensity crops (100 nm pixels, 128 x 128 pupil, NA 1.4,
   600 nm, circular polarisation) from the batched-emitter path, normalised by the
-  peak of the unaberrated in-focus PSF; this is both the training-data generator
-  and the audit / fallback of the surrogate.
+  mean pixel of the unaberrated in-focus crop (pixel values O(1), so that the
+  network's parameters, the crop basis included, sit at the O(1e-2..1) scale for
+  which Adam's step size is meant); this is both the training-data generator and
+  the audit / fallback of the surrogate.
 * ``train``       -- Adam on mini-batches drawn with a seeded device generator; every
   forward/backward/update is a librwpsf kernel.
 * ``audit``       -- rel-L2 of the surrogate against the plain path, per crop.
-* ``predict``     -- surrogate for in-distribution inputs, plain path for the rest
-  (any |c_q| > 4 x 0.05 waves or |z| > 1 um).
+* ``fit_gate``    -- error-gated fallback: a least-squares model of the log rel-L2
+  on input features, fitted on calibration crops the plain path judged, and the
+  threshold at which the accepted crops meet a stated bar.
+* ``predict``     -- surrogate for in-distribution inputs the gate accepts, plain path
+  for the rest (gate rejects, any |c_q| > 4 x 0.05 waves or |z| > 1 um).
+* ``judge``       -- the gated surrogate on held-out crops against the plain path.
 * ``save`` / ``load`` -- checkpoint with parameters, Adam moments and step.
 """
 from __future__ import annotations
@@ -20,9 +26,12 @@ import numpy as np
 import paper_2502_03170_amd as rw
 
 CROP = 64
+BASIS = 256
 SIGMA_C = 0.05
 Z_MAX = 1000.0
 OOD_SIGMAS = 4.0
+BATCH = 256         # training mini-batch
+LR = 1e-3           # peak Adam learning rate (cosine schedule after a linear warm-up)
 
 
 class CropEngine:
@@ -34,7 +43,7 @@ class CropEngine:
         z0 = torch.zeros(1, device="cuda")
         c0 = torch.zeros(1, 21, device="cuda")
         self.norm = 1.0
-        self.norm = float(self.crops(c0, z0).max().item())
+        self.norm = float(self.crops(c0, z0).mean().item())
 
     def crops(self, coef, z):
         """coef [B][21], z [B] (any device) -> [B][64][64] float32 on the GPU."""
@@ -60,20 +69,43 @@ def make_dataset(eng: CropEngine, n: int, seed: int):
     return dict(coef=coef, z=z, target=eng.crops(coef, z).contiguous())
 
 
-def init_params(seed: int, out_scale: float = 0.01, bias: float = 0.1) -> np.ndarray:
-    """He-normal weights, positive biases (live relus) and a small output layer (the
-    targets are O(1e-2) per pixel; a larger first output makes the first Adam steps
-    drive the decoder relus dead for some seeds), flat in the library's parameter order."""
+def init_params(seed: int, out_scale: float = 0.01, bias: float = 0.1, basis=None) -> np.ndarray:
+    """He-normal weights, positive biases (live relus), a small last convolution and small
+    basis coefficients (a large first output makes the first Adam steps drive the relus
+    dead), flat in the library's parameter order.
+    basis: (mean crop [4096], basis rows [256][4096]) for the linear branch, else a
+    random basis and a zero mean."""
     rng = np.random.default_rng(seed)
     parts = []
-    for a, b in ((22, 256), (256, 1024), (1024, 2048)):
+    for a, b in ((22, 1024), (1024, 1024), (1024, 1024)):
         parts += [rng.normal(0, math.sqrt(2.0 / a), a * b), np.full(b, bias)]
-    for i, (a, b) in enumerate(((32, 16), (16, 8), (8, 1))):
+    for i, (a, b) in enumerate(((16, 16), (16, 8), (8, 1))):
         w = rng.normal(0, math.sqrt(2.0 / (a * 4)), a * b * 16)
         if i == 2:
             w *= out_scale
         parts += [w, np.full(b, bias if i < 2 else 0.0)]
+    # the basis coefficients start near zero: the first output is about the mean crop
+    parts += [0.1 * rng.uniform(-1, 1, 1024 * BASIS) / math.sqrt(1024), np.zeros(BASIS)]
+    if basis is None:
+        parts += [rng.normal(0, 1e-3, BASIS * 4096), np.zeros(4096)]
+    else:
+        mean, rows = basis
+        parts += [np.asarray(rows, dtype=np.float64).ravel(), np.asarray(mean, dtype=np.float64).ravel()]
     return np.concatenate(parts).astype(np.float32)
+
+
+def crop_basis(data: dict, n: int = 4096):
+    """Mean crop and the leading BASIS principal directions of the first n training crops,
+    each scaled by its singular value / sqrt(n) (so that the branch's coefficients start
+    at O(1)).  Computed on the host in FP64 from the n x n Gram matrix of the centred
+    crops: with Yc Yc^T = U diag(lam) U^T the scaled directions are (Yc^T U)^T / sqrt(n)."""
+    Y = data["target"][:n].reshape(min(n, data["target"].shape[0]), -1).double().cpu().numpy()
+    mean = Y.mean(axis=0)
+    Yc = Y - mean
+    lam, U = np.linalg.eigh(Yc @ Yc.T)
+    top = np.argsort(lam)[::-1][:BASIS]
+    rows = (Yc.T @ U[:, top]).T / math.sqrt(Y.shape[0])
+    return mean, rows
 
 
 def train(sg: rw.Surrogate, data: dict, steps: int, batch: int, lr: float, seed: int, log_every: int = 50,
@@ -129,19 +161,72 @@ def out_of_distribution(coef, z):
     return (coef.abs() > OOD_SIGMAS * SIGMA_C).any(dim=1) | (z.abs() > Z_MAX)
 
 
-def predict(sg: rw.Surrogate, eng: CropEngine, coef, z, precision: int = rw.SG_BF16X3):
-    """Surrogate crops, with the plain path for out-of-distribution inputs."""
+def _forward_all(sg, coef, z, precision):
     import torch
-    ood = out_of_distribution(coef, z)
-    out = torch.empty((coef.shape[0], CROP, CROP), dtype=torch.float32, device="cuda")
-    ok = (~ood).nonzero().flatten()
-    bad = ood.nonzero().flatten()
-    for a in range(0, ok.numel(), sg.max_batch):
-        sel = ok[a:a + sg.max_batch]
-        out[sel] = sg.forward(coef[sel].contiguous(), z[sel].contiguous(), precision=precision)
+    B = coef.shape[0]
+    pred = torch.empty((B, CROP, CROP), dtype=torch.float32, device="cuda")
+    for a in range(0, B, sg.max_batch):
+        b = min(B, a + sg.max_batch)
+        sg.forward(coef[a:b], z[a:b], out=pred[a:b], precision=precision)
+    return pred
+
+
+def fit_gate(sg: rw.Surrogate, calib: dict, bar: float, quantile: float = 0.95,
+             precision: int = rw.SG_BF16X3):
+    """Error-gated fallback, fitted on calibration crops that the plain path judged.
+
+    The log rel-L2 of each calibration crop is regressed (least squares, FP64) on the
+    error-model features phi(c, z) of the library; the threshold on the predicted log
+    error is the largest one for which the calibration crops it accepts have their
+    `quantile` quantile of rel-L2 at or below `bar`.  Returns the gate (device weights,
+    threshold, bar, quantile, accepted fraction on the calibration crops)."""
+    import torch
+    pred = _forward_all(sg, calib["coef"], calib["z"], precision)
+    e = rel_l2_per_crop(pred, calib["target"]).double().cpu().numpy()
+    phi = sg.error_features(calib["coef"], calib["z"]).double().cpu().numpy()
+    w, *_ = np.linalg.lstsq(phi, np.log(np.maximum(e, 1e-7)), rcond=None)
+    wt = torch.tensor(w, dtype=torch.float32, device="cuda")
+    logp = sg.error_predict(calib["coef"], calib["z"], wt).double().cpu().numpy()
+    order = np.argsort(logp, kind="stable")
+    es = e[order]
+    k_best = 0
+    for k in range(len(es), 0, -max(1, len(es) // 512)):
+        if np.quantile(es[:k], quantile) <= bar:
+            k_best = k
+            break
+    thr = float(logp[order[k_best - 1]]) if k_best else -np.inf
+    return dict(weights=wt, log_threshold=thr, bar=bar, quantile=quantile,
+                accepted_calibration=k_best / len(es), fit_corr=float(np.corrcoef(logp, np.log(e))[0, 1]))
+
+
+def predict(sg: rw.Surrogate, eng: CropEngine, coef, z, gate: dict | None = None,
+            precision: int = rw.SG_BF16X3):
+    """Surrogate crops; the plain path serves the inputs the gate rejects (predicted error
+    above its threshold) and the out-of-distribution ones (any |c_q| > 4 x 0.05 waves or
+    |z| > 1 um).  Returns (crops, mask of the inputs the plain path served)."""
+    out = _forward_all(sg, coef, z, precision)
+    fallback = out_of_distribution(coef, z)
+    if gate is not None:
+        fallback = fallback | (sg.error_predict(coef, z, gate["weights"]) > gate["log_threshold"])
+    bad = fallback.nonzero().flatten()
     if bad.numel():
         out[bad] = eng.crops(coef[bad], z[bad])
-    return out, ood
+    return out, fallback
+
+
+def judge(sg: rw.Surrogate, eng: CropEngine, data: dict, gate: dict, precision: int = rw.SG_BF16X3):
+    """The gated surrogate on held-out crops, judged by the plain path: fraction sent to the
+    plain path, rel-L2 of the crops the network served, and of all crops."""
+    out, fb = predict(sg, eng, data["coef"], data["z"], gate, precision)
+    e = rel_l2_per_crop(out, data["target"]).cpu().numpy()
+    fbn = fb.cpu().numpy()
+    acc = e[~fbn]
+    return dict(fallback_fraction=float(fbn.mean()), n=int(e.size),
+                served_by_network=dict(median_rel_l2=float(np.median(acc)) if acc.size else None,
+                                       p95_rel_l2=float(np.percentile(acc, 95)) if acc.size else None,
+                                       max_rel_l2=float(acc.max()) if acc.size else None),
+                all_crops=dict(median_rel_l2=float(np.median(e)), p95_rel_l2=float(np.percentile(e, 95)),
+                               max_rel_l2=float(e.max())))
 
 
 def save(sg: rw.Surrogate, path: str):

@@ -13,11 +13,15 @@ D2 = "b" * 64
 
 
 def test_traffic_taken_only_at_the_recorded_digest():
-    text = f"# k\n\nsources sha256: {D1}  (...)\n  HBM bytes per dispatch: 123456\n"
-    assert bench.traffic_from_summary(text, D1) == 123456
-    assert bench.traffic_from_summary(text, D2) is None
-    assert bench.traffic_from_summary(text.replace("HBM bytes per dispatch", "bytes"), D1) is None
-    assert bench.traffic_from_summary("no digest here", D1) is None
+    text = (f"# k\n\nsources sha256: {D1}  (...)\n  HBM bytes per dispatch (gemm_pupil_kernel): 123456\n"
+            f"  trace average us (gemm_pupil_kernel): 861.25\n")
+    assert bench.traffic_from_summary(text, "gemm_pupil_kernel", D1) == 123456
+    assert bench.traffic_from_summary(text, "gemm_image_kernel", D1) is None
+    assert bench.traffic_from_summary(text, "gemm_pupil_kernel", D2) is None
+    assert bench.summary_field(text, "trace average us", "gemm_pupil_kernel", D1) == 861.25
+    assert bench.summary_field(text, "trace average us", "gemm_pupil_kernel", D2) is None
+    assert bench.traffic_from_summary(text.replace("HBM bytes per dispatch", "bytes"), "gemm_pupil_kernel", D1) is None
+    assert bench.traffic_from_summary("no digest here", "gemm_pupil_kernel", D1) is None
 
 
 def test_sources_digest_is_stable_and_hex():
@@ -27,7 +31,8 @@ def test_sources_digest_is_stable_and_hex():
 
 
 def test_missing_profile_gives_no_traffic():
-    assert bench.profiled_traffic("no_such_summary.txt") is None
+    assert bench.profiled_traffic("no_such_summary.txt", "gemm_pupil_kernel") is None
+    assert bench.profiled_average("no_such_summary.txt", "gemm_pupil_kernel") is None
 
 
 def test_more_than_one_gpu_is_refused():

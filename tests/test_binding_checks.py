@@ -1,5 +1,6 @@
 """The binding refuses tensors the library would misread before any pointer reaches it
 (host logic; no GPU needed)."""
+import numpy as np
 import pytest
 import torch
 
@@ -32,3 +33,22 @@ def test_phase_map_checked_when_stacks_are_marshalled():
         rw.make_stacks([dict(phase_map=torch.zeros(32, 32))], n_pupil=64)
     with pytest.raises(ValueError, match="CUDA"):
         rw.make_stacks([dict(phase_map=torch.zeros(64, 64))], n_pupil=64)
+
+
+def test_make_emitters_fills_every_field():
+    """The NumPy view that fills the ctypes emitter array puts each value in its C field."""
+    import ctypes
+    rng = np.random.default_rng(0)
+    n = 37
+    x0, y0, z = rng.normal(size=(3, n))
+    S, D = rng.integers(1, 65, n), rng.integers(1, 41, n)
+    c, ts = rng.normal(size=(n, 21)), rng.uniform(0, 5000, n)
+    a = rw.make_emitters(x0, y0, z, S, D, c, ts)
+    assert ctypes.sizeof(a) == n * ctypes.sizeof(rw.Emitter)
+    for i in range(n):
+        e = a[i]
+        assert (e.x0_nm, e.y0_nm, e.z_nm, e.crop, e.planes, e.t_s_nm) == (x0[i], y0[i], z[i], S[i], D[i], ts[i])
+        assert list(e.zernike_waves) == list(c[i])
+    b = rw.make_emitters([1.0], [2.0], [3.0], [5], [2], [[0.1, 0.2]])
+    assert (b[0].crop, b[0].planes, b[0].t_s_nm) == (5, 2, 0.0)
+    assert list(b[0].zernike_waves) == [0.1, 0.2] + [0.0] * 19

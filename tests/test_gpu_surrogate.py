@@ -11,12 +11,12 @@ pytestmark = pytest.mark.gpu
 
 
 def _flat(p):
-    return np.concatenate([p[k].ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3", "K1", "c1", "K2", "c2", "K3", "c3")])
+    return np.concatenate([p[k].ravel() for k in OS.KEYS])
 
 
 def _unflat(w, like):
     out, o = {}, 0
-    for k in ("W1", "b1", "W2", "b2", "W3", "b3", "K1", "c1", "K2", "c2", "K3", "c3"):
+    for k in OS.KEYS:
         n = like[k].size
         out[k] = w[o:o + n].reshape(like[k].shape).astype(np.float64)
         o += n
@@ -47,7 +47,7 @@ def _decisive_params(seed, x):
         p[f"W{i}"] *= 1.5 / np.abs(raw).max()
         p[f"W{i}"] = p[f"W{i}"].astype(np.float32).astype(np.float64)
         h = np.maximum(h @ p[f"W{i}"] + p[f"b{i}"], 0.0)
-    d = h.reshape(-1, 32, 8, 8)
+    d = h.reshape(-1, 16, 8, 8)
     for i in range(1, 4):
         p[f"c{i}"] = 3.0 * rng.choice([-1.0, 1.0], p[f"c{i}"].shape)
         raw = OS.deconv(d, p[f"K{i}"], np.zeros_like(p[f"c{i}"]))
@@ -129,33 +129,55 @@ def test_surrogate_gradient_is_deterministic(lib):
     np.testing.assert_array_equal(g1, g2)
 
 
-def test_surrogate_training_reduces_error_and_audit(lib):
-    """Train briefly on engine-generated crops; the loss falls and the audit/fallback work."""
+def test_surrogate_gated_fallback_meets_bar_and_beats_plain_path(lib):
+    """Train briefly on engine-generated crops, fit the error-gated fallback on calibration
+    crops, and judge it on held-out crops: the crops the network serves meet the stated bar,
+    the rest come from the plain path bit for bit, and serving through the gate is faster
+    than the plain path alone on the same inputs."""
+    import time
+
     import torch
     from paper_2502_03170_amd import surrogate_train as ST
     rw = lib
+    bar = 0.3           # p95 rel-L2 of the crops the network serves, after this short run
     eng = ST.CropEngine(max_emitters=4096)
     train = ST.make_dataset(eng, 65536, seed=505)
-    test = ST.make_dataset(eng, 512, seed=506)
-    sg = rw.Surrogate(max_batch=256)
-    sg.set_state(ST.init_params(0))
+    calib = ST.make_dataset(eng, 2048, seed=507)
+    test = ST.make_dataset(eng, 2048, seed=506)
+    sg = rw.Surrogate(max_batch=16384)
+    sg.set_state(ST.init_params(0, basis=ST.crop_basis(train, 2048)))
     before = ST.audit(sg, eng, test)
-    hist = ST.train(sg, train, steps=1500, batch=256, lr=2e-3, lr_end=1e-4, seed=0)
-    assert hist[-1] < 0.5 * hist[0], (hist[0], hist[-1])
+    hist = ST.train(sg, train, steps=8000, batch=ST.BATCH, lr=ST.LR, lr_end=1e-5, seed=0)
+    assert hist[-1] < 0.2 * hist[0], (hist[0], hist[-1])
     rep = ST.audit(sg, eng, test)
-    base = ST.mean_crop_baseline(train, test)
-    # a learned approximation: the bar is that the trained network uses its inputs -- it
-    # beats the best input-independent prediction (the mean training crop) by a clear
-    # margin (the absolute accuracy after a longer run is reported by the benchmark)
-    assert rep["median_rel_l2"] < 0.85 * base["median_rel_l2"], (before, rep, base)
     assert rep["median_rel_l2"] < 0.5 * before["median_rel_l2"], (before, rep)
-    # out-of-distribution inputs go to the plain path and match it exactly
-    coef = test["coef"][:4].clone()
+    gate = ST.fit_gate(sg, calib, bar)
+    j = ST.judge(sg, eng, test, gate)
+    assert 0.0 < j["fallback_fraction"] < 0.9, j
+    # the threshold was fitted on other crops: the held-out quantile may sit a little above
+    assert j["served_by_network"]["p95_rel_l2"] <= 1.2 * bar, j
+    # fallback crops (gate rejects and out-of-distribution inputs) are the plain path's
+    coef = test["coef"][:64].clone()
+    z = test["z"][:64].clone()
     coef[0, 5] = 1.0                 # 20 sigma
-    z = test["z"][:4].clone()
     z[1] = 3000.0                    # outside the trained defocus range
-    out, used_fallback = ST.predict(sg, eng, coef, z)
-    assert used_fallback.tolist() == [True, True, False, False]
-    plain = eng.crops(coef[:2], z[:2])
+    out, fb = ST.predict(sg, eng, coef, z, gate)
+    assert fb[0].item() and fb[1].item()
+    idx = fb.nonzero().flatten()
+    plain = eng.crops(coef[idx], z[idx])
     torch.cuda.synchronize()
-    np.testing.assert_array_equal(out[:2].cpu().numpy(), plain.cpu().numpy())
+    np.testing.assert_array_equal(out[idx].cpu().numpy(), plain.cpu().numpy())
+    # throughput on 16384 in-distribution inputs, both through the same host staging
+    big = ST.make_dataset(eng, 16384, seed=508)
+
+    def wall(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    t_plain = wall(lambda: eng.crops(big["coef"], big["z"]))
+    t_gated = wall(lambda: ST.predict(sg, eng, big["coef"], big["z"], gate))
+    assert t_gated < t_plain, (t_gated, t_plain, j)

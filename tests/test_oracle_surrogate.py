@@ -6,17 +6,25 @@ import torch
 from oracle import surrogate as OS
 
 
-def _torch_forward(p, x):
+def _torch_net(tp, x):
+    """The network from torch's float64 layers; tp maps parameter names to tensors."""
     h = torch.tensor(x)
+    hs = []
     for i in range(1, 4):
-        h = torch.relu(h @ torch.tensor(p[f"W{i}"]) + torch.tensor(p[f"b{i}"]))
-    d = h.reshape(-1, 32, 8, 8)
+        h = torch.relu(torch.nn.functional.linear(h, tp[f"W{i}"].T, tp[f"b{i}"]))
+        hs.append(h)
+    d = h.reshape(-1, 16, 8, 8)
     for i in range(1, 4):
-        d = torch.nn.functional.conv_transpose2d(d, torch.tensor(p[f"K{i}"]), torch.tensor(p[f"c{i}"]),
-                                                 stride=2, padding=1)
+        d = torch.nn.functional.conv_transpose2d(d, tp[f"K{i}"], tp[f"c{i}"], stride=2, padding=1)
         if i < 3:
             d = torch.relu(d)
-    return d[:, 0]
+    a = torch.nn.functional.linear(hs[2], tp["Wa"].T, tp["ba"])
+    yb = torch.nn.functional.linear(a, tp["Wb"].T, tp["bb"])
+    return d[:, 0] + yb.reshape(-1, 64, 64)
+
+
+def _torch_forward(p, x):
+    return _torch_net({k: torch.tensor(v) for k, v in p.items()}, x)
 
 
 def test_forward_matches_torch_layers():
@@ -38,15 +46,8 @@ def test_gradients_match_torch_autograd():
     target = rng.normal(0, 1, (3, 64, 64))
     loss, g = OS.loss_and_grads(p, x, target)
     tp = {k: torch.tensor(v, requires_grad=True) for k, v in p.items()}
-    h = torch.tensor(x)
-    for i in range(1, 4):
-        h = torch.relu(h @ tp[f"W{i}"] + tp[f"b{i}"])
-    d = h.reshape(-1, 32, 8, 8)
-    for i in range(1, 4):
-        d = torch.nn.functional.conv_transpose2d(d, tp[f"K{i}"], tp[f"c{i}"], stride=2, padding=1)
-        if i < 3:
-            d = torch.relu(d)
-    tl = ((d[:, 0] - torch.tensor(target)) ** 2).mean()
+    y = _torch_net(tp, x)
+    tl = ((y - torch.tensor(target)) ** 2).mean()
     tl.backward()
     assert abs(loss - tl.item()) < 1e-12 * abs(loss)
     for k in p:
@@ -59,8 +60,8 @@ def test_gradient_finite_differences():
     x = OS.features(rng.normal(0, 0.05, (2, 21)), rng.uniform(-1000, 1000, 2))
     target = rng.normal(0, 0.5, (2, 64, 64))
     _, g = OS.loss_and_grads(p, x, target)
-    for key, idx in [("W1", (3, 17)), ("W3", (100, 7)), ("b2", (11,)), ("K1", (2, 3, 1, 2)), ("K3", (5, 0, 3, 3)),
-                     ("c2", (4,))]:
+    for key, idx in [("W1", (3, 17)), ("W3", (100, 7)), ("W2", (900, 1000)), ("b2", (11,)), ("K1", (2, 3, 1, 2)), ("K3", (5, 0, 3, 3)),
+                     ("c2", (4,)), ("Wa", (700, 31)), ("ba", (5,)), ("Wb", (200, 2080)), ("bb", (2081,))]:
         h = 1e-6
         pp = {k: v.copy() for k, v in p.items()}
         pm = {k: v.copy() for k, v in p.items()}
