@@ -327,17 +327,22 @@ def bench_batched(rw, torch, steps, warmup):
     D = w["D"].astype(np.float64)
     n = w["n_pupil"]
     flops = float(np.sum(D * 3 * 4.0 * S * n * (n + S)))     # folded: U = A2_S Pf~, E' = U B1_S per plane
+    # executed work on the chosen row tiles (rows rounded up to the tile class)
+    SP = np.array([cfg["tile_rows"][(int(s) - 1) // 16] for s in w["S"]], dtype=np.float64)
+    flops_exec = float(np.sum(D * 3 * 4.0 * SP * n * (n + SP)))
     ach = flops / (ms * 1e-3) / 1e12
     return dict(workload="batched: 4096 emitters, crops U{24..64}, planes U{1..41}, 128x128 pupil, "
                          "Noll 4-21 N(0,0.04), sub-pixel x0/y0, intensity only, one persistent launch per "
-                         "tile class, replayed from a hipGraph, autotuned",
+                         "tile class (16/32/48/64-row tiles), replayed from a hipGraph, tile classes, k-stages "
+                         "and residency autotuned",
                 value=off[-1] / (ms * 1e-3), unit="voxels/s", ms_per_launch=ms, voxels=off[-1],
-                autotuned_config=dict(wg_per_cu=cfg[0], small_tile_max_crop=cfg[1]),
+                autotuned_config=dict(cfg, tuned_ms=tune_ms),
                 roofline=dict(kernel="batch_planes_kernel (+ phase GEMM)", bound="mfma",
                               achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
                               frac=round(ach / PEAK_FP32_TFLOPS, 4),
                               traffic=profiled_traffic("batch_planes_batched.txt", "batched call"),
-                              flops_per_launch=flops, avg_launch_us=ms * 1e3))
+                              flops_per_launch=flops, avg_launch_us=ms * 1e3,
+                              executed_over_algorithmic=round(flops_exec / flops, 4)))
 
 
 def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):

@@ -275,19 +275,28 @@ int rwpsf_batch_offsets(int n, const rwpsf_emitter* emitters, int64_t* offsets);
 
 /* Evaluate n emitters (host array, validated and copied before return).  I_out:
    device float [total voxels] or NULL; E_out: device complex64 [3 total voxels] or
-   NULL (not both NULL).  With graphs enabled the copy, phase GEMM and persistent
-   kernel are captured once per (n, outputs, configuration, stream) and replayed;
-   graph mode needs a created stream (not NULL).  Before the host staging area is
-   rewritten the call waits for the previous call's upload. */
+   NULL (not both NULL).  The emitters are staged in a pinned host area and copied to the
+   device at the start of the call's work on `stream`; with graphs enabled the kernels
+   (queue reset, phase GEMM, fold, persistent plane kernels) are captured once per (n,
+   outputs, configuration, launched tile classes, stream) and replayed after the copy;
+   graph mode needs a created stream (not NULL).  Before the staging area is rewritten
+   the call waits for the previous call's copy (not for its kernels). */
 int rwpsf_batch_compute(rwpsf_batch* batch, int n, const rwpsf_emitter* emitters, float* I_out,
                         void* E_out, void* stream);
 int rwpsf_batch_set_graph(rwpsf_batch* batch, int enable);
 
-/* Launch configuration: workgroups per CU of the persistent grid (1..4) and the
-   largest crop evaluated with 32-wide tiles (0 or 32; larger crops use 64). */
+/* Launch configuration.  Crops fall into four buckets by size (1-16, 17-32, 33-48 and
+   49-64 pixels); the crops of bucket q are evaluated on tiles of tile_rows[q] rows (16,
+   32, 48 or 64, at least 16 (q + 1)); the tile class of r rows stages its pupil GEMM in
+   k-stages of k_stage[r / 16 - 1] folded pupil rows (8 or 16); the persistent grid of
+   each class has wg_per_cu workgroups per CU (1..4).  The 32- and 64-row classes run
+   32 x 32 x 2 matrix-core tiles, the 16- and 48-row classes 16 x 16 x 4 ones.  The
+   default puts each bucket on its own class with k-stages of 16 and two workgroups per
+   CU. */
 typedef struct rwpsf_batch_config {
   int wg_per_cu;
-  int small_tile_max_crop;
+  int tile_rows[4];
+  int k_stage[4];
 } rwpsf_batch_config;
 int rwpsf_batch_set_config(rwpsf_batch* batch, const rwpsf_batch_config* cfg);
 int rwpsf_batch_get_config(const rwpsf_batch* batch, rwpsf_batch_config* cfg);

@@ -94,7 +94,21 @@ class Emitter(ctypes.Structure):
 
 
 class BatchConfig(ctypes.Structure):
-    _fields_ = [("wg_per_cu", c_int), ("small_tile_max_crop", c_int)]
+    _fields_ = [("wg_per_cu", c_int), ("tile_rows", c_int * 4), ("k_stage", c_int * 4)]
+
+    def as_dict(self) -> dict:
+        return dict(wg_per_cu=self.wg_per_cu, tile_rows=list(self.tile_rows), k_stage=list(self.k_stage))
+
+
+def batch_config(wg_per_cu: int = 2, tile_rows=(16, 32, 48, 64), k_stage=(16, 16, 16, 16)) -> BatchConfig:
+    """Launch configuration of the batched form: crops of 1-16, 17-32, 33-48, 49-64 pixels on
+    row tiles tile_rows[q]; the class of r-row tiles stages k_stage[r / 16 - 1] pupil rows."""
+    c = BatchConfig()
+    c.wg_per_cu = wg_per_cu
+    for q in range(4):
+        c.tile_rows[q] = int(tile_rows[q])
+        c.k_stage[q] = int(k_stage[q])
+    return c
 
 
 _lib = None
@@ -476,14 +490,14 @@ class Batch:
     def set_graph(self, enable: bool):
         _check(load().rwpsf_batch_set_graph(self.handle, int(bool(enable))))
 
-    def set_config(self, wg_per_cu: int, small_tile_max_crop: int):
-        cfg = BatchConfig(wg_per_cu, small_tile_max_crop)
+    def set_config(self, wg_per_cu: int = 2, tile_rows=(16, 32, 48, 64), k_stage=(16, 16, 16, 16)):
+        cfg = batch_config(wg_per_cu, tile_rows, k_stage)
         _check(load().rwpsf_batch_set_config(self.handle, byref(cfg)))
 
     def get_config(self):
         cfg = BatchConfig()
         _check(load().rwpsf_batch_get_config(self.handle, byref(cfg)))
-        return cfg.wg_per_cu, cfg.small_tile_max_crop
+        return cfg.as_dict()
 
     def compute(self, emitters, I=None, E=None, stream=None):
         """I float32 [total voxels] and E complex64 [3 total voxels] (CUDA; either may be None)."""
@@ -499,7 +513,7 @@ class Batch:
         cfg, ms = BatchConfig(), c_double()
         _check(load().rwpsf_batch_autotune(self.handle, len(emitters), emitters, i, _stream(stream),
                                            byref(cfg), byref(ms)))
-        return (cfg.wg_per_cu, cfg.small_tile_max_crop), ms.value
+        return cfg.as_dict(), ms.value
 
     def close(self):
         if self.handle:

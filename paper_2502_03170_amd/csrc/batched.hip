@@ -44,10 +44,7 @@ typedef float f16v_t __attribute__((ext_vector_type(16)));
 constexpr int kTabRows = 96;    // DFT table rows: x_r = (r - 32) * pixel
 constexpr int kBasisRows = 32;  // 21 Zernike + s_x + s_y, zero-padded
 constexpr int kMaxWgPerCu = 4;  // workgroups per CU of the persistent launch (configuration bound)
-constexpr int kQueues = 16;     // 8 XCD queues for each of the two tile classes (32- and 64-wide)
-constexpr int kBK = 16;                       // k-stage of the staged pupil GEMM
-constexpr int kLdaU = 64 + 4, kLdbU = 128 + 4;  // LDS row strides of its A (crop rows) and B (columns)
-constexpr int kStageU = kBK * (kLdaU + 2 * kLdbU);
+constexpr int kQueues = 32;     // 8 XCD queues for each of the four tile classes (16 .. 64 rows)
 
 struct BatchParam {
   double zoff;      // -z_e
@@ -140,11 +137,13 @@ __global__ void __launch_bounds__(256) batch_fold_kernel(BatchArgs a) {
 // Plane d of emitter `slot`:  U = A2 (D o Pf_c)  (real x complex),  E' = U B1
 // (complex x real),  E = -i E',  I = sum_c |E_c|^2, with the defocus D[jf][lf] =
 // exp(i k s_z z) of the folded cell, the same for its four mirror cells.
-template <int SP>
-__device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam& bp, int slot, int d,
+template <int SP, int BK>
+__device__ __forceinline__ void batch_plane32(const BatchArgs& a, const BatchParam& bp, int slot, int d,
                                             float* lds, int tid) {
   constexpr int TI = SP / 32;
   constexpr int LDU = SP + 1;
+  constexpr int kLdaU = 64 + 4, kLdbU = 128 + 4;   // LDS row strides of the staged A (crop rows) and B (columns)
+  constexpr int kStage32 = BK * (kLdaU + 2 * kLdbU);
   const int lane = tid & 63, w = tid >> 6, h = lane >> 5, l32 = lane & 31;
   const int N = a.N, NN = N * N, S = bp.S;
   const int r0 = 32 - S / 2;
@@ -167,36 +166,43 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
       float ra[4];      // A prefetch: BK x SP floats, up to 4 per thread
       float4 rp[4];     // B prefetch: BK x N/2 float4, up to 4 per thread
       double rd[4];     // k s_z of the staged folded cell
-      const int na = kBK * SP / 256, nb = kBK * (N / 2) / 256;
+      const int na = BK * SP, nb = BK * (N / 2);   // A floats and B float4 of one stage, up to 4 per thread
       auto load = [&](int k0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i < na) {
-            const int idx = tid + 256 * i, kk = idx / SP, m = idx % SP;
+        for (int i = 0; i < 4; ++i) {
+          const int idx = tid + 256 * i;
+          if (idx < na) {
+            const int kk = idx / SP, m = idx % SP;
             ra[i] = a.A2T[(k0 + kk) * kTabRows + r0 + m];
           }
+        }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i < nb) {
-            const int idx = tid + 256 * i, kk = idx / (N / 2), c2 = idx % (N / 2);
+        for (int i = 0; i < 4; ++i) {
+          const int idx = tid + 256 * i;
+          if (idx < nb) {
+            const int kk = idx / (N / 2), c2 = idx % (N / 2);
             rp[i] = *reinterpret_cast<const float4*>(Pc + (size_t)(k0 + kk) * N + 2 * c2);
             rd[i] = a.ksz[((k0 + kk) >> 1) * N + c2];
           }
+        }
       };
       auto store = [&](float* st) {
         float* sa = st;
-        float* sr = st + kBK * kLdaU;
-        float* si = sr + kBK * kLdbU;
+        float* sr = st + BK * kLdaU;
+        float* si = sr + BK * kLdbU;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i < na) {
-            const int idx = tid + 256 * i, kk = idx / SP, m = idx % SP;
+        for (int i = 0; i < 4; ++i) {
+          const int idx = tid + 256 * i;
+          if (idx < na) {
+            const int kk = idx / SP, m = idx % SP;
             sa[kk * kLdaU + m] = ra[i];
           }
+        }
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (i < nb) {
-            const int idx = tid + 256 * i, kk = idx / (N / 2), c2 = idx % (N / 2);
+        for (int i = 0; i < 4; ++i) {
+          const int idx = tid + 256 * i;
+          if (idx < nb) {
+            const int kk = idx / (N / 2), c2 = idx % (N / 2);
             float2 dz;   // exp(i k s_z z): FP64 phase in revolutions, hardware sine and cosine
             sincos_rev(rd[i] * zrev, &dz.y, &dz.x);
             *reinterpret_cast<float2*>(sr + kk * kLdbU + 2 * c2) =
@@ -204,6 +210,7 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
             *reinterpret_cast<float2*>(si + kk * kLdbU + 2 * c2) =
                 make_float2(rp[i].x * dz.y + rp[i].y * dz.x, rp[i].z * dz.y + rp[i].w * dz.x);
           }
+        }
       };
       f16v_t ur[TI], ui[TI];
 #pragma unroll
@@ -214,21 +221,21 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
           ui[i][r] = 0.f;
         }
       const bool has_cols = 32 * w < N;
-      const int KT = N / kBK;
+      const int KT = N / BK;
       load(0);
       store(lds);
       __syncthreads();
       for (int kt = 0; kt < KT; ++kt) {
-        float* cur = lds + (kt & 1) * kStageU;
-        float* nxt = lds + ((kt + 1) & 1) * kStageU;
+        float* cur = lds + (kt & 1) * kStage32;
+        float* nxt = lds + ((kt + 1) & 1) * kStage32;
         const bool more = kt + 1 < KT;
-        if (more) load((kt + 1) * kBK);
+        if (more) load((kt + 1) * BK);
         if (has_cols) {
           const float* sa = cur;
-          const float* sr = cur + kBK * kLdaU;
-          const float* si = sr + kBK * kLdbU;
+          const float* sr = cur + BK * kLdaU;
+          const float* si = sr + BK * kLdbU;
 #pragma unroll
-          for (int kp = 0; kp < kBK / 2; ++kp) {
+          for (int kp = 0; kp < BK / 2; ++kp) {
             const int kk = 2 * kp + h;
             const float br = sr[kk * kLdbU + 32 * w + l32], bi = si[kk * kLdbU + 32 * w + l32];
 #pragma unroll
@@ -345,7 +352,265 @@ __device__ __forceinline__ void batch_plane(const BatchArgs& a, const BatchParam
   __syncthreads();   // every wave is done with the LDS before the next item
 }
 
-constexpr int kBatchLdsBytes = 2 * 128 * 65 * 4;   // U for N <= 128, SP = 64
+// MFMA 16x16x4 f32: A lane l -> A[l%16][l/16], B lane l -> B[l/16][l%16],
+// C register r of lane l -> C[4(l/16) + r][l%16].
+//
+// Plane d of emitter `slot` on a tile of SP rows (SP = 16, 32, 48 or 64 >= S):
+//   U = A2 (D o Pf_c)  (real x complex, SP x N),  E' = U B1  (complex x real, SP x SP),
+//   E = -i E',  I = sum_c |E_c|^2,
+// with the defocus D[jf][lf] = exp(i k s_z z) of the folded cell, the same for its four
+// mirror cells.  U: wave w owns columns 32 w .. 32 w + 31 (two 16-wide column tiles) and
+// all SP / 16 row tiles; k-stages of BK folded rows are staged in LDS, double-buffered.
+// E': the (SP / 16)^2 output tiles are dealt round-robin to the four waves, each over the
+// whole K = N; a single tile (SP = 16) is split over K between the waves and the four
+// partial sums are added through LDS.
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <int SP, int BK>
+struct PlaneTile {
+  static constexpr int MT = SP / 16;                 // row tiles
+  static constexpr int T2 = MT * MT;                 // output tiles of E'
+  static constexpr bool KSPLIT = T2 < 4;             // SP = 16: one tile, K split four ways
+  static constexpr int TPW = KSPLIT ? 1 : (T2 + 3) / 4;   // output tiles per wave
+  static constexpr int LDA = SP + 4;                 // LDS row strides of the staged operands
+  static constexpr int LDB = 128 + 4;
+  static constexpr int STAGE = BK * (LDA + 2 * LDB);
+  static constexpr int LDU = SP + 1;                 // U: [col][m]
+  static constexpr int LDS_FLOATS = (2 * STAGE > 2 * 128 * LDU) ? 2 * STAGE : 2 * 128 * LDU;
+};
+
+template <int SP, int BK>
+__device__ __forceinline__ void batch_plane16(const BatchArgs& a, const BatchParam& bp, int slot, int d,
+                                              float* lds, int tid) {
+  using P = PlaneTile<SP, BK>;
+  constexpr int MT = P::MT, TPW = P::TPW;
+  const int lane = tid & 63, w = tid >> 6, g = lane >> 4, l16 = lane & 15;
+  const int N = a.N, NN = N * N, S = bp.S;
+  const int r0 = 32 - S / 2;
+  const float2* Pf = a.Pf + (size_t)slot * 3 * NN;
+  float* Ure = lds;
+  float* Uim = lds + 128 * P::LDU;
+  const double zrev = ((d - 0.5 * (bp.D - 1)) * a.pitch + bp.zoff) * (1.0 / kTwoPi);
+  f4_t isum[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) isum[t] = f4_t{0.f, 0.f, 0.f, 0.f};
+  for (int c = 0; c < 3; ++c) {
+    const float2* Pc = Pf + (size_t)c * NN;
+    // ---- U[m][col] = sum_k A2[r0 + m][k] (D o Pf)[k][col]
+    {
+      constexpr int NA = (BK * SP + 255) / 256;       // A loads per thread (the last may be partial)
+      constexpr int NB = (BK * 64 + 255) / 256;       // B loads (float4 = two complex) per thread, N <= 128
+      float ra[NA];
+      float4 rp[NB];
+      double rd[NB];
+      const int nbv = BK * (N / 2);                   // float4 of B per stage
+      auto load = [&](int k0) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+          const int idx = tid + 256 * i;
+          if (idx < BK * SP) {
+            const int kk = idx / SP, m = idx % SP;
+            ra[i] = a.A2T[(k0 + kk) * kTabRows + r0 + m];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int idx = tid + 256 * i;
+          if (idx < nbv) {
+            const int kk = idx / (N / 2), c2 = idx % (N / 2);
+            rp[i] = *reinterpret_cast<const float4*>(Pc + (size_t)(k0 + kk) * N + 2 * c2);
+            rd[i] = a.ksz[((k0 + kk) >> 1) * N + c2];
+          }
+        }
+      };
+      auto store = [&](float* st) {
+        float* sa = st;
+        float* sr = st + BK * P::LDA;
+        float* si = sr + BK * P::LDB;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+          const int idx = tid + 256 * i;
+          if (idx < BK * SP) {
+            const int kk = idx / SP, m = idx % SP;
+            sa[kk * P::LDA + m] = ra[i];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int idx = tid + 256 * i;
+          if (idx < nbv) {
+            const int kk = idx / (N / 2), c2 = idx % (N / 2);
+            float2 dz;   // exp(i k s_z z): FP64 phase in revolutions, hardware sine and cosine
+            sincos_rev(rd[i] * zrev, &dz.y, &dz.x);
+            *reinterpret_cast<float2*>(sr + kk * P::LDB + 2 * c2) =
+                make_float2(rp[i].x * dz.x - rp[i].y * dz.y, rp[i].z * dz.x - rp[i].w * dz.y);
+            *reinterpret_cast<float2*>(si + kk * P::LDB + 2 * c2) =
+                make_float2(rp[i].x * dz.y + rp[i].y * dz.x, rp[i].z * dz.y + rp[i].w * dz.x);
+          }
+        }
+      };
+      f4_t ur[MT][2], ui[MT][2];
+#pragma unroll
+      for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          ur[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+          ui[i][j] = f4_t{0.f, 0.f, 0.f, 0.f};
+        }
+      const bool has_cols = 32 * w < N;
+      const int KT = N / BK;
+      load(0);
+      store(lds);
+      __syncthreads();
+      for (int kt = 0; kt < KT; ++kt) {
+        float* cur = lds + (kt & 1) * P::STAGE;
+        float* nxt = lds + ((kt + 1) & 1) * P::STAGE;
+        const bool more = kt + 1 < KT;
+        if (more) load((kt + 1) * BK);
+        if (has_cols) {
+          const float* sa = cur;
+          const float* sr = cur + BK * P::LDA;
+          const float* si = sr + BK * P::LDB;
+#pragma unroll
+          for (int kq = 0; kq < BK / 4; ++kq) {
+            const int kk = 4 * kq + g;
+            float br[2], bi[2];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              br[j] = sr[kk * P::LDB + 32 * w + 16 * j + l16];
+              bi[j] = si[kk * P::LDB + 32 * w + 16 * j + l16];
+            }
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+              const float av = sa[kk * P::LDA + 16 * i + l16];
+#pragma unroll
+              for (int j = 0; j < 2; ++j) {
+                ur[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, br[j], ur[i][j], 0, 0, 0);
+                ui[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bi[j], ui[i][j], 0, 0, 0);
+              }
+            }
+          }
+        }
+        if (more) store(nxt);
+        __syncthreads();
+      }
+      // U overwrites the stage buffers: every wave has passed the last barrier above
+      if (has_cols) {
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const int col = 32 * w + 16 * j + l16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int m = 16 * i + 4 * g + r;
+              Ure[col * P::LDU + m] = ur[i][j][r];
+              Uim[col * P::LDU + m] = ui[i][j][r];
+            }
+          }
+      }
+    }
+    __syncthreads();
+    // ---- E'[m][n] = sum_col U[m][col] B1[col][r0 + n]
+    float2* Ec = a.E ? a.E + 3 * bp.off + ((size_t)(d * 3 + c) * S) * S : nullptr;
+    if (!P::KSPLIT) {
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = w + 4 * t;
+        if (tile < P::T2) {
+          const int mi = tile / MT, ni = tile % MT;
+          f4_t er = {0.f, 0.f, 0.f, 0.f}, ei = {0.f, 0.f, 0.f, 0.f};
+          // the y-table operand comes from global memory: chunks of four k-steps (16
+          // columns) are loaded one chunk ahead of the MFMAs that use them (N % 16 == 0)
+          const float* bsrc = a.B1T + r0 + 16 * ni + l16 + g * kTabRows;
+          float bc[4], bn[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) bc[q] = bsrc[(4 * q) * kTabRows];
+          for (int k0 = 0; k0 < N; k0 += 16) {
+            const bool more = k0 + 16 < N;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bn[q] = more ? bsrc[(k0 + 16 + 4 * q) * kTabRows] : 0.f;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int col = k0 + 4 * q + g;
+              const float ar = Ure[col * P::LDU + 16 * mi + l16], ai = Uim[col * P::LDU + 16 * mi + l16];
+              er = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, bc[q], er, 0, 0, 0);
+              ei = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, bc[q], ei, 0, 0, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) bc[q] = bn[q];
+          }
+          // E = -i E' = (Im E', -Re E')
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = 16 * mi + 4 * g + r, n = 16 * ni + l16;
+            isum[t][r] += er[r] * er[r] + ei[r] * ei[r];
+            if (Ec && m < S && n < S) Ec[m * S + n] = make_float2(ei[r], -er[r]);
+          }
+        }
+      }
+      __syncthreads();   // U is consumed
+    } else {
+      // one 16 x 16 tile: wave w sums columns [w N / 4, (w + 1) N / 4), partials through LDS
+      f4_t er = {0.f, 0.f, 0.f, 0.f}, ei = {0.f, 0.f, 0.f, 0.f};
+      const float* bsrc = a.B1T + r0 + l16;
+      const int ka = w * (N / 4), kb = (w + 1) * (N / 4);
+      for (int k0 = ka; k0 < kb; k0 += 4) {
+        const int col = k0 + g;
+        const float bv = bsrc[col * kTabRows];
+        er = __builtin_amdgcn_mfma_f32_16x16x4f32(Ure[col * P::LDU + l16], bv, er, 0, 0, 0);
+        ei = __builtin_amdgcn_mfma_f32_16x16x4f32(Uim[col * P::LDU + l16], bv, ei, 0, 0, 0);
+      }
+      __syncthreads();   // U is consumed; the partials reuse its space
+      float* part = lds + w * 2 * 256;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = 4 * g + r;
+        part[m * 16 + l16] = er[r];
+        part[256 + m * 16 + l16] = ei[r];
+      }
+      __syncthreads();
+      if (tid < 256) {
+        const int m = tid >> 4, n = tid & 15;
+        float sr = 0.f, si = 0.f;
+#pragma unroll
+        for (int ww = 0; ww < 4; ++ww) {
+          sr += lds[ww * 512 + m * 16 + n];
+          si += lds[ww * 512 + 256 + m * 16 + n];
+        }
+        // thread tid keeps element (m, n) = (tid / 16, tid % 16) of the single tile
+        isum[0][0] += sr * sr + si * si;
+        if (Ec && m < S && n < S) Ec[m * S + n] = make_float2(si, -sr);
+      }
+      __syncthreads();
+    }
+  }
+  if (a.I) {
+    float* Ip = a.I + bp.off + (size_t)d * S * S;
+    if (!P::KSPLIT) {
+#pragma unroll
+      for (int t = 0; t < TPW; ++t) {
+        const int tile = w + 4 * t;
+        if (tile < P::T2) {
+          const int mi = tile / MT, ni = tile % MT;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int m = 16 * mi + 4 * g + r, n = 16 * ni + l16;
+            if (m < S && n < S) Ip[m * S + n] = isum[t][r];
+          }
+        }
+      }
+    } else {
+      const int m = tid >> 4, n = tid & 15;
+      if (m < S && n < S) Ip[m * S + n] = isum[0][0];
+    }
+  }
+  __syncthreads();   // every wave is done with the LDS before the next item
+}
+
+// Tile classes: row tiles of 16, 32, 48, 64; class t serves queues 8 t .. 8 t + 7.
+constexpr int kTileClasses = 4;
+__host__ __device__ constexpr int class_rows(int t) { return 16 * (t + 1); }
 
 // Persistent plane kernel of one tile class (one launch per class, so that each has the
 // registers of its own tile shape).  Workgroup ids are dealt round-robin over the 8 XCDs,
@@ -353,12 +618,12 @@ constexpr int kBatchLdsBytes = 2 * 128 * 65 * 4;   // U for N <= 128, SP = 64
 // emitters assigned to that queue, in order, so that the planes of one emitter run at the
 // same time on one XCD and its folded pupil is read from that XCD's L2.  A workgroup exits
 // when its queue is exhausted; the grid has at least 8 workgroups, one per queue.
-template <int SP>
+template <int SP, int BK>
 __global__ void __launch_bounds__(256, 2) batch_planes_kernel(BatchArgs a) {
   extern __shared__ float lds[];
   __shared__ long long item;
   const int tid = threadIdx.x;
-  const int x = 8 * (SP == 64 ? 1 : 0) + (blockIdx.x & 7);
+  const int x = 8 * (SP / 16 - 1) + (blockIdx.x & 7);
   const int lo = a.qoff[x], hi = a.qoff[x + 1];
   const long long end = a.pre[hi];
   for (;;) {
@@ -376,15 +641,63 @@ __global__ void __launch_bounds__(256, 2) batch_planes_kernel(BatchArgs a) {
     const int slot = a.list[e0];
     const int d = (int)(it - a.pre[e0]);
     const BatchParam bp = a.params[slot];
-    batch_plane<SP>(a, bp, slot, d, lds, tid);
+    if constexpr (SP == 32 || SP == 64)
+      batch_plane32<SP, BK>(a, bp, slot, d, lds, tid);
+    else
+      batch_plane16<SP, BK>(a, bp, slot, d, lds, tid);
   }
 }
+
+// LDS of a class: the 32 x 32 tiles (SP = 32, 64) hold U of a 64-row tile (or the two
+// stage buffers, if larger); the 16 x 16 tiles size it for their own rows
+template <int SP, int BK>
+constexpr int plane_lds_bytes() {
+  return (SP == 32 || SP == 64) ? ((2 * 128 * 65 > 2 * BK * (68 + 2 * 132)) ? 2 * 128 * 65 : 2 * BK * (68 + 2 * 132)) * 4
+                                : PlaneTile<SP, BK>::LDS_FLOATS * 4;
+}
+
+// every (tile class, k-stage) instantiation, indexed [class][k-stage index] (BK = 8, 16)
+typedef void (*PlaneKernel)(BatchArgs);
+static const PlaneKernel kPlaneKernels[kTileClasses][2] = {
+    {batch_planes_kernel<16, 8>, batch_planes_kernel<16, 16>},
+    {batch_planes_kernel<32, 8>, batch_planes_kernel<32, 16>},
+    {batch_planes_kernel<48, 8>, batch_planes_kernel<48, 16>},
+    {batch_planes_kernel<64, 8>, batch_planes_kernel<64, 16>}};
+static const int kPlaneLds[kTileClasses][2] = {{plane_lds_bytes<16, 8>(), plane_lds_bytes<16, 16>()},
+                                               {plane_lds_bytes<32, 8>(), plane_lds_bytes<32, 16>()},
+                                               {plane_lds_bytes<48, 8>(), plane_lds_bytes<48, 16>()},
+                                               {plane_lds_bytes<64, 8>(), plane_lds_bytes<64, 16>()}};
 
 }  // namespace rw
 
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
+namespace rw {
+// each crop bucket on its own tile class, k-stages of 16, two workgroups per CU
+static rwpsf_batch_config default_config() {
+  rwpsf_batch_config c{};
+  c.wg_per_cu = 2;
+  for (int q = 0; q < 4; ++q) {
+    c.tile_rows[q] = 16 * (q + 1);
+    c.k_stage[q] = 16;
+  }
+  return c;
+}
+static bool config_valid(const rwpsf_batch_config& c) {
+  if (c.wg_per_cu < 1 || c.wg_per_cu > kMaxWgPerCu) return false;
+  for (int q = 0; q < 4; ++q) {
+    if (c.tile_rows[q] % 16 != 0 || c.tile_rows[q] < 16 * (q + 1) || c.tile_rows[q] > 64) return false;
+    if (c.k_stage[q] != 8 && c.k_stage[q] != 16) return false;
+  }
+  return true;
+}
+static bool config_equal(const rwpsf_batch_config& x, const rwpsf_batch_config& y) {
+  return x.wg_per_cu == y.wg_per_cu && std::equal(x.tile_rows, x.tile_rows + 4, y.tile_rows) &&
+         std::equal(x.k_stage, x.k_stage + 4, y.k_stage);
+}
+}  // namespace rw
+
 struct rwpsf_batch {
   int device = 0;
   rwpsf_optics opt{};
@@ -398,8 +711,8 @@ struct rwpsf_batch {
   float* d_B1T = nullptr;       // [N][96] folded y table
   float2* d_pf = nullptr;       // [max][3][N][N] folded pupils
   long long items = 0;          // (emitter, plane) items of the staged call
-  long long class_items[2] = {0, 0};   // of them, in the 32- and 64-wide tile classes
-  int class_grid[2] = {0, 0};          // persistent grid of each class (0 = class not launched)
+  long long class_items[4] = {0, 0, 0, 0};   // of them, in the 16-, 32-, 48- and 64-row tile classes
+  int class_grid[4] = {0, 0, 0, 0};          // persistent grid of each class (0 = class not launched)
   float* d_basis = nullptr;
   float* d_phi = nullptr;
   char* d_upload = nullptr;     // params [max] then coefT [32][max_pad]
@@ -409,15 +722,15 @@ struct rwpsf_batch {
   int max_pad = 0;
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
-  rwpsf_batch_config cfg{2, 32};
+  rwpsf_batch_config cfg = rw::default_config();
   bool use_graph = false;
   hipGraphExec_t gexec = nullptr;
   struct Key {
     int n = -1;
     void* I = nullptr;
     void* E = nullptr;
-    int wg = 0, small = 0;
-    int grid[2] = {0, 0};   // the captured launches: a replay must launch the same classes
+    rwpsf_batch_config cfg{};
+    int grid[4] = {0, 0, 0, 0};   // the captured launches: a replay must launch the same classes
     hipStream_t st = nullptr;
   } gkey;
   ~rwpsf_batch() {   // teardown: failures cannot be reported and are ignored
@@ -476,7 +789,7 @@ static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
   for (int i = 0; i < n; ++i) off[i + 1] = off[i] + (long long)e[i].planes * e[i].crop * e[i].crop;
   std::vector<int> order(n);
   std::iota(order.begin(), order.end(), 0);
-  auto sp_of = [&](int i) { return e[i].crop <= b->cfg.small_tile_max_crop ? 32 : 64; };
+  auto sp_of = [&](int i) { return b->cfg.tile_rows[(e[i].crop - 1) / 16]; };
   auto cost = [&](int i) { return (double)e[i].planes * sp_of(i) * (b->N + sp_of(i)); };
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cost(x) > cost(y); });
   BatchParam* prm = (BatchParam*)b->h_staging;
@@ -501,9 +814,9 @@ static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
   std::vector<int> queue(n);
   double load[kQueues] = {};
   int count[kQueues] = {};
-  b->class_items[0] = b->class_items[1] = 0;
+  for (int t = 0; t < kTileClasses; ++t) b->class_items[t] = 0;
   for (int slot = 0; slot < n; ++slot) {
-    const int t = prm[slot].SP == 64 ? 1 : 0;
+    const int t = prm[slot].SP / 16 - 1;
     const int x = 8 * t + (int)(std::min_element(load + 8 * t, load + 8 * t + 8) - (load + 8 * t));
     queue[slot] = x;
     load[x] += cost(order[slot]);
@@ -523,7 +836,7 @@ static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
   b->items = pre[n];
   // persistent grid of each class: at least one workgroup per queue, no more than the
   // configured residency, none for an empty class
-  for (int t = 0; t < 2; ++t) {
+  for (int t = 0; t < kTileClasses; ++t) {
     const long long want =
         std::max<long long>(8, std::min<long long>(b->class_items[t], (long long)b->num_cus * b->cfg.wg_per_cu));
     b->class_grid[t] =
@@ -531,10 +844,21 @@ static void batch_stage(rwpsf_batch* b, int n, const rwpsf_emitter* e) {
   }
 }
 
-static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t st) {
+// Copy the staged parameter block to the device and record upload_done right after it,
+// so that the next call may restage the pinned area while this call's kernels still run.
+static int batch_upload(rwpsf_batch* b, hipStream_t st) {
   int rc;
-  if ((rc = hip_check(hipMemcpyAsync(b->d_upload, b->h_staging, b->upload_bytes, hipMemcpyHostToDevice, st))))
+  if ((rc = hip_check(hipMemcpyAsync(b->d_upload, b->h_staging, b->upload_bytes, hipMemcpyHostToDevice, st))) ||
+      (rc = hip_check(hipEventRecord(b->upload_done, st))))
     return rc;
+  b->upload_pending = true;
+  return RWPSF_OK;
+}
+
+// The kernels of one call (they read the uploaded block in stream order): queue reset,
+// phase GEMM, fold, one persistent launch per tile class.  This is what a graph captures.
+static int batch_kernels(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t st) {
+  int rc;
   const long long* d_pre = (const long long*)(b->d_upload + off_pre(b));
   const int* d_qoff = (const int*)(b->d_upload + off_qoff(b));
   hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, st, b->d_counter, d_pre, d_qoff);
@@ -563,18 +887,21 @@ static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t
   a.pitch = b->pitch;
   hipLaunchKernelGGL(batch_fold_kernel, dim3(n), dim3(256), 0, st, a);
   if ((rc = hip_check(hipGetLastError()))) return rc;
-  // one launch per tile class, the wide tiles first; at least one workgroup per queue and
+  // one launch per tile class, the tall tiles first; at least one workgroup per queue and
   // no more than the configured residency
-  for (int t = 1; t >= 0; --t) {
+  for (int t = kTileClasses - 1; t >= 0; --t) {
     const int grid = b->class_grid[t];
     if (grid == 0) continue;
-    if (t == 1)
-      hipLaunchKernelGGL(batch_planes_kernel<64>, dim3(grid), dim3(256), kBatchLdsBytes, st, a);
-    else
-      hipLaunchKernelGGL(batch_planes_kernel<32>, dim3(grid), dim3(256), kBatchLdsBytes, st, a);
+    const int ki = b->cfg.k_stage[t] == 8 ? 0 : 1;
+    hipLaunchKernelGGL(kPlaneKernels[t][ki], dim3(grid), dim3(256), kPlaneLds[t][ki], st, a);
     if ((rc = hip_check(hipGetLastError()))) return rc;
   }
   return RWPSF_OK;
+}
+
+static int batch_enqueue(rwpsf_batch* b, int n, float* I, float2* E, hipStream_t st) {
+  const int rc = batch_upload(b, st);
+  return rc ? rc : batch_kernels(b, n, I, E, st);
 }
 
 }  // namespace rw
@@ -706,14 +1033,17 @@ int rwpsf_batch_create(const rwpsf_optics* o, int n_pupil, double pixel_nm, doub
        (rc = hip_check(hipMemcpy(b->d_gl, gl.data(), gl.size() * sizeof(double4), hipMemcpyHostToDevice)))) ||
       (rc = hip_check(hipMemcpy(b->d_basis, basis.data(), basis.size() * sizeof(float), hipMemcpyHostToDevice))) ||
       (rc = hip_check(hipMemcpy(b->d_upload, b->h_staging, b->upload_bytes, hipMemcpyHostToDevice))) ||
-      (rc = hip_check(hipFuncSetAttribute((const void*)batch_planes_kernel<32>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLdsBytes))) ||
-      (rc = hip_check(hipFuncSetAttribute((const void*)batch_planes_kernel<64>,
-                                          hipFuncAttributeMaxDynamicSharedMemorySize, kBatchLdsBytes))) ||
       (rc = hip_check(hipDeviceSynchronize()))) {
     delete b;
     return rc;
   }
+  for (int t = 0; t < kTileClasses; ++t)
+    for (int k = 0; k < 2; ++k)
+      if ((rc = hip_check(hipFuncSetAttribute((const void*)kPlaneKernels[t][k],
+                                              hipFuncAttributeMaxDynamicSharedMemorySize, kPlaneLds[t][k])))) {
+        delete b;
+        return rc;
+      }
   *out = b;
   return RWPSF_OK;
 }
@@ -735,9 +1065,7 @@ int rwpsf_batch_set_graph(rwpsf_batch* b, int enable) {
 }
 
 int rwpsf_batch_set_config(rwpsf_batch* b, const rwpsf_batch_config* c) {
-  if (!b || !c || c->wg_per_cu < 1 || c->wg_per_cu > rw::kMaxWgPerCu ||
-      (c->small_tile_max_crop != 0 && c->small_tile_max_crop != 32))
-    return RWPSF_ERR_INVALID_ARG;
+  if (!b || !c || !rw::config_valid(*c)) return RWPSF_ERR_INVALID_ARG;
   b->cfg = *c;
   return RWPSF_OK;
 }
@@ -760,13 +1088,13 @@ int rwpsf_batch_compute(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I,
   // the previous upload must have left the pinned staging area before it is rewritten
   if (b->upload_pending && (rc = hip_check(hipEventSynchronize(b->upload_done)))) return rc;
   batch_stage(b, n, e);
+  if ((rc = batch_upload(b, st))) return rc;
   if (!b->use_graph) {
-    rc = batch_enqueue(b, n, I, (float2*)E, st);
+    rc = batch_kernels(b, n, I, (float2*)E, st);
   } else {
     const bool same = b->gexec && b->gkey.n == n && b->gkey.I == I && b->gkey.E == E &&
-                      b->gkey.wg == b->cfg.wg_per_cu && b->gkey.small == b->cfg.small_tile_max_crop &&
-                      b->gkey.grid[0] == b->class_grid[0] && b->gkey.grid[1] == b->class_grid[1] &&
-                      b->gkey.st == st;
+                      config_equal(b->gkey.cfg, b->cfg) &&
+                      std::equal(b->class_grid, b->class_grid + kTileClasses, b->gkey.grid) && b->gkey.st == st;
     if (!same) {
       if (b->gexec) {
         (void)hipGraphExecDestroy(b->gexec);
@@ -774,7 +1102,7 @@ int rwpsf_batch_compute(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I,
       }
       hipGraph_t g = nullptr;
       if ((rc = hip_check(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)))) return rc;
-      const int erc = batch_enqueue(b, n, I, (float2*)E, st);
+      const int erc = batch_kernels(b, n, I, (float2*)E, st);
       hipError_t ce = hipStreamEndCapture(st, &g);
       if (erc) {
         if (g) (void)hipGraphDestroy(g);
@@ -784,40 +1112,46 @@ int rwpsf_batch_compute(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I,
       ce = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
       (void)hipGraphDestroy(g);
       if ((rc = hip_check(ce))) return rc;
-      b->gkey = {n, I, E, b->cfg.wg_per_cu, b->cfg.small_tile_max_crop, {b->class_grid[0], b->class_grid[1]}, st};
+      b->gkey.n = n;
+      b->gkey.I = I;
+      b->gkey.E = E;
+      b->gkey.cfg = b->cfg;
+      std::copy(b->class_grid, b->class_grid + kTileClasses, b->gkey.grid);
+      b->gkey.st = st;
     }
     rc = hip_check(hipGraphLaunch(b->gexec, st));
   }
-  if (rc) return rc;
-  if ((rc = hip_check(hipEventRecord(b->upload_done, st)))) return rc;
-  b->upload_pending = true;
-  return RWPSF_OK;
+  return rc;
 }
 
 }  // extern "C"
 
 namespace rw {
 
-// Autotune cache: a flat JSON object {"key": [wg_per_cu, small_tile_max_crop, ms], ...}
+// Autotune cache: a flat JSON object
+//   {"key": [wg_per_cu, tile_rows[0..3], k_stage[0..3], ms], ...}
 // in the file named by RWPSF_AUTOTUNE_CACHE.  Anything that does not parse is ignored
 // (and replaced on the next write).
 static std::string tune_key(const rwpsf_batch* b, int n, const rwpsf_emitter* e) {
-  int small = 0, large = 0;
+  int bucket[4] = {0, 0, 0, 0};
   long long planes = 0;
   for (int i = 0; i < n; ++i) {
-    (e[i].crop <= 32 ? small : large) += 1;
+    bucket[(e[i].crop - 1) / 16] += 1;
     planes += e[i].planes;
   }
   int nb = 1;
   while (nb < n) nb <<= 1;
-  char buf[160];
-  snprintf(buf, sizeof buf, "N%d_n%d_small%d_large%d_meanD%lld_cus%d", b->N, nb, (int)(16.0 * small / n),
-           (int)(16.0 * large / n), planes / n, b->num_cus);
+  char buf[200];
+  snprintf(buf, sizeof buf, "N%d_n%d_b%d-%d-%d-%d_meanD%lld_cus%d", b->N, nb, (int)(16.0 * bucket[0] / n),
+           (int)(16.0 * bucket[1] / n), (int)(16.0 * bucket[2] / n), (int)(16.0 * bucket[3] / n), planes / n,
+           b->num_cus);
   return buf;
 }
 
-static std::map<std::string, std::pair<rwpsf_batch_config, double>> cache_read(const char* path) {
-  std::map<std::string, std::pair<rwpsf_batch_config, double>> m;
+typedef std::map<std::string, std::pair<rwpsf_batch_config, double>> TuneCache;
+
+static TuneCache cache_read(const char* path) {
+  TuneCache m;
   FILE* f = fopen(path, "r");
   if (!f) return m;
   std::string text;
@@ -835,30 +1169,52 @@ static std::map<std::string, std::pair<rwpsf_batch_config, double>> cache_read(c
     const size_t b0 = text.find('[', k1);
     const size_t b1 = text.find(']', b0 == std::string::npos ? k1 : b0);
     if (b0 == std::string::npos || b1 == std::string::npos) return {};
-    int wg = 0, sm = 0;
+    rwpsf_batch_config c{};
     double ms = 0;
-    if (sscanf(text.c_str() + b0, "[%d ,%d ,%lf]", &wg, &sm, &ms) != 3 &&
-        sscanf(text.c_str() + b0, "[%d, %d, %lf]", &wg, &sm, &ms) != 3)
+    if (sscanf(text.c_str() + b0, "[%d , %d , %d , %d , %d , %d , %d , %d , %d , %lf]", &c.wg_per_cu, &c.tile_rows[0],
+               &c.tile_rows[1], &c.tile_rows[2], &c.tile_rows[3], &c.k_stage[0], &c.k_stage[1], &c.k_stage[2],
+               &c.k_stage[3], &ms) != 10)
       return {};
-    if (wg < 1 || wg > 4 || (sm != 0 && sm != 32)) return {};
-    m[text.substr(k0 + 1, k1 - k0 - 1)] = {rwpsf_batch_config{wg, sm}, ms};
+    if (!config_valid(c)) return {};
+    m[text.substr(k0 + 1, k1 - k0 - 1)] = {c, ms};
     pos = b1 + 1;
   }
   return m;
 }
 
-static void cache_write(const char* path, const std::map<std::string, std::pair<rwpsf_batch_config, double>>& m) {
+static void cache_write(const char* path, const TuneCache& m) {
   const std::string tmp = std::string(path) + ".tmp";
   FILE* f = fopen(tmp.c_str(), "w");
   if (!f) return;
   fprintf(f, "{\n");
   size_t i = 0;
-  for (const auto& kv : m)
-    fprintf(f, "  \"%s\": [%d, %d, %.6f]%s\n", kv.first.c_str(), kv.second.first.wg_per_cu,
-            kv.second.first.small_tile_max_crop, kv.second.second, ++i < m.size() ? "," : "");
+  for (const auto& kv : m) {
+    const rwpsf_batch_config& c = kv.second.first;
+    fprintf(f, "  \"%s\": [%d, %d, %d, %d, %d, %d, %d, %d, %d, %.6f]%s\n", kv.first.c_str(), c.wg_per_cu,
+            c.tile_rows[0], c.tile_rows[1], c.tile_rows[2], c.tile_rows[3], c.k_stage[0], c.k_stage[1], c.k_stage[2],
+            c.k_stage[3], kv.second.second, ++i < m.size() ? "," : "");
+  }
   fprintf(f, "}\n");
   fclose(f);
   rename(tmp.c_str(), path);
+}
+
+// Device time of one call with configuration c: the emitters are staged on the host once,
+// then one untimed and two timed enqueues, so the host staging stays outside the window.
+static int tune_trial(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I, hipStream_t st,
+                      const rwpsf_batch_config& c, hipEvent_t t0, hipEvent_t t1, float* ms) {
+  int rc;
+  if (b->upload_pending && (rc = hip_check(hipEventSynchronize(b->upload_done)))) return rc;
+  b->cfg = c;
+  batch_stage(b, n, e);
+  if ((rc = batch_enqueue(b, n, I, nullptr, st))) return rc;
+  if ((rc = hip_check(hipEventRecord(t0, st)))) return rc;
+  for (int r = 0; r < 2; ++r)
+    if ((rc = batch_enqueue(b, n, I, nullptr, st))) return rc;
+  if ((rc = hip_check(hipEventRecord(t1, st)))) return rc;
+  if ((rc = hip_check(hipEventSynchronize(t1))) || (rc = hip_check(hipEventElapsedTime(ms, t0, t1)))) return rc;
+  *ms *= 0.5f;
+  return RWPSF_OK;
 }
 
 }  // namespace rw
@@ -871,9 +1227,11 @@ int rwpsf_batch_autotune(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I
   int rc = batch_validate(b, n, e);
   if (rc) return rc;
   if (!I) return RWPSF_ERR_INVALID_ARG;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != b->device) return RWPSF_ERR_INVALID_ARG;
   const char* cache_path = getenv("RWPSF_AUTOTUNE_CACHE");
   std::string key;
-  std::map<std::string, std::pair<rwpsf_batch_config, double>> cache;
+  TuneCache cache;
   if (cache_path && *cache_path) {
     key = tune_key(b, n, e);
     cache = cache_read(cache_path);
@@ -887,36 +1245,53 @@ int rwpsf_batch_autotune(rwpsf_batch* b, int n, const rwpsf_emitter* e, float* I
   }
   hipStream_t st = (hipStream_t)stream;
   const rwpsf_batch_config saved = b->cfg;
-  const bool saved_graph = b->use_graph;
-  b->use_graph = false;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if ((rc = hip_check(hipEventCreate(&t0))) || (rc = hip_check(hipEventCreate(&t1)))) {
     if (t0) (void)hipEventDestroy(t0);
-    b->use_graph = saved_graph;
     return rc;
   }
-  rwpsf_batch_config best = saved;
+  // coordinate search from the default: workgroups per CU, then for each crop bucket the
+  // taller tile classes it could share (fewer, fuller launches against more padding),
+  // then the k-stage of each class in use
+  rwpsf_batch_config best = default_config();
   float best_t = 1e30f;
-  const int wgs[3] = {1, 2, 3};
-  const int smalls[2] = {0, 32};
-  for (int wi = 0; wi < 3; ++wi)
-    for (int si = 0; si < 2; ++si) {
-      b->cfg = {wgs[wi], smalls[si]};
-      if ((rc = rwpsf_batch_compute(b, n, e, I, nullptr, st))) break;   // warm-up
-      if ((rc = hip_check(hipEventRecord(t0, st)))) break;
-      for (int r = 0; r < 2 && !rc; ++r) rc = rwpsf_batch_compute(b, n, e, I, nullptr, st);
-      if (rc || (rc = hip_check(hipEventRecord(t1, st)))) break;
-      float ms = 0.f;
-      if ((rc = hip_check(hipEventSynchronize(t1))) || (rc = hip_check(hipEventElapsedTime(&ms, t0, t1)))) break;
-      ms *= 0.5f;
-      if (ms < best_t) {
-        best_t = ms;
-        best = b->cfg;
-      }
+  auto consider = [&](const rwpsf_batch_config& c) {
+    float ms = 0.f;
+    const int r = tune_trial(b, n, e, I, st, c, t0, t1, &ms);
+    if (r == RWPSF_OK && ms < best_t) {
+      best_t = ms;
+      best = c;
     }
+    return r;
+  };
+  rc = consider(best);
+  for (int wg = 1; wg <= 3 && !rc; ++wg) {
+    if (wg == best.wg_per_cu) continue;
+    rwpsf_batch_config c = best;
+    c.wg_per_cu = wg;
+    rc = consider(c);
+  }
+  bool used[4] = {false, false, false, false};
+  for (int i = 0; i < n; ++i) used[(e[i].crop - 1) / 16] = true;
+  for (int q = 0; q < 3 && !rc; ++q) {
+    if (!used[q]) continue;
+    const rwpsf_batch_config base = best;
+    for (int rows = base.tile_rows[q] + 16; rows <= 64 && !rc; rows += 16) {
+      rwpsf_batch_config c = base;
+      c.tile_rows[q] = rows;
+      rc = consider(c);
+    }
+  }
+  for (int t = 0; t < kTileClasses && !rc; ++t) {
+    bool in_use = false;
+    for (int q = 0; q < 4; ++q) in_use = in_use || (used[q] && best.tile_rows[q] == class_rows(t));
+    if (!in_use) continue;
+    rwpsf_batch_config c = best;
+    c.k_stage[t] = best.k_stage[t] == 16 ? 8 : 16;
+    rc = consider(c);
+  }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
-  b->use_graph = saved_graph;
   b->cfg = rc ? saved : best;
   if (rc) return rc;
   if (best_out) *best_out = best;

@@ -137,15 +137,26 @@ def test_batched_autotune_and_configs_agree(lib):
     b = _batch(rw, w, 200)
     I = torch.zeros(off[-1], dtype=torch.float32, device="cuda")
     cfg, ms = b.autotune(em, I)
-    assert cfg[0] in (1, 2, 3) and cfg[1] in (0, 32) and ms > 0
+    assert cfg["wg_per_cu"] in (1, 2, 3) and ms > 0
+    assert all(r >= 16 * (q + 1) and r in (16, 32, 48, 64) for q, r in enumerate(cfg["tile_rows"]))
+    assert all(k in (8, 16) for k in cfg["k_stage"])
     outs = []
-    for c in [(1, 0), (2, 32), (3, 0)]:
-        b.set_config(*c)
+    # every tile class and k-stage: each bucket on its own class, all on 64-row tiles,
+    # buckets merged upwards, shallow k-stages
+    for c in [dict(wg_per_cu=1), dict(wg_per_cu=2, tile_rows=(64, 64, 64, 64)),
+              dict(wg_per_cu=3, tile_rows=(32, 32, 64, 64), k_stage=(8, 8, 8, 8)),
+              dict(wg_per_cu=2, tile_rows=(16, 48, 48, 64), k_stage=(8, 16, 8, 16))]:
+        b.set_config(**c)
         I.zero_()
         b.compute(em, I=I)
         torch.cuda.synchronize()
         outs.append(I.cpu().numpy())
-    assert rel_l2(outs[0], outs[1]) < 1e-6 and rel_l2(outs[0], outs[2]) < 1e-6
+    for o in outs[1:]:
+        assert rel_l2(o, outs[0]) < 1e-6
+    with pytest.raises(rw.RwpsfError):
+        b.set_config(tile_rows=(16, 16, 48, 64))     # a 17..32 crop does not fit 16 rows
+    with pytest.raises(rw.RwpsfError):
+        b.set_config(k_stage=(16, 12, 16, 16))
 
 
 def test_batched_full_workload_sampled(lib):
@@ -236,7 +247,8 @@ def test_batched_autotune_cache(lib, tmp_path, monkeypatch):
     I = torch.zeros(off[-1], dtype=torch.float32, device="cuda")
     cfg1, ms1 = b.autotune(em, I)
     text = path.read_text()
-    assert text.strip().startswith("{") and str(list(cfg1))[1:-1].replace(" ", "") in text.replace(" ", "")
+    flat = [cfg1["wg_per_cu"], *cfg1["tile_rows"], *cfg1["k_stage"]]
+    assert text.strip().startswith("{") and str(flat)[1:-1].replace(" ", "") in text.replace(" ", "")
     b2 = _batch(rw, w, 64)
     cfg2, ms2 = b2.autotune(em, I)                    # served from the cache, no timing
     assert cfg2 == cfg1 and abs(ms2 - ms1) < 1e-3
@@ -251,9 +263,9 @@ def test_batched_graph_recaptures_when_tile_classes_change(lib):
     n = 40
     w = W.batched(n_emitters=n, seed=37)
     b = _batch(rw, w, n)
-    b.set_config(2, 32)
+    b.set_config(2)
     s = torch.cuda.Stream()
-    # capture: every crop above 32 (64-wide class only); then: half the crops at most 32
+    # capture: every crop in 33..48 (48-row class only); then: half the crops at most 32
     crops_a = np.full(n, 48)
     crops_b = np.where(np.arange(n) % 2 == 0, 24, 40)
     planes = np.full(n, 3)
