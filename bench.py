@@ -267,12 +267,15 @@ def bench_bessel(rw, torch, steps, warmup, n_stacks=256):
         plan.compute(one, E=E[:1], I=I[:1])
     torch.cuda.synchronize()
     single_ms = (time.perf_counter() - t0) * 1e3 / steps
-    plan.set_timing(True)
     t0 = time.perf_counter()
     for _ in range(steps):
         plan.compute(stacks, E=E, I=I)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / steps
+    plan.set_timing(True)          # per-launch events in a second pass
+    for _ in range(steps):
+        plan.compute(stacks, E=E, I=I)
+    torch.cuda.synchronize()
     kt = {name: plan.timing(k) for name, k in (("phi", rw.KERNEL_BESSEL_PHI),
                                                ("contract", rw.KERNEL_BESSEL_CONTRACT),
                                                ("epilogue", rw.KERNEL_BESSEL_EPILOGUE))}
@@ -369,8 +372,11 @@ def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    plan.set_timing(True)
+    # the step time without per-launch events (each adds a timestamp packet to the stream);
+    # the kernel breakdown from a second pass with them
     ms = _cuda_time(torch, step, max(3, steps // 4))
+    plan.set_timing(True)
+    _cuda_time(torch, step, max(3, steps // 4))
     kt = {k: plan.timing(v) for k, v in (("gemm_pupil", rw.KERNEL_GEMM_PUPIL), ("gemm_image", rw.KERNEL_GEMM_IMAGE),
                                           ("adj_h", rw.KERNEL_ADJ_H), ("adj_g", rw.KERNEL_ADJ_G),
                                           ("adj_reduce", rw.KERNEL_ADJ_REDUCE))}
@@ -389,6 +395,8 @@ def bench_adjoint(rw, torch, steps, warmup, n_stacks=64):
                 roofline=dict(kernel="whole step", bound="mfma", achieved=round(ach, 3), peak=PEAK_FP32_TFLOPS,
                               unit="TFLOP/s", frac=round(ach / PEAK_FP32_TFLOPS, 4),
                               traffic=profiled_traffic("adjoint_adjoint.txt", "adjoint step"),
+                              avg_launch_us=ms * 1e3,
+                              profiled_avg_us=profiled_average("adjoint_adjoint.txt", "adjoint step"),
                               flops_per_step=fwd + adj))
 
 
@@ -425,8 +433,9 @@ def bench_adjoint_bessel(rw, torch, steps, warmup, n_stacks=64):
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    plan.set_timing(True)
     ms = _cuda_time(torch, step, max(3, steps // 4))
+    plan.set_timing(True)
+    _cuda_time(torch, step, max(3, steps // 4))
     kt = {k: plan.timing(v) for k, v in (("bessel_phi", rw.KERNEL_BESSEL_PHI),
                                           ("bessel_contract", rw.KERNEL_BESSEL_CONTRACT),
                                           ("bessel_epilogue", rw.KERNEL_BESSEL_EPILOGUE),
@@ -534,8 +543,10 @@ def bench_surrogate(rw, torch, train_seconds, bar=0.1):
                 inference=res,
                 roofline=dict(kernel="whole inference (dense GEMMs + fused decoder)", bound="mfma",
                               achieved=round(ach, 2), peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
-                              frac=round(ach / PEAK_BF16_TFLOPS, 4), traffic=None,
-                              flops_per_batch=flops,
+                              frac=round(ach / PEAK_BF16_TFLOPS, 4),
+                              traffic=profiled_traffic("sg_inference_surrogate.txt", "surrogate inference"),
+                              flops_per_batch=flops, avg_launch_us=res["bf16x3"]["ms_per_batch"] * 1e3,
+                              profiled_avg_us=profiled_average("sg_inference_surrogate.txt", "surrogate inference"),
                               note="bf16x3 executes three BF16 products per algorithmic one"),
                 accuracy_network_vs_plain=acc,
                 gate=dict(bar=f"p95 rel-L2 <= {bar} over the crops the network serves", bar_value=bar,
