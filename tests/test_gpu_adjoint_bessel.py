@@ -12,7 +12,10 @@ from oracle.adjoint import mse_loss
 from tests.helpers import rel_l2
 
 pytestmark = pytest.mark.gpu
-TOL = 2e-4
+TOL = 1e-5   # the FP32 bar; measured 1e-7 to 8e-7 (forward fields 3e-7)
+# single per-stack scalars under a random dL/dI: each is a sum of ~1.4e5 terms of random
+# sign, so FP32 rounding of the terms is amplified by the cancellation (measured 1.7e-5)
+TOL_RANDOM_SCALAR = 1e-4
 GL = W.GIBSON_LANNI
 
 
@@ -141,8 +144,8 @@ def test_bessel_adjoint_workload_size_sampled_and_additive(lib):
         d1 = plan.adjoint_bessel([s], E[b:b + 1], g[b:b + 1].contiguous())
         torch.cuda.synchronize()
         assert rel_l2(_np(d1[0])[1:], rdc[1:]) < TOL
-        assert abs(_np(dts)[b] - rdts[0]) < TOL * abs(rdts[0])
-        assert abs(_np(dz)[b] - rdz[0]) < TOL * abs(rdz[0])
+        assert abs(_np(dts)[b] - rdts[0]) < TOL_RANDOM_SCALAR * abs(rdts[0])
+        assert abs(_np(dz)[b] - rdz[0]) < TOL_RANDOM_SCALAR * abs(rdz[0])
 
 
 def test_bessel_adjoint_rejects_other_forms(lib):
