@@ -251,15 +251,23 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
         }
     }
   };
+  // Two stages of global loads in flight: a stage's MFMAs take far less time than a
+  // load's latency, so stage kt + 2 is requested while stage kt is multiplied and stage
+  // kt + 1 (already in registers) is written to the other LDS buffer.  KT >= 2; the last
+  // two stages are peeled, so that no branch surrounds the loads and stores.
+  Staged g1 = load(FBK);
   store(shb, load(0));
   __syncthreads();
-  // the last stage is peeled, so that no branch surrounds the loads and stores
-  for (int kt = 0; kt < KT - 1; ++kt) {
-    const Staged g = load((kt + 1) * FBK);
+  for (int kt = 0; kt < KT - 2; ++kt) {
+    const Staged g2 = load((kt + 2) * FBK);
     mma(shb + (kt & 1) * STAGE);
-    store(shb + ((kt + 1) & 1) * STAGE, g);
+    store(shb + ((kt + 1) & 1) * STAGE, g1);
     __syncthreads();
+    g1 = g2;
   }
+  mma(shb + (KT & 1) * STAGE);
+  store(shb + ((KT - 1) & 1) * STAGE, g1);
+  __syncthreads();
   mma(shb + ((KT - 1) & 1) * STAGE);
   const bool raw = gridDim.y > 1;
 #pragma unroll
@@ -320,6 +328,7 @@ static hipError_t sg_gemm_fast(const float* A, const __bf16* Bh, const __bf16* B
          K / (2 * slices) >= 128 && (size_t)2 * slices * M * N <= ws_floats)
     slices *= 2;
   const dim3 grid(tiles, slices);
+  if (K / slices < 2 * FBK) return hipErrorInvalidValue;   // the pipeline needs two k-stages
   const int lds = 2 * 4 * FBM * FLD * (int)sizeof(__bf16);
   float* out = slices > 1 ? ws : C;
   if (nsplit > 1)
