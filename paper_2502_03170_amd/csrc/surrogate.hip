@@ -472,12 +472,16 @@ static hipError_t sg_colsum(const float* g, int rows, int cols, float* out, doub
 // channel-last with a zero border, so the eight k of a lane are eight consecutive
 // channels of one source pixel (two 16-byte reads), with no bounds tests.  Weights are
 // pre-arranged as B fragments ([class][k-step][lane][8] BF16 hi / lo) and held in
-// registers for all samples of the workgroup.
+// registers for all samples of the workgroup.  The inputs of the two matrix-core layers
+// are split into BF16 hi / lo once, when they are written to LDS (each value feeds up to
+// 16 fragments).
 constexpr int DC0 = 16, DC1 = 16, DC2 = 8;          // decoder channels (layer inputs)
-constexpr int DX0 = DC0 + 4, DX1 = DC1 + 4, DX2 = DC2;   // LDS floats per pixel (padded)
-constexpr int DL0 = 10 * 10 * DX0, DL1 = 18 * 18 * DX1, DL2 = 34 * 34 * DX2;
+// inputs of the matrix-core layers are held as BF16 hi / lo planes (split once, when
+// written), DXb BF16 per pixel (16-byte aligned, padded); the last layer's input in FP32
+constexpr int DX0b = DC0 + 8, DX1b = DC1 + 8, DX2 = DC2;
+constexpr int DL0b = 10 * 10 * DX0b, DL1b = 18 * 18 * DX1b, DL2 = 34 * 34 * DX2;   // elements per plane
 constexpr int DK1 = 4 * DC0 / 32, DK2 = 6 * DC1 / 32;    // k-steps of the layer-1 / layer-2 GEMMs
-constexpr int kDecLdsBytes = (DL0 + DL1 + DL2) * 4;
+constexpr int kDecLdsBytes = 2 * (DL0b + DL1b) * 2 + DL2 * 4;
 static_assert(DC1 == 16 && 2 * DC2 == 16 && DC0 % 8 == 0 && DC1 % 8 == 0, "decoder tile shapes");
 typedef float f4v_t __attribute__((ext_vector_type(4)));
 
@@ -512,16 +516,6 @@ __global__ void sg_dec_wprep_kernel(const float* __restrict__ K1, const float* _
   }
 }
 
-// eight FP32 values -> BF16 hi (and lo = bf16(x - hi))
-__device__ __forceinline__ void split8(const float4 u, const float4 v, bf8_t& hi, bf8_t& lo) {
-  const float x[8] = {u.x, u.y, u.z, u.w, v.x, v.y, v.z, v.w};
-#pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    hi[q] = (__bf16)x[q];
-    lo[q] = (__bf16)(x[q] - (float)hi[q]);
-  }
-}
-
 template <int NSPLIT>
 __device__ __forceinline__ f4v_t mma16(const bf8_t& ah, const bf8_t& al, const bf8_t& bh, const bf8_t& bl,
                                        f4v_t acc) {
@@ -549,11 +543,13 @@ __global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restr
                                                             float* __restrict__ y, float* __restrict__ d1g,
                                                             float* __restrict__ d2g) {
   extern __shared__ float dls[];
-  float* X0 = dls;            // [10][10][DX0]
-  float* X1 = X0 + DL0;       // [18][18][DX1]
-  float* X2 = X1 + DL1;       // [34][34][DX2]
+  __bf16* X0h = reinterpret_cast<__bf16*>(dls);   // [10][10][DX0b] hi, then lo
+  __bf16* X0l = X0h + DL0b;
+  __bf16* X1h = X0l + DL0b;                       // [18][18][DX1b] hi, then lo
+  __bf16* X1l = X1h + DL1b;
+  float* X2 = reinterpret_cast<float*>(X1l + DL1b);   // [34][34][DX2] FP32
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, g = lane >> 4, r16 = lane & 15;
-  for (int i = tid; i < DL0 + DL1 + DL2; i += 256) dls[i] = 0.f;   // zero borders (interiors are rewritten)
+  for (int i = tid; i < kDecLdsBytes / 4; i += 256) dls[i] = 0.f;   // zero borders (interiors are rewritten)
   // B fragments of this wave: layer-1 class p = w, layer-2 row class py2 = w / 2
   bf8_t w1h[DK1], w1l[DK1], w2h[DK2], w2l[DK2];
 #pragma unroll
@@ -589,8 +585,10 @@ __global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restr
       const float xs[4] = {hv[v].x, hv[v].y, hv[v].z, hv[v].w};
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const int Y = (pix + t) / 8, X = (pix + t) % 8;
-        X0[((Y + 1) * 10 + X + 1) * DX0 + ci] = xs[t];
+        const int Y = (pix + t) / 8, X = (pix + t) % 8, at = ((Y + 1) * 10 + X + 1) * DX0b + ci;
+        const __bf16 h = (__bf16)xs[t];
+        X0h[at] = h;
+        X0l[at] = (__bf16)(xs[t] - (float)h);
       }
     }
     fetch(b + gridDim.x);
@@ -606,16 +604,20 @@ __global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restr
         for (int s = 0; s < DK1; ++s) {
           const int k0 = 32 * s + 8 * g, tap = k0 / DC0, ci = k0 % DC0, a = tap >> 1, c = tap & 1;
           const int dy = py ? 1 - a : -a, dx = px ? 1 - c : -c;
-          const float* src = X0 + ((Y + dy + 1) * 10 + X + dx + 1) * DX0 + ci;
-          bf8_t ah, al;
-          split8(*reinterpret_cast<const float4*>(src), *reinterpret_cast<const float4*>(src + 4), ah, al);
+          const int at = ((Y + dy + 1) * 10 + X + dx + 1) * DX0b + ci;
+          const bf8_t ah = *reinterpret_cast<const bf8_t*>(X0h + at);
+          const bf8_t al = NSPLIT > 1 ? *reinterpret_cast<const bf8_t*>(X0l + at) : ah;
           acc = mma16<NSPLIT>(ah, al, w1h[s], w1l[s], acc);
         }
         // C: rows 4 g + i (pixels), column r16 (output channel)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int mm = 16 * mt + 4 * g + i, YY = mm >> 3, XX = mm & 7;
-          X1[((2 * YY + py + 1) * 18 + 2 * XX + px + 1) * DX1 + r16] = fmaxf(acc[i] + bias1, 0.f);
+          const int at = ((2 * YY + py + 1) * 18 + 2 * XX + px + 1) * DX1b + r16;
+          const float v = fmaxf(acc[i] + bias1, 0.f);
+          const __bf16 h = (__bf16)v;
+          X1h[at] = h;
+          X1l[at] = (__bf16)(v - (float)h);
         }
       }
     }
@@ -623,8 +625,8 @@ __global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restr
     if (d1g) {   // training: d1 [co][16][16]
       float* o = d1g + (size_t)b * DC1 * 256;
       for (int e = tid; e < DC1 * 256; e += 256) {
-        const int co = e / 256, pix = e % 256;
-        o[e] = X1[((pix / 16 + 1) * 18 + pix % 16 + 1) * DX1 + co];
+        const int co = e / 256, pix = e % 256, at = ((pix / 16 + 1) * 18 + pix % 16 + 1) * DX1b + co;
+        o[e] = (float)X1h[at] + (float)X1l[at];   // the value to 2^-16 relative (its sign exactly)
       }
     }
     // ---- layer 2: wave w = row class py2, M-tiles 8 (w & 1) .. + 7 of the 16 x 16 input
@@ -638,9 +640,9 @@ __global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restr
         for (int s = 0; s < DK2; ++s) {
           const int k0 = 32 * s + 8 * g, t6 = k0 / DC1, ci = k0 % DC1, a = t6 / 3, c3 = t6 % 3;
           const int dy = py2 ? 1 - a : -a, dx = c3 - 1;
-          const float* src = X1 + ((Y + dy + 1) * 18 + X + dx + 1) * DX1 + ci;
-          bf8_t ah, al;
-          split8(*reinterpret_cast<const float4*>(src), *reinterpret_cast<const float4*>(src + 4), ah, al);
+          const int at = ((Y + dy + 1) * 18 + X + dx + 1) * DX1b + ci;
+          const bf8_t ah = *reinterpret_cast<const bf8_t*>(X1h + at);
+          const bf8_t al = NSPLIT > 1 ? *reinterpret_cast<const bf8_t*>(X1l + at) : ah;
           acc = mma16<NSPLIT>(ah, al, w2h[s], w2l[s], acc);
         }
         const int px = r16 / DC2, co = r16 % DC2;
