@@ -474,12 +474,12 @@ def surrogate_flops_per_crop() -> float:
 def bench_surrogate(rw, torch, train_seconds, bar=0.1):
     """Train the surrogate for about `train_seconds` on 200000 engine crops, fit its
     error-gated fallback at the stated bar (p95 rel-L2 of the crops the network serves)
-    on 4096 calibration crops, judge it on 2048 held-out crops, and time inference and
+    on 8192 calibration crops, judge it on 2048 held-out crops, and time inference and
     gated serving against the plain path on 65536 inputs."""
     from paper_2502_03170_amd import surrogate_train as ST
     eng = ST.CropEngine(max_emitters=4096)
     train = ST.make_dataset(eng, 200_000, seed=505)
-    calib = ST.make_dataset(eng, 4096, seed=507)
+    calib = ST.make_dataset(eng, 8192, seed=507)
     test = ST.make_dataset(eng, 2048, seed=506)
     basis = ST.crop_basis(train, 4096)
     sg = rw.Surrogate(max_batch=65536)
@@ -550,7 +550,7 @@ def bench_surrogate(rw, torch, train_seconds, bar=0.1):
                               note="bf16x3 executes three BF16 products per algorithmic one"),
                 accuracy_network_vs_plain=acc,
                 gate=dict(bar=f"p95 rel-L2 <= {bar} over the crops the network serves", bar_value=bar,
-                          calibration_crops=4096, accepted_on_calibration=gate["accepted_calibration"],
+                          calibration_crops=8192, accepted_on_calibration=gate["accepted_calibration"],
                           error_model_corr=gate["fit_corr"]),
                 judged_held_out=judged,
                 serving_65536=dict(plain_ms=plain_ms, gated_ms=gated_ms, fallback_fraction=fallback_serve,
@@ -668,7 +668,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--forms", default="chirpz,sweep,bessel,batched,adjoint,adjoint_bessel,surrogate",
                     help="comma list of extra forms, or 'none'")
-    ap.add_argument("--train-seconds", type=float, default=90.0)
+    ap.add_argument("--train-seconds", type=float, default=150.0)
     ap.add_argument("--copy-reference", action="store_true",
                     help="also run a 256 MiB device-to-device copy (calibrates rocprofv3 byte counters)")
     args = ap.parse_args()

@@ -172,14 +172,16 @@ def _forward_all(sg, coef, z, precision):
 
 
 def fit_gate(sg: rw.Surrogate, calib: dict, bar: float, quantile: float = 0.95,
-             precision: int = rw.SG_BF16X3):
+             precision: int = rw.SG_BF16X3, margin: float = 0.97):
     """Error-gated fallback, fitted on calibration crops that the plain path judged.
 
     The log rel-L2 of each calibration crop is regressed (least squares, FP64) on the
     error-model features phi(c, z) of the library; the threshold on the predicted log
     error is the largest one for which the calibration crops it accepts have their
-    `quantile` quantile of rel-L2 at or below `bar`.  Returns the gate (device weights,
-    threshold, bar, quantile, accepted fraction on the calibration crops)."""
+    `quantile` quantile of rel-L2 at or below margin x `bar` (the margin keeps the
+    quantile of other crops, which scatters around the calibration one, under the bar).
+    Returns the gate (device weights, threshold, bar, quantile, accepted fraction on the
+    calibration crops)."""
     import torch
     pred = _forward_all(sg, calib["coef"], calib["z"], precision)
     e = rel_l2_per_crop(pred, calib["target"]).double().cpu().numpy()
@@ -191,7 +193,7 @@ def fit_gate(sg: rw.Surrogate, calib: dict, bar: float, quantile: float = 0.95,
     es = e[order]
     k_best = 0
     for k in range(len(es), 0, -max(1, len(es) // 512)):
-        if np.quantile(es[:k], quantile) <= bar:
+        if np.quantile(es[:k], quantile) <= margin * bar:
             k_best = k
             break
     thr = float(logp[order[k_best - 1]]) if k_best else -np.inf
