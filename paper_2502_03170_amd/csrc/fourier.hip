@@ -8,9 +8,11 @@
 // transform folds into even and odd parts with real coefficients cos / sin, and the
 // separable transform becomes two real GEMMs on the FP32 matrix cores with half the
 // flops of the complex matrix DFT:
-//   K1  pupil_build   P_c for up to 8 stacks (FP64 phase: Gibson-Lanni, Zernike,
-//                     free phase map, lateral emitter shift), complex64 [s][c][j][l]
-//   K1b pupil_fold    mirror-folded pupils Pf (four parities per folded cell)
+//   K1  pupil_build_folded   mirror-folded pupils Pf (four parities per folded cell)
+//                     of up to 8 stacks, each cell's P_c formed on the way (FP64
+//                     phase: Gibson-Lanni, Zernike, free phase map, lateral emitter
+//                     shift); the chirp-z and adjoint paths take the unfolded P_c of
+//                     pupil_build
 //   K2  gemm_pupil    T = Pf~ B1 (fold along y); the defocus factor is formed while the
 //                     pupil tile is staged (FP64 phase, reduced mod 2 pi, FP32 sincos)
 //   K3  gemm_image    E'_c = A2 T_c (fold along x) for c = x, y, z in one workgroup,
@@ -39,6 +41,34 @@ __global__ void zernike_table_kernel(float* __restrict__ out, int n, int nj) {
 // --------------------------------------------------------------------------
 // K1: base pupil of each stack.
 // --------------------------------------------------------------------------
+// exp(i W) (times the evanescent decay of a Gibson-Lanni layer) at cell (j, l) of stack
+// st.  The Zernike loads are unrolled to the maximum term count, so that a thread has
+// them all in flight at once instead of waiting for each in turn.
+template <class Args>
+__device__ __forceinline__ float2 pupil_phase_factor(const Args& a, const PupilStack& st,
+                                                     const float* __restrict__ ztab, int j, int l) {
+  const int n = a.n;
+  const int cell = j * n + l;   // unpadded index: Zernike table and user phase map
+  const double sx = (2.0 * j + 1.0 - n) * a.s_max / n;
+  const double sy = (2.0 * l + 1.0 - n) * a.s_max / n;
+  const double sin_t = sqrt(sx * sx + sy * sy);
+  float zv[RWPSF_MAX_ZERNIKE];
+#pragma unroll
+  for (int k = 0; k < RWPSF_MAX_ZERNIKE; ++k) zv[k] = k < a.max_zernike ? ztab[(size_t)k * n * n + cell] : 0.f;
+  double w_re = 0.0, w_im = 0.0;
+  if (a.gibson_lanni) gl_opd(a.gl, st.t_s, sin_t, &w_re, &w_im);
+  w_re -= a.k * (sx * st.x0 + sy * st.y0);
+  if (st.w0) w_re += (double)st.w0[cell];
+#pragma unroll
+  for (int k = 0; k < RWPSF_MAX_ZERNIKE; ++k) w_re += kTwoPi * st.coef[k] * (double)zv[k];
+  // the evanescent decay in FP32 (relative error ~1e-7, far below the tolerance), the
+  // phase reduced in FP64 in revolutions before the hardware sine and cosine
+  const float amp = w_im > 0.0 ? expf((float)-w_im) : 1.f;
+  float sn, cs;
+  sincos_rev(w_re * (1.0 / kTwoPi), &sn, &cs);
+  return make_float2(amp * cs, amp * sn);
+}
+
 // One thread per (padded cell, stack): grid.y is the stack.
 __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const float2* __restrict__ Q,
                                                           const float* __restrict__ ztab,
@@ -62,27 +92,12 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
     for (int c = 0; c < nc; ++c) out[c * npp] = make_float2(0.f, 0.f);
     return;
   }
-  const int cell = j * n + l;   // unpadded index: Zernike table and user phase map
-  const double sx = (2.0 * j + 1.0 - n) * a.s_max / n;
-  const double sy = (2.0 * l + 1.0 - n) * a.s_max / n;
-  const double sin_t = sqrt(sx * sx + sy * sy);
-  const PupilStack& st = a.s[s];
-  double w_re = 0.0, w_im = 0.0;
-  if (a.gibson_lanni) gl_opd(a.gl, st.t_s, sin_t, &w_re, &w_im);
-  w_re -= a.k * (sx * st.x0 + sy * st.y0);
-  if (st.w0) w_re += (double)st.w0[cell];
-  for (int k = 0; k < a.max_zernike; ++k) w_re += kTwoPi * st.coef[k] * (double)ztab[(size_t)k * n * n + cell];
-  // the evanescent decay in FP32 (relative error ~1e-7, far below the tolerance), the
-  // phase reduced in FP64 in revolutions before the hardware sine and cosine
-  const float amp = w_im > 0.0 ? expf((float)-w_im) : 1.f;
-  float sn, cs;
-  sincos_rev(w_re * (1.0 / kTwoPi), &sn, &cs);
-  const float er = amp * cs, ei = amp * sn;
-  for (int c = 0; c < nc; ++c) out[c * npp] = make_float2(q[c].x * er - q[c].y * ei, q[c].x * ei + q[c].y * er);
+  const float2 e = pupil_phase_factor(a, a.s[s], ztab, j, l);
+  for (int c = 0; c < nc; ++c) out[c * npp] = make_float2(q[c].x * e.x - q[c].y * e.y, q[c].x * e.y + q[c].y * e.x);
 }
 
 // --------------------------------------------------------------------------
-// K1b: mirror fold of the base pupils.
+// K1 of the Fourier form: mirror-folded pupils.
 //
 // The cell-centred grid is symmetric, s[n-1-j] = -s[j], so with jf < nh = ceil(n/2)
 // and its mirror j' = n-1-jf each 1-D transform splits into even and odd parts:
@@ -94,45 +109,74 @@ __global__ void __launch_bounds__(256) pupil_build_kernel(PupilArgs a, const flo
 // each is one real GEMM with half the flops of the complex one.  The defocus factor
 // depends on s_x^2 + s_y^2 only and is the same for all four mirrors.
 // Layout: Pf[s][c][q = 2 jf + pj][kk = 2 lf + pl], complex, (2 nhp) x (2 nhp).
+// The four mirror cells' pupils are formed in registers, so P never reaches memory.
 // --------------------------------------------------------------------------
-// One thread per (folded cell, stack): grid.y is the stack.
-__global__ void __launch_bounds__(256) pupil_fold_kernel(FoldArgs a) {
-  const int nhp = a.nhp, n = a.n, nh = (a.n + 1) / 2;
-  const int cell = blockIdx.x * blockDim.x + threadIdx.x;
+// The values of v in the four lanes of this lane's quad (DPP quad_perm(k, k, k, k)).
+__device__ __forceinline__ float4 quad_values(float v) {
+  const int b = __float_as_int(v);
+  return make_float4(__int_as_float(__builtin_amdgcn_update_dpp(0, b, 0x00, 0xF, 0xF, false)),
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, b, 0x55, 0xF, 0xF, false)),
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, b, 0xAA, 0xF, 0xF, false)),
+                     __int_as_float(__builtin_amdgcn_update_dpp(0, b, 0xFF, 0xF, 0xF, false)));
+}
+
+// Four lanes per (folded cell, stack), grid.y the stack: lane m of a quad forms the pupil
+// of mirror m = 2 a + b, i.e. of cell (mir_a(jf), mir_b(lf)), broadcasts it to the quad
+// (DPP quad permutes) and writes parity (pj, pl) = (m / 2, m % 2) of every channel.
+__global__ void __launch_bounds__(256) pupil_build_folded_kernel(PupilArgs a, const float2* __restrict__ Q,
+                                                                 const float* __restrict__ ztab,
+                                                                 float2* __restrict__ Pf, int nhp) {
+  const int n = a.n, np = a.np, nh = (a.n + 1) / 2;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int cell = gid >> 2, m = gid & 3;
   const int s = blockIdx.y;
-  if (cell >= nhp * nhp) return;
+  if (cell >= nhp * nhp) return;   // whole quads
   const int jf = cell / nhp, lf = cell % nhp;
-  const size_t npp = (size_t)a.np * a.np, fpp = (size_t)4 * nhp * nhp;
-  const int w = 2 * nhp;
-  const size_t o00 = (size_t)(2 * jf) * w + 2 * lf;   // (pj, pl) = (0, 0); (0,1) = +1; (1,0) = +w
+  const int pj = m >> 1, pl = m & 1;
+  const size_t npp = (size_t)np * np, fpp = (size_t)4 * nhp * nhp;
+  const int w = 2 * nhp, nc = a.nc;
+  float2* out = Pf + (size_t)s * nc * fpp + (size_t)(2 * jf + pj) * w + 2 * lf + pl;
   const float2 zero = make_float2(0.f, 0.f);
-  for (int c = 0; c < a.nc; ++c) {
-    float2* out = a.Pf + ((size_t)s * a.nc + c) * fpp + o00;
-    if (jf >= nh || lf >= nh) {
-      out[0] = zero;
-      out[1] = zero;
-      out[w] = zero;
-      out[w + 1] = zero;
-      continue;
-    }
-    const float2* P = a.P + ((size_t)s * a.nc + c) * npp;
-    const int j1 = n - 1 - jf, l1 = n - 1 - lf;
-    const bool dj = j1 != jf, dl = l1 != lf;
-    const float2 p00 = P[(size_t)jf * a.np + lf];
-    const float2 p01 = dl ? P[(size_t)jf * a.np + l1] : zero;
-    const float2 p10 = dj ? P[(size_t)j1 * a.np + lf] : zero;
-    const float2 p11 = (dj && dl) ? P[(size_t)j1 * a.np + l1] : zero;
-    // even/odd in l for each j mirror, then in j
-    const float2 e0 = make_float2(p00.x + p01.x, p00.y + p01.y), o0 = make_float2(p00.x - p01.x, p00.y - p01.y);
-    const float2 e1 = make_float2(p10.x + p11.x, p10.y + p11.y), o1 = make_float2(p10.x - p11.x, p10.y - p11.y);
-    const float2 ee = make_float2(e0.x + e1.x, e0.y + e1.y);
-    const float2 eo = dl ? make_float2(o0.x + o1.x, o0.y + o1.y) : zero;            // odd in l
-    const float2 oe = dj ? make_float2(e0.x - e1.x, e0.y - e1.y) : zero;            // odd in j
-    const float2 oo = (dj && dl) ? make_float2(o0.x - o1.x, o0.y - o1.y) : zero;
-    out[0] = ee;
-    out[1] = make_float2(-eo.y, eo.x);        // i * eo
-    out[w] = make_float2(-oe.y, oe.x);        // i * oe
-    out[w + 1] = make_float2(-oo.x, -oo.y);   // i^2 * oo
+  if (jf >= nh || lf >= nh) {   // whole quads
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (c < nc) out[c * fpp] = make_float2(0.f, 0.f);
+    return;
+  }
+  const int j1 = n - 1 - jf, l1 = n - 1 - lf;
+  const bool dj = j1 != jf, dl = l1 != lf;
+  // this lane's mirror; a mirror equal to the cell itself is absent (zero)
+  const int j = pj ? j1 : jf, l = pl ? l1 : lf;
+  const bool present = (pj ? dj : true) && (pl ? dl : true);
+  float2 q[3];
+  bool inside = false;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    q[c] = present && c < nc ? Q[c * npp + (size_t)j * np + l] : zero;
+    inside = inside || q[c].x != 0.f || q[c].y != 0.f;
+  }
+  if (inside) {
+    const float2 e = pupil_phase_factor(a, a.s[s], ztab, j, l);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) q[c] = make_float2(q[c].x * e.x - q[c].y * e.y, q[c].x * e.y + q[c].y * e.x);
+  }
+  // the mirror's sign in this lane's parity: (-1)^(a pj + b pl) for mirror (a, b)
+  const float s01 = pl ? -1.f : 1.f, s10 = pj ? -1.f : 1.f;
+  const bool odd_ok = (!pj || dj) && (!pl || dl);   // odd parts of a self-mirrored row vanish
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c >= nc) break;
+    const float4 vr = quad_values(q[c].x), vi = quad_values(q[c].y);
+    // mirrors (0,0) + s01 (0,1) + s10 [(1,0) + s01 (1,1)]
+    float re = (vr.x + s01 * vr.y) + s10 * (vr.z + s01 * vr.w);
+    float im = (vi.x + s01 * vi.y) + s10 * (vi.z + s01 * vi.w);
+    if (!odd_ok) re = im = 0.f;
+    // times i^(pj + pl)
+    float2 v;
+    if (pj + pl == 0) v = make_float2(re, im);
+    else if (pj + pl == 1) v = make_float2(-im, re);
+    else v = make_float2(-re, -im);
+    out[c * fpp] = v;
   }
 }
 
@@ -466,9 +510,11 @@ hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* 
   return hipGetLastError();
 }
 
-hipError_t launch_pupil_fold(const FoldArgs& a, hipStream_t st) {
-  const int cells = a.nhp * a.nhp;
-  hipLaunchKernelGGL(pupil_fold_kernel, dim3((cells + 255) / 256, a.nstk), dim3(256), 0, st, a);
+hipError_t launch_pupil_build_folded(const PupilArgs& a, const float2* Q, const float* ztab, float2* Pf, int nhp,
+                                     hipStream_t st) {
+  const int lanes = 4 * nhp * nhp;
+  hipLaunchKernelGGL(pupil_build_folded_kernel, dim3((lanes + 255) / 256, a.nstk), dim3(256), 0, st, a, Q, ztab, Pf,
+                     nhp);
   return hipGetLastError();
 }
 

@@ -130,9 +130,9 @@ int plan_init(rwpsf_plan* p, const rwpsf_optics& o, const rwpsf_grid& g, const r
   return bessel_plan_init(p);
 }
 
-// Base pupils P_{b,c} of up to 8 stacks into the plan's pupil workspace.
-int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st) {
-  PupilArgs pa{};
+// Pupil arguments of nb <= NS stacks.
+template <int NS>
+static void fill_pupil_args(const rwpsf_plan* p, const rwpsf_stack* s, int nb, PupilArgsT<NS>& pa) {
   pa.n = p->num.n_pupil;
   pa.np = p->np;
   pa.nstk = nb;
@@ -153,6 +153,12 @@ int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_
     maxz = std::max(maxz, x.n_zernike);
   }
   pa.max_zernike = maxz;
+}
+
+// Base pupils P_{b,c} of up to 8 stacks into the plan's pupil workspace.
+int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st) {
+  PupilArgs pa{};
+  fill_pupil_args(p, s, nb, pa);
   const int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
   const int rc = hip_check(launch_pupil_build(pa, p->d_Q, p->d_ztab, p->d_P, st));
   p->time_end(tr, st);
@@ -160,8 +166,8 @@ int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_
 }
 
 // --------------------------------------------------------------------------
-// Fourier dispatch: chunks of up to 8 stacks (pupil build + fold), then slabs of
-// stack-planes through the two GEMM kernels.
+// Fourier dispatch: chunks of up to 16 stacks (folded pupils in launches of 8), then
+// slabs of stack-planes through the two GEMM kernels.
 // --------------------------------------------------------------------------
 static int fourier_gemms(rwpsf_plan* p, int s_local, int ns, const double* zoff, int s_global, int z0, int nzs,
                          float2* E, float* I, hipStream_t st) {
@@ -210,17 +216,16 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != p->device) return RWPSF_ERR_INVALID_ARG;
   const int nz = p->grid.nz;
-  const size_t fpp = (size_t)4 * p->nhp * p->nhp;
   for (int b0 = 0; b0 < n; b0 += kGemmStacks) {
     const int nb = std::min(kGemmStacks, n - b0);
     int rc;
-    // pupils of the group in launches of up to kPupilStacks, folded side by side
+    // folded pupils of the group in launches of up to kPupilStacks, side by side
     for (int c0 = 0; c0 < nb; c0 += kPupilStacks) {
-      const int nc0 = std::min(kPupilStacks, nb - c0);
-      if ((rc = fourier_build_pupils(p, s + b0 + c0, nc0, st))) return rc;
-      FoldArgs fa{p->d_P, p->d_Pf + (size_t)c0 * p->nc * fpp, p->num.n_pupil, p->np, p->nhp, nc0, p->nc};
+      PupilArgs pa{};
+      fill_pupil_args(p, s + b0 + c0, std::min(kPupilStacks, nb - c0), pa);
+      float2* Pf = p->d_Pf + (size_t)c0 * p->nc * 4 * p->nhp * p->nhp;
       const int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
-      if ((rc = hip_check(launch_pupil_fold(fa, st)))) return rc;
+      if ((rc = hip_check(launch_pupil_build_folded(pa, p->d_Q, p->d_ztab, Pf, p->nhp, st)))) return rc;
       p->time_end(tr, st);
     }
     double zoff[kGemmStacks];

@@ -16,21 +16,19 @@ struct PupilStack {
 
 // Channels: nc = 3 (vectorial model, x, y, z) or 1 (scalar model); every per-channel
 // array below holds nc channels.
-struct PupilArgs {
+template <int NS>
+struct PupilArgsT {
   int n, np, nstk, max_zernike, gibson_lanni, nc;   // n: pupil cells per axis, np: padded stride
   double s_max, k;
   GLParams gl;
-  PupilStack s[kPupilStacks];
+  PupilStack s[NS];
 };
+using PupilArgs = PupilArgsT<kPupilStacks>;
+static_assert(sizeof(PupilArgs) <= 4000, "kernel arguments are passed by value (4 KB limit)");
 
 // Device operands are zero-padded: np = n rounded up to 64, nxp = nx rounded up
 // to 128, nyp = ny rounded up to 128, and the folded pupil axis nh = ceil(n/2) to
 // nhp = nh rounded up to 32 (so 2 nhp = np).
-struct FoldArgs {
-  const float2* P;     // [nstk][nc][np][np] base pupils
-  float2* Pf;          // [nstk][nc][2 nhp][2 nhp] folded pupils
-  int n, np, nhp, nstk, nc;
-};
 
 struct Gemm1Args {
   const float2* Pf;    // [nstk][nc][2 nhp][2 nhp]
@@ -58,7 +56,9 @@ inline int pad_axis(int n) { return n <= kPadSmall ? kPadSmall : round_up(n, kPa
 hipError_t launch_zernike_table(float* out, int n, int nj, hipStream_t st);
 hipError_t launch_pupil_build(const PupilArgs& a, const float2* Q, const float* ztab, float2* P,
                               hipStream_t st);
-hipError_t launch_pupil_fold(const FoldArgs& a, hipStream_t st);
+// Pf [nstk][nc][2 nhp][2 nhp] of the stacks of a (its np field is the stride of Q)
+hipError_t launch_pupil_build_folded(const PupilArgs& a, const float2* Q, const float* ztab, float2* Pf, int nhp,
+                                     hipStream_t st);
 hipError_t launch_gemm_pupil(const Gemm1Args& a, hipStream_t st);
 hipError_t launch_gemm_image(const Gemm2Args& a, hipStream_t st);
 hipError_t fourier_kernel_attributes();

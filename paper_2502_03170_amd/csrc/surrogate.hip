@@ -132,6 +132,7 @@ static hipError_t sg_gemm(const float* A, int lda, const float* B, int ldb, floa
 // 128 x 128, 4 waves of 64 x 64 (2 x 2 MFMA blocks of 32 x 32 x 16), k-stage 32, two LDS
 // stages; each lane reads its 8 consecutive k of an operand with one 16-byte LDS read.
 constexpr int FBM = 128, FBN = 128, FBK = 32, FLD = FBK + 8;   // LDS row: 40 bf16 (80 B)
+constexpr int kGroupM = 8;                                      // row blocks per band (XCD order)
 typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
 
 // W [K][N] FP32 -> Bt_hi / Bt_lo [N][K] BF16 (hi = bf16(w), lo = bf16(w - hi))
@@ -157,7 +158,21 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
   constexpr int STAGE = 4 * PL;             // A hi, A lo, B hi, B lo
   extern __shared__ __bf16 shb[];
   const int tiles_n = N / FBN;
-  const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+  {
+    // Workgroups go to the 8 XCDs round robin, and each XCD has its own L2.  When the row
+    // blocks divide evenly, XCD x takes a contiguous eighth of them and walks it in bands
+    // of kGroupM row blocks, column tile by column tile, so that the workgroups resident
+    // on one XCD share A row blocks and B column tiles in its L2 (with the plain order the
+    // 8 column tiles of a row block would sit on 8 XCDs and A would be fetched 8 times).
+    const int rb = gridDim.x / tiles_n;
+    if (rb % (8 * kGroupM) == 0) {
+      const int xcd = blockIdx.x & 7, local = blockIdx.x >> 3;
+      const int band = local / (kGroupM * tiles_n), w = local % (kGroupM * tiles_n);
+      tm = xcd * (rb >> 3) + band * kGroupM + w % kGroupM;
+      tn = w / kGroupM;
+    }
+  }
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
   const int row0 = tm * FBM, col0 = tn * FBN;
