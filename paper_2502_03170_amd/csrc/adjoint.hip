@@ -118,7 +118,7 @@ __global__ void __launch_bounds__(CfgAdjH::NT, 2) adj_h_kernel(AdjHArgs a) {
   lb.ld = a.nyp;
   RgAcc<Cfg> acc;
   acc.zero();
-  rg_mainloop<Cfg, true>(acc, la, lb, 0, a.ny, lds, tid, wrow, wcol, lane);
+  rg_mainloop<Cfg, kOrderFull>(acc, la, lb, 0, a.ny, lds, tid, wrow, wcol, lane);
   // rows 2m + ri: registers r and r + 1 (r even) are the re/im parts of one H'[m][col]
   float2* H = a.H + (size_t)item * a.nxp * a.w;
 #pragma unroll
@@ -218,7 +218,7 @@ __global__ void __launch_bounds__(CfgAdjG::NT, 3) adj_g_kernel(AdjGArgs a) {
   for (int zi = z_begin; zi < z_end; ++zi) {
     RgAcc<Cfg> acc;
     acc.zero();
-    rg_mainloop_pre<Cfg, false>(acc, la, lb, ra, rb, 0, a.nxp, lds, tid, wrow, wcol, lane);
+    rg_mainloop_pre<Cfg, kOrderFree>(acc, la, lb, ra, rb, 0, a.nxp, lds, tid, wrow, wcol, lane);
     // the next plane's first stage (the last plane reloads its own, unused) is loaded
     // before this plane's epilogue, which hides its latency
     lb.src = hsrc + ((size_t)(s * a.nz + min(zi + 1, z_end - 1)) * 3 + c) * hplane;

@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(Cfg::NT, OCC) gemm_pupil_kernel(Gemm1Args a) {
   RgAcc<Cfg> acc;
   acc.zero();
   // unordered: the compiler's interleaving of the defocus arithmetic measured faster here
-  rg_mainloop<Cfg, false>(acc, la, lb, k_begin, k_end, lds, tid, wrow, wcol, lane);
+  rg_mainloop<Cfg, kOrderFree>(acc, la, lb, k_begin, k_end, lds, tid, wrow, wcol, lane);
 
   // rows 2q + ri: registers r and r + 1 (r even) are the re/im parts of one T[q][n]
   float2* T = a.T + (((size_t)s * a.nzs + zi) * a.nc + c) * (size_t)w * a.nyp;
@@ -377,7 +377,7 @@ __device__ __forceinline__ void image_channel(const Gemm2Args& a, float* lds, in
   const int ri = lane & 1;   // columns alternate re/im with the lane index
   RgAcc<Cfg> acc;
   acc.zero();
-  rg_mainloop_pre<Cfg, true>(acc, la, lb, ra, rb, 0, w, lds, tid, wrow, wcol, lane);
+  rg_mainloop_pre<Cfg, kOrderFull>(acc, la, lb, ra, rb, 0, w, lds, tid, wrow, wcol, lane);
   // first stage of the next channel (the last channel reloads its own, unused)
   lb.src = tsrc + (size_t)min(c + 1, a.nc - 1) * tch;
   ra = la.load(0, tid);

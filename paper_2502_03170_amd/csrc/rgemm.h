@@ -174,12 +174,16 @@ __device__ __forceinline__ void rg_stage_mma(RgAcc<Cfg>& acc, const float* a, co
 // K loop whose first stage (k_begin) the caller has already loaded into registers
 // (ra0, rb0), so that a caller can issue those loads before other memory work.
 // The last stage is peeled so that the loop body has no branch around the loads and
-// stores (a conditional there leaves the staged registers in scratch memory).  ORDERED
-// adds scheduling barriers that keep the order loads / MFMAs / stores: without them
-// the compiler may sink the global loads to their LDS stores, or hoist the loader's
-// arithmetic into the MFMA stream, and a wave then waits on global memory once per
-// stage.  Which order is faster depends on the loader (measured per kernel).
-template <class Cfg, bool ORDERED, class ALoader, class BLoader>
+// stores (a conditional there leaves the staged registers in scratch memory).  ORDER
+// places scheduling barriers: without them (kOrderFree) the compiler tends to sink the
+// global loads of the next stage to the end of the MFMA stream, right before their
+// LDS stores, and a wave then waits out the load latency once per stage.
+// kOrderLoadsFirst pins the loads ahead of the MFMAs and leaves the loader's
+// arithmetic free to interleave with them; kOrderFull also keeps that arithmetic and
+// the stores after the MFMAs.  Which order is faster depends on the loader (measured
+// per kernel).
+constexpr int kOrderFree = 0, kOrderFull = 1, kOrderLoadsFirst = 2;
+template <class Cfg, int ORDER, class ALoader, class BLoader>
 __device__ __forceinline__ void rg_mainloop_pre(RgAcc<Cfg>& acc, const ALoader& la, const BLoader& lb,
                                                 const typename ALoader::Regs& ra0,
                                                 const typename BLoader::Regs& rb0, int k_begin, int k_end,
@@ -195,9 +199,9 @@ __device__ __forceinline__ void rg_mainloop_pre(RgAcc<Cfg>& acc, const ALoader& 
     float* nxt = lds + ((kt + 1) & 1) * Cfg::STAGE_FLOATS;
     const auto ra = la.load(k_begin + (kt + 1) * Cfg::BK, tid);
     const auto rb = lb.load(k_begin + (kt + 1) * Cfg::BK, tid);
-    if constexpr (ORDERED) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (ORDER != kOrderFree) __builtin_amdgcn_sched_barrier(0);
     rg_stage_mma<Cfg>(acc, cur, cur + Cfg::A_FLOATS, wrow, wcol, lane);
-    if constexpr (ORDERED) __builtin_amdgcn_sched_barrier(0);
+    if constexpr (ORDER == kOrderFull) __builtin_amdgcn_sched_barrier(0);
     la.store(nxt, tid, ra);
     lb.store(nxt + Cfg::A_FLOATS, tid, rb);
     __syncthreads();
@@ -209,12 +213,12 @@ __device__ __forceinline__ void rg_mainloop_pre(RgAcc<Cfg>& acc, const ALoader& 
 
 // K loop over [k_begin, k_end) (multiples of BK, k_end > k_begin) with double-buffered
 // LDS.  The loaders provide Regs load(k0, tid) and store(lds_tile, tid, regs).
-template <class Cfg, bool ORDERED, class ALoader, class BLoader>
+template <class Cfg, int ORDER, class ALoader, class BLoader>
 __device__ __forceinline__ void rg_mainloop(RgAcc<Cfg>& acc, const ALoader& la, const BLoader& lb, int k_begin,
                                             int k_end, float* lds, int tid, int wrow, int wcol, int lane) {
   const auto ra = la.load(k_begin, tid);
   const auto rb = lb.load(k_begin, tid);
-  rg_mainloop_pre<Cfg, ORDERED>(acc, la, lb, ra, rb, k_begin, k_end, lds, tid, wrow, wcol, lane);
+  rg_mainloop_pre<Cfg, ORDER>(acc, la, lb, ra, rb, k_begin, k_end, lds, tid, wrow, wcol, lane);
 }
 
 // Row/column of accumulator register r in 32 x 32 block (i, j) of this wave.
