@@ -95,15 +95,21 @@ struct PhiArgs {
   PhiStack s[kPhiStacks];
 };
 
-// fq: per node (Re q_s, Im q_s, Re q_p, Im q_p) when V = 2.
+// fq: per node (Re q_s, Im q_s, Re q_p, Im q_p) when V = 2.  One thread per (node,
+// stack, group of kPhiZ planes): the plane-independent part (apodization, envelope,
+// Gibson-Lanni, Zernike phase; FP64 transcendentals) is formed once per thread, then
+// only the defocus phase per plane.  phi: this launch's first column; ld: the row
+// stride of the Phi matrix in complex entries.
+constexpr int kPhiZ = 4;
 __global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
                                   const double* __restrict__ z, const double* __restrict__ fq,
-                                  float2* __restrict__ phi, int ld_cols) {
+                                  float2* __restrict__ phi, int ld) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int per_q = a.nstk * a.nz;
+  const int nzg = (a.nz + kPhiZ - 1) / kPhiZ;
+  const int per_q = a.nstk * nzg;
   if (idx >= a.T * per_q) return;
   const int q = idx / per_q, rem = idx % per_q;
-  const int si = rem / a.nz, zi = rem % a.nz;
+  const int si = rem / nzg, z0 = (rem % nzg) * kPhiZ;
   const PhiStack& st = a.s[si];
   const double t = theta[q];
   const double sin_t = sin(t), cos_t = cos(t);
@@ -116,19 +122,28 @@ __global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
   const double r = sin_t / a.s_max;
   for (int j = 0; j < kAxiTerms; ++j)
     if (st.coef[j] != 0.0) w_re += kTwoPi * st.coef[j] * zernike_noll(kAxiNoll[j], r, 1.0, 0.0);
-  const double ph = w_re + a.k * (z[zi] + st.zoff) * cos_t;
-  float sn, cs;
-  sincosf((float)reduce_2pi(ph), &sn, &cs);
   const float m = (float)(amp * exp(-w_im));
-  float2* out = phi + (size_t)q * ld_cols + (size_t)rem * a.V;
-  if (a.V == 1) {
-    out[0] = make_float2(m * cs, m * sn);
-  } else {
-    const float qsr = (float)fq[4 * q], qsi = (float)fq[4 * q + 1];
-    const float qpr = (float)fq[4 * q + 2], qpi = (float)fq[4 * q + 3];
+  const double kc = a.k * cos_t;
+  float qsr = 0.f, qsi = 0.f, qpr = 0.f, qpi = 0.f;
+  if (a.V == 2) {
+    qsr = (float)fq[4 * q];
+    qsi = (float)fq[4 * q + 1];
+    qpr = (float)fq[4 * q + 2];
+    qpi = (float)fq[4 * q + 3];
+  }
+  const int z1 = min(z0 + kPhiZ, a.nz);
+  float2* out = phi + (size_t)q * ld + ((size_t)si * a.nz + z0) * a.V;
+  for (int zi = z0; zi < z1; ++zi, out += a.V) {
+    const double ph = w_re + kc * (z[zi] + st.zoff);
+    float sn, cs;
+    sincosf((float)reduce_2pi(ph), &sn, &cs);
     const float pr = m * cs, pi = m * sn;
-    out[0] = make_float2(pr * qsr - pi * qsi, pr * qsi + pi * qsr);
-    out[1] = make_float2(pr * qpr - pi * qpi, pr * qpi + pi * qpr);
+    if (a.V == 1) {
+      out[0] = make_float2(pr, pi);
+    } else {
+      out[0] = make_float2(pr * qsr - pi * qsi, pr * qsi + pi * qsr);
+      out[1] = make_float2(pr * qpr - pi * qpi, pr * qpi + pi * qpr);
+    }
   }
 }
 
@@ -229,12 +244,14 @@ hipError_t launch_rgemm(const float* A, int lda, const float* B, int ldb, float*
 // (variant, re/im) x [G][R], are combined into I_n and staged in LDS as
 // [re/im][NI][R] (NI = 3 integrals, or 1 for the scalar model).
 // --------------------------------------------------------------------------
+constexpr int kEpiStacks = 256;   // stacks per contraction and epilogue launch
 struct EpiArgs {
   int nx, ny, nz, R, nstk, s_base, mode;
   float dx, dy, inv_drho;
   float exr, exi, eyr, eyi;   // polarisation times -(i f k / 2); scalar: exr + i exi = -i f k
-  float x0[kPhiStacks], y0[kPhiStacks];
+  float x0[kEpiStacks], y0[kEpiStacks];
 };
+static_assert(sizeof(EpiArgs) <= 4000, "kernel arguments are passed by value (4 KB limit)");
 
 __global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const float* __restrict__ In,
                                                               float2* __restrict__ E,
@@ -416,7 +433,7 @@ int bessel_plan_init(rwpsf_plan* p) {
   if ((st = dev_alloc(p, &p->d_wtheta, T))) return st;
   if ((st = dev_alloc(p, &p->d_btab, (size_t)G * R * T))) return st;
   if ((st = dev_alloc(p, &p->d_z, (size_t)p->grid.nz))) return st;
-  p->bessel_stacks = kPhiStacks;
+  p->bessel_stacks = kEpiStacks;
   if ((st = bessel_scratch_init(p->device, &p->scratch))) return st;
   if ((st = dev_alloc(p, &p->d_phi, (size_t)T * p->bessel_stacks * p->grid.nz * V))) return st;
   if ((st = dev_alloc(p, (float**)&p->d_In, (size_t)p->bessel_stacks * p->grid.nz * V * 2 * G * R))) return st;
@@ -450,8 +467,9 @@ int bessel_plan_init(rwpsf_plan* p) {
   return hip_check(hipDeviceSynchronize());
 }
 
-// Pupil x defocus on the theta nodes for stacks s[0..nb) into the plan's Phi workspace.
-static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* phi, hipStream_t st) {
+// Pupil x defocus on the theta nodes for stacks s[0..nb), nb <= kPhiStacks, into the Phi
+// matrix at phi (its first column for these stacks), row stride ld complex entries.
+static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* phi, int ld, hipStream_t st) {
   const int T = p->n_theta_total, nz = p->grid.nz;
   PhiArgs pa{};
   pa.T = T;
@@ -475,14 +493,24 @@ static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* phi, 
     maxz = std::max(maxz, x.n_zernike);
   }
   pa.max_zernike = maxz;
-  const int cols = nb * nz;   // complex columns of Phi per variant
-  const int total = T * cols;
+  const int total = T * nb * ((nz + kPhiZ - 1) / kPhiZ);
   const int tr = p->time_begin(RWPSF_KERNEL_BESSEL_PHI, st);
   hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, p->d_theta,
-                     p->d_z, p->d_fq, phi, cols * pa.V);
+                     p->d_z, p->d_fq, phi, ld);
   const int rc = hip_check(hipGetLastError());
   p->time_end(tr, st);
   return rc;
+}
+
+// Phi of stacks s[0..nb) (in launches of up to kPhiStacks) into the Phi matrix of nb
+// stacks.
+static int bessel_phi_all(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* phi, hipStream_t st) {
+  const int V = bessel_variants(p->bessel_mode), nz = p->grid.nz;
+  for (int c0 = 0; c0 < nb; c0 += kPhiStacks) {
+    const int rc = bessel_phi(p, s + c0, std::min(kPhiStacks, nb - c0), phi + (size_t)c0 * nz * V, nb * nz * V, st);
+    if (rc) return rc;
+  }
+  return RWPSF_OK;
 }
 
 // Polarisation factors of the angular combination with the prefactor folded in:
@@ -501,8 +529,9 @@ static void bessel_pol(const rwpsf_plan* p, float out[4]) {
   out[3] = (float)ey.imag();
 }
 
-// Stacks s[0..n) in chunks of up to `chunk` stacks, with Phi and I_n of a chunk in the
-// workspaces phi ([T][chunk nz V] complex) and In ([chunk nz V][2][G][R] float).
+// Stacks s[0..n) in chunks of up to `chunk` (<= kEpiStacks) stacks, with Phi and I_n of a
+// chunk in the workspaces phi ([T][chunk nz V] complex) and In ([chunk nz V][2][G][R]
+// float): one contraction and one epilogue launch per chunk.
 static int bessel_compute_ws(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, float2* phi,
                              float* In, int chunk, hipStream_t st) {
   int cur = -1;
@@ -514,7 +543,7 @@ static int bessel_compute_ws(rwpsf_plan* p, int n, const rwpsf_stack* s, float2*
   bessel_pol(p, pol);
   for (int b0 = 0; b0 < n; b0 += chunk) {
     const int nb = std::min(chunk, n - b0);
-    int rc = bessel_phi(p, s + b0, nb, phi, st);
+    int rc = bessel_phi_all(p, s + b0, nb, phi, st);
     if (rc) return rc;
     const int cols = nb * nz;
     const int M = 2 * cols * V, N = G * R;
@@ -553,7 +582,7 @@ static int bessel_compute_ws(rwpsf_plan* p, int n, const rwpsf_stack* s, float2*
 }
 
 int bessel_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st) {
-  return bessel_compute_ws(p, n, s, E, I, p->d_phi, (float*)p->d_In, kPhiStacks, st);
+  return bessel_compute_ws(p, n, s, E, I, p->d_phi, (float*)p->d_In, kEpiStacks, st);
 }
 
 // --------------------------------------------------------------------------
@@ -599,7 +628,7 @@ int bessel_compute_noalloc(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E
   if (!p->scratch) return RWPSF_ERR_HIP;   // the plan could not resolve the array's address
   const size_t per = bessel_scratch_per_stack(p);
   if (per + kScratchAlign > kScratchFloats) return RWPSF_ERR_SCRATCH_LIMIT;
-  const int chunk = (int)std::min<size_t>(kPhiStacks, (kScratchFloats - kScratchAlign) / per);
+  const int chunk = (int)std::min<size_t>(kEpiStacks, (kScratchFloats - kScratchAlign) / per);
   const size_t V = bessel_variants(p->bessel_mode);
   const size_t phi_floats = 2 * (size_t)p->n_theta_total * chunk * p->grid.nz * V;
   const size_t in_off = (phi_floats + kScratchAlign - 1) / kScratchAlign * kScratchAlign;
@@ -888,7 +917,7 @@ int bessel_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E, 
   bessel_pol(p, pol);
   for (int b0 = 0; b0 < n; b0 += kPhiStacks) {
     const int nb = std::min(kPhiStacks, n - b0);
-    if ((rc = bessel_phi(p, s + b0, nb, p->d_phi, st))) return rc;
+    if ((rc = bessel_phi(p, s + b0, nb, p->d_phi, nb * nz * V, st))) return rc;
     const int M = 2 * nb * nz * V;
     AdjRadArgs ra{};
     ra.nx = p->grid.nx;
