@@ -132,6 +132,7 @@ static hipError_t sg_gemm(const float* A, int lda, const float* B, int ldb, floa
 // 128 x 128, 4 waves of 64 x 64 (2 x 2 MFMA blocks of 32 x 32 x 16), k-stage 32, two LDS
 // stages; each lane reads its 8 consecutive k of an operand with one 16-byte LDS read.
 constexpr int FBM = 128, FBN = 128, FBK = 32, FLD = FBK + 8;   // LDS row: 40 bf16 (80 B)
+static_assert(4 * 64 * (64 + 4) * 4 <= 2 * 4 * FBM * FLD * 2, "the epilogue tiles fit in the stage buffers");
 constexpr int kGroupM = 8;                                      // row blocks per band (XCD order)
 typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
 
@@ -284,25 +285,37 @@ __global__ void __launch_bounds__(256, 2) sg_gemm_fast_kernel(const float* __res
   store(shb + ((KT - 1) & 1) * STAGE, g1);
   __syncthreads();
   mma(shb + ((KT - 1) & 1) * STAGE);
+  // Epilogue through LDS (the stage buffers are free now): each wave writes its 64 x 64
+  // tile row-major, then stores whole 16-byte row pieces, a quarter of the store
+  // instructions of one value per lane per accumulator register.
+  __syncthreads();
+  constexpr int TLD = 64 + 4;   // floats per LDS row of a wave's tile
+  float* tw = reinterpret_cast<float*>(shb) + wave * 64 * TLD;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        tw[(32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * TLD + 32 * j + (lane & 31)] = acc[i][j][r];
+  __syncthreads();
   const bool raw = gridDim.y > 1;
-#pragma unroll
-  for (int j = 0; j < 2; ++j) {
-    const int n = col0 + wn + 32 * j + (lane & 31);
-    const float bn = (bias && !raw) ? bias[n] : 0.f;
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int m = row0 + wm + 32 * i + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        if (m < M) {
-          float v = acc[i][j][r];
-          if (!raw) {
-            v += bn + (accumulate ? C[(size_t)m * N + n] : 0.f);
-            if (relu) v = fmaxf(v, 0.f);
-          }
-          C[(size_t)m * N + n] = v;
-        }
+  const int c4 = lane & 15, n = col0 + wn + 4 * c4;
+  float4 bn = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (bias && !raw) bn = make_float4(bias[n], bias[n + 1], bias[n + 2], bias[n + 3]);   // (bias is 4-byte aligned)
+#pragma unroll 4
+  for (int it = 0; it < 16; ++it) {
+    const int row = 4 * it + (lane >> 4), m = row0 + wm + row;
+    if (m < M) {
+      float4 v = *reinterpret_cast<const float4*>(tw + row * TLD + 4 * c4);
+      float4* dst = reinterpret_cast<float4*>(C + (size_t)m * N + n);
+      if (!raw) {
+        const float4 prev = accumulate ? *dst : make_float4(0.f, 0.f, 0.f, 0.f);
+        v = make_float4(v.x + bn.x + prev.x, v.y + bn.y + prev.y, v.z + bn.z + prev.z, v.w + bn.w + prev.w);
+        if (relu) v = make_float4(fmaxf(v.x, 0.f), fmaxf(v.y, 0.f), fmaxf(v.z, 0.f), fmaxf(v.w, 0.f));
       }
+      *dst = v;
+    }
   }
 }
 
@@ -593,6 +606,12 @@ __global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restr
   fetch(blockIdx.x);
   __syncthreads();   // borders zeroed before any interior write
   for (int b = blockIdx.x; b < B; b += gridDim.x) {
+    // this sample's basis-branch output under the thread's 4 x 4 outputs of layer 3,
+    // requested now so that its latency passes under layers 1 and 2
+    float* yo = y + (size_t)b * 4096 + (4 * (tid >> 4)) * 64 + 4 * (tid & 15);
+    float4 yprev[4];
+#pragma unroll
+    for (int oy = 0; oy < 4; ++oy) yprev[oy] = *reinterpret_cast<const float4*>(yo + oy * 64);
     // ---- stage h3 [ci][Y][X] -> X0 [Y+1][X+1][ci]
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -716,11 +735,10 @@ __global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restr
         }
       }
       // y holds the basis branch already: add the convolution branch to it
-      float* o = y + (size_t)b * 4096 + (4 * Yb) * 64 + 4 * Xb;
 #pragma unroll
       for (int oy = 0; oy < 4; ++oy) {
-        const float4 prev = *reinterpret_cast<const float4*>(o + oy * 64);
-        *reinterpret_cast<float4*>(o + oy * 64) =
+        const float4 prev = yprev[oy];
+        *reinterpret_cast<float4*>(yo + oy * 64) =
             make_float4(prev.x + out[oy][0], prev.y + out[oy][1], prev.z + out[oy][2], prev.w + out[oy][3]);
       }
     }
