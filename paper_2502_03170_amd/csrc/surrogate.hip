@@ -544,17 +544,6 @@ __global__ void sg_dec_wprep_kernel(const float* __restrict__ K1, const float* _
   }
 }
 
-template <int NSPLIT>
-__device__ __forceinline__ f4v_t mma16(const bf8_t& ah, const bf8_t& al, const bf8_t& bh, const bf8_t& bl,
-                                       f4v_t acc) {
-  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
-  if (NSPLIT > 1) {
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
-  }
-  return acc;
-}
-
 // h3 [B][DC0][8][8] (relu applied) -> y [B][64][64] += T(T(T(h3))); d1 [B][DC1][16][16] and d2
 // [B][DC2][32][32] (post-relu) are also written when the pointers are not null (training).
 // Persistent: workgroup g serves samples g, g + gridDim.x, ...
@@ -627,33 +616,48 @@ __global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restr
     }
     fetch(b + gridDim.x);
     __syncthreads();
-    // ---- layer 1: wave w = class (py, px); M-tiles of 16 pixels (Y, X) of the 8 x 8 input
+    // ---- layer 1: wave w = class (py, px); the four M-tiles of 16 pixels (Y, X) of the
+    // 8 x 8 input, their accumulator chains interleaved
     {
       const int py = w >> 1, px = w & 1;
+      f4v_t acc[4];
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt) {
-        const int m = 16 * mt + r16, Y = m >> 3, X = m & 7;
-        f4v_t acc = {0.f, 0.f, 0.f, 0.f};
+      for (int mt = 0; mt < 4; ++mt) acc[mt] = f4v_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int s = 0; s < DK1; ++s) {
-          const int k0 = 32 * s + 8 * g, tap = k0 / DC0, ci = k0 % DC0, a = tap >> 1, c = tap & 1;
-          const int dy = py ? 1 - a : -a, dx = px ? 1 - c : -c;
+      for (int s = 0; s < DK1; ++s) {
+        const int k0 = 32 * s + 8 * g, tap = k0 / DC0, ci = k0 % DC0, a = tap >> 1, c = tap & 1;
+        const int dy = py ? 1 - a : -a, dx = px ? 1 - c : -c;
+        bf8_t ah[4], al[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+          const int m = 16 * mt + r16, Y = m >> 3, X = m & 7;
           const int at = ((Y + dy + 1) * 10 + X + dx + 1) * DX0b + ci;
-          const bf8_t ah = *reinterpret_cast<const bf8_t*>(X0h + at);
-          const bf8_t al = NSPLIT > 1 ? *reinterpret_cast<const bf8_t*>(X0l + at) : ah;
-          acc = mma16<NSPLIT>(ah, al, w1h[s], w1l[s], acc);
+          ah[mt] = *reinterpret_cast<const bf8_t*>(X0h + at);
+          al[mt] = NSPLIT > 1 ? *reinterpret_cast<const bf8_t*>(X0l + at) : ah[mt];
         }
-        // C: rows 4 g + i (pixels), column r16 (output channel)
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], w1h[s], acc[mt], 0, 0, 0);
+        if (NSPLIT > 1) {
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[mt], w1l[s], acc[mt], 0, 0, 0);
+#pragma unroll
+          for (int mt = 0; mt < 4; ++mt)
+            acc[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[mt], w1h[s], acc[mt], 0, 0, 0);
+        }
+      }
+      // C: rows 4 g + i (pixels), column r16 (output channel)
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
           const int mm = 16 * mt + 4 * g + i, YY = mm >> 3, XX = mm & 7;
           const int at = ((2 * YY + py + 1) * 18 + 2 * XX + px + 1) * DX1b + r16;
-          const float v = fmaxf(acc[i] + bias1, 0.f);
+          const float v = fmaxf(acc[mt][i] + bias1, 0.f);
           const __bf16 h = (__bf16)v;
           X1h[at] = h;
           X1l[at] = (__bf16)(v - (float)h);
         }
-      }
     }
     __syncthreads();
     if (d1g) {   // training: d1 [co][16][16]
@@ -663,28 +667,47 @@ __global__ void __launch_bounds__(256, 2) sg_decoder_kernel(const float* __restr
         o[e] = (float)X1h[at] + (float)X1l[at];   // the value to 2^-16 relative (its sign exactly)
       }
     }
-    // ---- layer 2: wave w = row class py2, M-tiles 8 (w & 1) .. + 7 of the 16 x 16 input
+    // ---- layer 2: wave w = row class py2, M-tiles 8 (w & 1) .. + 7 of the 16 x 16 input,
+    // in groups of L2G tiles whose accumulator chains are interleaved (a chain's next
+    // product waits for the previous one; the group's other chains fill the gap)
     {
-#pragma unroll 2
-      for (int t = 0; t < 8; ++t) {
-        const int mt = 8 * (w & 1) + t;
-        const int m = 16 * mt + r16, Y = m >> 4, X = m & 15;
-        f4v_t acc = {0.f, 0.f, 0.f, 0.f};
+      constexpr int L2G = 4;
+#pragma unroll 1
+      for (int t0 = 0; t0 < 8; t0 += L2G) {
+        f4v_t acc[L2G];
+#pragma unroll
+        for (int u = 0; u < L2G; ++u) acc[u] = f4v_t{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int s = 0; s < DK2; ++s) {
           const int k0 = 32 * s + 8 * g, t6 = k0 / DC1, ci = k0 % DC1, a = t6 / 3, c3 = t6 % 3;
           const int dy = py2 ? 1 - a : -a, dx = c3 - 1;
-          const int at = ((Y + dy + 1) * 18 + X + dx + 1) * DX1b + ci;
-          const bf8_t ah = *reinterpret_cast<const bf8_t*>(X1h + at);
-          const bf8_t al = NSPLIT > 1 ? *reinterpret_cast<const bf8_t*>(X1l + at) : ah;
-          acc = mma16<NSPLIT>(ah, al, w2h[s], w2l[s], acc);
+          bf8_t ah[L2G], al[L2G];
+#pragma unroll
+          for (int u = 0; u < L2G; ++u) {
+            const int m = 16 * (8 * (w & 1) + t0 + u) + r16, Y = m >> 4, X = m & 15;
+            const int at = ((Y + dy + 1) * 18 + X + dx + 1) * DX1b + ci;
+            ah[u] = *reinterpret_cast<const bf8_t*>(X1h + at);
+            al[u] = NSPLIT > 1 ? *reinterpret_cast<const bf8_t*>(X1l + at) : ah[u];
+          }
+#pragma unroll
+          for (int u = 0; u < L2G; ++u) acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u], w2h[s], acc[u], 0, 0, 0);
+          if (NSPLIT > 1) {
+#pragma unroll
+            for (int u = 0; u < L2G; ++u)
+              acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[u], w2l[s], acc[u], 0, 0, 0);
+#pragma unroll
+            for (int u = 0; u < L2G; ++u)
+              acc[u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[u], w2h[s], acc[u], 0, 0, 0);
+          }
         }
         const int px = r16 / DC2, co = r16 % DC2;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const int mm = 16 * mt + 4 * g + i, YY = mm >> 4, XX = mm & 15;
-          X2[((2 * YY + py2 + 1) * 34 + 2 * XX + px + 1) * DX2 + co] = fmaxf(acc[i] + bias2, 0.f);
-        }
+        for (int u = 0; u < L2G; ++u)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int mm = 16 * (8 * (w & 1) + t0 + u) + 4 * g + i, YY = mm >> 4, XX = mm & 15;
+            X2[((2 * YY + py2 + 1) * 34 + 2 * XX + px + 1) * DX2 + co] = fmaxf(acc[u][i] + bias2, 0.f);
+          }
       }
     }
     __syncthreads();
