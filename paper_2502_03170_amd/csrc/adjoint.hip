@@ -35,6 +35,7 @@
 
 namespace rw {
 
+constexpr int kAdjStacks = 32;   // stacks per adj_h / adj_g launch (every launch boundary costs ~10 us)
 using CfgAdjH = RgCfg<128, 64, 16, 64, 32>;   // rows 2m + re/im, columns 2lf + p, k = n
 using CfgAdjG = RgCfg<64, 128, 16, 32, 64>;   // rows 2jf + p, columns 2(2lf + p) + re/im, k = m
 
@@ -141,7 +142,7 @@ struct AdjGArgs {
   const double* ksz;   // [np][np]
   const float2* D;     // [nz][np][np] exp(i k s_z z) of the plan's planes
   float* partial;      // [stacks * 3 * zgroups][np][np]
-  double zoff[kPupilStacks];
+  double zoff[kAdjStacks];
   int s0, nstk, nz, nxp, w, n;
   int zgroups, zper;   // planes are split into zgroups runs of zper (the last may be shorter)
 };
@@ -338,7 +339,7 @@ hipError_t adjoint_kernel_attributes() {
 // Plane groups of adj_g: enough workgroups to fill the chip (>= 4 per CU of 256).
 static int adjoint_zgroups(const rwpsf_plan* p) {
   const int tiles = (p->np / CfgAdjG::BM) * (2 * p->np / CfgAdjG::BN);
-  const int per_group = kPupilStacks * 3 * tiles;
+  const int per_group = kAdjStacks * 3 * tiles;
   return std::max(1, std::min(p->grid.nz, (1024 + per_group - 1) / per_group));
 }
 
@@ -381,7 +382,13 @@ static int adjoint_prepare(rwpsf_plan* p, int n_stacks) {
     if ((st = dev_alloc(p, &p->d_CxT, CxT.size()))) return st;
     if ((st = dev_alloc(p, &p->d_CyT, CyT.size()))) return st;
     if ((st = dev_alloc(p, &p->d_dphi, (size_t)N * N))) return st;
-    if ((st = dev_alloc(p, &p->d_H, (size_t)kPupilStacks * p->grid.nz * 3 * nxp * w))) return st;
+    if ((st = dev_alloc(p, &p->d_H, (size_t)kAdjStacks * p->grid.nz * 3 * nxp * w))) return st;
+    if (p->P_stacks < kAdjStacks) {   // base pupils of a whole adjoint group
+      float2* P = nullptr;
+      if ((st = dev_alloc(p, &P, (size_t)kAdjStacks * 3 * np * np))) return st;
+      p->d_P = P;
+      p->P_stacks = kAdjStacks;
+    }
     const size_t nzpp = (size_t)p->grid.nz * np * np;
     if ((st = dev_alloc(p, &p->d_adjD, nzpp))) return st;
     hipLaunchKernelGGL(adj_defocus_kernel, dim3((unsigned)((nzpp + 255) / 256)), dim3(256), 0, 0, p->d_ksz, p->d_z,
@@ -414,9 +421,10 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
   if (rc) return rc;
   const int nxp = p->nxp, w = 2 * p->nhp;
   const int zg = adjoint_zgroups(p);
-  for (int b0 = 0; b0 < n; b0 += kPupilStacks) {
-    const int nb = std::min(kPupilStacks, n - b0);
-    if ((rc = fourier_build_pupils(p, s + b0, nb, st))) return rc;
+  for (int b0 = 0; b0 < n; b0 += kAdjStacks) {
+    const int nb = std::min(kAdjStacks, n - b0);
+    for (int c0 = 0; c0 < nb; c0 += kPupilStacks)
+      if ((rc = fourier_build_pupils(p, s + b0 + c0, std::min(kPupilStacks, nb - c0), st, c0))) return rc;
     AdjHArgs ha{E, dLdI, p->d_CyT, p->d_H, b0, nb, nz, nx, ny, p->nyp, nxp, w};
     const int hblocks = nb * nz * 3 * (2 * nxp / CfgAdjH::BM) * (w / CfgAdjH::BN);
     int tr = p->time_begin(RWPSF_KERNEL_ADJ_H, st);

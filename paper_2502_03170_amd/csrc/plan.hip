@@ -155,12 +155,15 @@ static void fill_pupil_args(const rwpsf_plan* p, const rwpsf_stack* s, int nb, P
   pa.max_zernike = maxz;
 }
 
-// Base pupils P_{b,c} of up to 8 stacks into the plan's pupil workspace.
-int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st) {
+// Base pupils P_{b,c} of up to 8 stacks into the plan's pupil workspace, from stack slot
+// `slot` on (the workspace holds P_stacks stacks).
+int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st, int slot) {
+  if (slot < 0 || slot + nb > p->P_stacks) return RWPSF_ERR_INVALID_ARG;
   PupilArgs pa{};
   fill_pupil_args(p, s, nb, pa);
   const int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
-  const int rc = hip_check(launch_pupil_build(pa, p->d_Q, p->d_ztab, p->d_P, st));
+  float2* P = p->d_P + (size_t)slot * 3 * p->np * p->np;
+  const int rc = hip_check(launch_pupil_build(pa, p->d_Q, p->d_ztab, P, st));
   p->time_end(tr, st);
   return rc;
 }
