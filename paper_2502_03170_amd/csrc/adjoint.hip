@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(CfgAdjH::NT, 2) adj_h_kernel(AdjHArgs a) {
 struct AdjGArgs {
   const float* CxT;    // [w][nxp] rows 2jf + p: pref {cos, sin}(k s_jf x_m)
   const float2* H;     // [chunk][nz][3][nxp][w]
-  const float2* P;     // [chunk][3][np][np] base pupils (np = w)
+  const float2* Pf;    // [chunk][3][w][w] mirror-folded pupils (the forward's fold)
   const double* ksz;   // [np][np]
   const float2* D;     // [nz][np][np] exp(i k s_z z) of the plan's planes
   float* partial;      // [stacks * 3 * zgroups][np][np]
@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(CfgAdjG::NT, 3) adj_g_kernel(AdjGArgs a) {
   const int row0 = tm * Cfg::BM, col0 = tn * Cfg::BN;
   const int n = a.n, nh = (n + 1) / 2;
   const size_t npp = (size_t)a.w * a.w;
-  const float2* P = a.P + ((size_t)s * 3 + c) * npp;
+  const float2* Pf = a.Pf + ((size_t)s * 3 + c) * npp;
   // lane quad q = lane & 3 of columns 2(2lf + p) + ri: q = 2p + ri.  After the exchange the
   // lane owns mirror cell q: (jf, lf), (jf, l'), (j', lf), (j', l').
   const int q = lane & 3;
@@ -189,8 +189,17 @@ __global__ void __launch_bounds__(CfgAdjG::NT, 3) adj_g_kernel(AdjGArgs a) {
         const bool own = jf < nh && lf < nh && !((q & 2) && jc == jf) && !((q & 1) && lc == lf);
         float2 v = make_float2(0.f, 0.f);
         if (own) {
+          // the pupil at mirror (a, b) = (q / 2, q % 2) from the four parities of the
+          // folded cell: P_ab = sum_{pj, pl} (-1)^(a pj + b pl) (-i)^(pj + pl) Pf_{pj, pl},
+          // over 2 per folded axis with two mirrors (a self-mirrored row has no odd part)
+          const float2* f = Pf + (size_t)(2 * jf) * a.w + 2 * lf;
+          const float2 f00 = f[0], f01 = f[1], f10 = f[a.w], f11 = f[a.w + 1];
+          const float sb = (q & 1) ? -1.f : 1.f, sa = (q & 2) ? -1.f : 1.f;
+          const float scale = (jf != n - 1 - jf ? 0.5f : 1.f) * (lf != n - 1 - lf ? 0.5f : 1.f);
+          // (-i) (x + i y) = y - i x
+          const float2 pp = make_float2(scale * (f00.x + sb * f01.y + sa * f10.y - sa * sb * f11.x),
+                                        scale * (f00.y - sb * f01.x - sa * f10.x - sa * sb * f11.y));
           const size_t cell = (size_t)jc * a.w + lc;
-          const float2 pp = P[cell];
           float sn, cs;
           sincosf((float)reduce_2pi(a.ksz[cell] * a.zoff[s]), &sn, &cs);
           v = make_float2(pp.x * cs - pp.y * sn, pp.x * sn + pp.y * cs);
@@ -383,12 +392,8 @@ static int adjoint_prepare(rwpsf_plan* p, int n_stacks) {
     if ((st = dev_alloc(p, &p->d_CyT, CyT.size()))) return st;
     if ((st = dev_alloc(p, &p->d_dphi, (size_t)N * N))) return st;
     if ((st = dev_alloc(p, &p->d_H, (size_t)kAdjStacks * p->grid.nz * 3 * nxp * w))) return st;
-    if (p->P_stacks < kAdjStacks) {   // base pupils of a whole adjoint group
-      float2* P = nullptr;
-      if ((st = dev_alloc(p, &P, (size_t)kAdjStacks * 3 * np * np))) return st;
-      p->d_P = P;
-      p->P_stacks = kAdjStacks;
-    }
+    // folded pupils of a whole adjoint group
+    if ((st = dev_alloc(p, &p->d_adjPf, (size_t)kAdjStacks * 3 * w * w))) return st;
     const size_t nzpp = (size_t)p->grid.nz * np * np;
     if ((st = dev_alloc(p, &p->d_adjD, nzpp))) return st;
     hipLaunchKernelGGL(adj_defocus_kernel, dim3((unsigned)((nzpp + 255) / 256)), dim3(256), 0, 0, p->d_ksz, p->d_z,
@@ -424,7 +429,9 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
   for (int b0 = 0; b0 < n; b0 += kAdjStacks) {
     const int nb = std::min(kAdjStacks, n - b0);
     for (int c0 = 0; c0 < nb; c0 += kPupilStacks)
-      if ((rc = fourier_build_pupils(p, s + b0 + c0, std::min(kPupilStacks, nb - c0), st, c0))) return rc;
+      if ((rc = fourier_build_folded(p, s + b0 + c0, std::min(kPupilStacks, nb - c0),
+                                     p->d_adjPf + (size_t)c0 * 3 * w * w, st)))
+        return rc;
     AdjHArgs ha{E, dLdI, p->d_CyT, p->d_H, b0, nb, nz, nx, ny, p->nyp, nxp, w};
     const int hblocks = nb * nz * 3 * (2 * nxp / CfgAdjH::BM) * (w / CfgAdjH::BN);
     int tr = p->time_begin(RWPSF_KERNEL_ADJ_H, st);
@@ -434,7 +441,7 @@ int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E,
     AdjGArgs ga{};
     ga.CxT = p->d_CxT;
     ga.H = p->d_H;
-    ga.P = p->d_P;
+    ga.Pf = p->d_adjPf;
     ga.ksz = p->d_ksz;
     ga.D = p->d_adjD;
     ga.partial = p->d_partial;

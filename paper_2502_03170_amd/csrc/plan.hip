@@ -155,15 +155,22 @@ static void fill_pupil_args(const rwpsf_plan* p, const rwpsf_stack* s, int nb, P
   pa.max_zernike = maxz;
 }
 
-// Base pupils P_{b,c} of up to 8 stacks into the plan's pupil workspace, from stack slot
-// `slot` on (the workspace holds P_stacks stacks).
-int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st, int slot) {
-  if (slot < 0 || slot + nb > p->P_stacks) return RWPSF_ERR_INVALID_ARG;
+// Base pupils P_{b,c} of up to 8 stacks into the plan's pupil workspace.
+int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st) {
   PupilArgs pa{};
   fill_pupil_args(p, s, nb, pa);
   const int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
-  float2* P = p->d_P + (size_t)slot * 3 * p->np * p->np;
-  const int rc = hip_check(launch_pupil_build(pa, p->d_Q, p->d_ztab, P, st));
+  const int rc = hip_check(launch_pupil_build(pa, p->d_Q, p->d_ztab, p->d_P, st));
+  p->time_end(tr, st);
+  return rc;
+}
+
+// Mirror-folded pupils of up to 8 stacks into Pf ([nb][nc][2 nhp][2 nhp]).
+int fourier_build_folded(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* Pf, hipStream_t st) {
+  PupilArgs pa{};
+  fill_pupil_args(p, s, nb, pa);
+  const int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
+  const int rc = hip_check(launch_pupil_build_folded(pa, p->d_Q, p->d_ztab, Pf, p->nhp, st));
   p->time_end(tr, st);
   return rc;
 }
@@ -223,14 +230,10 @@ int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float
     const int nb = std::min(kGemmStacks, n - b0);
     int rc;
     // folded pupils of the group in launches of up to kPupilStacks, side by side
-    for (int c0 = 0; c0 < nb; c0 += kPupilStacks) {
-      PupilArgs pa{};
-      fill_pupil_args(p, s + b0 + c0, std::min(kPupilStacks, nb - c0), pa);
-      float2* Pf = p->d_Pf + (size_t)c0 * p->nc * 4 * p->nhp * p->nhp;
-      const int tr = p->time_begin(RWPSF_KERNEL_PUPIL_BUILD, st);
-      if ((rc = hip_check(launch_pupil_build_folded(pa, p->d_Q, p->d_ztab, Pf, p->nhp, st)))) return rc;
-      p->time_end(tr, st);
-    }
+    for (int c0 = 0; c0 < nb; c0 += kPupilStacks)
+      if ((rc = fourier_build_folded(p, s + b0 + c0, std::min(kPupilStacks, nb - c0),
+                                     p->d_Pf + (size_t)c0 * p->nc * 4 * p->nhp * p->nhp, st)))
+        return rc;
     double zoff[kGemmStacks];
     for (int i = 0; i < nb; ++i) zoff[i] = s[b0 + i].z_offset_nm;
     // slabs over (stack, plane): a slab is a run of planes of one or more stacks

@@ -176,6 +176,7 @@ struct rwpsf_plan {
   float* d_CxT = nullptr;       // [2 nhp][nxp] folded x table (prefactor included), pixels contiguous
   float* d_CyT = nullptr;       // [2 nhp][nyp] folded y table, pixels contiguous
   float2* d_H = nullptr;        // [32 stacks][nz][3][nxp][2 nhp] folded H
+  float2* d_adjPf = nullptr;    // [32 stacks][3][2 nhp][2 nhp] folded pupils of an adjoint group
   float* d_partial = nullptr;   // [stacks * 3][np][np] per-(stack, component) dL/dPhi
   int partial_groups = 0;
   double* d_dphi = nullptr;     // [N][N]

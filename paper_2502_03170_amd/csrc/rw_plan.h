@@ -12,7 +12,8 @@ int validate_stacks(const rwpsf_optics* o, const rwpsf_grid* g, const rwpsf_nume
                     const rwpsf_stack* s);
 int plan_init(rwpsf_plan* p, const rwpsf_optics& o, const rwpsf_grid& g, const rwpsf_numerics& nm);
 int fourier_compute(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, hipStream_t st);
-int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st, int slot = 0);
+int fourier_build_pupils(rwpsf_plan* p, const rwpsf_stack* s, int nb, hipStream_t st);
+int fourier_build_folded(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* Pf, hipStream_t st);
 int fourier_adjoint(rwpsf_plan* p, int n, const rwpsf_stack* s, const float2* E, const float* dLdI,
                     int n_zernike, float* dc, float* dW0, hipStream_t st);
 int czt_plan_init(rwpsf_plan* p);
