@@ -1,7 +1,8 @@
 // Hand-written adjoint of the Fourier form.
 //
 // Forward (per stack b, plane z, component c): E = Ax' P~ Ay^T with
-// P~ = P_{b,c} exp(i k s_z z), P_{b,c} = Q_c exp(i Phi_b) (the pupil-build kernel).
+// P~ = P_{b,c} exp(i k s_z z), P_{b,c} = Q_c exp(i Phi_b) (read from the forward's
+// mirror-folded pupils: each lane recovers its own mirror cell from the four parities).
 // For a real loss L(I), I = sum_c |E_c|^2, with g = dL/dI:
 //   dL/dPhi[j,l] = sum_{b,z,c} Im( G[j,l] conj(P~[j,l]) ),  G = Ax'^H (2 g E) conj(Ay)
 //   dL/dW0 = dL/dPhi,  dL/dc_q = 2 pi sum_cells dL/dPhi Z_q.
