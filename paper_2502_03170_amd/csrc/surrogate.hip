@@ -112,6 +112,40 @@ __global__ void __launch_bounds__(256) sg_gemm_kernel(const float* __restrict__ 
   }
 }
 
+// h1 = relu(x W1 + b1) for the 22-feature input layer, in FP32 on the vector units: with
+// K = 22 the layer is bound by writing h1, and a matrix-core tile would spend more on
+// staging and splitting than on its products.  Thread t owns columns 4t .. 4t + 3 with
+// their 22 weights in registers and walks kDense1Rows rows (x of a row is the same for
+// the whole workgroup, staged in LDS); bias first, then k in order.
+constexpr int kDense1Rows = 64;
+__global__ void __launch_bounds__(256) sg_dense1_kernel(const float* __restrict__ x, const float* __restrict__ W1,
+                                                        const float* __restrict__ b1, int B, float* __restrict__ h1) {
+  const int n = 4 * threadIdx.x;
+  float4 w[22];
+#pragma unroll
+  for (int k = 0; k < 22; ++k) w[k] = *reinterpret_cast<const float4*>(W1 + k * 1024 + n);
+  const float4 bias = make_float4(b1[n], b1[n + 1], b1[n + 2], b1[n + 3]);
+  const int r0 = blockIdx.x * kDense1Rows, r1 = min(B, r0 + kDense1Rows);
+  // the workgroup's rows of x, staged once (every lane then reads the same word: a broadcast)
+  __shared__ float xs[kDense1Rows * 22];
+  for (int i = threadIdx.x; i < (r1 - r0) * 22; i += 256) xs[i] = x[(size_t)r0 * 22 + i];
+  __syncthreads();
+  for (int m = r0; m < r1; ++m) {
+    const float* xm = xs + (m - r0) * 22;
+    float4 acc = bias;
+#pragma unroll
+    for (int k = 0; k < 22; ++k) {
+      const float xv = xm[k];
+      acc.x = fmaf(xv, w[k].x, acc.x);
+      acc.y = fmaf(xv, w[k].y, acc.y);
+      acc.z = fmaf(xv, w[k].z, acc.z);
+      acc.w = fmaf(xv, w[k].w, acc.w);
+    }
+    *reinterpret_cast<float4*>(h1 + (size_t)m * 1024 + n) =
+        make_float4(fmaxf(acc.x, 0.f), fmaxf(acc.y, 0.f), fmaxf(acc.z, 0.f), fmaxf(acc.w, 0.f));
+  }
+}
+
 template <bool TA, bool TB>
 static hipError_t sg_gemm(const float* A, int lda, const float* B, int ldb, float* C, int ldc, int M, int N,
                           int K, const float* bias, int relu, int nsplit, hipStream_t st, int accumulate = 0) {
@@ -940,9 +974,10 @@ static int sg_forward_impl(rwpsf_sg* s, int B, const float* coef, const float* z
   int rc;
   hipLaunchKernelGGL(sg_features_kernel, dim3((B * 22 + 255) / 256), dim3(256), 0, st, coef, z, B, s->x);
   if ((rc = hip_check(hipGetLastError()))) return rc;
-  // the two wide layers on the aligned fast path, with the weights split to BF16 planes
-  if ((rc = hip_check(sg_gemm<false, false>(s->x, 22, s->w + L.W1, 1024, s->h1, 1024, B, 1024, 22, s->w + L.b1, 1,
-                                            nsplit, st)))) return rc;
+  // (W1 is the first parameter block, so its rows are 16-byte aligned)
+  hipLaunchKernelGGL(sg_dense1_kernel, dim3((B + kDense1Rows - 1) / kDense1Rows), dim3(256), 0, st, s->x,
+                     s->w + L.W1, s->w + L.b1, B, s->h1);
+  if ((rc = hip_check(hipGetLastError()))) return rc;
   // the wide layers on the aligned fast path, with the weights split to BF16 planes
   __bf16* w2h = s->wsplit;
   __bf16* w2l = w2h + 1024 * 1024;
