@@ -245,8 +245,13 @@ hipError_t launch_rgemm(const float* A, int lda, const float* B, int ldb, float*
 // [re/im][NI][R] (NI = 3 integrals, or 1 for the scalar model).
 // --------------------------------------------------------------------------
 constexpr int kEpiStacks = 256;   // stacks per contraction and epilogue launch
+// Workgroups per plane in the epilogue: a call with few planes splits each plane into 4
+// runs of pixels, so that more CUs work on it (one stack: 40 -> 31-34 us per call); a call
+// with many planes keeps one workgroup per plane (4 per plane made the 256-stack call's
+// epilogue 246 -> 303 us).  The split does not change any result.
+constexpr int kEpiSplitFew = 4, kEpiFewPlanes = 1024;
 struct EpiArgs {
-  int nx, ny, nz, R, nstk, s_base, mode;
+  int nx, ny, nz, R, nstk, s_base, mode, split;   // split: workgroups per plane
   float dx, dy, inv_drho;
   float exr, exi, eyr, eyi;   // polarisation times -(i f k / 2); scalar: exr + i exi = -i f k
   float x0[kEpiStacks], y0[kEpiStacks];
@@ -257,7 +262,9 @@ __global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const f
                                                               float2* __restrict__ E,
                                                               float* __restrict__ I) {
   extern __shared__ float sh[];  // [2][NI][R]
-  const int si = blockIdx.x / a.nz, zi = blockIdx.x % a.nz;
+  // a.split workgroups per plane, each a contiguous run of its pixels
+  const int part = blockIdx.x % a.split, pl = blockIdx.x / a.split;
+  const int si = pl / a.nz, zi = pl % a.nz;
   const int R = a.R;
   const int G = a.mode == kModeFresnel ? 5 : (a.mode == kModeScalar ? 1 : 3);
   const int V = a.mode == kModeFresnel ? 2 : 1;
@@ -283,8 +290,10 @@ __global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const f
   float2* Eb = E ? E + (gs * a.nz + zi) * NI * plane : nullptr;
   float* Ib = I ? I + (gs * a.nz + zi) * plane : nullptr;
   const float x0 = a.x0[si], y0 = a.y0[si];
+  const int run = ((int)plane + a.split - 1) / a.split;
+  const int pbeg = part * run, pend = min((int)plane, pbeg + run);
   if (a.mode == kModeScalar) {
-    for (int pix = threadIdx.x; pix < (int)plane; pix += blockDim.x) {
+    for (int pix = pbeg + threadIdx.x; pix < pend; pix += blockDim.x) {
       const int i = pix / a.ny, j = pix % a.ny;
       const float x = (float)(i - a.nx / 2) * a.dx - x0;
       const float y = (float)(j - a.ny / 2) * a.dy - y0;
@@ -304,7 +313,7 @@ __global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const f
     }
     return;
   }
-  for (int pix = threadIdx.x; pix < (int)plane; pix += blockDim.x) {
+  for (int pix = pbeg + threadIdx.x; pix < pend; pix += blockDim.x) {
     const int i = pix / a.ny, j = pix % a.ny;
     const float x = (float)(i - a.nx / 2) * a.dx - x0;
     const float y = (float)(j - a.ny / 2) * a.dy - y0;
@@ -573,7 +582,8 @@ static int bessel_compute_ws(rwpsf_plan* p, int n, const rwpsf_stack* s, float2*
       ea.y0[i] = (float)s[b0 + i].y0_nm;
     }
     tr = p->time_begin(RWPSF_KERNEL_BESSEL_EPILOGUE, st);
-    hipLaunchKernelGGL(bessel_epilogue_kernel, dim3(nb * nz), dim3(256), 6 * R * sizeof(float), st, ea,
+    ea.split = nb * nz < kEpiFewPlanes ? kEpiSplitFew : 1;
+    hipLaunchKernelGGL(bessel_epilogue_kernel, dim3(nb * nz * ea.split), dim3(256), 6 * R * sizeof(float), st, ea,
                        (const float*)In, E, I);
     if ((rc = hip_check(hipGetLastError()))) return rc;
     p->time_end(tr, st);
