@@ -176,7 +176,7 @@ int fourier_build_folded(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* Pf
 }
 
 // --------------------------------------------------------------------------
-// Fourier dispatch: chunks of up to 16 stacks (folded pupils in launches of 8), then
+// Fourier dispatch: chunks of up to 64 stacks (folded pupils in launches of 8), then
 // slabs of stack-planes through the two GEMM kernels.
 // --------------------------------------------------------------------------
 static int fourier_gemms(rwpsf_plan* p, int s_local, int ns, const double* zoff, int s_global, int z0, int nzs,

@@ -51,6 +51,33 @@ def test_fourier_small_all_corrections(lib, n_pupil, nx, ny):
         assert rel_l2(_np(I[b]), OF.intensity(ref)) < TOL
 
 
+def test_fourier_many_stacks_span_chunks(lib):
+    """70 stacks in one call: more than one chunk of the stacks-per-launch limit and more
+    than one pupil launch per chunk; sampled stacks against the oracle, and each stack's
+    intensity against the same stack computed alone."""
+    import torch
+    rw = lib
+    w = W.fourier_plain(n_stacks=1, seed=13)
+    zp = np.linspace(-500.0, 500.0, 3)
+    plan = _fourier_plan(rw, w, 32, 24, 24, 40.0, zp, gl=False)
+    rng = np.random.default_rng(14)
+    coef = rng.normal(0.0, 0.05, (70, 21))
+    stacks = [dict(zernike=coef[b], x0=float(rng.uniform(-30, 30)), z_offset=float(rng.uniform(-100, 100)))
+              for b in range(70)]
+    E, I = plan.compute(stacks)
+    torch.cuda.synchronize()
+    opt = oracle_optics(w, gl=False)
+    for b in (0, 7, 8, 63, 64, 69):
+        ref = oracle_fourier_stack(opt, 32, 24, 24, 40.0, 40.0, zp + stacks[b]["z_offset"], zernike=coef[b],
+                                   x0=stacks[b]["x0"])
+        assert rel_l2(_np(E[b]), ref) < TOL, b
+        assert rel_l2(_np(I[b]), OF.intensity(ref)) < TOL, b
+    for b in (5, 66):
+        _, I1 = plan.compute([stacks[b]], fields=False)
+        torch.cuda.synchronize()
+        assert rel_l2(_np(I1[0]), _np(I[b])) < 1e-6, b
+
+
 def test_fourier_outputs_optional_and_single_plane(lib):
     import torch
     rw = lib
