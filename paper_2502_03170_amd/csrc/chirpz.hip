@@ -153,6 +153,62 @@ __device__ __forceinline__ void fft(float2* buf, int lane) {
   if (rem == 2) fft_pass<2, L>(buf, Ns, lane);
 }
 
+// The convolution of one row or column for L = 512 = 8^3 with the values in registers
+// between the two transforms.  Lane j holds x[j + 64 r], r = 0..7, which is what the
+// first radix-8 pass of the Stockham transform reads (butterfly j takes j + r L / 8) and,
+// with one butterfly per lane, also what the last pass writes (d + r Ns = j + 64 r).  So
+// the first pass starts from registers, the spectrum product and the conjugation of the
+// inverse transform happen in registers, the second transform starts from them too, and
+// its last pass leaves y[j + 64 r] in registers: 4 LDS round trips per pair instead of 8,
+// plus the fill and read-back of the buffer.  v: in x (already multiplied by the pre-chirp),
+// out conj(FFT(conj(FFT(x) ch))) where ch = the lane's chat values.
+__device__ __forceinline__ void czt_pass_first512(float2* buf, float2 (&v)[8], int lane) {
+  dft_small<8>(v);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) buf[pidx(8 * lane + r)] = v[r];
+  wave_lds_order();
+}
+template <int NS>
+__device__ __forceinline__ void czt_pass_mid512(float2* buf, int lane) {
+  float2 v[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = buf[pidx(lane + 64 * r)];
+  wave_lds_order();
+  const int k = lane % NS;
+  float2 w[8];
+  twiddles_pow<8, 512>(k * (512 / (NS * 8)), w);
+#pragma unroll
+  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], w[r]);
+  dft_small<8>(v);
+  const int d = (lane / NS) * NS * 8 + k;
+#pragma unroll
+  for (int r = 0; r < 8; ++r) buf[pidx(d + r * NS)] = v[r];
+  wave_lds_order();
+}
+__device__ __forceinline__ void czt_pass_last512(float2* buf, float2 (&v)[8], int lane) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) v[r] = buf[pidx(lane + 64 * r)];
+  wave_lds_order();
+  float2 w[8];
+  twiddles_pow<8, 512>(lane, w);   // Ns = 64: k = lane, step 1
+#pragma unroll
+  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], w[r]);
+  dft_small<8>(v);                 // output j + 64 r
+}
+__device__ __forceinline__ void czt_pair512(float2* buf, float2 (&v)[8], const float2 (&ch)[8], int lane) {
+  czt_pass_first512(buf, v, lane);
+  czt_pass_mid512<8>(buf, lane);
+  czt_pass_last512(buf, v, lane);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const float2 t = cmul(v[r], ch[r]);
+    v[r] = make_float2(t.x, -t.y);
+  }
+  czt_pass_first512(buf, v, lane);
+  czt_pass_mid512<8>(buf, lane);
+  czt_pass_last512(buf, v, lane);
+}
+
 struct CztRowArgs {
   const float2* P;       // [nstk][nc][np][np] base pupils
   const double* ksz;     // [np][np]
@@ -191,6 +247,30 @@ __global__ void __launch_bounds__(256) czt_rows_kernel(CztRowArgs a) {
       sincos_rev(a.ksz[(size_t)j * a.np + l] * zrev, &sn, &cs);
       dz[t] = cmul(make_float2(cs, sn), a.pre[l]);
     }
+  }
+  if constexpr (L == 512) {
+    float2 ch[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) ch[r] = a.chat[lane + 64 * r];
+    for (int c = 0; c < a.nc; ++c) {
+      const float2* Pr = a.P + ((size_t)s * a.nc + c) * npp + (size_t)(live ? j : 0) * a.np;
+      float2 v[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int l = lane + 64 * r;
+        v[r] = (live && l < a.n) ? cmul(Pr[l], dz[r]) : make_float2(0.f, 0.f);
+      }
+      czt_pair512(buf, v, ch, lane);
+      if (live) {
+        float2* Tr = a.T + (((size_t)s * a.nzs + zi) * a.nc + c) * (size_t)a.n * a.ny + (size_t)j * a.ny;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int n = lane + 64 * r;
+          if (n < a.ny) Tr[n] = cmul(make_float2(v[r].x, -v[r].y), a.post[n]);
+        }
+      }
+    }
+    return;
   }
   for (int c = 0; c < a.nc; ++c) {
     const float2* Pr = a.P + ((size_t)s * a.nc + c) * npp + (size_t)(live ? j : 0) * a.np;
@@ -254,6 +334,26 @@ __global__ void __launch_bounds__(256) czt_cols_kernel(CztColArgs a) {
       stage[cc * a.n + j] = (n0 + cc < a.ny) ? Tc[(size_t)j * a.ny + n0 + cc] : make_float2(0.f, 0.f);
     }
     __syncthreads();
+    if constexpr (L == 512) {
+      float2 ch[8];
+#pragma unroll
+      for (int r = 0; r < 8; ++r) ch[r] = a.chat[lane + 64 * r];
+      for (int q = 0; q < CB / 4; ++q) {
+        const int cc = 4 * q + wave;
+        float2 v[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int j = lane + 64 * r;
+          v[r] = j < a.n ? cmul(stage[cc * a.n + j], a.pre[j]) : make_float2(0.f, 0.f);
+        }
+        czt_pair512(buf, v, ch, lane);
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const int m = lane + 64 * r;
+          if (m < a.nx) outs[cc * a.nx + m] = cmul(make_float2(v[r].x, -v[r].y), a.post[m]);
+        }
+      }
+    } else
     for (int r = 0; r < CB / 4; ++r) {
       const int cc = 4 * r + wave;
       for (int j = lane; j < L; j += 64)
