@@ -153,60 +153,81 @@ __device__ __forceinline__ void fft(float2* buf, int lane) {
   if (rem == 2) fft_pass<2, L>(buf, Ns, lane);
 }
 
-// The convolution of one row or column for L = 512 = 8^3 with the values in registers
-// between the two transforms.  Lane j holds x[j + 64 r], r = 0..7, which is what the
-// first radix-8 pass of the Stockham transform reads (butterfly j takes j + r L / 8) and,
-// with one butterfly per lane, also what the last pass writes (d + r Ns = j + 64 r).  So
-// the first pass starts from registers, the spectrum product and the conjugation of the
-// inverse transform happen in registers, the second transform starts from them too, and
-// its last pass leaves y[j + 64 r] in registers: 4 LDS round trips per pair instead of 8,
-// plus the fill and read-back of the buffer.  v: in x (already multiplied by the pre-chirp),
-// out conj(FFT(conj(FFT(x) ch))) where ch = the lane's chat values.
-__device__ __forceinline__ void czt_pass_first512(float2* buf, float2 (&v)[8], int lane) {
-  dft_small<8>(v);
+// The convolution of one row or column for L = 512 . 2^e (e = 0, 1, 2: radix-8 passes
+// at Ns = 1, 8, 64, then for 1024 and 2048 one radix-2 or radix-4 pass at Ns = 512) with
+// the values in registers between the two transforms.  Lane j holds x[j + 64 u],
+// u = 0 .. L/64 - 1: the first pass's butterfly j + 64 t reads exactly these
+// (u = t + r L/512), and the last pass's butterfly j + 64 t writes them (d = j + 64 t,
+// outputs d + r Ns, so u = t + r Ns/64).  The first pass therefore starts from registers,
+// the last leaves its outputs in them, and the spectrum product and the conjugation of
+// the inverse transform happen in registers: 2 LDS round trips fewer per transform, and
+// no fill or read-back of the buffer.
+template <int L>
+constexpr int czt_reg_last_radix() { return L == 512 ? 8 : (L == 1024 ? 2 : 4); }
+template <int L>
+constexpr bool czt_reg_ok() { return L == 512 || L == 1024 || L == 2048; }
+
+template <int L>
+__device__ __forceinline__ void czt_first_reg(float2* buf, float2 (&v)[L / 64], int lane) {
+  constexpr int T1 = L / 8 / 64;
 #pragma unroll
-  for (int r = 0; r < 8; ++r) buf[pidx(8 * lane + r)] = v[r];
-  wave_lds_order();
-}
-template <int NS>
-__device__ __forceinline__ void czt_pass_mid512(float2* buf, int lane) {
-  float2 v[8];
+  for (int t = 0; t < T1; ++t) {
+    float2 b[8];
 #pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = buf[pidx(lane + 64 * r)];
-  wave_lds_order();
-  const int k = lane % NS;
-  float2 w[8];
-  twiddles_pow<8, 512>(k * (512 / (NS * 8)), w);
+    for (int r = 0; r < 8; ++r) b[r] = v[t + r * T1];
+    dft_small<8>(b);
+    const int j = lane + 64 * t;
 #pragma unroll
-  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], w[r]);
-  dft_small<8>(v);
-  const int d = (lane / NS) * NS * 8 + k;
-#pragma unroll
-  for (int r = 0; r < 8; ++r) buf[pidx(d + r * NS)] = v[r];
-  wave_lds_order();
-}
-__device__ __forceinline__ void czt_pass_last512(float2* buf, float2 (&v)[8], int lane) {
-#pragma unroll
-  for (int r = 0; r < 8; ++r) v[r] = buf[pidx(lane + 64 * r)];
-  wave_lds_order();
-  float2 w[8];
-  twiddles_pow<8, 512>(lane, w);   // Ns = 64: k = lane, step 1
-#pragma unroll
-  for (int r = 1; r < 8; ++r) v[r] = cmul(v[r], w[r]);
-  dft_small<8>(v);                 // output j + 64 r
-}
-__device__ __forceinline__ void czt_pair512(float2* buf, float2 (&v)[8], const float2 (&ch)[8], int lane) {
-  czt_pass_first512(buf, v, lane);
-  czt_pass_mid512<8>(buf, lane);
-  czt_pass_last512(buf, v, lane);
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    const float2 t = cmul(v[r], ch[r]);
-    v[r] = make_float2(t.x, -t.y);
+    for (int r = 0; r < 8; ++r) buf[pidx(8 * j + r)] = b[r];
   }
-  czt_pass_first512(buf, v, lane);
-  czt_pass_mid512<8>(buf, lane);
-  czt_pass_last512(buf, v, lane);
+  wave_lds_order();
+}
+template <int L>
+__device__ __forceinline__ void czt_last_reg(float2* buf, float2 (&v)[L / 64], int lane) {
+  constexpr int R = czt_reg_last_radix<L>(), NS = L / R, T2 = NS / 64;
+#pragma unroll
+  for (int t = 0; t < T2; ++t)
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[t + r * T2] = buf[pidx(lane + 64 * t + r * NS)];
+  wave_lds_order();
+#pragma unroll
+  for (int t = 0; t < T2; ++t) {
+    float2 b[R], w[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) b[r] = v[t + r * T2];
+    twiddles_pow<R, L>(lane + 64 * t, w);   // k = j, step 1
+#pragma unroll
+    for (int r = 1; r < R; ++r) b[r] = cmul(b[r], w[r]);
+    dft_small<R>(b);
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[t + r * T2] = b[r];
+  }
+}
+template <int L>
+__device__ __forceinline__ void czt_fft_reg(float2* buf, float2 (&v)[L / 64], int lane) {
+  czt_first_reg<L>(buf, v, lane);
+  fft_pass<8, L>(buf, 8, lane);
+  if (L > 512) fft_pass<8, L>(buf, 64, lane);
+  czt_last_reg<L>(buf, v, lane);
+}
+// v: in x (already multiplied by the pre-chirp), out conj(FFT(conj(FFT(x) chat)))
+template <int L>
+__device__ __forceinline__ void czt_pair_reg(float2* buf, float2 (&v)[L / 64], const float2* __restrict__ chat,
+                                             int lane) {
+  // at L = 512 the lane's spectrum factors are requested before the first transform (16
+  // registers); the longer transforms have no registers to spare and read them after it
+  constexpr int CH = L == 512 ? L / 64 : 1;
+  float2 ch[CH];
+  if constexpr (L == 512)
+#pragma unroll
+    for (int u = 0; u < CH; ++u) ch[u] = chat[lane + 64 * u];
+  czt_fft_reg<L>(buf, v, lane);
+#pragma unroll
+  for (int u = 0; u < L / 64; ++u) {
+    const float2 t = cmul(v[u], L == 512 ? ch[u % CH] : chat[lane + 64 * u]);
+    v[u] = make_float2(t.x, -t.y);
+  }
+  czt_fft_reg<L>(buf, v, lane);
 }
 
 struct CztRowArgs {
@@ -248,25 +269,22 @@ __global__ void __launch_bounds__(256) czt_rows_kernel(CztRowArgs a) {
       dz[t] = cmul(make_float2(cs, sn), a.pre[l]);
     }
   }
-  if constexpr (L == 512) {
-    float2 ch[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) ch[r] = a.chat[lane + 64 * r];
+  if constexpr (czt_reg_ok<L>()) {
     for (int c = 0; c < a.nc; ++c) {
       const float2* Pr = a.P + ((size_t)s * a.nc + c) * npp + (size_t)(live ? j : 0) * a.np;
-      float2 v[8];
+      float2 v[MAXT];
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int l = lane + 64 * r;
-        v[r] = (live && l < a.n) ? cmul(Pr[l], dz[r]) : make_float2(0.f, 0.f);
+      for (int u = 0; u < MAXT; ++u) {
+        const int l = lane + 64 * u;
+        v[u] = (live && l < a.n) ? cmul(Pr[l], dz[u]) : make_float2(0.f, 0.f);
       }
-      czt_pair512(buf, v, ch, lane);
+      czt_pair_reg<L>(buf, v, a.chat, lane);
       if (live) {
         float2* Tr = a.T + (((size_t)s * a.nzs + zi) * a.nc + c) * (size_t)a.n * a.ny + (size_t)j * a.ny;
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int n = lane + 64 * r;
-          if (n < a.ny) Tr[n] = cmul(make_float2(v[r].x, -v[r].y), a.post[n]);
+        for (int u = 0; u < MAXT; ++u) {
+          const int n = lane + 64 * u;
+          if (n < a.ny) Tr[n] = cmul(make_float2(v[u].x, -v[u].y), a.post[n]);
         }
       }
     }
@@ -334,23 +352,21 @@ __global__ void __launch_bounds__(256) czt_cols_kernel(CztColArgs a) {
       stage[cc * a.n + j] = (n0 + cc < a.ny) ? Tc[(size_t)j * a.ny + n0 + cc] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    if constexpr (L == 512) {
-      float2 ch[8];
-#pragma unroll
-      for (int r = 0; r < 8; ++r) ch[r] = a.chat[lane + 64 * r];
+    if constexpr (czt_reg_ok<L>()) {
+      constexpr int U = L / 64;
       for (int q = 0; q < CB / 4; ++q) {
         const int cc = 4 * q + wave;
-        float2 v[8];
+        float2 v[U];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int j = lane + 64 * r;
-          v[r] = j < a.n ? cmul(stage[cc * a.n + j], a.pre[j]) : make_float2(0.f, 0.f);
+        for (int u = 0; u < U; ++u) {
+          const int j = lane + 64 * u;
+          v[u] = j < a.n ? cmul(stage[cc * a.n + j], a.pre[j]) : make_float2(0.f, 0.f);
         }
-        czt_pair512(buf, v, ch, lane);
+        czt_pair_reg<L>(buf, v, a.chat, lane);
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          const int m = lane + 64 * r;
-          if (m < a.nx) outs[cc * a.nx + m] = cmul(make_float2(v[r].x, -v[r].y), a.post[m]);
+        for (int u = 0; u < U; ++u) {
+          const int m = lane + 64 * u;
+          if (m < a.nx) outs[cc * a.nx + m] = cmul(make_float2(v[u].x, -v[u].y), a.post[m]);
         }
       }
     } else
