@@ -381,6 +381,7 @@ enum rwpsf_kernel_id {
   RWPSF_KERNEL_ADJB_RADIAL = 11,      /* Bessel adjoint: pixels -> radial samples (transposed interpolation) */
   RWPSF_KERNEL_ADJB_CONTRACT = 12,    /* Bessel adjoint: transposed theta contraction on the matrix cores */
   RWPSF_KERNEL_ADJB_REDUCE = 13,      /* Bessel adjoint: fixed-order reductions to the parameter gradients */
+  RWPSF_KERNEL_BESSEL_FUSED = 14,     /* Bessel, calls of few planes: phase, contraction and epilogue in one launch */
   RWPSF_KERNEL_COUNT = 16
 };
 int rwpsf_plan_set_timing(rwpsf_plan* plan, int enable);   /* also resets the totals */

@@ -46,6 +46,7 @@ KERNEL_CZT_COLS = 10
 KERNEL_ADJB_RADIAL = 11
 KERNEL_ADJB_CONTRACT = 12
 KERNEL_ADJB_REDUCE = 13
+KERNEL_BESSEL_FUSED = 14
 ERR_SCRATCH_LIMIT = -7
 NOALLOC_SCRATCH_BYTES = 16 << 20
 MAX_ZERNIKE = 36

@@ -22,6 +22,8 @@
 //                                       (real GEMM on MFMA, re/im as two rows)
 //          radial epilogue: the I_n from the (v, g) products, 4-point Lagrange in rho
 //          (parity ghosts I_n(-rho) = (-1)^n I_n(rho)), angular combination, |E|^2.
+//          A single stack of few planes runs all three steps in one launch, one
+//          workgroup per radial band of a plane.
 // Modes (groups g: order n_g, weight h_g; variants v: factor u_v):
 //   vectorial       g = (J0, sin t (1 + cos t)), (J1, sin^2 t), (J2, sin t (cos t - 1)); u = 1
 //   with Fresnel    g = (J0, sin t), (J0, sin t cos t), (J1, sin^2 t), (J2, sin t cos t),
@@ -88,12 +90,47 @@ struct PhiStack {
   double coef[kAxiTerms];
 };
 constexpr int kPhiStacks = 64;
-struct PhiArgs {
+template <int NS>
+struct PhiArgsT {
   int T, nz, nstk, V, max_zernike, gibson_lanni, apod, extra_sz;   // V: variants per column
   double k, s_max, s_env;
   GLParams gl;
-  PhiStack s[kPhiStacks];
+  PhiStack s[NS];
 };
+using PhiArgs = PhiArgsT<kPhiStacks>;
+
+// The plane-independent part of the pupil of stack `st` at node angle t: the amplitude
+// m = apodization x envelope x extra s_z x exp(-Im W) and the real phase W (Gibson-Lanni
+// and the axisymmetric Zernike terms), FP64 transcendentals.
+template <class A>
+__device__ __forceinline__ void phi_node(const A& a, const PhiStack& st, double sin_t, double cos_t, float* m,
+                                         double* w) {
+  double amp = 1.0;
+  if (a.apod) amp *= sqrt(cos_t);
+  if (a.s_env > 0.0) amp *= exp(-(sin_t * sin_t) / (a.s_env * a.s_env));
+  if (a.extra_sz) amp *= cos_t;
+  double w_re = 0.0, w_im = 0.0;
+  if (a.gibson_lanni) gl_opd(a.gl, st.t_s, sin_t, &w_re, &w_im);
+  const double r = sin_t / a.s_max;
+  for (int j = 0; j < kAxiTerms; ++j)
+    if (st.coef[j] != 0.0) w_re += kTwoPi * st.coef[j] * zernike_noll(kAxiNoll[j], r, 1.0, 0.0);
+  *m = (float)(amp * exp(-w_im));
+  *w = w_re;
+}
+
+// Phi of one node and plane: the pupil times the defocus exp(i k z cos t) (FP64 phase,
+// reduced before the FP32 sine and cosine), times q_s and q_p when V = 2.
+__device__ __forceinline__ void phi_plane(float m, double ph, int V, const float* qsp, float2* out) {
+  float sn, cs;
+  sincosf((float)reduce_2pi(ph), &sn, &cs);
+  const float pr = m * cs, pi = m * sn;
+  if (V == 1) {
+    out[0] = make_float2(pr, pi);
+  } else {
+    out[0] = make_float2(pr * qsp[0] - pi * qsp[1], pr * qsp[1] + pi * qsp[0]);
+    out[1] = make_float2(pr * qsp[2] - pi * qsp[3], pr * qsp[3] + pi * qsp[2]);
+  }
+}
 
 // fq: per node (Re q_s, Im q_s, Re q_p, Im q_p) when V = 2.  One thread per (node,
 // stack, group of kPhiZ planes): the plane-independent part (apodization, envelope,
@@ -113,38 +150,16 @@ __global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
   const PhiStack& st = a.s[si];
   const double t = theta[q];
   const double sin_t = sin(t), cos_t = cos(t);
-  double amp = 1.0;
-  if (a.apod) amp *= sqrt(cos_t);
-  if (a.s_env > 0.0) amp *= exp(-(sin_t * sin_t) / (a.s_env * a.s_env));
-  if (a.extra_sz) amp *= cos_t;
-  double w_re = 0.0, w_im = 0.0;
-  if (a.gibson_lanni) gl_opd(a.gl, st.t_s, sin_t, &w_re, &w_im);
-  const double r = sin_t / a.s_max;
-  for (int j = 0; j < kAxiTerms; ++j)
-    if (st.coef[j] != 0.0) w_re += kTwoPi * st.coef[j] * zernike_noll(kAxiNoll[j], r, 1.0, 0.0);
-  const float m = (float)(amp * exp(-w_im));
+  float m;
+  double w_re;
+  phi_node(a, st, sin_t, cos_t, &m, &w_re);
   const double kc = a.k * cos_t;
-  float qsr = 0.f, qsi = 0.f, qpr = 0.f, qpi = 0.f;
-  if (a.V == 2) {
-    qsr = (float)fq[4 * q];
-    qsi = (float)fq[4 * q + 1];
-    qpr = (float)fq[4 * q + 2];
-    qpi = (float)fq[4 * q + 3];
-  }
+  float qsp[4] = {0.f, 0.f, 0.f, 0.f};
+  if (a.V == 2)
+    for (int i = 0; i < 4; ++i) qsp[i] = (float)fq[4 * q + i];
   const int z1 = min(z0 + kPhiZ, a.nz);
   float2* out = phi + (size_t)q * ld + ((size_t)si * a.nz + z0) * a.V;
-  for (int zi = z0; zi < z1; ++zi, out += a.V) {
-    const double ph = w_re + kc * (z[zi] + st.zoff);
-    float sn, cs;
-    sincosf((float)reduce_2pi(ph), &sn, &cs);
-    const float pr = m * cs, pi = m * sn;
-    if (a.V == 1) {
-      out[0] = make_float2(pr, pi);
-    } else {
-      out[0] = make_float2(pr * qsr - pi * qsi, pr * qsi + pi * qsr);
-      out[1] = make_float2(pr * qpr - pi * qpi, pr * qpi + pi * qpr);
-    }
-  }
+  for (int zi = z0; zi < z1; ++zi, out += a.V) phi_plane(m, w_re + kc * (z[zi] + st.zoff), a.V, qsp, out);
 }
 
 // --------------------------------------------------------------------------
@@ -373,8 +388,234 @@ __global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const f
 }
 
 // --------------------------------------------------------------------------
+// Calls of one stack: phase, contraction and radial epilogue in one launch.  With a few
+// dozen planes the three-launch path is bound by its launch boundaries (the contraction
+// GEMM then has a dozen workgroups, each walking the whole theta range), so here one
+// workgroup serves one radial band of one plane.  It forms Phi of its plane on every
+// node into LDS, contracts it with the Bessel-table columns of the radial samples its
+// pixels' stencils reach (vector FMAs; the node range split between thread groups, eight
+// table loads in flight per thread, the partial sums added in a fixed order), then walks
+// the plane and writes the pixels whose stencil base sample r0 lies in the band.  The
+// host sets the band edges so that the bands cost about the same (contraction samples
+// against pixels).
+// --------------------------------------------------------------------------
+// Measured on the 65 x 65 x 33 stack: one stack 29.9 -> 21.7 us per call; two stacks
+// 30.9 us either way, three or more slower than the three launches, so only a single
+// stack of at most 64 planes takes this path (at least 8 bands per plane).
+constexpr int kFusedStacks = 1;      // a call of at most this many stacks ...
+constexpr int kFusedPlanes = 64;     // ... and planes takes the fused path
+constexpr int kFusedBands = 64;      // bands per plane, at most
+constexpr int kFusedLdsBytes = 64 * 1024;
+struct FusedArgs {
+  PhiArgsT<kFusedStacks> phi;
+  int nx, ny, R, P;   // P: bands per plane
+  float dx, dy, inv_drho;
+  float exr, exi, eyr, eyi;
+  float x0[kFusedStacks], y0[kFusedStacks];
+  int edge[kFusedBands + 1];   // band b: pixels with r0 in [edge[b], edge[b + 1])
+};
+static_assert(sizeof(FusedArgs) <= 4000, "kernel arguments are passed by value (4 KB limit)");
+
+template <int MODE>
+struct FusedTerms {
+  static constexpr int NI = MODE == kModeScalar ? 1 : 3;
+  static constexpr int G = MODE == kModeFresnel ? 5 : (MODE == kModeScalar ? 1 : 3);
+  static constexpr int V = MODE == kModeFresnel ? 2 : 1;
+};
+
+// LDS floats of one fused workgroup: Phi [T][V] complex, partial sums [2][max(256,
+// items)], the band's integrals [2][items] (items = NI x samples).
+__host__ __device__ inline int fused_lds_floats(int T, int V, int items) {
+  return 2 * T * V + 2 * (items > 256 ? items : 256) + 2 * items;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(256) bessel_fused_kernel(FusedArgs a, const double* __restrict__ theta,
+                                                           const double* __restrict__ z,
+                                                           const double* __restrict__ fq,
+                                                           const float* __restrict__ btab,
+                                                           float2* __restrict__ E, float* __restrict__ I) {
+  using FT = FusedTerms<MODE>;
+  constexpr int NI = FT::NI, G = FT::G, V = FT::V;
+  extern __shared__ float sh[];
+  const int tid = threadIdx.x;
+  const int band = blockIdx.x % a.P, pl = blockIdx.x / a.P;
+  const int nz = a.phi.nz, T = a.phi.T, R = a.R;
+  const int si = pl / nz, zi = pl % nz;
+  const PhiStack& st = a.phi.s[si];
+  // ---- Phi of this plane on every node
+  float2* ph = reinterpret_cast<float2*>(sh);
+  for (int q = tid; q < T; q += 256) {
+    const double t = theta[q];
+    const double sin_t = sin(t), cos_t = cos(t);
+    float m;
+    double w;
+    phi_node(a.phi, st, sin_t, cos_t, &m, &w);
+    float qsp[4] = {0.f, 0.f, 0.f, 0.f};
+    if (V == 2)
+      for (int k = 0; k < 4; ++k) qsp[k] = (float)fq[4 * q + k];
+    phi_plane(m, w + a.phi.k * cos_t * (z[zi] + st.zoff), V, qsp, ph + (size_t)q * V);
+  }
+  // ---- the band's radial samples: stencils r0 - 1 .. r0 + 2 of r0 in [e0, e1); the
+  // ghost of r0 = 0 reads sample 1, which the band then holds (e1 >= 1)
+  const int e0 = a.edge[band], e1 = a.edge[band + 1];
+  const int ra = max(e0 - 1, 0), rb = min(e1 + 2, R);
+  const int ns = rb - ra, items = NI * ns;
+  const int stride = max(256, items);
+  float* part = sh + 2 * T * V;
+  float* inl = part + 2 * stride;   // [re/im][NI][ns]
+  __syncthreads();
+  const int groups = items >= 256 ? 1 : 256 / items;
+  for (int u = tid; u < items * groups; u += 256) {
+    const int g = u / items, it = u % items;
+    const int n = it / ns, r = ra + it % ns;
+    const int q0 = (int)((long long)g * T / groups), q1 = (int)((long long)(g + 1) * T / groups);
+    // I_n = [v1, table group g1] + sg2 [v2, g2]; with Fresnel factors I_0 = [s, 0] +
+    // [p, 1], I_1 = [p, 2], I_2 = [p, 3] - [s, 4], otherwise I_n = [0, n]
+    int v1 = 0, o1 = n * R, v2 = 0, o2 = 0;
+    float sg2 = 0.f;
+    if (MODE == kModeFresnel) {
+      v1 = n == 0 ? 0 : 1;
+      o1 = (n == 0 ? 0 : n + 1) * R;
+      v2 = n == 0 ? 1 : 0;
+      o2 = (n == 0 ? 1 : 4) * R;
+      sg2 = n == 0 ? 1.f : (n == 2 ? -1.f : 0.f);
+    }
+    float sr = 0.f, si_ = 0.f;
+    const float* bcol = btab + r;
+    for (int q = q0; q < q1; q += 8) {
+      float b1[8], b2[8];
+#pragma unroll
+      for (int u8 = 0; u8 < 8; ++u8) {
+        const size_t row = (size_t)min(q + u8, q1 - 1) * G * R;
+        b1[u8] = bcol[row + o1];
+        b2[u8] = MODE == kModeFresnel ? bcol[row + o2] : 0.f;
+      }
+#pragma unroll
+      for (int u8 = 0; u8 < 8; ++u8) {
+        if (q + u8 < q1) {
+          const float2* pq = ph + (size_t)(q + u8) * V;
+          const float2 p1 = pq[v1];
+          sr += p1.x * b1[u8];
+          si_ += p1.y * b1[u8];
+          if (MODE == kModeFresnel) {
+            const float2 p2 = pq[v2];
+            sr += sg2 * (p2.x * b2[u8]);
+            si_ += sg2 * (p2.y * b2[u8]);
+          }
+        }
+      }
+    }
+    part[g * items + it] = sr;
+    part[stride + g * items + it] = si_;
+  }
+  __syncthreads();
+  for (int it = tid; it < items; it += 256) {
+    float sr = 0.f, si_ = 0.f;
+    for (int g = 0; g < groups; ++g) {
+      sr += part[g * items + it];
+      si_ += part[stride + g * items + it];
+    }
+    inl[it] = sr;
+    inl[items + it] = si_;
+  }
+  // ---- the band's pixels (same interpolation and angular combination as the epilogue
+  // kernel, samples indexed from ra)
+  const float* re = inl - ra;
+  const float* im = inl + items - ra;
+  const int plane = a.nx * a.ny;
+  const size_t gp = (size_t)si * nz + zi;
+  float2* Eb = E ? E + gp * NI * plane : nullptr;
+  float* Ib = I ? I + gp * plane : nullptr;
+  const float x0 = a.x0[si], y0 = a.y0[si];
+  __syncthreads();
+  for (int pix = tid; pix < plane; pix += 256) {
+    const int i = pix / a.ny, j = pix % a.ny;
+    const float x = (float)(i - a.nx / 2) * a.dx - x0;
+    const float y = (float)(j - a.ny / 2) * a.dy - y0;
+    const float rho = sqrtf(x * x + y * y);
+    const float t = rho * a.inv_drho;
+    const int r0 = min((int)t, R - 3);
+    if (r0 < e0 || r0 >= e1) continue;
+    const float f = t - (float)r0;
+    const float wm = -f * (f - 1.f) * (f - 2.f) * (1.f / 6.f);
+    const float w0 = (f + 1.f) * (f - 1.f) * (f - 2.f) * 0.5f;
+    const float w1 = -(f + 1.f) * f * (f - 2.f) * 0.5f;
+    const float w2 = (f + 1.f) * f * (f - 1.f) * (1.f / 6.f);
+    if (MODE == kModeScalar) {
+      const int rm = r0 == 0 ? 1 : r0 - 1;   // I_0 is even in rho
+      const float vr = wm * re[rm] + w0 * re[r0] + w1 * re[r0 + 1] + w2 * re[r0 + 2];
+      const float vi = wm * im[rm] + w0 * im[r0] + w1 * im[r0 + 1] + w2 * im[r0 + 2];
+      const float er = a.exr * vr - a.exi * vi, ei = a.exr * vi + a.exi * vr;
+      if (Eb) Eb[pix] = make_float2(er, ei);
+      if (Ib) Ib[pix] = er * er + ei * ei;
+      continue;
+    }
+    float vr[3], vi[3];
+#pragma unroll
+    for (int n = 0; n < 3; ++n) {
+      const float* pr = re + n * ns;
+      const float* pi = im + n * ns;
+      float gr, gi;
+      if (r0 == 0) {  // ghost at -drho: I_n(-rho) = (-1)^n I_n(rho)
+        const float sg = (n == 1) ? -1.f : 1.f;
+        gr = sg * pr[1];
+        gi = sg * pi[1];
+      } else {
+        gr = pr[r0 - 1];
+        gi = pi[r0 - 1];
+      }
+      vr[n] = wm * gr + w0 * pr[r0] + w1 * pr[r0 + 1] + w2 * pr[r0 + 2];
+      vi[n] = wm * gi + w0 * pi[r0] + w1 * pi[r0 + 1] + w2 * pi[r0 + 2];
+    }
+    float c1 = 1.f, s1 = 0.f;
+    if (rho > 0.f) {
+      c1 = x / rho;
+      s1 = y / rho;
+    }
+    const float c2 = c1 * c1 - s1 * s1, s2 = 2.f * s1 * c1;
+    const float Ar = vr[0] - vr[2] * c2, Ai = vi[0] - vi[2] * c2;
+    const float Br = vr[2] * s2, Bi = vi[2] * s2;
+    const float Cr = vr[0] + vr[2] * c2, Ci = vi[0] + vi[2] * c2;
+    const float exr = a.exr, exi = a.exi, eyr = a.eyr, eyi = a.eyi;
+    const float Exr = exr * Ar - exi * Ai - (eyr * Br - eyi * Bi);
+    const float Exi = exr * Ai + exi * Ar - (eyr * Bi + eyi * Br);
+    const float Eyr = -(exr * Br - exi * Bi) + (eyr * Cr - eyi * Ci);
+    const float Eyi = -(exr * Bi + exi * Br) + (eyr * Ci + eyi * Cr);
+    const float pr_ = exr * c1 + eyr * s1, pi_ = exi * c1 + eyi * s1;
+    const float qr = pr_ * vr[1] - pi_ * vi[1], qi = pr_ * vi[1] + pi_ * vr[1];
+    const float Ezr = 2.f * qi, Ezi = -2.f * qr;
+    if (Eb) {
+      Eb[pix] = make_float2(Exr, Exi);
+      Eb[plane + pix] = make_float2(Eyr, Eyi);
+      Eb[2 * plane + pix] = make_float2(Ezr, Ezi);
+    }
+    if (Ib) Ib[pix] = Exr * Exr + Exi * Exi + Eyr * Eyr + Eyi * Eyi + Ezr * Ezr + Ezi * Ezi;
+  }
+}
+
+// --------------------------------------------------------------------------
 // Plan and dispatch
 // --------------------------------------------------------------------------
+// Cost of the fused path per stencil base sample r0 = 0 .. R - 3, accumulated: per
+// radial sample the contraction (one table read, one Phi read and two FMAs per term and
+// node), per pixel its interpolation, angular combination and stores (the pixels of the
+// unshifted grid; a shifted stack only moves the balance).
+static void fused_plan_cost(rwpsf_plan* p) {
+  const int R = p->num.n_rho, T = p->n_theta_total, nr = R - 2;
+  const int terms = p->bessel_mode == kModeFresnel ? 5 : (p->bessel_mode == kModeScalar ? 1 : 3);
+  constexpr double kPixelCost = 120.0;
+  std::vector<double> cost(nr, 4.0 * terms * T);
+  const float inv = (float)(1.0 / p->drho), dx = (float)p->grid.dx_nm, dy = (float)p->grid.dy_nm;
+  for (int i = 0; i < p->grid.nx; ++i)
+    for (int j = 0; j < p->grid.ny; ++j) {
+      const float x = (float)(i - p->grid.nx / 2) * dx, y = (float)(j - p->grid.ny / 2) * dy;
+      cost[std::min((int)(std::sqrt(x * x + y * y) * inv), R - 3)] += kPixelCost;
+    }
+  p->fused_cum.assign(nr + 1, 0.0);
+  for (int r = 0; r < nr; ++r) p->fused_cum[r + 1] = p->fused_cum[r] + cost[r];
+}
+
 int bessel_scratch_init(int dev, float** out);
 
 int bessel_plan_init(rwpsf_plan* p) {
@@ -437,6 +678,7 @@ int bessel_plan_init(rwpsf_plan* p) {
   const double hx = (p->grid.nx / 2) * p->grid.dx_nm + p->grid.dx_nm;
   const double hy = (p->grid.ny / 2) * p->grid.dy_nm + p->grid.dy_nm;
   p->drho = std::sqrt(hx * hx + hy * hy) / (R - 3);
+  fused_plan_cost(p);
   int st;
   if ((st = dev_alloc(p, &p->d_theta, T))) return st;
   if ((st = dev_alloc(p, &p->d_wtheta, T))) return st;
@@ -473,16 +715,20 @@ int bessel_plan_init(rwpsf_plan* p) {
   if ((st = hip_check(hipFuncSetAttribute((const void*)bessel_epilogue_kernel,
                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024))))
     return st;
+  const void* fused[3] = {(const void*)bessel_fused_kernel<kModeVectorial>,
+                          (const void*)bessel_fused_kernel<kModeFresnel>, (const void*)bessel_fused_kernel<kModeScalar>};
+  for (const void* k : fused)
+    if ((st = hip_check(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, kFusedLdsBytes))))
+      return st;
   return hip_check(hipDeviceSynchronize());
 }
 
 // Pupil x defocus on the theta nodes for stacks s[0..nb), nb <= kPhiStacks, into the Phi
 // matrix at phi (its first column for these stacks), row stride ld complex entries.
-static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* phi, int ld, hipStream_t st) {
-  const int T = p->n_theta_total, nz = p->grid.nz;
-  PhiArgs pa{};
-  pa.T = T;
-  pa.nz = nz;
+template <int NS>
+static void fill_phi_args(const rwpsf_plan* p, const rwpsf_stack* s, int nb, PhiArgsT<NS>& pa) {
+  pa.T = p->n_theta_total;
+  pa.nz = p->grid.nz;
   pa.nstk = nb;
   pa.V = bessel_variants(p->bessel_mode);
   pa.gibson_lanni = p->opt.gibson_lanni;
@@ -502,6 +748,12 @@ static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* phi, 
     maxz = std::max(maxz, x.n_zernike);
   }
   pa.max_zernike = maxz;
+}
+
+static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* phi, int ld, hipStream_t st) {
+  const int T = p->n_theta_total, nz = p->grid.nz;
+  PhiArgs pa{};
+  fill_phi_args(p, s, nb, pa);
   const int total = T * nb * ((nz + kPhiZ - 1) / kPhiZ);
   const int tr = p->time_begin(RWPSF_KERNEL_BESSEL_PHI, st);
   hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, p->d_theta,
@@ -538,14 +790,86 @@ static void bessel_pol(const rwpsf_plan* p, float out[4]) {
   out[3] = (float)ey.imag();
 }
 
+// The fused launch of a call of n stacks: P bands per plane (about two workgroups per CU
+// in all) at equal shares of the plan's cost estimate, strictly increasing.  False when
+// the call is too large for it or its LDS does not fit.
+struct FusedPlan {
+  int P, ns_max;
+  int edge[kFusedBands + 1];
+};
+static bool fused_plan(const rwpsf_plan* p, int n, FusedPlan* f) {
+  const int nz = p->grid.nz, R = p->num.n_rho, nr = R - 2, T = p->n_theta_total;
+  if (n < 1 || n > kFusedStacks || n * nz > kFusedPlanes) return false;
+  const int P = std::max(1, std::min(std::min(kFusedBands, nr), 512 / (n * nz)));
+  const std::vector<double>& cum = p->fused_cum;
+  f->P = P;
+  f->edge[0] = 0;
+  f->edge[P] = nr;
+  int r = 0;
+  for (int b = 1; b < P; ++b) {
+    const double target = cum[nr] * b / P;
+    while (r < nr && cum[r] < target) ++r;
+    f->edge[b] = std::min(std::max(r, f->edge[b - 1] + 1), nr - (P - b));
+  }
+  f->ns_max = 0;
+  for (int b = 0; b < P; ++b)
+    f->ns_max = std::max(f->ns_max, std::min(f->edge[b + 1] + 2, R) - std::max(f->edge[b] - 1, 0));
+  const int NI = p->bessel_mode == kModeScalar ? 1 : 3;
+  return (size_t)fused_lds_floats(T, bessel_variants(p->bessel_mode), NI * f->ns_max) * sizeof(float) <=
+         (size_t)kFusedLdsBytes;
+}
+
+static int bessel_fused(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, const FusedPlan& f,
+                        hipStream_t st) {
+  const int mode = p->bessel_mode, NI = mode == kModeScalar ? 1 : 3;
+  FusedArgs a{};
+  fill_phi_args(p, s, n, a.phi);
+  a.nx = p->grid.nx;
+  a.ny = p->grid.ny;
+  a.R = p->num.n_rho;
+  a.P = f.P;
+  a.dx = (float)p->grid.dx_nm;
+  a.dy = (float)p->grid.dy_nm;
+  a.inv_drho = (float)(1.0 / p->drho);
+  float pol[4];
+  bessel_pol(p, pol);
+  a.exr = pol[0];
+  a.exi = pol[1];
+  a.eyr = pol[2];
+  a.eyi = pol[3];
+  for (int i = 0; i < n; ++i) {
+    a.x0[i] = (float)s[i].x0_nm;
+    a.y0[i] = (float)s[i].y0_nm;
+  }
+  for (int b = 0; b <= f.P; ++b) a.edge[b] = f.edge[b];
+  const size_t lds = (size_t)fused_lds_floats(p->n_theta_total, bessel_variants(mode), NI * f.ns_max) * sizeof(float);
+  const dim3 grid(n * p->grid.nz * f.P);
+  const int tr = p->time_begin(RWPSF_KERNEL_BESSEL_FUSED, st);
+  if (mode == kModeFresnel)
+    hipLaunchKernelGGL(bessel_fused_kernel<kModeFresnel>, grid, dim3(256), lds, st, a, p->d_theta, p->d_z, p->d_fq,
+                       p->d_btab, E, I);
+  else if (mode == kModeScalar)
+    hipLaunchKernelGGL(bessel_fused_kernel<kModeScalar>, grid, dim3(256), lds, st, a, p->d_theta, p->d_z, p->d_fq,
+                       p->d_btab, E, I);
+  else
+    hipLaunchKernelGGL(bessel_fused_kernel<kModeVectorial>, grid, dim3(256), lds, st, a, p->d_theta, p->d_z,
+                       p->d_fq, p->d_btab, E, I);
+  const int rc = hip_check(hipGetLastError());
+  p->time_end(tr, st);
+  return rc;
+}
+
 // Stacks s[0..n) in chunks of up to `chunk` (<= kEpiStacks) stacks, with Phi and I_n of a
 // chunk in the workspaces phi ([T][chunk nz V] complex) and In ([chunk nz V][2][G][R]
-// float): one contraction and one epilogue launch per chunk.
+// float): one contraction and one epilogue launch per chunk.  A call of one stack of few
+// planes takes the fused launch instead (no workspace).
 static int bessel_compute_ws(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, float* I, float2* phi,
                              float* In, int chunk, hipStream_t st) {
   int cur = -1;
   if (hipGetDevice(&cur) != hipSuccess || cur != p->device) return RWPSF_ERR_INVALID_ARG;
   if (6 * p->num.n_rho * 4 > 160 * 1024) return RWPSF_ERR_UNSUPPORTED;
+  FusedPlan fp;
+  if (fused_plan(p, n, &fp)) return bessel_fused(p, n, s, E, I, fp, st);
   const int T = p->n_theta_total, R = p->num.n_rho, nz = p->grid.nz;
   const int mode = p->bessel_mode, G = bessel_groups(mode), V = bessel_variants(mode);
   float pol[4];

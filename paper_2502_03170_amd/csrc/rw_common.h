@@ -202,6 +202,7 @@ struct rwpsf_plan {
   float2* d_phi = nullptr;      // workspace [T][stacks][nz][V] pupil x defocus (x q_v)
   float2* d_In = nullptr;       // workspace [stacks][nz][V][re/im][G][R]
   int bessel_stacks = 0;        // capacity of the Bessel workspaces
+  std::vector<double> fused_cum;   // Bessel, few stacks: accumulated cost per radial base sample
   float* scratch = nullptr;     // device address of the allocation-free entry point's fixed array
   double drho = 0;              // radial sample pitch
   // Bessel-form adjoint (built on first use)

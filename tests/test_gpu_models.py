@@ -150,6 +150,46 @@ def test_bessel_scalar_extra_sz_no_apodization(lib):
     _bessel_case(rw, torch, rw.MODEL_SCALAR, rw.THETA_SIMPSON, 101, extra_sz=True, apod=False)
 
 
+@pytest.mark.parametrize("mode", ["vectorial", "fresnel", "scalar"])
+def test_bessel_few_plane_launch_matches_chunked_path(lib, mode):
+    """A call of one stack takes one launch (phase, contraction and epilogue per radial
+    band of a plane); a call of more stacks takes the phase kernel, the matrix-core
+    contraction and the epilogue kernel.  The same six stacks (shifts, axisymmetric
+    Zernike terms, Gibson-Lanni depths) through both, stack by stack, and the many-stack
+    call against the oracle."""
+    import torch
+    rw = lib
+    w = W.bessel_plain(n_stacks=6, seed=103)
+    z = np.linspace(-900.0, 600.0, 9)
+    o = w["optics"]
+    scalar = mode == "scalar"
+    plan = rw.Plan(form=rw.FORM_BESSEL, na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], nx=45, ny=45,
+                   dx=20.0, dy=20.0, z=z, e_inc=W.X_LINEAR, n_theta=200, n_rho=256,
+                   model=rw.MODEL_SCALAR if scalar else rw.MODEL_VECTORIAL,
+                   fresnel=FRESNEL if mode == "fresnel" else None)
+    rng = np.random.default_rng(8)
+    stacks = []
+    for b in range(6):
+        c = np.zeros(22)
+        c[3], c[10], c[21] = rng.normal(0, 0.05, 3)
+        stacks.append(dict(z_offset=w["z_offsets"][b], x0=rng.uniform(-15, 15), y0=rng.uniform(-15, 15),
+                           zernike=c))
+    E, I = plan.compute(stacks)                 # six stacks: the chunked path
+    for b in range(6):
+        Eb, Ib = plan.compute([stacks[b]])      # one stack of 9 planes: the single launch
+        torch.cuda.synchronize()
+        assert rel_l2(_np(Eb[0]), _np(E[b])) < 1e-6, b
+        assert rel_l2(_np(Ib[0]), _np(I[b])) < 1e-6, b
+    opt = O.Optics(na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], e_inc=W.X_LINEAR,
+                   fresnel_media=FRESNEL if mode == "fresnel" else ())
+    for b in (0, 5):
+        s = stacks[b]
+        ref = OB.field_bessel(opt, 45, 45, 20.0, 20.0, z + s["z_offset"], x0=s["x0"], y0=s["y0"],
+                              n_theta=200, zernike=s["zernike"], scalar=scalar)
+        assert rel_l2(_np(E[b]), ref) < TOL, b
+        assert rel_l2(_np(I[b]), OF.intensity(ref)) < TOL, b
+
+
 # ------------------------------------------------------- accuracy benchmark (Sec. 5.2.2)
 NA, LAM, NI = 1.4, 532.0, 1.518
 
