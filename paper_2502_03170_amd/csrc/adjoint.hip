@@ -36,7 +36,7 @@
 
 namespace rw {
 
-constexpr int kAdjStacks = 32;   // stacks per adj_h / adj_g launch (every launch boundary costs ~10 us)
+constexpr int kAdjStacks = 32;   // stacks per adj_h / adj_g launch (fewer kernel prologues and tails)
 using CfgAdjH = RgCfg<128, 64, 16, 64, 32>;   // rows 2m + re/im, columns 2lf + p, k = n
 using CfgAdjG = RgCfg<64, 128, 16, 32, 64>;   // rows 2jf + p, columns 2(2lf + p) + re/im, k = m
 

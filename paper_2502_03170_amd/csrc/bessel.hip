@@ -389,9 +389,9 @@ __global__ void __launch_bounds__(256) bessel_epilogue_kernel(EpiArgs a, const f
 
 // --------------------------------------------------------------------------
 // Calls of one stack: phase, contraction and radial epilogue in one launch.  With a few
-// dozen planes the three-launch path is bound by its launch boundaries (the contraction
-// GEMM then has a dozen workgroups, each walking the whole theta range), so here one
-// workgroup serves one radial band of one plane.  It forms Phi of its plane on every
+// dozen planes the three-launch path is bound by its contraction (the GEMM then has a
+// dozen workgroups, each walking the whole theta range), so here one workgroup serves
+// one radial band of one plane.  It forms Phi of its plane on every
 // node into LDS, contracts it with the Bessel-table columns of the radial samples its
 // pixels' stencils reach (vector FMAs; the node range split between thread groups, eight
 // table loads in flight per thread, the partial sums added in a fixed order), then walks

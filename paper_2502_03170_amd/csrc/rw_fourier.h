@@ -6,9 +6,9 @@
 namespace rw {
 
 constexpr int kPupilStacks = 8;  // stacks per pupil launch (by-value arguments stay < 4 KB)
-constexpr int kGemmStacks = 64;  // stacks per GEMM launch (folded pupils of up to 8 pupil launches): every
-                                 // launch boundary costs about 10 us, and small outputs need many stacks
-                                 // per launch to fill the GPU
+constexpr int kGemmStacks = 64;  // stacks per GEMM launch (folded pupils of up to 8 pupil launches): fewer
+                                 // kernel prologues and tails, and small outputs need many stacks per
+                                 // launch to fill the GPU
 
 struct PupilStack {
   double t_s, x0, y0;
