@@ -150,42 +150,51 @@ def test_bessel_scalar_extra_sz_no_apodization(lib):
     _bessel_case(rw, torch, rw.MODEL_SCALAR, rw.THETA_SIMPSON, 101, extra_sz=True, apod=False)
 
 
-@pytest.mark.parametrize("mode", ["vectorial", "fresnel", "scalar"])
+@pytest.mark.parametrize("mode", ["vectorial", "fresnel", "scalar", "simpson_envelope_gl"])
 def test_bessel_few_plane_launch_matches_chunked_path(lib, mode):
     """A call of one stack takes one launch (phase, contraction and epilogue per radial
     band of a plane); a call of more stacks takes the phase kernel, the matrix-core
     contraction and the epilogue kernel.  The same six stacks (shifts, axisymmetric
-    Zernike terms, Gibson-Lanni depths) through both, stack by stack, and the many-stack
-    call against the oracle."""
+    Zernike terms; in the last case also the Simpson rule, the Gaussian envelope, the
+    extra s_z factor and Gibson-Lanni depths) through both, stack by stack, and the
+    many-stack call against the oracle."""
     import torch
     rw = lib
     w = W.bessel_plain(n_stacks=6, seed=103)
     z = np.linspace(-900.0, 600.0, 9)
     o = w["optics"]
     scalar = mode == "scalar"
+    extra = mode == "simpson_envelope_gl"
+    rule, n_theta = (rw.THETA_SIMPSON, 201) if extra else (rw.THETA_GAUSS, 200)
     plan = rw.Plan(form=rw.FORM_BESSEL, na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], nx=45, ny=45,
-                   dx=20.0, dy=20.0, z=z, e_inc=W.X_LINEAR, n_theta=200, n_rho=256,
+                   dx=20.0, dy=20.0, z=z, e_inc=W.X_LINEAR, n_theta=n_theta, n_rho=256, theta_rule=rule,
                    model=rw.MODEL_SCALAR if scalar else rw.MODEL_VECTORIAL,
-                   fresnel=FRESNEL if mode == "fresnel" else None)
+                   fresnel=FRESNEL if mode == "fresnel" else None, s_env=0.5 if extra else 0.0,
+                   extra_sz=extra, gibson_lanni=dict(GL) if extra else None)
     rng = np.random.default_rng(8)
     stacks = []
     for b in range(6):
         c = np.zeros(22)
         c[3], c[10], c[21] = rng.normal(0, 0.05, 3)
         stacks.append(dict(z_offset=w["z_offsets"][b], x0=rng.uniform(-15, 15), y0=rng.uniform(-15, 15),
-                           zernike=c))
+                           zernike=c, t_s=float(rng.uniform(0.0, 3000.0)) if extra else 0.0))
     E, I = plan.compute(stacks)                 # six stacks: the chunked path
     for b in range(6):
         Eb, Ib = plan.compute([stacks[b]])      # one stack of 9 planes: the single launch
         torch.cuda.synchronize()
         assert rel_l2(_np(Eb[0]), _np(E[b])) < 1e-6, b
         assert rel_l2(_np(Ib[0]), _np(I[b])) < 1e-6, b
+    gl = None
+    if extra:
+        gl = O.GibsonLanni(n_s=GL["n_s"], n_g=GL["n_g"], n_g_design=GL["n_g_design"], n_i_design=GL["n_i_design"],
+                           t_g=GL["t_g"], t_g_design=GL["t_g_design"], t_i_design=GL["t_i_design"])
     opt = O.Optics(na=o["na"], wavelength=o["wavelength"], n_i=o["n_i"], e_inc=W.X_LINEAR,
-                   fresnel_media=FRESNEL if mode == "fresnel" else ())
+                   fresnel_media=FRESNEL if mode == "fresnel" else (), s_env=0.5 if extra else 0.0, gl=gl)
     for b in (0, 5):
         s = stacks[b]
         ref = OB.field_bessel(opt, 45, 45, 20.0, 20.0, z + s["z_offset"], x0=s["x0"], y0=s["y0"],
-                              n_theta=200, zernike=s["zernike"], scalar=scalar)
+                              n_theta=n_theta, zernike=s["zernike"], scalar=scalar, t_s=s["t_s"],
+                              rule="simpson" if extra else "gauss", extra_cos=extra)
         assert rel_l2(_np(E[b]), ref) < TOL, b
         assert rel_l2(_np(I[b]), OF.intensity(ref)) < TOL, b
 
