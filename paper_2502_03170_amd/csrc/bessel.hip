@@ -92,29 +92,31 @@ struct PhiStack {
 constexpr int kPhiStacks = 64;
 template <int NS>
 struct PhiArgsT {
-  int T, nz, nstk, V, max_zernike, gibson_lanni, apod, extra_sz;   // V: variants per column
-  double k, s_max, s_env;
+  int T, nz, nstk, V, max_zernike, gibson_lanni;   // V: variants per column
+  double s_max;
   GLParams gl;
   PhiStack s[NS];
 };
 using PhiArgs = PhiArgsT<kPhiStacks>;
 
-// The plane-independent part of the pupil of stack `st` at node angle t: the amplitude
-// m = apodization x envelope x extra s_z x exp(-Im W) and the real phase W (Gibson-Lanni
-// and the axisymmetric Zernike terms), FP64 transcendentals.
+// Per theta node, from the plan (FP64): sin t, cos t, the stack-independent amplitude
+// (apodization x envelope x extra s_z factor) and k cos t.
+struct BesselNode {
+  double sin_t, cos_t, amp, kc;
+};
+
+// The plane-independent part of the pupil of stack `st` at node nd: the amplitude
+// m = nd.amp x exp(-Im W) and the real phase W (Gibson-Lanni and the axisymmetric
+// Zernike terms), FP64.
 template <class A>
-__device__ __forceinline__ void phi_node(const A& a, const PhiStack& st, double sin_t, double cos_t, float* m,
+__device__ __forceinline__ void phi_node(const A& a, const PhiStack& st, const BesselNode& nd, float* m,
                                          double* w) {
-  double amp = 1.0;
-  if (a.apod) amp *= sqrt(cos_t);
-  if (a.s_env > 0.0) amp *= exp(-(sin_t * sin_t) / (a.s_env * a.s_env));
-  if (a.extra_sz) amp *= cos_t;
   double w_re = 0.0, w_im = 0.0;
-  if (a.gibson_lanni) gl_opd(a.gl, st.t_s, sin_t, &w_re, &w_im);
-  const double r = sin_t / a.s_max;
+  if (a.gibson_lanni) gl_opd(a.gl, st.t_s, nd.sin_t, &w_re, &w_im);
+  const double r = nd.sin_t / a.s_max;
   for (int j = 0; j < kAxiTerms; ++j)
     if (st.coef[j] != 0.0) w_re += kTwoPi * st.coef[j] * zernike_noll(kAxiNoll[j], r, 1.0, 0.0);
-  *m = (float)(amp * exp(-w_im));
+  *m = (float)(w_im != 0.0 ? nd.amp * exp(-w_im) : nd.amp);
   *w = w_re;
 }
 
@@ -138,7 +140,7 @@ __device__ __forceinline__ void phi_plane(float m, double ph, int V, const float
 // only the defocus phase per plane.  phi: this launch's first column; ld: the row
 // stride of the Phi matrix in complex entries.
 constexpr int kPhiZ = 4;
-__global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
+__global__ void bessel_phi_kernel(PhiArgs a, const BesselNode* __restrict__ node,
                                   const double* __restrict__ z, const double* __restrict__ fq,
                                   float2* __restrict__ phi, int ld) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -148,12 +150,11 @@ __global__ void bessel_phi_kernel(PhiArgs a, const double* __restrict__ theta,
   const int q = idx / per_q, rem = idx % per_q;
   const int si = rem / nzg, z0 = (rem % nzg) * kPhiZ;
   const PhiStack& st = a.s[si];
-  const double t = theta[q];
-  const double sin_t = sin(t), cos_t = cos(t);
+  const BesselNode nd = node[q];
   float m;
   double w_re;
-  phi_node(a, st, sin_t, cos_t, &m, &w_re);
-  const double kc = a.k * cos_t;
+  phi_node(a, st, nd, &m, &w_re);
+  const double kc = nd.kc;
   float qsp[4] = {0.f, 0.f, 0.f, 0.f};
   if (a.V == 2)
     for (int i = 0; i < 4; ++i) qsp[i] = (float)fq[4 * q + i];
@@ -414,6 +415,7 @@ struct FusedArgs {
   float x0[kFusedStacks], y0[kFusedStacks];
   int edge[kFusedBands + 1];   // band b: pixels with r0 in [edge[b], edge[b + 1])
 };
+static_assert(sizeof(BesselNode) == 4 * sizeof(double), "the plan stores four doubles per node");
 static_assert(sizeof(FusedArgs) <= 4000, "kernel arguments are passed by value (4 KB limit)");
 
 template <int MODE>
@@ -430,7 +432,7 @@ __host__ __device__ inline int fused_lds_floats(int T, int V, int items) {
 }
 
 template <int MODE>
-__global__ void __launch_bounds__(256) bessel_fused_kernel(FusedArgs a, const double* __restrict__ theta,
+__global__ void __launch_bounds__(256) bessel_fused_kernel(FusedArgs a, const BesselNode* __restrict__ node,
                                                            const double* __restrict__ z,
                                                            const double* __restrict__ fq,
                                                            const float* __restrict__ btab,
@@ -446,15 +448,14 @@ __global__ void __launch_bounds__(256) bessel_fused_kernel(FusedArgs a, const do
   // ---- Phi of this plane on every node
   float2* ph = reinterpret_cast<float2*>(sh);
   for (int q = tid; q < T; q += 256) {
-    const double t = theta[q];
-    const double sin_t = sin(t), cos_t = cos(t);
+    const BesselNode nd = node[q];
     float m;
     double w;
-    phi_node(a.phi, st, sin_t, cos_t, &m, &w);
+    phi_node(a.phi, st, nd, &m, &w);
     float qsp[4] = {0.f, 0.f, 0.f, 0.f};
     if (V == 2)
       for (int k = 0; k < 4; ++k) qsp[k] = (float)fq[4 * q + k];
-    phi_plane(m, w + a.phi.k * cos_t * (z[zi] + st.zoff), V, qsp, ph + (size_t)q * V);
+    phi_plane(m, w + nd.kc * (z[zi] + st.zoff), V, qsp, ph + (size_t)q * V);
   }
   // ---- the band's radial samples: stencils r0 - 1 .. r0 + 2 of r0 in [e0, e1); the
   // ghost of r0 = 0 reads sample 1, which the band then holds (e1 >= 1)
@@ -704,6 +705,20 @@ int bessel_plan_init(rwpsf_plan* p) {
       return st;
   }
   if ((st = hip_check(hipMemcpy(p->d_theta, th.data(), T * sizeof(double), hipMemcpyHostToDevice)))) return st;
+  {
+    std::vector<BesselNode> nodes(T);
+    for (int q = 0; q < T; ++q) {
+      const double sn = std::sin(th[q]), cs = std::cos(th[q]);
+      double amp = 1.0;
+      if (p->opt.apodization) amp *= std::sqrt(cs);
+      if (p->opt.s_env > 0.0) amp *= std::exp(-(sn * sn) / (p->opt.s_env * p->opt.s_env));
+      if (p->opt.extra_sz) amp *= cs;
+      nodes[q] = BesselNode{sn, cs, amp, p->k * cs};
+    }
+    if ((st = dev_alloc(p, &p->d_node, 4 * (size_t)T))) return st;
+    if ((st = hip_check(hipMemcpy(p->d_node, nodes.data(), T * sizeof(BesselNode), hipMemcpyHostToDevice))))
+      return st;
+  }
   if ((st = hip_check(hipMemcpy(p->d_wtheta, wt.data(), T * sizeof(double), hipMemcpyHostToDevice)))) return st;
   if ((st = hip_check(hipMemcpy(p->d_z, p->z.data(), p->z.size() * sizeof(double), hipMemcpyHostToDevice)))) return st;
   const int total = G * R * T;
@@ -732,11 +747,7 @@ static void fill_phi_args(const rwpsf_plan* p, const rwpsf_stack* s, int nb, Phi
   pa.nstk = nb;
   pa.V = bessel_variants(p->bessel_mode);
   pa.gibson_lanni = p->opt.gibson_lanni;
-  pa.apod = p->opt.apodization;
-  pa.extra_sz = p->opt.extra_sz;
-  pa.k = p->k;
   pa.s_max = p->s_max;
-  pa.s_env = p->opt.s_env;
   pa.gl = p->gl;
   int maxz = 0;
   for (int i = 0; i < nb; ++i) {
@@ -756,7 +767,7 @@ static int bessel_phi(rwpsf_plan* p, const rwpsf_stack* s, int nb, float2* phi, 
   fill_phi_args(p, s, nb, pa);
   const int total = T * nb * ((nz + kPhiZ - 1) / kPhiZ);
   const int tr = p->time_begin(RWPSF_KERNEL_BESSEL_PHI, st);
-  hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, p->d_theta,
+  hipLaunchKernelGGL(bessel_phi_kernel, dim3((total + 255) / 256), dim3(256), 0, st, pa, reinterpret_cast<const BesselNode*>(p->d_node),
                      p->d_z, p->d_fq, phi, ld);
   const int rc = hip_check(hipGetLastError());
   p->time_end(tr, st);
@@ -846,13 +857,13 @@ static int bessel_fused(rwpsf_plan* p, int n, const rwpsf_stack* s, float2* E, f
   const dim3 grid(n * p->grid.nz * f.P);
   const int tr = p->time_begin(RWPSF_KERNEL_BESSEL_FUSED, st);
   if (mode == kModeFresnel)
-    hipLaunchKernelGGL(bessel_fused_kernel<kModeFresnel>, grid, dim3(256), lds, st, a, p->d_theta, p->d_z, p->d_fq,
+    hipLaunchKernelGGL(bessel_fused_kernel<kModeFresnel>, grid, dim3(256), lds, st, a, reinterpret_cast<const BesselNode*>(p->d_node), p->d_z, p->d_fq,
                        p->d_btab, E, I);
   else if (mode == kModeScalar)
-    hipLaunchKernelGGL(bessel_fused_kernel<kModeScalar>, grid, dim3(256), lds, st, a, p->d_theta, p->d_z, p->d_fq,
+    hipLaunchKernelGGL(bessel_fused_kernel<kModeScalar>, grid, dim3(256), lds, st, a, reinterpret_cast<const BesselNode*>(p->d_node), p->d_z, p->d_fq,
                        p->d_btab, E, I);
   else
-    hipLaunchKernelGGL(bessel_fused_kernel<kModeVectorial>, grid, dim3(256), lds, st, a, p->d_theta, p->d_z,
+    hipLaunchKernelGGL(bessel_fused_kernel<kModeVectorial>, grid, dim3(256), lds, st, a, reinterpret_cast<const BesselNode*>(p->d_node), p->d_z,
                        p->d_fq, p->d_btab, E, I);
   const int rc = hip_check(hipGetLastError());
   p->time_end(tr, st);

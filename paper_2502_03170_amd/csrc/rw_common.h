@@ -196,6 +196,7 @@ struct rwpsf_plan {
   int n_theta_total = 0;        // nodes after the critical-angle split
   double* d_theta = nullptr;    // [T] nodes
   double* d_wtheta = nullptr;   // [T] weights
+  double* d_node = nullptr;     // [T][4] Bessel form: sin, cos, stack-independent amplitude, k cos of each node
   int bessel_mode = 0;          // 0 vectorial, 1 vectorial with Fresnel factors, 2 scalar
   float* d_btab = nullptr;      // [T][G][R] w_t h_g(t) J_{n_g}(k rho_r sin t)
   double* d_fq = nullptr;       // [T][4] Fresnel products q_s, q_p per node (Fresnel mode)
